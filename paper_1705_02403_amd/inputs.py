@@ -1,0 +1,290 @@
+"""Seeded synthetic planning problems.
+
+This module only draws inputs; it holds none of the planner's arithmetic (no
+costs, radii, neighbour tests or collision checks along edges).  Both the HIP
+library and the CPU oracle are fed from here.
+
+Every coordinate is a multiple of 2^-20 (``QSCALE``), which FP32 represents
+exactly on [-1, 1]; the planner's Euclidean distances, goal tests and box
+tests are then exact integer arithmetic on both sides.
+
+State spaces (Section II, Problem 1; Section V-A for the double integrator):
+
+* ``euclid``: X = [0,1]^d, d in {2, 3}; boxes and samples live in all d dims.
+* ``di``: 6D double integrator, position in [0,1]^3 and velocity in the unit
+  ball; boxes and the goal ball constrain the 3 position dims only.
+
+Box worlds follow the workloads' recipe: per box and per axis a side
+U[smin, smax] and a lower corner U[0, 1-side]; a box containing the start or
+touching the closed goal ball is redrawn.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+QBITS = 20
+QSCALE = 1 << QBITS  # grid units per unit length
+
+
+def to_grid(x) -> np.ndarray:
+    """Float coordinates -> int64 grid units (round to nearest)."""
+    return np.rint(np.asarray(x, dtype=np.float64) * QSCALE).astype(np.int64)
+
+
+def from_grid(k) -> np.ndarray:
+    """int64 grid units -> FP32 coordinates (exact)."""
+    return (np.asarray(k, dtype=np.float64) / QSCALE).astype(np.float32)
+
+
+def on_grid(x) -> bool:
+    """True when every value is an exact multiple of 2^-20."""
+    a = np.asarray(x, dtype=np.float64) * QSCALE
+    return bool(np.all(a == np.rint(a)))
+
+
+@dataclasses.dataclass
+class Problem:
+    """One planning query (Problem 1): sample set, start, goal ball, boxes.
+
+    ``samples`` is SoA FP32 ``[dim][n]``; ``boxes`` is FP32 ``[m][2*pdim]`` with
+    the lower corner first.  ``goal_radius`` is an FP32 value held as a Python
+    float.  ``r`` is set for workloads whose radius is a fixed constant (the
+    double integrator); Euclidean workloads derive it from Theorem 1 with
+    ``r_factor`` = (1+eta)^(1/d).
+    """
+
+    kind: str
+    dim: int
+    pdim: int
+    samples: np.ndarray
+    x_init: np.ndarray
+    goal_center: np.ndarray
+    goal_radius: float
+    boxes: np.ndarray
+    lam: float
+    step: float = 0.0
+    traj_points: int = 16
+    r: Optional[float] = None
+    r_factor: float = 1.1
+    seed: int = 0
+    sample_seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.samples.shape[1])
+
+    @property
+    def m(self) -> int:
+        return int(self.boxes.shape[0])
+
+    def with_boxes(self, boxes: np.ndarray) -> "Problem":
+        return dataclasses.replace(self, boxes=np.ascontiguousarray(boxes, np.float32))
+
+
+# ---------------------------------------------------------------------------
+# drawing helpers (grid units)
+# ---------------------------------------------------------------------------
+
+def _in_any_box(p_q: np.ndarray, boxes_q: np.ndarray) -> np.ndarray:
+    """p_q [k, pd] int64, boxes_q [m, 2pd] int64 -> bool [k] (closed boxes)."""
+    if boxes_q.shape[0] == 0:
+        return np.zeros(p_q.shape[0], dtype=bool)
+    pd = p_q.shape[1]
+    lo = boxes_q[None, :, :pd]
+    hi = boxes_q[None, :, pd:]
+    p = p_q[:, None, :]
+    inside = np.all((p >= lo) & (p <= hi), axis=2)
+    return np.any(inside, axis=1)
+
+
+def _in_ball(p_q: np.ndarray, c_q: np.ndarray, radius: float) -> np.ndarray:
+    d = p_q - c_q[None, :]
+    dd = np.sum(d * d, axis=1).astype(np.float64)
+    rq = float(radius) * float(radius) * float(QSCALE) * float(QSCALE)
+    return dd <= rq
+
+
+def _box_touches_ball(lo: np.ndarray, hi: np.ndarray, c_q: np.ndarray, radius: float) -> bool:
+    gap = np.maximum(np.maximum(lo - c_q, 0), c_q - hi)
+    dd = float(np.sum(gap * gap))
+    return dd <= float(radius) * float(radius) * float(QSCALE) * float(QSCALE)
+
+
+def draw_boxes(rng: np.random.Generator, m: int, pdim: int, smin: float, smax: float,
+               start_q: np.ndarray, goal_q: np.ndarray, goal_radius: float) -> np.ndarray:
+    """m boxes (int64 grid units [m, 2*pdim]) avoiding the start and the goal ball."""
+    out = []
+    while len(out) < m:
+        side = rng.uniform(smin, smax, size=pdim)
+        lo = rng.uniform(0.0, 1.0 - side)
+        lo_q = to_grid(lo)
+        hi_q = np.minimum(to_grid(lo + side), QSCALE)
+        if np.all((start_q[:pdim] >= lo_q) & (start_q[:pdim] <= hi_q)):
+            continue
+        if _box_touches_ball(lo_q, hi_q, goal_q, goal_radius):
+            continue
+        out.append(np.concatenate([lo_q, hi_q]))
+    if not out:
+        return np.zeros((0, 2 * pdim), dtype=np.int64)
+    return np.stack(out).astype(np.int64)
+
+
+def draw_positions(rng: np.random.Generator, k: int, pdim: int) -> np.ndarray:
+    return rng.integers(0, QSCALE + 1, size=(k, pdim), dtype=np.int64)
+
+
+def draw_velocities(rng: np.random.Generator, k: int) -> np.ndarray:
+    """k velocities uniform in the closed unit ball (rejection from the cube)."""
+    out = np.zeros((0, 3), dtype=np.int64)
+    q2 = QSCALE * QSCALE
+    while out.shape[0] < k:
+        need = k - out.shape[0]
+        v = rng.integers(-QSCALE, QSCALE + 1, size=(2 * need + 16, 3), dtype=np.int64)
+        ok = np.sum(v * v, axis=1) <= q2
+        out = np.concatenate([out, v[ok]])
+    return out[:k]
+
+
+def _ensure_goal_sample(rng, pos_q: np.ndarray, goal_q: np.ndarray, goal_radius: float,
+                        boxes_q: Optional[np.ndarray]) -> None:
+    """If no position lies in the closed goal ball, replace the last one by a draw
+    from goal ball (and outside the boxes when given)."""
+    if np.any(_in_ball(pos_q, goal_q, goal_radius)):
+        return
+    pd = pos_q.shape[1]
+    rq = int(math.ceil(goal_radius * QSCALE))
+    lo = np.maximum(goal_q - rq, 0)
+    hi = np.minimum(goal_q + rq, QSCALE)
+    while True:
+        p = rng.integers(lo, hi + 1, size=(64, pd), dtype=np.int64)
+        ok = _in_ball(p, goal_q, goal_radius)
+        if boxes_q is not None:
+            ok &= ~_in_any_box(p, boxes_q)
+        if np.any(ok):
+            pos_q[-1] = p[np.argmax(ok)]
+            return
+
+
+def draw_free_positions(rng, n: int, pdim: int, boxes_q: np.ndarray) -> np.ndarray:
+    """n grid positions uniform in [0,1]^pdim minus the closed boxes."""
+    out = np.zeros((0, pdim), dtype=np.int64)
+    while out.shape[0] < n:
+        need = n - out.shape[0]
+        p = draw_positions(rng, int(need * 1.6) + 64, pdim)
+        out = np.concatenate([out, p[~_in_any_box(p, boxes_q)]])
+    return out[:n]
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def geometric_problem(seed: int, dim: int, n: int, m: int, smin: float, smax: float,
+                      lam: float = 0.5, step: float = 0.005, goal_radius: float = 0.05,
+                      r_factor: float = 1.1, start: float = 0.05, goal: float = 0.95) -> Problem:
+    """Euclidean box world (the 2D / 3D workloads): samples rejected from boxes,
+    start at (start,...), goal ball of radius 0.05 at (goal,...)."""
+    rng = np.random.default_rng(seed)
+    start_q = to_grid(np.full(dim, start))
+    goal_q = to_grid(np.full(dim, goal))
+    gr = float(np.float32(goal_radius))
+    boxes_q = draw_boxes(rng, m, dim, smin, smax, start_q, goal_q, gr)
+    pos_q = draw_free_positions(rng, n, dim, boxes_q)
+    _ensure_goal_sample(rng, pos_q, goal_q, gr, boxes_q)
+    return Problem(kind="euclid", dim=dim, pdim=dim,
+                   samples=np.ascontiguousarray(from_grid(pos_q.T)),
+                   x_init=from_grid(start_q), goal_center=from_grid(goal_q),
+                   goal_radius=gr, boxes=np.ascontiguousarray(from_grid(boxes_q)),
+                   lam=float(lam), step=float(step), r=None, r_factor=float(r_factor),
+                   seed=int(seed), sample_seed=int(seed))
+
+
+def problem_2d(seed: int, n: int = 2000, lam: float = 0.5) -> Problem:
+    """2D geometric workload: 20 boxes, sides U[0.05, 0.15], step 0.005."""
+    return geometric_problem(seed, 2, n, 20, 0.05, 0.15, lam=lam, step=0.005)
+
+
+def problem_3d(seed: int, n: int = 16384, lam: float = 0.5) -> Problem:
+    """3D geometric workload: 60 boxes, sides U[0.05, 0.2], step 0.002."""
+    return geometric_problem(seed, 3, n, 60, 0.05, 0.2, lam=lam, step=0.002)
+
+
+DI_RADIUS = 1.75          # connection radius of the double-integrator workload
+DI_START = (0.05, 0.05, 0.05)
+DI_GOAL = (0.95, 0.95, 0.95)
+
+
+def di_samples(sample_seed: int, n: int, goal_radius: float = 0.05) -> np.ndarray:
+    """SoA FP32 [6][n] double-integrator samples: position uniform in the unit
+    cube, velocity uniform in the unit ball; at least one position in the goal
+    ball.  Independent of any box world, so one sample set serves many queries."""
+    rng = np.random.default_rng(10_000_019 + int(sample_seed))
+    pos = draw_positions(rng, n, 3)
+    vel = draw_velocities(rng, n)
+    gr = float(np.float32(goal_radius))
+    _ensure_goal_sample(rng, pos, to_grid(np.array(DI_GOAL)), gr, None)
+    return np.ascontiguousarray(from_grid(np.concatenate([pos, vel], axis=1).T))
+
+
+def di_problem(seed: int, samples: np.ndarray, m: int = 40, smin: float = 0.05, smax: float = 0.2,
+               lam: float = 0.5, r: float = DI_RADIUS, jitter: float = 0.03,
+               traj_points: int = 16, sample_seed: int = 0) -> Problem:
+    """6D double-integrator query on a given sample set: start at rest near
+    (0.05,0.05,0.05) jittered by U[-jitter, jitter] per axis, goal ball of radius
+    0.05 about (0.95,0.95,0.95) over position (any velocity), m boxes."""
+    rng = np.random.default_rng(20_000_003 + int(seed))
+    start_p = np.array(DI_START) + rng.uniform(-jitter, jitter, size=3)
+    start_q = np.concatenate([to_grid(start_p), np.zeros(3, np.int64)])
+    goal_q = to_grid(np.array(DI_GOAL))
+    gr = float(np.float32(0.05))
+    boxes_q = draw_boxes(rng, m, 3, smin, smax, start_q, goal_q, gr)
+    return Problem(kind="di", dim=6, pdim=3, samples=samples,
+                   x_init=from_grid(start_q), goal_center=from_grid(goal_q), goal_radius=gr,
+                   boxes=np.ascontiguousarray(from_grid(boxes_q)), lam=float(lam), step=0.0,
+                   traj_points=int(traj_points), r=float(r), seed=int(seed),
+                   sample_seed=int(sample_seed))
+
+
+def problem_di(seed: int, n: int = 16384, sample_seed: Optional[int] = None, lam: float = 0.5,
+               r: float = DI_RADIUS) -> Problem:
+    """Headline workload: 6D double integrator, n samples, 40 boxes, lambda 0.5."""
+    ss = (seed % 8) if sample_seed is None else sample_seed
+    return di_problem(seed, di_samples(ss, n), lam=lam, r=r, sample_seed=ss)
+
+
+def problem_ids(count: int, first: int = 0) -> List[int]:
+    return list(range(first, first + count))
+
+
+def poisson_arrivals(count: int, rate_hz: float = 2000.0, seed: int = 7) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson stream: exponential inter-arrival."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_hz, size=count))
+
+
+def batch_specs(count: int = 512, seed: int = 7, sample_seeds: int = 4):
+    """Mixed batch: dim in {2, 3, 6}, n log-uniform in [1k, 32k], m in U{10..100}.
+
+    Returns dicts (dim, n, m, sample_seed, problem_seed); n is rounded to a
+    multiple of 256 so that problems share resident sample sets."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        dim = int(rng.choice([2, 3, 6]))
+        n = int(round(math.exp(rng.uniform(math.log(1024), math.log(32768)))))
+        n = max(1024, min(32768, 256 * int(round(n / 256))))
+        m = int(rng.integers(10, 101))
+        out.append(dict(dim=dim, n=n, m=m, sample_seed=int(rng.integers(0, sample_seeds)),
+                        problem_seed=1_000 + k))
+    return out
+
+
+def tiny_problem(seed: int, dim: int, n: int, m: int, lam: float, step: float = 0.01,
+                 smin: float = 0.1, smax: float = 0.3) -> Problem:
+    """Small Euclidean instance for brute-force cross-checks."""
+    return geometric_problem(seed, dim, n, m, smin, smax, lam=lam, step=step)
