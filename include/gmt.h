@@ -1,0 +1,234 @@
+/*
+ * gmt.h -- C ABI of the GMT* (Group Marching Tree) planning library for AMD
+ * Instinct MI355X (gfx950).  Every planning step runs in the library's HIP
+ * kernels; callers pass plain host or device pointers and sizes.
+ *
+ * Method: Ichter, Schmerling, Pavone, "Group Marching Tree: Sampling-Based
+ * Approximately Optimal Motion Planning on GPUs".  Problem 1 (Section II) is
+ * optimal path planning from x_init to a goal region through free space,
+ * reporting failure when no path exists; Algorithm 1 (Section III-A) is the
+ * group expansion solved here.
+ *
+ * Conventions (all entry points):
+ *  - Node numbering: samples are nodes 0..n-1; the start state x_init is node
+ *    n, the root of the tree.  Outputs of size n+1 are indexed by node.
+ *  - Coordinates (samples, x_init, goal centre, box corners) must be exact
+ *    multiples of 2^-20 (GMT_GRID); FP32 holds such values exactly on [-1, 1].
+ *    Positions lie in [0, 1]; double-integrator velocities in [-1, 1].  This
+ *    makes Euclidean distances, goal tests and box tests exact integer
+ *    arithmetic.  Inputs off the grid return GMT_EINVAL.
+ *  - Neighbours: u -> v is an edge when c(u -> v) < r (strict), the connection
+ *    rule stated before Algorithm 1.  For the Euclidean cost the test is
+ *    d2 < fl(r*r) * 2^40 with d2 the exact squared distance in grid units.
+ *  - Costs: Euclidean arc length (Section II), or for the 6D double
+ *    integrator x'' = u (Section V-A) the optimal J = tau + int |u|^2 dt over
+ *    the arrival time tau (two-point BVP cost, Section II footnote).  Edge
+ *    costs and costs-to-come are FP64.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls that
+ *    return host results synchronise that stream before returning.
+ *  - Errors: every function returns a gmt_status; nothing throws or aborts
+ *    across the ABI.  gmt_last_error() gives a thread-local message for the
+ *    last failing call on the calling thread.
+ *  - Device memory is obtained through the allocator installed with
+ *    gmt_set_allocator (default: hipMalloc/hipFree).
+ */
+#ifndef GMT_H
+#define GMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMT_GRID (1.0 / 1048576.0) /* coordinate quantum, 2^-20 */
+#define GMT_MAX_BOXES 2048         /* boxes per problem, staged in LDS (<= 48 KB) */
+#define GMT_MAX_DIM 6
+
+typedef enum {
+    GMT_OK = 0,        /* a node of the final group lies in the goal (Alg. 1 line 12b) */
+    GMT_NO_PATH = 1,   /* the open set emptied: report failure (Problem 1; Alg. 1 line 12a) */
+    GMT_ETIMEOUT = 2,  /* the threshold index reached opts.max_iters */
+    GMT_EINVAL = -1,   /* invalid argument (see each entry point) */
+    GMT_ENOMEM = -2,   /* the allocator returned NULL */
+    GMT_EDEVICE = -3,  /* a HIP call failed, or a kernel reported an internal fault */
+    GMT_EBUSY = -4     /* resource held by another call (engine slots full) */
+} gmt_status;
+
+typedef enum {
+    GMT_COST_EUCLIDEAN = 0,        /* state space [0,1]^d, d in {2, 3} */
+    GMT_COST_DOUBLE_INTEGRATOR = 1 /* state (p, v), p in [0,1]^3, v in [-1,1]^3, dim = 6 */
+} gmt_cost_kind;
+
+/* Opaque device-resident roadmap: a sample set with its r-disk neighbour
+ * table (Section V-A precomputes exactly this offline).  Read-only while
+ * plans run, so concurrent plans on different streams may share it. */
+typedef struct gmt_roadmap *gmt_roadmap_t;
+
+/* Device allocator callbacks.  alloc returns device memory of at least
+ * `bytes` bytes usable on `stream` (NULL on failure); free releases it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx, void *stream);
+    void (*free)(void *ptr, void *ctx, void *stream);
+    void *ctx;
+} gmt_allocator;
+
+/* Goal region X_goal: closed ball of `radius` about `center` over the first
+ * `ndims` coordinates (the position), other coordinates free.  ndims = d for
+ * the Euclidean cost, 3 for the double integrator. */
+typedef struct {
+    float center[GMT_MAX_DIM];
+    float radius;
+    int32_t ndims;
+} gmt_goal;
+
+/* Per-plan options.
+ *  edge_step   Euclidean lazy check: points y + k (x-y)/K1, k = 0..K1, with
+ *              K1 the least k >= 1 such that K1 * step >= |x - y| (the paper
+ *              discretises edges; Section V-A).  Must be > 0 for Euclidean.
+ *  traj_points double integrator: the optimal trajectory is checked at
+ *              traj_points times t_k = k tau/(traj_points-1) (>= 2).
+ *  max_iters   cap on the threshold index i of Algorithm 1 (<= 0: none).
+ *  team_wgs    workgroups cooperating on one plan (0: library choice).
+ *  lanes       lanes per candidate in the parent search: 0 (library choice)
+ *              or one of 4, 16, 64.  Results do not depend on it.  */
+typedef struct {
+    double edge_step;
+    int32_t traj_points;
+    int32_t max_iters;
+    int32_t team_wgs;
+    int32_t lanes;
+} gmt_plan_opts;
+
+/* Install the device allocator (NULL restores hipMalloc/hipFree).  Affects
+ * allocations made after the call; memory is returned to the allocator that
+ * produced it. */
+gmt_status gmt_set_allocator(const gmt_allocator *allocator);
+
+/* Build the r-disk neighbour table over n samples on the GPU (the offline
+ * precompute of Section V-A; neighbour rule before Algorithm 1).
+ *  d_samples  device FP32 SoA [dim][n], on the 2^-20 grid; copied.
+ *  kind       GMT_COST_EUCLIDEAN (dim 2 or 3) or GMT_COST_DOUBLE_INTEGRATOR
+ *             (dim 6).
+ *  r_n        connection radius (> 0).  For the double integrator the cost
+ *             threshold on J.
+ *  out        receives the roadmap; free with gmt_roadmap_free.
+ * The table holds, for every sample x, its in-neighbours y (c(y -> x) < r)
+ * in ascending order with FP64 costs (and FP64 arrival times for the double
+ * integrator), plus the out-neighbour table; for the symmetric Euclidean cost
+ * one table serves both.  Synchronises `stream` once (to size the table).
+ * Errors: GMT_EINVAL for n < 1, a bad dim/kind pair, r_n <= 0 or non-finite,
+ * samples off the grid or outside the state space, or a row of more than
+ * 4096 neighbours; GMT_ENOMEM; GMT_EDEVICE. */
+gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim, gmt_cost_kind kind,
+                               double r_n, void *stream, gmt_roadmap_t *out);
+
+/* Wrap an externally computed in-neighbour table (host arrays, copied):
+ * samples SoA [dim][n], row_ptr [n+1], col [nnz] (each row ascending, no
+ * self edges), cost [nnz] FP64, tau [nnz] FP64 (double integrator only, else
+ * NULL).  The out-neighbour table is derived.  Same errors as
+ * gmt_build_neighbors, plus GMT_EINVAL for a malformed table. */
+gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int32_t dim, gmt_cost_kind kind,
+                                double r_n, const int32_t *row_ptr, const int32_t *col,
+                                const double *cost, const double *tau, void *stream,
+                                gmt_roadmap_t *out);
+
+/* Sizes of a roadmap: samples, state dimension, cost kind, number of edges. */
+gmt_status gmt_roadmap_info(gmt_roadmap_t rm, int32_t *n, int32_t *dim, int32_t *kind,
+                            int64_t *nnz);
+
+/* Copy the in-neighbour table to host arrays: row_ptr [n+1], col [nnz],
+ * cost [nnz], tau [nnz] (any of col/cost/tau may be NULL). */
+gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int32_t *col, double *cost,
+                              double *tau, void *stream);
+
+/* Release a roadmap (NULL is accepted). */
+gmt_status gmt_roadmap_free(gmt_roadmap_t rm);
+
+/* Solve one query with Algorithm 1 on a resident roadmap.
+ *  x_init     host [dim], in free space (Problem 1 requires x_init in X_free).
+ *  goal       goal ball (see gmt_goal).
+ *  boxes      host FP32 [m][2*pdim]: lower corner then upper corner, closed
+ *             axis-aligned obstacle boxes over the position (pdim = d, or 3
+ *             for the double integrator); 0 <= m <= GMT_MAX_BOXES.
+ *  lambda     group cost threshold factor in [0, 1]; delta = lambda * r.
+ *             lambda = 0 expands only the least-cost open nodes (FMT*).
+ *  opts       may be NULL (Euclidean step then must come from opts: NULL is
+ *             only valid for the double integrator, traj_points 16).
+ *  d_parent, d_cost, d_group_iter, d_added_iter  optional device outputs of
+ *             n+1 entries: parent node (-1 for the root and nodes outside the
+ *             tree), FP64 cost-to-come (+inf outside the tree), the iteration
+ *             whose group expanded the node (-1 never), the iteration that
+ *             added it (-1 root, -2 outside the tree).
+ *  path       host buffer of path_cap nodes, root first; *path_len receives
+ *             the full length (only the first path_cap nodes are written).
+ *  path_cost  FP64 cost of the returned goal node.
+ *  iters      the iteration index i at termination (may be NULL).
+ * Returns GMT_OK, GMT_NO_PATH or GMT_ETIMEOUT (trees are written in all
+ * three cases), or an error: GMT_EINVAL for a NULL roadmap, x_init outside
+ * the state space or inside a box, off-grid inputs, lambda outside [0,1], m
+ * outside [0, GMT_MAX_BOXES], edge_step <= 0 (Euclidean), traj_points < 2;
+ * GMT_ENOMEM; GMT_EDEVICE.  Synchronises `stream`. */
+gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
+                    const float *boxes, int32_t m, double lambda, const gmt_plan_opts *opts,
+                    int32_t *d_parent, double *d_cost, int32_t *d_group_iter,
+                    int32_t *d_added_iter, int32_t *path, int32_t path_cap, int32_t *path_len,
+                    double *path_cost, int32_t *iters, void *stream);
+
+/* One query of a batch. */
+typedef struct {
+    gmt_roadmap_t roadmap;
+    const float *x_init; /* host [dim] */
+    gmt_goal goal;
+    const float *boxes; /* host [m][2*pdim] */
+    int32_t m;
+    double lambda;
+} gmt_problem;
+
+/* Result of one batched query: status, iteration index at termination, path
+ * length and cost; `path` (host, path_cap entries, root first) is filled when
+ * not NULL; the optional device arrays get the tree as in gmt_plan. */
+typedef struct {
+    int32_t status;
+    int32_t iters;
+    int32_t path_len;
+    int32_t path_cap;
+    double path_cost;
+    int32_t *path;
+    int32_t *d_parent;
+    double *d_cost;
+    int32_t *d_group_iter;
+    int32_t *d_added_iter;
+} gmt_result;
+
+/* Batch options: the plan options shared by every query, and the launch
+ * shape: `workgroups` persistent workgroups (0: fill the GPU) that pull
+ * queries from a device queue, `team_wgs` workgroups per query (1 = one
+ * workgroup per query).  Results do not depend on the launch shape. */
+typedef struct {
+    gmt_plan_opts plan;
+    int32_t workgroups;
+    int32_t threads;
+} gmt_batch_opts;
+
+/* Solve `count` independent queries (possibly on different roadmaps, of
+ * different n and m) in one persistent launch.  Each result equals what
+ * gmt_plan returns for the same query.  Per-query statuses go to
+ * results[k].status; the call returns GMT_OK when the batch ran (even if
+ * some queries found no path), or an error for an invalid query (no query
+ * is run then) or a device failure.  Synchronises `stream`. */
+gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count, const gmt_batch_opts *opts,
+                          gmt_result *results, void *stream);
+
+/* Thread-local message describing the last error on this thread. */
+const char *gmt_last_error(void);
+
+/* Library version string. */
+const char *gmt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMT_H */

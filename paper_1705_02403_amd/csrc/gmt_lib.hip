@@ -1,0 +1,881 @@
+// gmt_lib.hip -- host side of the C ABI declared in include/gmt.h.
+//
+// Roadmaps and per-query workspaces live in device memory obtained from the
+// installed allocator.  A query is staged into pinned host memory (problem
+// descriptor, box list, queue counter), copied with one H2D transfer, solved
+// by the persistent kernel k_plan and read back with one D2H transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gmt.h"
+#include "gmt_build.hpp"
+#include "gmt_dev.hpp"
+#include "gmt_plan.hpp"
+
+using namespace gmt;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static gmt_status fail(gmt_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(GMT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// allocator
+// ---------------------------------------------------------------------------
+static std::mutex g_alloc_mu;
+static gmt_allocator g_alloc = {nullptr, nullptr, nullptr};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    gmt_allocator a{nullptr, nullptr, nullptr};
+};
+
+static gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
+    gmt_allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    bytes = bytes ? (bytes + 255) & ~size_t(255) : 256;
+    void *p = nullptr;
+    if (a.alloc) {
+        p = a.alloc(bytes, a.ctx, (void *)s);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (!p) return fail(GMT_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    b.p = p;
+    b.bytes = bytes;
+    b.a = a;
+    return GMT_OK;
+}
+
+static void dev_free(DevBuf &b, hipStream_t s) {
+    if (!b.p) return;
+    if (b.a.free)
+        b.a.free(b.p, b.a.ctx, (void *)s);
+    else if (!b.a.alloc)
+        (void)hipFree(b.p);
+    b.p = nullptr;
+}
+
+extern "C" gmt_status gmt_set_allocator(const gmt_allocator *allocator) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (allocator && (!allocator->alloc || !allocator->free))
+        return fail(GMT_EINVAL, "allocator needs both alloc and free");
+    g_alloc = allocator ? *allocator : gmt_allocator{nullptr, nullptr, nullptr};
+    return GMT_OK;
+}
+
+extern "C" const char *gmt_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *gmt_version(void) { return "gmt-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// roadmap
+// ---------------------------------------------------------------------------
+struct gmt_roadmap {
+    int n = 0, dim = 0, kind = 0;
+    double r = 0.0;
+    long long nnz = 0;
+    DevBuf s, in_ptr, in_col, in_cost, in_tau, out_ptr, out_col;
+    bool out_shared = false;
+};
+
+static bool on_grid(double x) {
+    double q = x * GMT_QS;
+    return std::isfinite(q) && q == std::floor(q);
+}
+
+static int pdim_of(int kind, int dim) { return kind == GMT_COST_DOUBLE_INTEGRATOR ? 3 : dim; }
+
+static gmt_status check_shape(int32_t n, int32_t dim, gmt_cost_kind kind, double r) {
+    if (n < 1) return fail(GMT_EINVAL, "n must be >= 1 (got %d)", n);
+    if (kind == GMT_COST_EUCLIDEAN) {
+        if (dim != 2 && dim != 3) return fail(GMT_EINVAL, "Euclidean roadmaps need dim 2 or 3 (got %d)", dim);
+    } else if (kind == GMT_COST_DOUBLE_INTEGRATOR) {
+        if (dim != 6) return fail(GMT_EINVAL, "double-integrator roadmaps need dim 6 (got %d)", dim);
+    } else {
+        return fail(GMT_EINVAL, "unknown cost kind %d", (int)kind);
+    }
+    if (!(r > 0.0) || !std::isfinite(r)) return fail(GMT_EINVAL, "radius must be finite and > 0");
+    return GMT_OK;
+}
+
+static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
+    dev_free(rm->s, s);
+    dev_free(rm->in_ptr, s);
+    dev_free(rm->in_col, s);
+    dev_free(rm->in_cost, s);
+    dev_free(rm->in_tau, s);
+    if (!rm->out_shared) {
+        dev_free(rm->out_ptr, s);
+        dev_free(rm->out_col, s);
+    }
+}
+
+#define TRY(expr)                        \
+    do {                                 \
+        gmt_status st_ = (expr);         \
+        if (st_ != GMT_OK) return st_;   \
+    } while (0)
+
+static inline unsigned blocks_for(long long threads, int per) { return (unsigned)((threads + per - 1) / per); }
+
+// out-neighbour table by transposing the in-table, rows sorted
+static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
+    const int n = rm->n;
+    DevBuf deg, cursor, flags;
+    TRY(dev_alloc(rm->out_ptr, sizeof(int) * (n + 1), s));
+    TRY(dev_alloc(rm->out_col, sizeof(int) * std::max<long long>(rm->nnz, 1), s));
+    rm->out_shared = false;
+    TRY(dev_alloc(deg, sizeof(int) * n, s));
+    TRY(dev_alloc(cursor, sizeof(int) * n, s));
+    TRY(dev_alloc(flags, 64, s));
+    k_fill_int<<<1, 64, 0, s>>>((int *)flags.p, 16, 0);
+    k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)deg.p, n, 0);
+    k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)cursor.p, n, 0);
+    k_out_count<<<blocks_for(n, 256), 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
+                                                   (int *)deg.p);
+    k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->out_ptr.p, nullptr);
+    k_out_place<<<blocks_for(n, 256), 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
+                                                   (const int *)rm->out_ptr.p, (int *)cursor.p,
+                                                   (int *)rm->out_col.p);
+    // rows of up to 4096 entries sorted in LDS by one wave each
+    k_rows_sort<<<blocks_for((long long)n * GMT_WAVE, 64), 64, 4096 * sizeof(int), s>>>(
+        (const int *)rm->out_ptr.p, n, 4096, (int *)rm->out_col.p, (int *)flags.p);
+    HIPCHK(hipGetLastError());
+    int hf = 0;
+    HIPCHK(hipMemcpyAsync(&hf, flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(deg, s);
+    dev_free(cursor, s);
+    dev_free(flags, s);
+    if (hf) return fail(GMT_EINVAL, "a node has more than 4096 out-neighbours: radius too large");
+    return GMT_OK;
+}
+
+static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
+    const int n = rm->n, dim = rm->dim;
+    const double R2 = rm->r * rm->r * GMT_Q2;
+    EuGrid g;
+    g.dim = dim;
+    double inv = 1.0 / rm->r;
+    int Gmax = dim == 2 ? 2048 : 160;
+    g.G = inv >= Gmax ? Gmax : std::max(1, (int)std::floor(inv));
+    g.ncell = 1;
+    for (int a = 0; a < dim; ++a) g.ncell *= g.G;
+    DevBuf cell_of, cell_cnt, cell_start, cursor, perm, sq, deg, scal;
+    TRY(dev_alloc(cell_of, sizeof(int) * n, s));
+    TRY(dev_alloc(cell_cnt, sizeof(int) * g.ncell, s));
+    TRY(dev_alloc(cell_start, sizeof(int) * (g.ncell + 1), s));
+    TRY(dev_alloc(cursor, sizeof(int) * g.ncell, s));
+    TRY(dev_alloc(perm, sizeof(int) * n, s));
+    TRY(dev_alloc(sq, sizeof(int) * (size_t)dim * n, s));
+    TRY(dev_alloc(deg, sizeof(int) * n, s));
+    TRY(dev_alloc(scal, 64, s));  // [0] flags, [1] maxdeg, [2..3] total (long long)
+    TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
+    int *flags = (int *)scal.p, *maxdeg = flags + 1;
+    long long *total = (long long *)(flags + 2);
+    k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
+    k_fill_int<<<blocks_for(g.ncell, 256), 256, 0, s>>>((int *)cell_cnt.p, g.ncell, 0);
+    k_fill_int<<<blocks_for(g.ncell, 256), 256, 0, s>>>((int *)cursor.p, g.ncell, 0);
+    k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, dim, 0, flags);
+    k_eu_bin<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (int *)cell_of.p,
+                                               (int *)cell_cnt.p);
+    k_scan_small<<<1, 1024, 0, s>>>((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr);
+    k_eu_scatter<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (const int *)cell_of.p,
+                                                   (const int *)cell_start.p, (int *)cursor.p,
+                                                   (int *)perm.p, (int *)sq.p);
+    k_eu_count<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
+        n, g, (const int *)sq.p, (const int *)perm.p, (const int *)cell_start.p, R2, (int *)deg.p, maxdeg);
+    k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
+    HIPCHK(hipGetLastError());
+    int hs[4];
+    HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long long E;
+    std::memcpy(&E, hs + 2, sizeof E);
+    gmt_status st = GMT_OK;
+    if (hs[0]) st = fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
+    else if (hs[1] > 4096) st = fail(GMT_EINVAL, "a row has %d neighbours (limit 4096): radius too large", hs[1]);
+    else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    if (st == GMT_OK) {
+        rm->nnz = E;
+        st = dev_alloc(rm->in_col, sizeof(int) * std::max<long long>(E, 1), s);
+        if (st == GMT_OK) st = dev_alloc(rm->in_cost, sizeof(double) * std::max<long long>(E, 1), s);
+    }
+    if (st == GMT_OK) {
+        int cap = std::max(64, (hs[1] + 63) / 64 * 64);
+        int threads = (cap * 12 * 4 <= 64 * 1024) ? 256 : 64;
+        size_t lds = (size_t)(threads / GMT_WAVE) * cap * 12;
+        k_eu_fill<<<blocks_for((long long)n * GMT_WAVE, threads), threads, lds, s>>>(
+            n, g, (const int *)sq.p, (const int *)perm.p, (const int *)cell_start.p, R2,
+            (const int *)rm->in_ptr.p, cap, (int *)rm->in_col.p, (double *)rm->in_cost.p);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
+    }
+    dev_free(cell_of, s);
+    dev_free(cell_cnt, s);
+    dev_free(cell_start, s);
+    dev_free(cursor, s);
+    dev_free(perm, s);
+    dev_free(sq, s);
+    dev_free(deg, s);
+    dev_free(scal, s);
+    if (st != GMT_OK) return st;
+    rm->out_ptr = rm->in_ptr;
+    rm->out_col = rm->in_col;
+    rm->out_shared = true;
+    return GMT_OK;
+}
+
+static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
+    const int n = rm->n;
+    DevBuf deg, scal;
+    TRY(dev_alloc(deg, sizeof(int) * n, s));
+    TRY(dev_alloc(scal, 64, s));
+    TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
+    int *flags = (int *)scal.p, *maxdeg = flags + 1;
+    long long *total = (long long *)(flags + 2);
+    k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
+    k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
+    k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
+        (const float *)rm->s.p, n, rm->r, 1, nullptr, (int *)deg.p, maxdeg, nullptr, nullptr, nullptr);
+    k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
+    HIPCHK(hipGetLastError());
+    int hs[4];
+    HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long long E;
+    std::memcpy(&E, hs + 2, sizeof E);
+    gmt_status st = GMT_OK;
+    if (hs[0]) st = fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, on the 2^-20 grid");
+    else if (hs[1] > 4096) st = fail(GMT_EINVAL, "a row has %d neighbours (limit 4096): radius too large", hs[1]);
+    else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    if (st == GMT_OK) {
+        rm->nnz = E;
+        size_t e1 = (size_t)std::max<long long>(E, 1);
+        st = dev_alloc(rm->in_col, sizeof(int) * e1, s);
+        if (st == GMT_OK) st = dev_alloc(rm->in_cost, sizeof(double) * e1, s);
+        if (st == GMT_OK) st = dev_alloc(rm->in_tau, sizeof(double) * e1, s);
+    }
+    if (st == GMT_OK) {
+        k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
+            (const float *)rm->s.p, n, rm->r, 0, (const int *)rm->in_ptr.p, (int *)deg.p, maxdeg,
+            (int *)rm->in_col.p, (double *)rm->in_cost.p, (double *)rm->in_tau.p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
+    }
+    dev_free(deg, s);
+    if (st == GMT_OK) st = build_out_table(rm, s);
+    dev_free(scal, s);
+    return st;
+}
+
+extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim,
+                                          gmt_cost_kind kind, double r_n, void *stream,
+                                          gmt_roadmap_t *out) {
+    if (!out || !d_samples) return fail(GMT_EINVAL, "null argument");
+    *out = nullptr;
+    TRY(check_shape(n, dim, kind, r_n));
+    hipStream_t s = (hipStream_t)stream;
+    gmt_roadmap *rm = new gmt_roadmap;
+    rm->n = n;
+    rm->dim = dim;
+    rm->kind = kind;
+    rm->r = r_n;
+    gmt_status st = dev_alloc(rm->s, sizeof(float) * (size_t)dim * n, s);
+    if (st == GMT_OK) {
+        hipError_t e = hipMemcpyAsync(rm->s.p, d_samples, sizeof(float) * (size_t)dim * n,
+                                      hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "sample copy failed: %s", hipGetErrorString(e));
+    }
+    if (st == GMT_OK) st = (kind == GMT_COST_EUCLIDEAN) ? build_euclid(rm, s) : build_di(rm, s);
+    if (st != GMT_OK) {
+        (void)hipStreamSynchronize(s);
+        roadmap_release(rm, s);
+        delete rm;
+        return st;
+    }
+    *out = rm;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int32_t dim,
+                                           gmt_cost_kind kind, double r_n, const int32_t *row_ptr,
+                                           const int32_t *col, const double *cost, const double *tau,
+                                           void *stream, gmt_roadmap_t *out) {
+    if (!out || !samples || !row_ptr || (!col && row_ptr[n] > 0) || (!cost && row_ptr[n] > 0))
+        return fail(GMT_EINVAL, "null argument");
+    *out = nullptr;
+    TRY(check_shape(n, dim, kind, r_n));
+    if (kind == GMT_COST_DOUBLE_INTEGRATOR && !tau && row_ptr[n] > 0)
+        return fail(GMT_EINVAL, "double-integrator tables need arrival times");
+    const int pd = pdim_of(kind, dim);
+    for (int a = 0; a < dim; ++a)
+        for (int i = 0; i < n; ++i) {
+            double x = samples[(size_t)a * n + i];
+            double lo = a < pd ? 0.0 : -1.0;
+            if (!on_grid(x) || x < lo || x > 1.0) return fail(GMT_EINVAL, "sample %d off the grid or out of range", i);
+        }
+    if (row_ptr[0] != 0) return fail(GMT_EINVAL, "row_ptr[0] must be 0");
+    for (int i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(GMT_EINVAL, "row_ptr must be non-decreasing");
+        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n || col[e] == i) return fail(GMT_EINVAL, "bad column in row %d", i);
+            if (e > row_ptr[i] && col[e] <= col[e - 1]) return fail(GMT_EINVAL, "row %d not strictly ascending", i);
+            if (!(cost[e] >= 0.0) || !std::isfinite(cost[e])) return fail(GMT_EINVAL, "bad cost in row %d", i);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    gmt_roadmap *rm = new gmt_roadmap;
+    rm->n = n;
+    rm->dim = dim;
+    rm->kind = kind;
+    rm->r = r_n;
+    rm->nnz = row_ptr[n];
+    size_t e1 = (size_t)std::max<long long>(rm->nnz, 1);
+    gmt_status st = GMT_OK;
+    auto up = [&](DevBuf &b, const void *h, size_t bytes) {
+        if (st != GMT_OK) return;
+        st = dev_alloc(b, bytes, s);
+        if (st != GMT_OK || !h || !bytes) return;
+        hipError_t e = hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    };
+    up(rm->s, samples, sizeof(float) * (size_t)dim * n);
+    up(rm->in_ptr, row_ptr, sizeof(int) * (n + 1));
+    up(rm->in_col, col, sizeof(int) * rm->nnz);
+    up(rm->in_cost, cost, sizeof(double) * rm->nnz);
+    (void)e1;
+    if (kind == GMT_COST_DOUBLE_INTEGRATOR) up(rm->in_tau, tau, sizeof(double) * rm->nnz);
+    if (st == GMT_OK) st = build_out_table(rm, s);
+    if (st != GMT_OK) {
+        (void)hipStreamSynchronize(s);
+        roadmap_release(rm, s);
+        delete rm;
+        return st;
+    }
+    *out = rm;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_roadmap_info(gmt_roadmap_t rm, int32_t *n, int32_t *dim, int32_t *kind,
+                                       int64_t *nnz) {
+    if (!rm) return fail(GMT_EINVAL, "null roadmap");
+    if (n) *n = rm->n;
+    if (dim) *dim = rm->dim;
+    if (kind) *kind = rm->kind;
+    if (nnz) *nnz = rm->nnz;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int32_t *col,
+                                         double *cost, double *tau, void *stream) {
+    if (!rm) return fail(GMT_EINVAL, "null roadmap");
+    hipStream_t s = (hipStream_t)stream;
+    if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, rm->in_ptr.p, sizeof(int) * (rm->n + 1), hipMemcpyDeviceToHost, s));
+    if (col && rm->nnz) HIPCHK(hipMemcpyAsync(col, rm->in_col.p, sizeof(int) * rm->nnz, hipMemcpyDeviceToHost, s));
+    if (cost && rm->nnz) HIPCHK(hipMemcpyAsync(cost, rm->in_cost.p, sizeof(double) * rm->nnz, hipMemcpyDeviceToHost, s));
+    if (tau && rm->nnz && rm->in_tau.p)
+        HIPCHK(hipMemcpyAsync(tau, rm->in_tau.p, sizeof(double) * rm->nnz, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_roadmap_free(gmt_roadmap_t rm) {
+    if (!rm) return GMT_OK;
+    (void)hipDeviceSynchronize();
+    roadmap_release(rm, nullptr);
+    delete rm;
+    return GMT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces: per-team planning state, reused across calls
+// ---------------------------------------------------------------------------
+struct WsBlock {
+    int teams = 0, cap = 0;
+    DevBuf mem;       // all teams' arrays
+    DevBuf d_ws;      // Ws[teams]
+    DevBuf stage_d;   // device copy of the staged queries
+    void *stage_h = nullptr;  // pinned: [queue counter][ProbDev x count][boxes]
+    size_t stage_bytes = 0;
+    DevBuf res_d;     // Result[count]
+    Result *res_h = nullptr;  // pinned
+    int res_count = 0;
+    bool busy = false;
+};
+
+static std::mutex g_ws_mu;
+static std::vector<WsBlock *> g_ws;
+
+static size_t ws_team_bytes(int cap) {
+    size_t c = (size_t)cap;
+    size_t b = 16 * c;           // node
+    b += 4 * c * 6;              // parent, stamp, open0, open1, glist, hits
+    b += (c + 15) / 16 * 16;     // goal
+    b += 256;                    // ctl
+    return (b + 255) & ~size_t(255);
+}
+
+static gmt_status ws_acquire(int teams, int cap, hipStream_t s, WsBlock **out) {
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (WsBlock *w : g_ws)
+            if (!w->busy && w->teams >= teams && w->cap >= cap) {
+                w->busy = true;
+                *out = w;
+                return GMT_OK;
+            }
+    }
+    WsBlock *w = new WsBlock;
+    w->teams = teams;
+    w->cap = cap;
+    size_t tb = ws_team_bytes(cap);
+    gmt_status st = dev_alloc(w->mem, tb * teams, s);
+    if (st == GMT_OK) st = dev_alloc(w->d_ws, sizeof(Ws) * teams, s);
+    if (st != GMT_OK) {
+        dev_free(w->mem, s);
+        delete w;
+        return st;
+    }
+    std::vector<Ws> h(teams);
+    char *base = (char *)w->mem.p;
+    for (int k = 0; k < teams; ++k) {
+        char *p = base + tb * k;
+        Ws &x = h[k];
+        x.node = (NodeState *)p;
+        p += 16 * (size_t)cap;
+        x.parent = (int *)p;
+        p += 4 * (size_t)cap;
+        x.stamp = (int *)p;
+        p += 4 * (size_t)cap;
+        x.open[0] = (int *)p;
+        p += 4 * (size_t)cap;
+        x.open[1] = (int *)p;
+        p += 4 * (size_t)cap;
+        x.glist = (int *)p;
+        p += 4 * (size_t)cap;
+        x.hits = (int *)p;
+        p += 4 * (size_t)cap;
+        x.goal = (unsigned char *)p;
+        p += ((size_t)cap + 15) / 16 * 16;
+        p = (char *)(((uintptr_t)p + 255) & ~uintptr_t(255));
+        x.ctl = (Ctl *)p;
+        x.cap = cap;
+        x.pad = 0;
+    }
+    if (hipMemsetAsync(w->mem.p, 0, tb * teams, s) != hipSuccess ||
+        hipMemcpyAsync(w->d_ws.p, h.data(), sizeof(Ws) * teams, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        dev_free(w->mem, s);
+        dev_free(w->d_ws, s);
+        delete w;
+        return fail(GMT_EDEVICE, "workspace initialisation failed");
+    }
+    w->busy = true;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_ws.push_back(w);
+    *out = w;
+    return GMT_OK;
+}
+
+static void ws_release(WsBlock *w) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    w->busy = false;
+}
+
+static gmt_status ws_stage(WsBlock *w, size_t bytes, int count, hipStream_t s) {
+    if (w->stage_bytes < bytes) {
+        if (w->stage_h) (void)hipHostFree(w->stage_h);
+        dev_free(w->stage_d, s);
+        w->stage_h = nullptr;
+        w->stage_bytes = 0;
+        size_t b = std::max(bytes, (size_t)65536);
+        if (hipHostMalloc(&w->stage_h, b, hipHostMallocDefault) != hipSuccess)
+            return fail(GMT_ENOMEM, "pinned staging allocation failed");
+        TRY(dev_alloc(w->stage_d, b, s));
+        w->stage_bytes = b;
+    }
+    if (w->res_count < count) {
+        if (w->res_h) (void)hipHostFree(w->res_h);
+        dev_free(w->res_d, s);
+        w->res_h = nullptr;
+        w->res_count = 0;
+        int c = std::max(count, 16);
+        if (hipHostMalloc((void **)&w->res_h, sizeof(Result) * c, hipHostMallocDefault) != hipSuccess)
+            return fail(GMT_ENOMEM, "pinned result allocation failed");
+        TRY(dev_alloc(w->res_d, sizeof(Result) * c, s));
+        w->res_count = c;
+    }
+    return GMT_OK;
+}
+
+// clear barrier state after a faulted launch
+static void ws_reset_ctl(WsBlock *w, hipStream_t s) {
+    size_t tb = ws_team_bytes(w->cap);
+    (void)hipMemsetAsync(w->mem.p, 0, tb * w->teams, s);
+    (void)hipStreamSynchronize(s);
+}
+
+// ---------------------------------------------------------------------------
+// query validation and staging
+// ---------------------------------------------------------------------------
+struct QueryIn {
+    const gmt_roadmap *rm;
+    const float *x_init;
+    const gmt_goal *goal;
+    const float *boxes;
+    int m;
+    double lambda;
+};
+
+static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev &P, int *boxbuf,
+                              int box_off) {
+    const gmt_roadmap *rm = q.rm;
+    if (!rm) return fail(GMT_EINVAL, "null roadmap");
+    if (!q.x_init || !q.goal) return fail(GMT_EINVAL, "null x_init or goal");
+    if (q.m < 0 || q.m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", q.m, GMT_MAX_BOXES);
+    if (q.m > 0 && !q.boxes) return fail(GMT_EINVAL, "null boxes");
+    if (!(q.lambda >= 0.0 && q.lambda <= 1.0)) return fail(GMT_EINVAL, "lambda must lie in [0, 1]");
+    const int dim = rm->dim, pd = pdim_of(rm->kind, dim);
+    std::memset(&P, 0, sizeof P);
+    P.rm.n = rm->n;
+    P.rm.dim = dim;
+    P.rm.kind = rm->kind;
+    P.rm.r = rm->r;
+    P.rm.R2 = rm->r * rm->r * GMT_Q2;
+    P.rm.s = (const float *)rm->s.p;
+    P.rm.in_ptr = (const int *)rm->in_ptr.p;
+    P.rm.in_col = (const int *)rm->in_col.p;
+    P.rm.in_cost = (const double *)rm->in_cost.p;
+    P.rm.in_tau = (const double *)rm->in_tau.p;
+    P.rm.out_ptr = (const int *)rm->out_ptr.p;
+    P.rm.out_col = (const int *)rm->out_col.p;
+    P.pd = pd;
+    P.m = q.m;
+    P.box_off = box_off;
+    P.max_iters = o.max_iters > 0 ? o.max_iters : 0x7fffffff;
+    P.lambda = q.lambda;
+    P.delta = q.lambda * rm->r;
+    if (rm->kind == GMT_COST_EUCLIDEAN) {
+        if (!(o.edge_step > 0.0) || !std::isfinite(o.edge_step)) return fail(GMT_EINVAL, "edge_step must be > 0");
+        P.step_q = (long long)std::llround(o.edge_step * GMT_QS);
+        if (P.step_q < 1) return fail(GMT_EINVAL, "edge_step below the grid quantum");
+        P.traj_points = 0;
+    } else {
+        if (o.traj_points < 2 || o.traj_points > 4096) return fail(GMT_EINVAL, "traj_points must lie in [2, 4096]");
+        P.traj_points = o.traj_points;
+        P.step_q = 1;
+    }
+    for (int a = 0; a < dim; ++a) {
+        double x = q.x_init[a];
+        double lo = a < pd ? 0.0 : -1.0;
+        if (!on_grid(x) || x < lo || x > 1.0) return fail(GMT_EINVAL, "x_init[%d] off the grid or out of range", a);
+        P.x_q[a] = (int)(x * GMT_QS);
+        P.x_d[a] = x;
+    }
+    const gmt_goal &g = *q.goal;
+    if (g.ndims < 1 || g.ndims > pd) return fail(GMT_EINVAL, "goal.ndims must lie in [1, %d]", pd);
+    if (!(g.radius >= 0.0f) || !std::isfinite(g.radius)) return fail(GMT_EINVAL, "bad goal radius");
+    P.goal_dims = g.ndims;
+    for (int a = 0; a < g.ndims; ++a) {
+        if (!on_grid(g.center[a])) return fail(GMT_EINVAL, "goal centre off the grid");
+        P.goal_q[a] = (int)((double)g.center[a] * GMT_QS);
+    }
+    P.goal_r2q = (double)g.radius * (double)g.radius * GMT_Q2;
+    for (int b = 0; b < q.m; ++b) {
+        const float *bx = q.boxes + (size_t)b * 2 * pd;
+        bool inside = true;
+        for (int k = 0; k < 2 * pd; ++k) {
+            if (!on_grid(bx[k]) || std::fabs(bx[k]) > 2.0f) return fail(GMT_EINVAL, "box %d off the grid", b);
+            boxbuf[b * 2 * pd + k] = (int)std::llround((double)bx[k] * GMT_QS);
+        }
+        for (int a = 0; a < pd; ++a)
+            if (P.x_q[a] < boxbuf[b * 2 * pd + a] || P.x_q[a] > boxbuf[b * 2 * pd + pd + a]) inside = false;
+        if (inside) return fail(GMT_EINVAL, "x_init lies inside box %d (it must be in free space)", b);
+    }
+    return GMT_OK;
+}
+
+static gmt_plan_opts default_opts(const gmt_plan_opts *o) {
+    gmt_plan_opts d;
+    if (o) return *o;
+    d.edge_step = 0.0;
+    d.traj_points = 16;
+    d.max_iters = 0;
+    d.team_wgs = 0;
+    d.lanes = 0;
+    return d;
+}
+
+static int g_num_cu = 0;
+static int num_cus() {
+    if (g_num_cu == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) g_num_cu = pr.multiProcessorCount;
+        if (g_num_cu <= 0) g_num_cu = 256;
+    }
+    return g_num_cu;
+}
+
+static const void *plan_kernel(int kind) {
+    return kind == GMT_COST_EUCLIDEAN ? (const void *)k_plan<0> : (const void *)k_plan<1>;
+}
+
+// Launch the persistent planning kernel over staged queries [first,
+// first+count) of one cost kind; queue counter `qslot` of the staging header.
+static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int teams,
+                                   int team_wgs, int box_words, int qslot, hipStream_t s) {
+    char *sd = (char *)w->stage_d.p;
+    int *queue = (int *)sd + qslot;
+    const ProbDev *probs = (const ProbDev *)(sd + 256) + first;
+    const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
+    const Ws *wss = (const Ws *)w->d_ws.p;
+    Result *res = (Result *)w->res_d.p + first;
+    size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
+    dim3 grid(teams * team_wgs), block(256);
+    if (team_wgs > 1) {
+        void *args[] = {&probs, &count, &boxes, &box_words, &queue, &wss, &team_wgs, &res};
+        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind), grid, block, args, (unsigned)lds, s));
+    } else if (kind == GMT_COST_EUCLIDEAN) {
+        k_plan<0><<<grid, block, lds, s>>>(probs, count, boxes, box_words, queue, wss, team_wgs, res);
+        HIPCHK(hipGetLastError());
+    } else {
+        k_plan<1><<<grid, block, lds, s>>>(probs, count, boxes, box_words, queue, wss, team_wgs, res);
+        HIPCHK(hipGetLastError());
+    }
+    return GMT_OK;
+}
+
+static int max_coop_wgs(size_t lds, int kind) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind), 256, lds) != hipSuccess || per < 1)
+        per = 1;
+    return per * num_cus();
+}
+
+// Stage-copy, launch per kind (queries sorted Euclidean first), read back.
+static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int teams, int team_wgs, int box_words,
+                              size_t stage_used, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, stage_used, hipMemcpyHostToDevice, s));
+    if (n_euclid > 0)
+        TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, n_euclid, count, std::min(teams, n_euclid), team_wgs,
+                             box_words, 0, s));
+    if (count - n_euclid > 0)
+        TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, n_euclid, count - n_euclid, count,
+                             std::min(teams, count - n_euclid), team_wgs, box_words, 1, s));
+    HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return GMT_OK;
+}
+
+static gmt_status status_of(int st) {
+    switch (st) {
+    case ST_OK: return GMT_OK;
+    case ST_NO_PATH: return GMT_NO_PATH;
+    case ST_TIMEOUT: return GMT_ETIMEOUT;
+    default: return GMT_EDEVICE;
+    }
+}
+
+// full path from the parent array when it exceeds the inline copy
+static gmt_status long_path(const Ws &hw, int N, int z, int *path, int cap, hipStream_t s) {
+    std::vector<int> par(N);
+    HIPCHK(hipMemcpyAsync(par.data(), hw.parent, sizeof(int) * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> rev;
+    for (int v = z; v >= 0 && (int)rev.size() <= N; v = par[v]) rev.push_back(v);
+    for (int k = 0; k < (int)rev.size() && k < cap; ++k) path[k] = rev[rev.size() - 1 - k];
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
+                               const float *boxes, int32_t m, double lambda,
+                               const gmt_plan_opts *opts_in, int32_t *d_parent, double *d_cost,
+                               int32_t *d_group_iter, int32_t *d_added_iter, int32_t *path,
+                               int32_t path_cap, int32_t *path_len, double *path_cost,
+                               int32_t *iters, void *stream) {
+    if (!rm) return fail(GMT_EINVAL, "null roadmap");
+    if (path_cap > 0 && !path) return fail(GMT_EINVAL, "null path buffer");
+    gmt_plan_opts o = default_opts(opts_in);
+    if (!opts_in && rm->kind == GMT_COST_EUCLIDEAN) return fail(GMT_EINVAL, "Euclidean plans need opts.edge_step");
+    hipStream_t s = (hipStream_t)stream;
+    const int pd = pdim_of(rm->kind, rm->dim);
+    const int box_words = m * 2 * pd;
+    const size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
+    int team_wgs = o.team_wgs > 0 ? o.team_wgs : num_cus();
+    team_wgs = std::min(team_wgs, max_coop_wgs(lds, rm->kind));
+    WsBlock *w = nullptr;
+    TRY(ws_acquire(1, rm->n + 1, s, &w));
+    size_t used = 256 + sizeof(ProbDev) + sizeof(int) * (size_t)box_words;
+    gmt_status st = ws_stage(w, used, 1, s);
+    if (st == GMT_OK) {
+        char *sh = (char *)w->stage_h;
+        ((int *)sh)[0] = 0;  // queue counters
+        ((int *)sh)[1] = 0;
+        ProbDev *P = (ProbDev *)(sh + 256);
+        int *bx = (int *)(sh + 256 + sizeof(ProbDev));
+        QueryIn q{rm, x_init, goal, boxes, m, lambda};
+        st = stage_query(q, o, *P, bx, 0);
+        if (st == GMT_OK) {
+            P->out_parent = d_parent;
+            P->out_cost = d_cost;
+            P->out_group = d_group_iter;
+            P->out_added = d_added_iter;
+            st = launch_plan(w, 1, rm->kind == GMT_COST_EUCLIDEAN ? 1 : 0, 1, team_wgs, box_words, used, s);
+        }
+    }
+    if (st == GMT_OK) {
+        const Result &r = w->res_h[0];
+        if (r.abort || r.status == ST_FAULT) {
+            ws_reset_ctl(w, s);
+            st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
+        } else {
+            if (path_len) *path_len = r.path_len;
+            if (path_cost) *path_cost = r.path_cost;
+            if (iters) *iters = r.iters;
+            if (path && r.status == ST_OK) {
+                if (r.path_len <= GMT_PATH_INLINE) {
+                    for (int k = 0; k < r.path_len && k < path_cap; ++k) path[k] = r.path[k];
+                } else {
+                    Ws hw;
+                    (void)hipMemcpy(&hw, w->d_ws.p, sizeof hw, hipMemcpyDeviceToHost);
+                    st = long_path(hw, rm->n + 1, r.z, path, path_cap, s);
+                }
+            }
+            if (st == GMT_OK) st = status_of(r.status);
+        }
+    }
+    ws_release(w);
+    return st;
+}
+
+extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
+                                     const gmt_batch_opts *bopts, gmt_result *results, void *stream) {
+    if (count < 0 || (count > 0 && (!problems || !results))) return fail(GMT_EINVAL, "bad batch arguments");
+    if (count == 0) return GMT_OK;
+    gmt_batch_opts bo;
+    if (bopts) bo = *bopts;
+    else {
+        std::memset(&bo, 0, sizeof bo);
+        bo.plan.traj_points = 16;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int cap = 1, box_words = 1;
+    size_t total_boxes = 0;
+    // Euclidean queries are staged first, double-integrator ones after
+    std::vector<int> order;
+    order.reserve(count);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < count; ++k) {
+            const gmt_problem &pr = problems[k];
+            if (!pr.roadmap) return fail(GMT_EINVAL, "problem %d: null roadmap", k);
+            if ((pr.roadmap->kind == GMT_COST_EUCLIDEAN) == (pass == 0)) order.push_back(k);
+        }
+    int n_euclid = 0;
+    for (int k = 0; k < count; ++k) {
+        const gmt_problem &pr = problems[k];
+        if (pr.roadmap->kind == GMT_COST_EUCLIDEAN) ++n_euclid;
+        cap = std::max(cap, pr.roadmap->n + 1);
+        if (pr.m < 0 || pr.m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "problem %d: box count out of range", k);
+        int words = pr.m * 2 * pdim_of(pr.roadmap->kind, pr.roadmap->dim);
+        box_words = std::max(box_words, words);
+        total_boxes += (size_t)words;
+    }
+    int team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
+    const size_t lds = (size_t)box_words * sizeof(int);
+    int resident = std::min(max_coop_wgs(lds, 0), max_coop_wgs(lds, 1));
+    int teams = bo.workgroups > 0 ? bo.workgroups / team_wgs : resident / team_wgs;
+    teams = std::max(1, std::min(teams, count));
+    if (team_wgs > 1) teams = std::max(1, std::min(teams, resident / team_wgs));
+    WsBlock *w = nullptr;
+    TRY(ws_acquire(teams, cap, s, &w));
+    size_t used = 256 + sizeof(ProbDev) * count + sizeof(int) * total_boxes;
+    gmt_status st = ws_stage(w, used, count, s);
+    if (st == GMT_OK) {
+        char *sh = (char *)w->stage_h;
+        ((int *)sh)[0] = 0;
+        ((int *)sh)[1] = 0;
+        ProbDev *P = (ProbDev *)(sh + 256);
+        int *bx = (int *)(sh + 256 + sizeof(ProbDev) * count);
+        int off = 0;
+        for (int j = 0; j < count && st == GMT_OK; ++j) {
+            const int k = order[j];
+            const gmt_problem &pr = problems[k];
+            QueryIn q{pr.roadmap, pr.x_init, &pr.goal, pr.boxes, pr.m, pr.lambda};
+            st = stage_query(q, bo.plan, P[j], bx + off, off);
+            if (st != GMT_OK) {
+                std::string msg = g_last_error;
+                st = fail(st, "problem %d: %s", k, msg.c_str());
+                break;
+            }
+            P[j].out_parent = results[k].d_parent;
+            P[j].out_cost = results[k].d_cost;
+            P[j].out_group = results[k].d_group_iter;
+            P[j].out_added = results[k].d_added_iter;
+            off += P[j].m * 2 * P[j].pd;
+        }
+        if (st == GMT_OK) st = launch_plan(w, count, n_euclid, teams, team_wgs, box_words, used, s);
+    }
+    if (st == GMT_OK) {
+        bool fault = false;
+        for (int j = 0; j < count; ++j) {
+            const int k = order[j];
+            const Result &r = w->res_h[j];
+            gmt_result &o = results[k];
+            if (r.abort || r.status == ST_FAULT) fault = true;
+            o.status = (int)status_of(r.status);
+            o.iters = r.iters;
+            o.path_len = r.path_len;
+            o.path_cost = r.path_cost;
+            if (o.path && r.status == ST_OK) {
+                if (r.path_len <= GMT_PATH_INLINE)
+                    for (int i = 0; i < r.path_len && i < o.path_cap; ++i) o.path[i] = r.path[i];
+                else if (o.d_parent) {
+                    std::vector<int> par(problems[k].roadmap->n + 1);
+                    (void)hipMemcpy(par.data(), o.d_parent, sizeof(int) * par.size(), hipMemcpyDeviceToHost);
+                    std::vector<int> rev;
+                    for (int v = r.z; v >= 0 && rev.size() <= par.size(); v = par[v]) rev.push_back(v);
+                    for (int i = 0; i < (int)rev.size() && i < o.path_cap; ++i) o.path[i] = rev[rev.size() - 1 - i];
+                }
+            }
+        }
+        if (fault) {
+            ws_reset_ctl(w, s);
+            st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
+        }
+    }
+    ws_release(w);
+    return st;
+}

@@ -1,0 +1,379 @@
+"""ctypes binding of ``libgmt.so`` (declared in ``include/gmt.h``).
+
+Argument marshalling only: every planning step runs in the library's HIP
+kernels.  Functions carry the C names (``gmt_build_neighbors``, ``gmt_plan``,
+``gmt_plan_batch``, ...).  Device buffers are torch tensors on the current
+GPU; torch's caching allocator backs the library's device allocations
+(``gmt_set_allocator``) and torch streams are passed as ``hipStream_t``.
+
+Loading never compiles: ``lib()`` raises when the library has not been built
+(``build_library()``, also run by ``__graft_entry__.build()``).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB_PATH = os.path.join(BUILD, "libgmt.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
+GMT_OK, GMT_NO_PATH, GMT_ETIMEOUT = 0, 1, 2
+GMT_EINVAL, GMT_ENOMEM, GMT_EDEVICE, GMT_EBUSY = -1, -2, -3, -4
+GMT_COST_EUCLIDEAN, GMT_COST_DOUBLE_INTEGRATOR = 0, 1
+STATUS_NAMES = {0: "GMT_OK", 1: "GMT_NO_PATH", 2: "GMT_ETIMEOUT", -1: "GMT_EINVAL",
+                -2: "GMT_ENOMEM", -3: "GMT_EDEVICE", -4: "GMT_EBUSY"}
+
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+# symbols the header declares (checked by the CPU tests)
+EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
+           "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_batch",
+           "gmt_last_error", "gmt_version"]
+
+
+class GmtError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s (%s): %s" % (what, STATUS_NAMES.get(status, status), last_error()))
+        self.status = status
+
+
+def sources() -> List[str]:
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))
+            if f.endswith((".hip", ".hpp"))] + [os.path.join(INCLUDE, "gmt.h")]
+
+
+def build_library(force: bool = True) -> str:
+    """Compile libgmt.so for gfx950 with hipcc (in-tree, under ``_build/``)."""
+    os.makedirs(BUILD, exist_ok=True)
+    if not force and os.path.exists(LIB_PATH):
+        newest = max(os.path.getmtime(p) for p in sources())
+        if os.path.getmtime(LIB_PATH) >= newest:
+            return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp, os.path.join(CSRC, "gmt_lib.hip")]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+# ---------------------------------------------------------------------------
+# structs
+# ---------------------------------------------------------------------------
+class gmt_allocator(C.Structure):
+    _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)),
+                ("ctx", C.c_void_p)]
+
+
+class gmt_goal(C.Structure):
+    _fields_ = [("center", C.c_float * 6), ("radius", C.c_float), ("ndims", C.c_int32)]
+
+
+class gmt_plan_opts(C.Structure):
+    _fields_ = [("edge_step", C.c_double), ("traj_points", C.c_int32), ("max_iters", C.c_int32),
+                ("team_wgs", C.c_int32), ("lanes", C.c_int32)]
+
+
+class gmt_problem(C.Structure):
+    _fields_ = [("roadmap", C.c_void_p), ("x_init", C.POINTER(C.c_float)), ("goal", gmt_goal),
+                ("boxes", C.POINTER(C.c_float)), ("m", C.c_int32), ("lambda_", C.c_double)]
+
+
+class gmt_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("path_len", C.c_int32),
+                ("path_cap", C.c_int32), ("path_cost", C.c_double),
+                ("path", C.POINTER(C.c_int32)), ("d_parent", C.c_void_p), ("d_cost", C.c_void_p),
+                ("d_group_iter", C.c_void_p), ("d_added_iter", C.c_void_p)]
+
+
+class gmt_batch_opts(C.Structure):
+    _fields_ = [("plan", gmt_plan_opts), ("workgroups", C.c_int32), ("threads", C.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+_alloc_keep = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libgmt.so is not built (%s); run __graft_entry__.build() or "
+                                   "paper_1705_02403_amd.gmt.build_library()" % LIB_PATH)
+            L = C.CDLL(LIB_PATH)
+            P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+            L.gmt_set_allocator.argtypes = [C.POINTER(gmt_allocator)]
+            L.gmt_build_neighbors.argtypes = [P, i32, i32, i32, f64, P, C.POINTER(P)]
+            L.gmt_roadmap_from_csr.argtypes = [P, i32, i32, i32, f64, P, P, P, P, P, C.POINTER(P)]
+            L.gmt_roadmap_info.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                           C.POINTER(i64)]
+            L.gmt_roadmap_export.argtypes = [P, P, P, P, P, P]
+            L.gmt_roadmap_free.argtypes = [P]
+            L.gmt_plan.argtypes = [P, P, C.POINTER(gmt_goal), P, i32, f64, C.POINTER(gmt_plan_opts),
+                                   P, P, P, P, P, i32, C.POINTER(i32), C.POINTER(f64),
+                                   C.POINTER(i32), P]
+            L.gmt_plan_batch.argtypes = [C.POINTER(gmt_problem), i32, C.POINTER(gmt_batch_opts),
+                                         C.POINTER(gmt_result), P]
+            L.gmt_last_error.restype = C.c_char_p
+            L.gmt_version.restype = C.c_char_p
+            for name in EXPORTS:
+                if name not in ("gmt_last_error", "gmt_version"):
+                    getattr(L, name).restype = i32
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    try:
+        return lib().gmt_last_error().decode()
+    except Exception:  # pragma: no cover - library absent
+        return ""
+
+
+def gmt_version() -> str:
+    return lib().gmt_version().decode()
+
+
+def _check(st: int, what: str, ok=(GMT_OK,)) -> int:
+    if st not in ok:
+        raise GmtError(st, what)
+    return st
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _host_f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def use_torch_allocator() -> None:
+    """Route the library's device allocations through torch's caching allocator."""
+    global _alloc_keep
+    import torch
+
+    @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+    def _alloc(nbytes, ctx, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0) or None)
+        except Exception:
+            return None
+
+    @C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+    def _free(ptr, ctx, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = gmt_allocator(_alloc, _free, None)
+    _alloc_keep = (a, _alloc, _free)
+    _check(lib().gmt_set_allocator(C.byref(a)), "gmt_set_allocator")
+
+
+# ---------------------------------------------------------------------------
+# roadmaps
+# ---------------------------------------------------------------------------
+class Roadmap:
+    """Owns a ``gmt_roadmap_t`` handle."""
+
+    def __init__(self, handle: int, n: int, dim: int, kind: int, r: float):
+        self.handle = C.c_void_p(handle)
+        self.n, self.dim, self.kind, self.r = n, dim, kind, r
+
+    @property
+    def nnz(self) -> int:
+        n, d, k = C.c_int32(), C.c_int32(), C.c_int32()
+        e = C.c_int64()
+        _check(lib().gmt_roadmap_info(self.handle, C.byref(n), C.byref(d), C.byref(k), C.byref(e)),
+               "gmt_roadmap_info")
+        return int(e.value)
+
+    def export(self, stream=None):
+        """(row_ptr, col, cost, tau) of the in-neighbour table as numpy arrays."""
+        E = self.nnz
+        rp = np.zeros(self.n + 1, np.int32)
+        col = np.zeros(max(E, 1), np.int32)
+        cost = np.zeros(max(E, 1), np.float64)
+        tau = np.zeros(max(E, 1), np.float64) if self.kind == GMT_COST_DOUBLE_INTEGRATOR else None
+        _check(lib().gmt_roadmap_export(self.handle, rp.ctypes.data, col.ctypes.data,
+                                        cost.ctypes.data, None if tau is None else tau.ctypes.data,
+                                        _stream(stream)), "gmt_roadmap_export")
+        return rp, col[:E], cost[:E], (None if tau is None else tau[:E])
+
+    def free(self) -> None:
+        if self.handle:
+            lib().gmt_roadmap_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None) -> Roadmap:
+    """samples: CUDA float32 tensor [dim][n] (SoA) on the 2^-20 grid."""
+    import torch
+    assert samples.is_cuda and samples.dtype == torch.float32 and samples.dim() == 2
+    s = samples.contiguous()
+    dim, n = int(s.shape[0]), int(s.shape[1])
+    h = C.c_void_p()
+    _check(lib().gmt_build_neighbors(s.data_ptr(), n, dim, int(kind), float(r_n), _stream(stream),
+                                     C.byref(h)), "gmt_build_neighbors")
+    return Roadmap(h.value, n, dim, int(kind), float(r_n))
+
+
+def gmt_roadmap_from_csr(samples, kind: int, r_n: float, row_ptr, col, cost, tau=None,
+                         stream=None) -> Roadmap:
+    """Host arrays: samples [dim][n] float32, CSR int32/int32/float64 (+ tau float64)."""
+    s = _host_f32(samples)
+    dim, n = s.shape
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    cs = np.ascontiguousarray(cost, np.float64)
+    tt = None if tau is None else np.ascontiguousarray(tau, np.float64)
+    h = C.c_void_p()
+    _check(lib().gmt_roadmap_from_csr(s.ctypes.data, n, dim, int(kind), float(r_n), rp.ctypes.data,
+                                      cl.ctypes.data if len(cl) else None,
+                                      cs.ctypes.data if len(cs) else None,
+                                      None if tt is None or not len(tt) else tt.ctypes.data,
+                                      _stream(stream), C.byref(h)), "gmt_roadmap_from_csr")
+    return Roadmap(h.value, n, dim, int(kind), float(r_n))
+
+
+# ---------------------------------------------------------------------------
+# planning
+# ---------------------------------------------------------------------------
+@dataclass
+class PlanResult:
+    status: int
+    path: np.ndarray
+    path_cost: float
+    iters: int
+    parent: object = None      # torch tensors when requested
+    cost: object = None
+    group_iter: object = None
+    added_iter: object = None
+
+
+def make_goal(center: Sequence[float], radius: float, ndims: int) -> gmt_goal:
+    g = gmt_goal()
+    for a, c in enumerate(center):
+        g.center[a] = float(c)
+    g.radius = float(radius)
+    g.ndims = int(ndims)
+    return g
+
+
+def make_opts(edge_step: float = 0.0, traj_points: int = 16, max_iters: int = 0,
+              team_wgs: int = 0, lanes: int = 0) -> gmt_plan_opts:
+    return gmt_plan_opts(float(edge_step), int(traj_points), int(max_iters), int(team_wgs),
+                         int(lanes))
+
+
+def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_plan_opts,
+             outputs: bool = True, stream=None, path_cap: int = 4096) -> PlanResult:
+    """One query; returns the path and (optionally) the tree as device tensors."""
+    import torch
+    xi = _host_f32(x_init)
+    bx = _host_f32(boxes).reshape(-1)
+    pd = 3 if rm.kind == GMT_COST_DOUBLE_INTEGRATOR else rm.dim
+    m = int(bx.size // (2 * pd)) if bx.size else 0
+    N = rm.n + 1
+    dev = torch.device("cuda", torch.cuda.current_device())
+    par = cst = gi = ai = None
+    if outputs:
+        par = torch.empty(N, dtype=torch.int32, device=dev)
+        cst = torch.empty(N, dtype=torch.float64, device=dev)
+        gi = torch.empty(N, dtype=torch.int32, device=dev)
+        ai = torch.empty(N, dtype=torch.int32, device=dev)
+    path = np.zeros(path_cap, np.int32)
+    plen = C.c_int32()
+    pcost = C.c_double()
+    iters = C.c_int32()
+    st = lib().gmt_plan(rm.handle, xi.ctypes.data, C.byref(goal), bx.ctypes.data if m else None, m,
+                        float(lam), C.byref(opts), _ptr(par), _ptr(cst), _ptr(gi), _ptr(ai),
+                        path.ctypes.data, path_cap, C.byref(plen), C.byref(pcost), C.byref(iters),
+                        _stream(stream))
+    _check(st, "gmt_plan", ok=(GMT_OK, GMT_NO_PATH, GMT_ETIMEOUT))
+    L = int(plen.value) if st == GMT_OK else 0
+    return PlanResult(int(st), path[:min(L, path_cap)].copy(), float(pcost.value), int(iters.value),
+                      par, cst, gi, ai)
+
+
+@dataclass
+class BatchQuery:
+    roadmap: Roadmap
+    x_init: np.ndarray
+    goal: gmt_goal
+    boxes: np.ndarray
+    lam: float
+
+
+def gmt_plan_batch(queries: Sequence[BatchQuery], opts: gmt_plan_opts, workgroups: int = 0,
+                   outputs: bool = False, stream=None, path_cap: int = 1024):
+    """Solve queries in one persistent launch; returns a list of PlanResult."""
+    import torch
+    k = len(queries)
+    probs = (gmt_problem * k)()
+    res = (gmt_result * k)()
+    keep = []
+    outs = []
+    dev = torch.device("cuda", torch.cuda.current_device())
+    for j, q in enumerate(queries):
+        xi = _host_f32(q.x_init)
+        bx = _host_f32(q.boxes).reshape(-1)
+        pd = 3 if q.roadmap.kind == GMT_COST_DOUBLE_INTEGRATOR else q.roadmap.dim
+        m = int(bx.size // (2 * pd)) if bx.size else 0
+        path = np.zeros(path_cap, np.int32)
+        keep += [xi, bx, path]
+        probs[j].roadmap = q.roadmap.handle
+        probs[j].x_init = xi.ctypes.data_as(C.POINTER(C.c_float))
+        probs[j].goal = q.goal
+        probs[j].boxes = bx.ctypes.data_as(C.POINTER(C.c_float)) if m else None
+        probs[j].m = m
+        probs[j].lambda_ = float(q.lam)
+        res[j].path = path.ctypes.data_as(C.POINTER(C.c_int32))
+        res[j].path_cap = path_cap
+        o = [None] * 4
+        if outputs:
+            N = q.roadmap.n + 1
+            o = [torch.empty(N, dtype=torch.int32, device=dev),
+                 torch.empty(N, dtype=torch.float64, device=dev),
+                 torch.empty(N, dtype=torch.int32, device=dev),
+                 torch.empty(N, dtype=torch.int32, device=dev)]
+            res[j].d_parent, res[j].d_cost = o[0].data_ptr(), o[1].data_ptr()
+            res[j].d_group_iter, res[j].d_added_iter = o[2].data_ptr(), o[3].data_ptr()
+        outs.append((path, o))
+    bo = gmt_batch_opts(opts, int(workgroups), 0)
+    _check(lib().gmt_plan_batch(probs, k, C.byref(bo), res, _stream(stream)), "gmt_plan_batch")
+    out = []
+    for j in range(k):
+        path, o = outs[j]
+        L = int(res[j].path_len) if res[j].status == GMT_OK else 0
+        out.append(PlanResult(int(res[j].status), path[:min(L, path_cap)].copy(),
+                              float(res[j].path_cost), int(res[j].iters), *o))
+    return out

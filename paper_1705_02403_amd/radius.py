@@ -1,0 +1,49 @@
+"""Connection radius of Theorem 1 for Euclidean workloads.
+
+r = (1+eta)^(1/d) * 4 * (1/d)^(1/d) * (mu(X_free)/zeta_d)^(1/d) * (log n / n)^(1/d)
+with zeta_d the volume of the unit d-ball and mu(X_free) the free volume of
+[0,1]^d minus a union of closed boxes, computed exactly by coordinate
+compression (every cell between consecutive distinct box coordinates is
+either inside some box or free).  FP64 on the host.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def free_volume(pdim: int, boxes) -> float:
+    b = np.clip(np.asarray(boxes, dtype=np.float64).reshape(-1, 2 * pdim), 0.0, 1.0)
+    lo, hi = b[:, :pdim], b[:, pdim:]
+    axes = [np.unique(np.concatenate([[0.0, 1.0], lo[:, a], hi[:, a]])) for a in range(pdim)]
+    mids = np.meshgrid(*[0.5 * (c[1:] + c[:-1]) for c in axes], indexing="ij")
+    widths = np.meshgrid(*[np.diff(c) for c in axes], indexing="ij")
+    vol = np.ones_like(widths[0])
+    for w in widths:
+        vol = vol * w
+    covered = np.zeros(vol.shape, dtype=bool)
+    for k in range(b.shape[0]):
+        inside = np.ones(vol.shape, dtype=bool)
+        for a in range(pdim):
+            inside &= (mids[a] > lo[k, a]) & (mids[a] < hi[k, a])
+        covered |= inside
+    return float(1.0 - vol[covered].sum())
+
+
+def unit_ball_volume(d: int) -> float:
+    return math.pi ** (d / 2.0) / math.gamma(d / 2.0 + 1.0)
+
+
+def theorem1_radius(d: int, mu: float, n: int, factor: float = 1.1) -> float:
+    """factor stands for (1+eta)^(1/d)."""
+    return (factor * 4.0 * (1.0 / d) ** (1.0 / d) * (mu / unit_ball_volume(d)) ** (1.0 / d)
+            * (math.log(n) / n) ** (1.0 / d))
+
+
+def problem_radius(prob) -> float:
+    """Radius of a generated problem: its fixed r, else Theorem 1."""
+    if prob.r is not None:
+        return float(prob.r)
+    return theorem1_radius(prob.dim, free_volume(prob.pdim, prob.boxes), prob.n, prob.r_factor)

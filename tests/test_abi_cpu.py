@@ -1,0 +1,60 @@
+"""CPU checks of the boundary: the library loads and exports every symbol the
+header declares; host-side helpers agree with the oracle.  No GPU calls."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1705_02403_amd import gmt, inputs, radius
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "gmt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_lists_the_bound_symbols():
+    assert header_functions() == sorted(gmt.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(gmt.LIB_PATH):
+        gmt.build_library()
+    L = ctypes.CDLL(gmt.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(L, name), name
+    assert "gfx950" in gmt.gmt_version()
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    """Validation happens on the host before any device work."""
+    L = gmt.lib()
+    h = ctypes.c_void_p()
+    assert L.gmt_build_neighbors(None, 10, 2, 0, 0.1, None, ctypes.byref(h)) == gmt.GMT_EINVAL
+    assert L.gmt_plan(None, None, None, None, 0, 0.5, None, None, None, None, None, None, 0,
+                      None, None, None, None) == gmt.GMT_EINVAL
+    assert "null" in gmt.last_error()
+    bad = gmt.gmt_allocator()
+    assert L.gmt_set_allocator(ctypes.byref(bad)) == gmt.GMT_EINVAL
+    assert L.gmt_set_allocator(None) == gmt.GMT_OK
+
+
+def test_product_radius_matches_oracle():
+    for f, s in [(inputs.problem_2d, 0), (inputs.problem_2d, 3), (inputs.problem_3d, 1)]:
+        p = f(s)
+        mu_o = O.free_volume(p.pdim, p.boxes)
+        mu_p = radius.free_volume(p.pdim, p.boxes)
+        assert abs(mu_o - mu_p) <= 1e-12
+        assert abs(radius.problem_radius(p) - O.euclid_radius(p)) <= 1e-14 * O.euclid_radius(p)
+
+
+def test_inputs_in_the_library_range():
+    p = inputs.problem_di(0, n=512)
+    assert inputs.on_grid(p.samples) and np.all(np.abs(p.samples) <= 1.0)

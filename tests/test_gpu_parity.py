@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Euclidean workloads are exact on both sides (integer geometry, FP64 edge
+costs from the same correctly rounded square root, same FP64 sums), so trees,
+group indices and costs must match bit for bit on every instance.  For the
+double integrator the two sides solve the arrival-time quartic with different
+code; trees must match wherever the oracle's decision margins exceed what
+FP64 rounding can move, and costs agree to 1e-12 relative.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1705_02403_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1705_02403_amd import gmt
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    gmt.use_torch_allocator()
+    yield
+    torch.cuda.synchronize()
+
+
+def build(prob, r):
+    kind = gmt.GMT_COST_DOUBLE_INTEGRATOR if prob.kind == "di" else gmt.GMT_COST_EUCLIDEAN
+    return gmt.gmt_build_neighbors(torch.from_numpy(np.ascontiguousarray(prob.samples)).cuda(), kind, r)
+
+
+def goal_of(prob):
+    return gmt.make_goal(prob.goal_center, prob.goal_radius, prob.pdim)
+
+
+def opts_of(prob, **kw):
+    return gmt.make_opts(edge_step=prob.step, traj_points=prob.traj_points, **kw)
+
+
+def compare_tree(res, ref, exact_cost=True):
+    assert res.status == ref.status
+    assert res.iters == ref.iters
+    np.testing.assert_array_equal(res.parent.cpu().numpy(), ref.parent)
+    np.testing.assert_array_equal(res.group_iter.cpu().numpy(), ref.group_iter)
+    np.testing.assert_array_equal(res.added_iter.cpu().numpy(), ref.added_iter)
+    c = res.cost.cpu().numpy()
+    fin = np.isfinite(ref.cost)
+    np.testing.assert_array_equal(np.isfinite(c), fin)
+    if exact_cost:
+        np.testing.assert_array_equal(c[fin], ref.cost[fin])
+    else:
+        np.testing.assert_allclose(c[fin], ref.cost[fin], rtol=1e-12, atol=0)
+    if ref.status == O.OK:
+        assert list(res.path) == list(ref.path)
+        if exact_cost:
+            assert res.path_cost == ref.path_cost
+        else:
+            assert abs(res.path_cost - ref.path_cost) <= 1e-12 * ref.path_cost
+
+
+# --- neighbour tables -------------------------------------------------------
+
+EU_TABLES = [("2d", 0, 2000), ("2d", 1, 2000), ("2d", 2, 5003), ("3d", 0, 16384), ("3d", 3, 3001)]
+
+
+@pytest.mark.parametrize("kind,seed,n", EU_TABLES)
+def test_euclid_table_bit_exact(kind, seed, n):
+    say("euclid table %s seed %d n %d" % (kind, seed, n))
+    prob = I.problem_2d(seed, n=n) if kind == "2d" else I.problem_3d(seed, n=n)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    rp, col, cost, _ = rm.export()
+    ref = O.neighbors(prob.samples, O.EUCLID, r)
+    np.testing.assert_array_equal(rp, ref.row_ptr)
+    np.testing.assert_array_equal(col, ref.col)
+    np.testing.assert_array_equal(cost, ref.cost)  # same correctly rounded sqrt
+    rm.free()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 65])
+def test_euclid_table_tiny(n):
+    say("euclid tiny table n %d" % n)
+    prob = I.tiny_problem(n, 2, n, 0, 0.5)
+    r = 0.7
+    rm = build(prob, r)
+    rp, col, cost, _ = rm.export()
+    ref = O.neighbors(prob.samples, O.EUCLID, r)
+    np.testing.assert_array_equal(rp, ref.row_ptr)
+    np.testing.assert_array_equal(col, ref.col)
+    np.testing.assert_array_equal(cost, ref.cost)
+    rm.free()
+
+
+@pytest.mark.parametrize("seed,n", [(0, 1024), (1, 2048), (2, 777)])
+def test_di_table(seed, n):
+    say("di table seed %d n %d" % (seed, n))
+    s = I.di_samples(seed, n)
+    r = 1.75 * (16384.0 / n) ** (1.0 / 6.0)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, r)
+    rp, col, cost, tau = rm.export()
+    ref = O.neighbors(s, O.DI, r)
+    if ref.margin > 1e-9:
+        np.testing.assert_array_equal(rp, ref.row_ptr)
+        np.testing.assert_array_equal(col, ref.col)
+        np.testing.assert_allclose(cost, ref.cost, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(tau, ref.tau, rtol=1e-9, atol=0)
+    else:  # a pair sits within rounding of the radius: compare the rest
+        a = set(zip(np.repeat(np.arange(n), np.diff(rp)), col))
+        b = set(zip(np.repeat(np.arange(n), np.diff(ref.row_ptr)), ref.col))
+        assert len(a ^ b) <= 2
+    assert rm.nnz == len(col)
+    rm.free()
+
+
+# --- plans: Euclidean, bit-exact -------------------------------------------
+
+PLANS_2D = [(seed, lam) for seed in range(4) for lam in (0.0, 0.2, 0.5, 1.0)]
+
+
+@pytest.mark.parametrize("seed,lam", PLANS_2D)
+def test_plan_2d_bit_exact(seed, lam):
+    say("plan 2d seed %d lambda %.1f" % (seed, lam))
+    prob = I.problem_2d(seed, lam=lam)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, lam, opts_of(prob))
+    compare_tree(res, O.plan(prob, r))
+    rm.free()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_plan_3d_full_size_bit_exact(seed):
+    say("plan 3d n=16384 seed %d" % seed)
+    prob = I.problem_3d(seed)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, prob.lam, opts_of(prob))
+    compare_tree(res, O.plan(prob, r))
+    rm.free()
+
+
+@pytest.mark.parametrize("team_wgs", [1, 3, 16, 0])
+def test_launch_shape_does_not_change_results(team_wgs):
+    say("team shape %d" % team_wgs)
+    prob = I.problem_2d(7, lam=0.5)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5, opts_of(prob, team_wgs=team_wgs))
+    compare_tree(res, O.plan(prob, r))
+    rm.free()
+
+
+# --- plans: double integrator ----------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_plan_di_on_oracle_table(seed):
+    """Oracle-built table imported through gmt_roadmap_from_csr: only the
+    root's edges and the trajectory points are computed by the GPU."""
+    say("plan di imported seed %d" % seed)
+    n = 4096
+    s = I.di_samples(seed % 2, n)
+    r = 1.75 * (16384.0 / n) ** (1.0 / 6.0)
+    prob = I.di_problem(seed, s, r=r)
+    tab = O.neighbors(s, O.DI, r)
+    ref = O.plan(prob, r, tab)
+    rm = gmt.gmt_roadmap_from_csr(s, gmt.GMT_COST_DOUBLE_INTEGRATOR, r, tab.row_ptr, tab.col,
+                                  tab.cost, tab.tau)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, prob.lam, opts_of(prob))
+    if ref.margins[O.MG_ROOT] > 1e-9 and ref.margins[O.MG_COLLIDE] > 1e-9:
+        compare_tree(res, ref, exact_cost=False)
+    else:
+        assert res.status == ref.status
+    rm.free()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_plan_di_end_to_end(seed):
+    say("plan di end-to-end seed %d" % seed)
+    n = 4096
+    s = I.di_samples(2 + seed, n)
+    r = 1.75 * (16384.0 / n) ** (1.0 / 6.0)
+    prob = I.di_problem(10 + seed, s, r=r)
+    tab = O.neighbors(s, O.DI, r)
+    ref = O.plan(prob, r, tab)
+    rm = build(prob, r)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, prob.lam, opts_of(prob))
+    if min(tab.margin, ref.margins[O.MG_ROOT], ref.margins[O.MG_COLLIDE]) > 1e-9:
+        compare_tree(res, ref, exact_cost=False)
+    else:
+        assert res.status == ref.status
+        if ref.status == O.OK:
+            assert abs(res.path_cost - ref.path_cost) <= 1e-5 * ref.path_cost
+    rm.free()
+
+
+# --- batch ------------------------------------------------------------------
+
+def test_batch_equals_single_plans():
+    say("batch of mixed queries")
+    qs, refs, rms = [], [], []
+    for seed in range(6):
+        prob = I.problem_2d(seed, lam=0.5)
+        r = O.euclid_radius(prob)
+        rm = build(prob, r)
+        rms.append(rm)
+        qs.append(gmt.BatchQuery(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5))
+        refs.append(O.plan(prob, r))
+    s = I.di_samples(0, 2048)
+    r = 1.75 * 8.0 ** (1.0 / 6.0)
+    tab = O.neighbors(s, O.DI, r)
+    rmd = gmt.gmt_roadmap_from_csr(s, gmt.GMT_COST_DOUBLE_INTEGRATOR, r, tab.row_ptr, tab.col,
+                                   tab.cost, tab.tau)
+    rms.append(rmd)
+    di_refs = []
+    for seed in range(4):
+        prob = I.di_problem(seed, s, r=r)
+        qs.append(gmt.BatchQuery(rmd, prob.x_init, goal_of(prob), prob.boxes, 0.5))
+        di_refs.append(O.plan(prob, r, tab))
+    out = gmt.gmt_plan_batch(qs, gmt.make_opts(edge_step=0.005, traj_points=16), outputs=True)
+    for res, ref in zip(out[:6], refs):
+        compare_tree(res, ref)
+    for res, ref in zip(out[6:], di_refs):
+        assert res.status == ref.status
+        if ref.status == O.OK:
+            assert abs(res.path_cost - ref.path_cost) <= 1e-12 * ref.path_cost
+    for rm in rms:
+        rm.free()
+
+
+# --- edge cases ------------------------------------------------------------
+
+def test_errors_and_degenerate_queries():
+    say("edge cases")
+    prob = I.problem_2d(0, lam=0.5)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    g = goal_of(prob)
+    o = opts_of(prob)
+    # start inside a box: Problem 1 requires x_init in free space
+    b = prob.boxes[0]
+    inside = I.from_grid(I.to_grid(0.5 * (b[:2] + b[2:])))
+    with pytest.raises(gmt.GmtError) as e:
+        gmt.gmt_plan(rm, inside, g, prob.boxes, 0.5, o)
+    assert e.value.status == gmt.GMT_EINVAL
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_plan(rm, prob.x_init, g, prob.boxes, 1.5, o)
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_plan(rm, np.array([0.1000001, 0.2], np.float32), g, prob.boxes, 0.5, o)
+    # goal walled off: failure (Algorithm 1 line 12a)
+    wall = I.from_grid(I.to_grid(np.array([[0.8, 0.8, 1.0, 0.805], [0.8, 0.8, 0.805, 1.0]])))
+    pw = prob.with_boxes(np.concatenate([prob.boxes, wall]))
+    res = gmt.gmt_plan(rm, pw.x_init, g, pw.boxes, 0.5, o)
+    compare_tree(res, O.plan(pw, r))
+    assert res.status == gmt.GMT_NO_PATH
+    # iteration cap
+    res = gmt.gmt_plan(rm, prob.x_init, g, prob.boxes, 0.5, opts_of(prob, max_iters=4))
+    compare_tree(res, O.plan(prob, r, max_iters=4))
+    assert res.status == gmt.GMT_ETIMEOUT and res.iters == 4
+    # no obstacles
+    p0 = prob.with_boxes(np.zeros((0, 4), np.float32))
+    res = gmt.gmt_plan(rm, p0.x_init, g, p0.boxes, 0.5, o)
+    compare_tree(res, O.plan(p0, r))
+    # the start already in the goal
+    pg = I.Problem(**{**prob.__dict__, "goal_center": prob.x_init.copy()})
+    res = gmt.gmt_plan(rm, pg.x_init, goal_of(pg), pg.boxes, 0.5, o)
+    compare_tree(res, O.plan(pg, r))
+    assert list(res.path) == [prob.n] and res.path_cost == 0.0
+    rm.free()
