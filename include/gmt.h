@@ -176,6 +176,29 @@ gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
                     int32_t *d_added_iter, int32_t *path, int32_t path_cap, int32_t *path_len,
                     double *path_cost, int32_t *iters, void *stream);
 
+/* Exact work of one query (or the sum over a batch), counted by the plan
+ * kernel: out-edges walked from group members (Alg. 1 line 4), in-edges
+ * scanned for parents (lines 5-6), candidates processed, nodes added (lines
+ * 8-9), open-list entries partitioned (line 3), non-empty iterations. */
+typedef struct {
+    int64_t out_edges;
+    int64_t in_edges;
+    int64_t candidates;
+    int64_t commits;
+    int64_t open_entries;
+    int64_t iterations;
+} gmt_work;
+
+/* Work of the last gmt_plan / gmt_plan_batch call on this thread. */
+gmt_status gmt_last_work(gmt_work *out);
+
+/* Kernel timing: while enabled, planning launches are bracketed by HIP events
+ * on their stream and the elapsed kernel time is accumulated.
+ * gmt_profile_read returns the total milliseconds and launch count since the
+ * last read (and resets them). */
+gmt_status gmt_profile_enable(int32_t enable);
+gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches);
+
 /* One query of a batch. */
 typedef struct {
     gmt_roadmap_t roadmap;
@@ -188,7 +211,8 @@ typedef struct {
 
 /* Result of one batched query: status, iteration index at termination, path
  * length and cost; `path` (host, path_cap entries, root first) is filled when
- * not NULL; the optional device arrays get the tree as in gmt_plan. */
+ * not NULL; the optional device arrays get the tree as in gmt_plan; `work`
+ * receives the query's work counters. */
 typedef struct {
     int32_t status;
     int32_t iters;
@@ -200,6 +224,7 @@ typedef struct {
     double *d_cost;
     int32_t *d_group_iter;
     int32_t *d_added_iter;
+    gmt_work work;
 } gmt_result;
 
 /* Batch options: the plan options shared by every query, and the launch

@@ -102,36 +102,41 @@ struct Team {
 
 #define GMT_SPIN_LIMIT (1 << 25)
 
-// Barrier over the team's workgroups.  Every thread first makes its own
-// writes visible at agent scope; the last arriving workgroup bumps the
-// generation; waiters poll it with a bounded spin (on overrun they raise
-// *abort and leave, so every wave still terminates).
+// Barrier over the team's workgroups.  Each wave first waits for its own
+// memory operations to complete (they are then in this XCD's L2); after the
+// workgroup barrier one thread per workgroup releases at agent scope (L2
+// write-back covers every wave's stores), arrives, and the last arrival bumps
+// the generation.  Waiters poll it with a bounded spin (on overrun they raise
+// *abort and leave, so every wave still terminates), then acquire at agent
+// scope (L1/L2 invalidation covers the whole workgroup) before the closing
+// workgroup barrier releases the other waves.
 __device__ __forceinline__ void team_sync(const Team &t) {
     if (t.nwg == 1) {
         __syncthreads();
         return;
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned gen = __hip_atomic_load(&t.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned gen = __hip_atomic_load(&t.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned prev = __hip_atomic_fetch_add(&t.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == (unsigned)t.nwg - 1u) {
             __hip_atomic_store(&t.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&t.bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             int spins = 0;
-            while (__hip_atomic_load(&t.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&t.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > GMT_SPIN_LIMIT) {
                     __hip_atomic_store(t.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __threadfence();
 }
 
 // ---------------------------------------------------------------------------

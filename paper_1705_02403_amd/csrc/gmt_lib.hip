@@ -94,6 +94,44 @@ extern "C" gmt_status gmt_set_allocator(const gmt_allocator *allocator) {
 }
 
 extern "C" const char *gmt_last_error(void) { return g_last_error.c_str(); }
+
+static thread_local gmt_work g_last_work = {0, 0, 0, 0, 0, 0};
+
+extern "C" gmt_status gmt_last_work(gmt_work *out) {
+    if (!out) return fail(GMT_EINVAL, "null argument");
+    *out = g_last_work;
+    return GMT_OK;
+}
+
+// kernel timing (opt-in)
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static double g_prof_ms = 0.0;
+static long long g_prof_launches = 0;
+
+extern "C" gmt_status gmt_profile_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (kernel_ms) *kernel_ms = g_prof_ms;
+    if (launches) *launches = g_prof_launches;
+    g_prof_ms = 0.0;
+    g_prof_launches = 0;
+    return GMT_OK;
+}
+
+static void work_add(gmt_work &w, const unsigned long long *c) {
+    w.out_edges += (int64_t)c[0];
+    w.in_edges += (int64_t)c[1];
+    w.candidates += (int64_t)c[2];
+    w.commits += (int64_t)c[3];
+    w.open_entries += (int64_t)c[4];
+    w.iterations += (int64_t)c[5];
+}
 extern "C" const char *gmt_version(void) { return "gmt-mi355x 0.1 (gfx950)"; }
 
 // ---------------------------------------------------------------------------
@@ -689,14 +727,35 @@ static int max_coop_wgs(size_t lds, int kind) {
 static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int teams, int team_wgs, int box_words,
                               size_t stage_used, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, stage_used, hipMemcpyHostToDevice, s));
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+    }
     if (n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, n_euclid, count, std::min(teams, n_euclid), team_wgs,
                              box_words, 0, s));
     if (count - n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, n_euclid, count - n_euclid, count,
                              std::min(teams, count - n_euclid), team_wgs, box_words, 1, s));
+    if (prof) HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (prof) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_ms += ms;
+        g_prof_launches += (n_euclid > 0) + (count - n_euclid > 0);
+    }
     return GMT_OK;
 }
 
@@ -762,6 +821,8 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
             ws_reset_ctl(w, s);
             st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
         } else {
+            g_last_work = gmt_work{0, 0, 0, 0, 0, 0};
+            work_add(g_last_work, r.work);
             if (path_len) *path_len = r.path_len;
             if (path_cost) *path_cost = r.path_cost;
             if (iters) *iters = r.iters;
@@ -850,10 +911,14 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
     }
     if (st == GMT_OK) {
         bool fault = false;
+        g_last_work = gmt_work{0, 0, 0, 0, 0, 0};
         for (int j = 0; j < count; ++j) {
             const int k = order[j];
             const Result &r = w->res_h[j];
             gmt_result &o = results[k];
+            o.work = gmt_work{0, 0, 0, 0, 0, 0};
+            work_add(o.work, r.work);
+            work_add(g_last_work, r.work);
             if (r.abort || r.status == ST_FAULT) fault = true;
             o.status = (int)status_of(r.status);
             o.iters = r.iters;

@@ -60,10 +60,16 @@ struct ProbDev {
     int *out_added;
 };
 
+// work counters of one query (exact): out-edges walked, in-edges scanned,
+// candidates processed, nodes committed, open-list entries partitioned,
+// non-empty iterations
+enum { W_OUT = 0, W_IN = 1, W_CAND = 2, W_COMMIT = 3, W_OPEN = 4, W_ITERS = 5, W_COUNT = 6 };
+
 struct Result {
     int status, iters, path_len, z;
     double path_cost;
     int abort, pad;
+    unsigned long long work[W_COUNT];
     int path[GMT_PATH_INLINE];
 };
 
@@ -229,7 +235,9 @@ __device__ void run_query(const Team &t, const ProbDev &P, const Ws &ws, const i
     const int n = R.n, N = n + 1, root = n;
     Ctl *ctl = ws.ctl;
 
+    unsigned long long w_out = 0, w_in = 0, w_cand = 0, w_commit = 0, w_open = 0, w_iters = 0;
     if (t.rank == 0) {
+        for (int k = 0; k < W_COUNT; ++k) res->work[k] = 0ull;
         ctl->open_cnt[0] = 0;
         ctl->open_cnt[1] = 0;
         ctl->g_cnt[0] = 0;
@@ -350,6 +358,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const Ws &ws, const i
             break;
         }
         const int ii = (int)i;
+        if (t.rank == 0) {
+            w_open += (unsigned long long)cnt;
+            ++w_iters;
+        }
         // ---- select ----
         const int *cur = ws.open[p];
         int *nxt = ws.open[p ^ 1];
@@ -383,6 +395,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const Ws &ws, const i
         for (int gi = t.wave; gi < gc; gi += t.nwaves) {
             const int g = ws.glist[gi];
             const int ob = R.out_ptr[g], oe = R.out_ptr[g + 1];
+            if (t.lane == 0) w_out += (unsigned long long)(oe - ob);
             for (int e0 = ob; e0 < oe; e0 += GMT_WAVE) {
                 int e = e0 + t.lane;
                 int x = -1;
@@ -399,6 +412,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const Ws &ws, const i
                     const int xx = __shfl(x, src);
                     // locally optimal parent among open in-neighbours (lines 5-6)
                     const int ib = R.in_ptr[xx], ie = R.in_ptr[xx + 1];
+                    if (t.lane == 0) {
+                        w_in += (unsigned long long)(ie - ib);
+                        ++w_cand;
+                    }
                     double best = __longlong_as_double(COST_INF_BITS);
                     int by = 0x7fffffff, be = -1;
                     for (int f0 = ib; f0 < ie; f0 += GMT_WAVE) {
@@ -426,6 +443,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const Ws &ws, const i
                         st.close = CLOSE_NEVER;
                         ws.node[xx] = st;
                         ws.parent[xx] = by;
+                        ++w_commit;
                         int slot = atomicAdd(&ctl->open_cnt[p ^ 1], 1);
                         nxt[slot] = xx;
                         atomic_min_cost(&ctl->min_bits[p ^ 1], best);
@@ -477,6 +495,16 @@ __device__ void run_query(const Team &t, const ProbDev &P, const Ws &ws, const i
         rs->z = z;
         rs->path_cost = pc;
         rs->abort = (t.nwg > 1) ? ld_acquire(t.abort) : 0;
+    }
+    // ---- work counters: one atomic per wave and counter ----
+    {
+        unsigned long long wv[W_COUNT] = {w_out, w_in, w_cand, w_commit, w_open, w_iters};
+        for (int k = 0; k < W_COUNT; ++k) {
+            unsigned long long v = wv[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (t.lane == 0 && v) atomicAdd(&res->work[k], v);
+        }
     }
     // ---- tree outputs ----
     if (P.out_parent || P.out_cost || P.out_group || P.out_added) {

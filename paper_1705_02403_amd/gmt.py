@@ -39,6 +39,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 # symbols the header declares (checked by the CPU tests)
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_batch",
+           "gmt_last_work", "gmt_profile_enable", "gmt_profile_read",
            "gmt_last_error", "gmt_version"]
 
 
@@ -90,11 +91,19 @@ class gmt_problem(C.Structure):
                 ("boxes", C.POINTER(C.c_float)), ("m", C.c_int32), ("lambda_", C.c_double)]
 
 
+class gmt_work(C.Structure):
+    _fields_ = [("out_edges", C.c_int64), ("in_edges", C.c_int64), ("candidates", C.c_int64),
+                ("commits", C.c_int64), ("open_entries", C.c_int64), ("iterations", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class gmt_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("path_len", C.c_int32),
                 ("path_cap", C.c_int32), ("path_cost", C.c_double),
                 ("path", C.POINTER(C.c_int32)), ("d_parent", C.c_void_p), ("d_cost", C.c_void_p),
-                ("d_group_iter", C.c_void_p), ("d_added_iter", C.c_void_p)]
+                ("d_group_iter", C.c_void_p), ("d_added_iter", C.c_void_p), ("work", gmt_work)]
 
 
 class gmt_batch_opts(C.Structure):
@@ -128,6 +137,9 @@ def lib():
                                    C.POINTER(i32), P]
             L.gmt_plan_batch.argtypes = [C.POINTER(gmt_problem), i32, C.POINTER(gmt_batch_opts),
                                          C.POINTER(gmt_result), P]
+            L.gmt_last_work.argtypes = [C.POINTER(gmt_work)]
+            L.gmt_profile_enable.argtypes = [i32]
+            L.gmt_profile_read.argtypes = [C.POINTER(f64), C.POINTER(i64)]
             L.gmt_last_error.restype = C.c_char_p
             L.gmt_version.restype = C.c_char_p
             for name in EXPORTS:
@@ -146,6 +158,24 @@ def last_error() -> str:
 
 def gmt_version() -> str:
     return lib().gmt_version().decode()
+
+
+def gmt_last_work() -> dict:
+    w = gmt_work()
+    _check(lib().gmt_last_work(C.byref(w)), "gmt_last_work")
+    return w.as_dict()
+
+
+def gmt_profile_enable(enable: bool = True) -> None:
+    _check(lib().gmt_profile_enable(int(bool(enable))), "gmt_profile_enable")
+
+
+def gmt_profile_read():
+    """(kernel milliseconds, launches) since the last read."""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(lib().gmt_profile_read(C.byref(ms), C.byref(n)), "gmt_profile_read")
+    return float(ms.value), int(n.value)
 
 
 def _check(st: int, what: str, ok=(GMT_OK,)) -> int:
@@ -277,6 +307,7 @@ class PlanResult:
     cost: object = None
     group_iter: object = None
     added_iter: object = None
+    work: Optional[dict] = None
 
 
 def make_goal(center: Sequence[float], radius: float, ndims: int) -> gmt_goal:
@@ -321,7 +352,7 @@ def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_p
     _check(st, "gmt_plan", ok=(GMT_OK, GMT_NO_PATH, GMT_ETIMEOUT))
     L = int(plen.value) if st == GMT_OK else 0
     return PlanResult(int(st), path[:min(L, path_cap)].copy(), float(pcost.value), int(iters.value),
-                      par, cst, gi, ai)
+                      par, cst, gi, ai, gmt_last_work())
 
 
 @dataclass
@@ -375,5 +406,6 @@ def gmt_plan_batch(queries: Sequence[BatchQuery], opts: gmt_plan_opts, workgroup
         path, o = outs[j]
         L = int(res[j].path_len) if res[j].status == GMT_OK else 0
         out.append(PlanResult(int(res[j].status), path[:min(L, path_cap)].copy(),
-                              float(res[j].path_cost), int(res[j].iters), *o))
+                              float(res[j].path_cost), int(res[j].iters), *o,
+                              work=res[j].work.as_dict()))
     return out
