@@ -457,16 +457,18 @@ extern "C" gmt_status gmt_roadmap_free(gmt_roadmap_t rm) {
 }
 
 // ---------------------------------------------------------------------------
-// workspaces: per-team planning state, reused across calls
+// workspaces: per-query planning state and per-team barrier state, reused
+// across calls
 // ---------------------------------------------------------------------------
 struct WsBlock {
-    int teams = 0, cap = 0;
-    DevBuf mem;       // all teams' arrays
-    DevBuf d_ws;      // Ws[teams]
-    DevBuf stage_d;   // device copy of the staged queries
-    void *stage_h = nullptr;  // pinned: [queue counter][ProbDev x count][boxes]
+    DevBuf mem;  // per-query workspaces
+    size_t mem_bytes = 0;
+    DevBuf tctl;  // TeamCtl[teams]
+    int teams = 0;
+    DevBuf stage_d;           // device copy of the staged queries
+    void *stage_h = nullptr;  // pinned: [queue counters][ProbDev x count][boxes]
     size_t stage_bytes = 0;
-    DevBuf res_d;     // Result[count]
+    DevBuf res_d;             // Result[count]
     Result *res_h = nullptr;  // pinned
     int res_count = 0;
     bool busy = false;
@@ -475,70 +477,60 @@ struct WsBlock {
 static std::mutex g_ws_mu;
 static std::vector<WsBlock *> g_ws;
 
-static size_t ws_team_bytes(int cap) {
-    size_t c = (size_t)cap;
-    size_t b = 16 * c;           // node
-    b += 4 * c * 6;              // parent, stamp, open0, open1, glist, hits
-    b += (c + 15) / 16 * 16;     // goal
-    b += 256;                    // ctl
-    return (b + 255) & ~size_t(255);
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// bytes of one query's workspace over N nodes (tree arrays included when the
+// caller does not supply them)
+static size_t qws_bytes(int N, bool own_tree) {
+    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 6 * al256(4 * (size_t)N);
+    if (own_tree) b += al256(8 * (size_t)N) + 3 * al256(4 * (size_t)N);
+    return b;
 }
 
-static gmt_status ws_acquire(int teams, int cap, hipStream_t s, WsBlock **out) {
+static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi, int *ai) {
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += al256(bytes);
+        return q;
+    };
+    w.ctl = (Ctl *)take(sizeof(Ctl));
+    w.st = (unsigned char *)take((size_t)N);
+    w.open[0] = (int *)take(4 * (size_t)N);
+    w.open[1] = (int *)take(4 * (size_t)N);
+    w.glist[0] = (int *)take(4 * (size_t)N);
+    w.glist[1] = (int *)take(4 * (size_t)N);
+    w.clist = (int *)take(4 * (size_t)N);
+    w.hits = (int *)take(4 * (size_t)N);
+    w.cost = cost ? cost : (double *)take(8 * (size_t)N);
+    w.parent = parent ? parent : (int *)take(4 * (size_t)N);
+    w.gi = gi ? gi : (int *)take(4 * (size_t)N);
+    w.ai = ai ? ai : (int *)take(4 * (size_t)N);
+}
+
+static gmt_status ws_acquire(size_t bytes, int teams, hipStream_t s, WsBlock **out) {
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         for (WsBlock *w : g_ws)
-            if (!w->busy && w->teams >= teams && w->cap >= cap) {
+            if (!w->busy && w->mem_bytes >= bytes && w->teams >= teams) {
                 w->busy = true;
                 *out = w;
                 return GMT_OK;
             }
     }
     WsBlock *w = new WsBlock;
-    w->teams = teams;
-    w->cap = cap;
-    size_t tb = ws_team_bytes(cap);
-    gmt_status st = dev_alloc(w->mem, tb * teams, s);
-    if (st == GMT_OK) st = dev_alloc(w->d_ws, sizeof(Ws) * teams, s);
+    gmt_status st = dev_alloc(w->mem, bytes, s);
+    if (st == GMT_OK) st = dev_alloc(w->tctl, sizeof(TeamCtl) * teams, s);
+    if (st == GMT_OK && (hipMemsetAsync(w->tctl.p, 0, sizeof(TeamCtl) * teams, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+        st = fail(GMT_EDEVICE, "workspace initialisation failed");
     if (st != GMT_OK) {
         dev_free(w->mem, s);
+        dev_free(w->tctl, s);
         delete w;
         return st;
     }
-    std::vector<Ws> h(teams);
-    char *base = (char *)w->mem.p;
-    for (int k = 0; k < teams; ++k) {
-        char *p = base + tb * k;
-        Ws &x = h[k];
-        x.node = (NodeState *)p;
-        p += 16 * (size_t)cap;
-        x.parent = (int *)p;
-        p += 4 * (size_t)cap;
-        x.stamp = (int *)p;
-        p += 4 * (size_t)cap;
-        x.open[0] = (int *)p;
-        p += 4 * (size_t)cap;
-        x.open[1] = (int *)p;
-        p += 4 * (size_t)cap;
-        x.glist = (int *)p;
-        p += 4 * (size_t)cap;
-        x.hits = (int *)p;
-        p += 4 * (size_t)cap;
-        x.goal = (unsigned char *)p;
-        p += ((size_t)cap + 15) / 16 * 16;
-        p = (char *)(((uintptr_t)p + 255) & ~uintptr_t(255));
-        x.ctl = (Ctl *)p;
-        x.cap = cap;
-        x.pad = 0;
-    }
-    if (hipMemsetAsync(w->mem.p, 0, tb * teams, s) != hipSuccess ||
-        hipMemcpyAsync(w->d_ws.p, h.data(), sizeof(Ws) * teams, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        dev_free(w->mem, s);
-        dev_free(w->d_ws, s);
-        delete w;
-        return fail(GMT_EDEVICE, "workspace initialisation failed");
-    }
+    w->mem_bytes = bytes;
+    w->teams = teams;
     w->busy = true;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     g_ws.push_back(w);
@@ -579,8 +571,7 @@ static gmt_status ws_stage(WsBlock *w, size_t bytes, int count, hipStream_t s) {
 
 // clear barrier state after a faulted launch
 static void ws_reset_ctl(WsBlock *w, hipStream_t s) {
-    size_t tb = ws_team_bytes(w->cap);
-    (void)hipMemsetAsync(w->mem.p, 0, tb * w->teams, s);
+    (void)hipMemsetAsync(w->tctl.p, 0, sizeof(TeamCtl) * w->teams, s);
     (void)hipStreamSynchronize(s);
 }
 
@@ -687,75 +678,93 @@ static int num_cus() {
     return g_num_cu;
 }
 
-static const void *plan_kernel(int kind) {
-    return kind == GMT_COST_EUCLIDEAN ? (const void *)k_plan<0> : (const void *)k_plan<1>;
+// LDS bytes of the plan kernel: boxes, plus the state bytes when kept in LDS
+static size_t plan_lds(int box_words, int nmax, bool lds_st) {
+    size_t b = (size_t)((std::max(box_words, 1) + 3) & ~3) * sizeof(int);
+    if (lds_st) b += (size_t)((nmax + 1 + 3) & ~3);
+    return b;
 }
 
-// Launch the persistent planning kernel over staged queries [first,
-// first+count) of one cost kind; queue counter `qslot` of the staging header.
-static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int teams,
-                                   int team_wgs, int box_words, int qslot, hipStream_t s) {
+static const size_t kLdsStateLimit = 48 * 1024;
+
+static const void *plan_kernel(int kind, bool lds_st) {
+    if (kind == GMT_COST_EUCLIDEAN) return lds_st ? (const void *)k_plan<0, true> : (const void *)k_plan<0, false>;
+    return lds_st ? (const void *)k_plan<1, true> : (const void *)k_plan<1, false>;
+}
+
+// Launch init + persistent planning over staged queries [first, first+count)
+// of one cost kind; queue counter `qslot` of the staging header.
+static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int nmax,
+                                   int teams, int team_wgs, int box_words, int qslot, bool prof,
+                                   hipStream_t s) {
     char *sd = (char *)w->stage_d.p;
     int *queue = (int *)sd + qslot;
     const ProbDev *probs = (const ProbDev *)(sd + 256) + first;
     const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
-    const Ws *wss = (const Ws *)w->d_ws.p;
+    TeamCtl *tctl = (TeamCtl *)w->tctl.p;
     Result *res = (Result *)w->res_d.p + first;
     size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
-    dim3 grid(teams * team_wgs), block(256);
-    if (team_wgs > 1) {
-        void *args[] = {&probs, &count, &boxes, &box_words, &queue, &wss, &team_wgs, &res};
-        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind), grid, block, args, (unsigned)lds, s));
-    } else if (kind == GMT_COST_EUCLIDEAN) {
-        k_plan<0><<<grid, block, lds, s>>>(probs, count, boxes, box_words, queue, wss, team_wgs, res);
-        HIPCHK(hipGetLastError());
-    } else {
-        k_plan<1><<<grid, block, lds, s>>>(probs, count, boxes, box_words, queue, wss, team_wgs, res);
-        HIPCHK(hipGetLastError());
+    const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
+    const size_t plds = plan_lds(box_words, nmax, lds_st);
+    for (int c0 = 0; c0 < count; c0 += 65535) {
+        dim3 ig(blocks_for((long long)nmax + 1, 256), std::min(65535, count - c0));
+        if (kind == GMT_COST_EUCLIDEAN)
+            k_plan_init<0><<<ig, 256, lds, s>>>(probs + c0, boxes);
+        else
+            k_plan_init<1><<<ig, 256, lds, s>>>(probs + c0, boxes);
     }
-    return GMT_OK;
-}
-
-static int max_coop_wgs(size_t lds, int kind) {
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind), 256, lds) != hipSuccess || per < 1)
-        per = 1;
-    return per * num_cus();
-}
-
-// Stage-copy, launch per kind (queries sorted Euclidean first), read back.
-static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int teams, int team_wgs, int box_words,
-                              size_t stage_used, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, stage_used, hipMemcpyHostToDevice, s));
-    bool prof;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        prof = g_prof_on;
-    }
+    HIPCHK(hipGetLastError());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, s));
     }
-    if (n_euclid > 0)
-        TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, n_euclid, count, std::min(teams, n_euclid), team_wgs,
-                             box_words, 0, s));
-    if (count - n_euclid > 0)
-        TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, n_euclid, count - n_euclid, count,
-                             std::min(teams, count - n_euclid), team_wgs, box_words, 1, s));
-    if (prof) HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    dim3 grid(teams * team_wgs), block(256);
+    void *args[] = {&probs, &count, &boxes, &box_words, &queue, &tctl, &team_wgs, &res};
+    if (team_wgs > 1)
+        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, false), grid, block, args, (unsigned)plds, s));
+    else
+        HIPCHK(hipLaunchKernel(plan_kernel(kind, lds_st), grid, block, args, plds, s));
     if (prof) {
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof_ms += ms;
-        g_prof_launches += (n_euclid > 0) + (count - n_euclid > 0);
+        g_prof_launches += 1;
     }
+    return GMT_OK;
+}
+
+static int max_coop_wgs(size_t lds, int kind, bool lds_st = false) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, lds_st), 256, lds) != hipSuccess ||
+        per < 1)
+        per = 1;
+    return per * num_cus();
+}
+
+// Stage-copy, launch per kind (queries sorted Euclidean first), read back.
+static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int nmax_e, int nmax_d, int teams,
+                              int team_wgs, int box_words, size_t stage_used, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, stage_used, hipMemcpyHostToDevice, s));
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    if (n_euclid > 0)
+        TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, n_euclid, count, nmax_e, std::min(teams, n_euclid),
+                             team_wgs, box_words, 0, prof, s));
+    if (count - n_euclid > 0)
+        TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, n_euclid, count - n_euclid, count, nmax_d,
+                             std::min(teams, count - n_euclid), team_wgs, box_words, 1, prof, s));
+    HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return GMT_OK;
 }
 
@@ -768,10 +777,10 @@ static gmt_status status_of(int st) {
     }
 }
 
-// full path from the parent array when it exceeds the inline copy
-static gmt_status long_path(const Ws &hw, int N, int z, int *path, int cap, hipStream_t s) {
+// full path from a device parent array when it exceeds the inline copy
+static gmt_status long_path(const int *d_parent, int N, int z, int *path, int cap, hipStream_t s) {
     std::vector<int> par(N);
-    HIPCHK(hipMemcpyAsync(par.data(), hw.parent, sizeof(int) * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(par.data(), d_parent, sizeof(int) * N, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     std::vector<int> rev;
     for (int v = z; v >= 0 && (int)rev.size() <= N; v = par[v]) rev.push_back(v);
@@ -791,14 +800,19 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
     if (!opts_in && rm->kind == GMT_COST_EUCLIDEAN) return fail(GMT_EINVAL, "Euclidean plans need opts.edge_step");
     hipStream_t s = (hipStream_t)stream;
     const int pd = pdim_of(rm->kind, rm->dim);
+    if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
     const int box_words = m * 2 * pd;
     const size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
     int team_wgs = o.team_wgs > 0 ? o.team_wgs : num_cus();
     team_wgs = std::min(team_wgs, max_coop_wgs(lds, rm->kind));
+    const int N = rm->n + 1;
+    // the tree arrays are the caller's when all four are given
+    const bool own = !(d_parent && d_cost && d_group_iter && d_added_iter);
     WsBlock *w = nullptr;
-    TRY(ws_acquire(1, rm->n + 1, s, &w));
+    TRY(ws_acquire(qws_bytes(N, true), 1, s, &w));
     size_t used = 256 + sizeof(ProbDev) + sizeof(int) * (size_t)box_words;
     gmt_status st = ws_stage(w, used, 1, s);
+    const int *tree_parent = nullptr;
     if (st == GMT_OK) {
         char *sh = (char *)w->stage_h;
         ((int *)sh)[0] = 0;  // queue counters
@@ -808,12 +822,25 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
         QueryIn q{rm, x_init, goal, boxes, m, lambda};
         st = stage_query(q, o, *P, bx, 0);
         if (st == GMT_OK) {
-            P->out_parent = d_parent;
-            P->out_cost = d_cost;
-            P->out_group = d_group_iter;
-            P->out_added = d_added_iter;
-            st = launch_plan(w, 1, rm->kind == GMT_COST_EUCLIDEAN ? 1 : 0, 1, team_wgs, box_words, used, s);
+            if (own)
+                qws_carve((char *)w->mem.p, N, P->w, nullptr, nullptr, nullptr, nullptr);
+            else
+                qws_carve((char *)w->mem.p, N, P->w, d_cost, d_parent, d_group_iter, d_added_iter);
+            tree_parent = P->w.parent;
+            const bool eu = rm->kind == GMT_COST_EUCLIDEAN;
+            st = launch_plan(w, 1, eu ? 1 : 0, eu ? rm->n : 0, eu ? 0 : rm->n, 1, team_wgs, box_words, used, s);
         }
+    }
+    if (st == GMT_OK && own && (d_parent || d_cost || d_group_iter || d_added_iter)) {
+        // some but not all tree arrays requested: copy those out
+        const QWs &qw = ((ProbDev *)((char *)w->stage_h + 256))->w;
+        hipError_t e = hipSuccess;
+        if (d_parent) e = hipMemcpyAsync(d_parent, qw.parent, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && d_cost) e = hipMemcpyAsync(d_cost, qw.cost, 8 * (size_t)N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && d_group_iter) e = hipMemcpyAsync(d_group_iter, qw.gi, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && d_added_iter) e = hipMemcpyAsync(d_added_iter, qw.ai, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "tree copy failed: %s", hipGetErrorString(e));
     }
     if (st == GMT_OK) {
         const Result &r = w->res_h[0];
@@ -830,9 +857,7 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
                 if (r.path_len <= GMT_PATH_INLINE) {
                     for (int k = 0; k < r.path_len && k < path_cap; ++k) path[k] = r.path[k];
                 } else {
-                    Ws hw;
-                    (void)hipMemcpy(&hw, w->d_ws.p, sizeof hw, hipMemcpyDeviceToHost);
-                    st = long_path(hw, rm->n + 1, r.z, path, path_cap, s);
+                    st = long_path(tree_parent, N, r.z, path, path_cap, s);
                 }
             }
             if (st == GMT_OK) st = status_of(r.status);
@@ -853,8 +878,8 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
         bo.plan.traj_points = 16;
     }
     hipStream_t s = (hipStream_t)stream;
-    int cap = 1, box_words = 1;
-    size_t total_boxes = 0;
+    int box_words = 1, nmax_e = 0, nmax_d = 0;
+    size_t total_boxes = 0, ws_bytes = 0;
     // Euclidean queries are staged first, double-integrator ones after
     std::vector<int> order;
     order.reserve(count);
@@ -864,24 +889,36 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
             if (!pr.roadmap) return fail(GMT_EINVAL, "problem %d: null roadmap", k);
             if ((pr.roadmap->kind == GMT_COST_EUCLIDEAN) == (pass == 0)) order.push_back(k);
         }
+    std::vector<size_t> ws_off(count);
     int n_euclid = 0;
-    for (int k = 0; k < count; ++k) {
-        const gmt_problem &pr = problems[k];
-        if (pr.roadmap->kind == GMT_COST_EUCLIDEAN) ++n_euclid;
-        cap = std::max(cap, pr.roadmap->n + 1);
-        if (pr.m < 0 || pr.m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "problem %d: box count out of range", k);
+    for (int j = 0; j < count; ++j) {
+        const gmt_problem &pr = problems[order[j]];
+        const gmt_result &rr = results[order[j]];
+        const bool eu = pr.roadmap->kind == GMT_COST_EUCLIDEAN;
+        if (eu) {
+            ++n_euclid;
+            nmax_e = std::max(nmax_e, pr.roadmap->n);
+        } else {
+            nmax_d = std::max(nmax_d, pr.roadmap->n);
+        }
+        if (pr.m < 0 || pr.m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "problem %d: box count out of range", order[j]);
         int words = pr.m * 2 * pdim_of(pr.roadmap->kind, pr.roadmap->dim);
         box_words = std::max(box_words, words);
         total_boxes += (size_t)words;
+        const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
+        ws_off[j] = ws_bytes;
+        ws_bytes += qws_bytes(pr.roadmap->n + 1, own);
     }
     int team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
-    const size_t lds = (size_t)box_words * sizeof(int);
-    int resident = std::min(max_coop_wgs(lds, 0), max_coop_wgs(lds, 1));
+    const int nmax = std::max(nmax_e, nmax_d);
+    const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
+    const size_t lds = plan_lds(box_words, nmax, lds_st);
+    int resident = std::min(max_coop_wgs(lds, 0, lds_st), max_coop_wgs(lds, 1, lds_st));
     int teams = bo.workgroups > 0 ? bo.workgroups / team_wgs : resident / team_wgs;
     teams = std::max(1, std::min(teams, count));
     if (team_wgs > 1) teams = std::max(1, std::min(teams, resident / team_wgs));
     WsBlock *w = nullptr;
-    TRY(ws_acquire(teams, cap, s, &w));
+    TRY(ws_acquire(ws_bytes, teams, s, &w));
     size_t used = 256 + sizeof(ProbDev) * count + sizeof(int) * total_boxes;
     gmt_status st = ws_stage(w, used, count, s);
     if (st == GMT_OK) {
@@ -901,17 +938,38 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
                 st = fail(st, "problem %d: %s", k, msg.c_str());
                 break;
             }
-            P[j].out_parent = results[k].d_parent;
-            P[j].out_cost = results[k].d_cost;
-            P[j].out_group = results[k].d_group_iter;
-            P[j].out_added = results[k].d_added_iter;
+            const gmt_result &rr = results[k];
+            const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
+            char *base = (char *)w->mem.p + ws_off[j];
+            if (own)
+                qws_carve(base, pr.roadmap->n + 1, P[j].w, nullptr, nullptr, nullptr, nullptr);
+            else
+                qws_carve(base, pr.roadmap->n + 1, P[j].w, rr.d_cost, rr.d_parent, rr.d_group_iter, rr.d_added_iter);
             off += P[j].m * 2 * P[j].pd;
         }
-        if (st == GMT_OK) st = launch_plan(w, count, n_euclid, teams, team_wgs, box_words, used, s);
+        if (st == GMT_OK) st = launch_plan(w, count, n_euclid, nmax_e, nmax_d, teams, team_wgs, box_words, used, s);
+    }
+    if (st == GMT_OK) {
+        // partial tree requests: copy the requested arrays out
+        const ProbDev *P = (const ProbDev *)((char *)w->stage_h + 256);
+        for (int j = 0; j < count && st == GMT_OK; ++j) {
+            const gmt_result &rr = results[order[j]];
+            const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
+            if (!own || !(rr.d_parent || rr.d_cost || rr.d_group_iter || rr.d_added_iter)) continue;
+            const size_t N = (size_t)P[j].rm.n + 1;
+            hipError_t e = hipSuccess;
+            if (rr.d_parent) e = hipMemcpyAsync(rr.d_parent, P[j].w.parent, 4 * N, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess && rr.d_cost) e = hipMemcpyAsync(rr.d_cost, P[j].w.cost, 8 * N, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess && rr.d_group_iter) e = hipMemcpyAsync(rr.d_group_iter, P[j].w.gi, 4 * N, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess && rr.d_added_iter) e = hipMemcpyAsync(rr.d_added_iter, P[j].w.ai, 4 * N, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) st = fail(GMT_EDEVICE, "tree copy failed: %s", hipGetErrorString(e));
+        }
+        if (st == GMT_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(GMT_EDEVICE, "stream sync failed");
     }
     if (st == GMT_OK) {
         bool fault = false;
         g_last_work = gmt_work{0, 0, 0, 0, 0, 0};
+        const ProbDev *P = (const ProbDev *)((char *)w->stage_h + 256);
         for (int j = 0; j < count; ++j) {
             const int k = order[j];
             const Result &r = w->res_h[j];
@@ -925,14 +983,11 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
             o.path_len = r.path_len;
             o.path_cost = r.path_cost;
             if (o.path && r.status == ST_OK) {
-                if (r.path_len <= GMT_PATH_INLINE)
+                if (r.path_len <= GMT_PATH_INLINE) {
                     for (int i = 0; i < r.path_len && i < o.path_cap; ++i) o.path[i] = r.path[i];
-                else if (o.d_parent) {
-                    std::vector<int> par(problems[k].roadmap->n + 1);
-                    (void)hipMemcpy(par.data(), o.d_parent, sizeof(int) * par.size(), hipMemcpyDeviceToHost);
-                    std::vector<int> rev;
-                    for (int v = r.z; v >= 0 && rev.size() <= par.size(); v = par[v]) rev.push_back(v);
-                    for (int i = 0; i < (int)rev.size() && i < o.path_cap; ++i) o.path[i] = rev[rev.size() - 1 - i];
+                } else {
+                    gmt_status ls = long_path(P[j].w.parent, P[j].rm.n + 1, r.z, o.path, o.path_cap, s);
+                    if (ls != GMT_OK) st = ls;
                 }
             }
         }
