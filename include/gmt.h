@@ -91,8 +91,8 @@ typedef struct {
  *              traj_points times t_k = k tau/(traj_points-1) (>= 2).
  *  max_iters   cap on the threshold index i of Algorithm 1 (<= 0: none).
  *  team_wgs    workgroups cooperating on one plan (0: library choice).
- *  lanes       lanes per candidate in the parent search: 0 (library choice)
- *              or one of 4, 16, 64.  Results do not depend on it.  */
+ *  lanes       lanes per candidate in the parent search: 0 (library choice,
+ *              16) or 8.  Results do not depend on it.  */
 typedef struct {
     double edge_step;
     int32_t traj_points;
@@ -179,7 +179,9 @@ gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
 /* Exact work of one query (or the sum over a batch), counted by the plan
  * kernel: out-edges walked from group members (Alg. 1 line 4), in-edges
  * scanned for parents (lines 5-6), candidates processed, nodes added (lines
- * 8-9), open-list entries partitioned (line 3), non-empty iterations. */
+ * 8-9), open nodes partitioned (line 3), non-empty iterations; then the
+ * time the query's team spent in setup and in the select / frontier /
+ * connect phases (device wall clock, first thread's view, nanoseconds). */
 typedef struct {
     int64_t out_edges;
     int64_t in_edges;
@@ -187,6 +189,10 @@ typedef struct {
     int64_t commits;
     int64_t open_entries;
     int64_t iterations;
+    int64_t setup_ns;
+    int64_t select_ns;
+    int64_t frontier_ns;
+    int64_t connect_ns;
 } gmt_work;
 
 /* Work of the last gmt_plan / gmt_plan_batch call on this thread. */

@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) k_eu_fill(int n, EuGrid g, const int *__r
                                                  const int *__restrict__ cell_start, double R2,
                                                  const int *__restrict__ row_ptr, int cap,
                                                  int *__restrict__ col, double *__restrict__ cost) {
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int wl = threadIdx.x / GMT_WAVE;
     int *bj = (int *)lds_raw + (size_t)wl * cap * 3;
     long long *bd = (long long *)(bj + cap);  // 8-byte aligned: cap*4 bytes offset, cap even
@@ -342,7 +342,7 @@ __global__ void k_out_place(const int *__restrict__ in_ptr, const int *__restric
 // rows longer than `cap` are left unsorted and flagged in flags[0]
 __global__ void __launch_bounds__(256) k_rows_sort(const int *__restrict__ ptr, int n, int cap,
                                                    int *__restrict__ col, int *__restrict__ flags) {
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int wl = threadIdx.x / GMT_WAVE;
     int *buf = (int *)lds_raw + (size_t)wl * cap;
     int row = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;

@@ -95,7 +95,7 @@ extern "C" gmt_status gmt_set_allocator(const gmt_allocator *allocator) {
 
 extern "C" const char *gmt_last_error(void) { return g_last_error.c_str(); }
 
-static thread_local gmt_work g_last_work = {0, 0, 0, 0, 0, 0};
+static thread_local gmt_work g_last_work = {};
 
 extern "C" gmt_status gmt_last_work(gmt_work *out) {
     if (!out) return fail(GMT_EINVAL, "null argument");
@@ -124,6 +124,19 @@ extern "C" gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches) {
     return GMT_OK;
 }
 
+static double g_tick_ns = 0.0;  // wall-clock tick of the device, ns
+
+static double tick_ns() {
+    if (g_tick_ns == 0.0) {
+        int dev = 0, khz = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+        g_tick_ns = 1.0e6 / (double)khz;
+    }
+    return g_tick_ns;
+}
+
 static void work_add(gmt_work &w, const unsigned long long *c) {
     w.out_edges += (int64_t)c[0];
     w.in_edges += (int64_t)c[1];
@@ -131,6 +144,11 @@ static void work_add(gmt_work &w, const unsigned long long *c) {
     w.commits += (int64_t)c[3];
     w.open_entries += (int64_t)c[4];
     w.iterations += (int64_t)c[5];
+    const double ns = tick_ns();
+    w.setup_ns += (int64_t)((double)c[6] * ns);
+    w.select_ns += (int64_t)((double)c[7] * ns);
+    w.frontier_ns += (int64_t)((double)c[8] * ns);
+    w.connect_ns += (int64_t)((double)c[9] * ns);
 }
 extern "C" const char *gmt_version(void) { return "gmt-mi355x 0.1 (gfx950)"; }
 
@@ -482,7 +500,7 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // bytes of one query's workspace over N nodes (tree arrays included when the
 // caller does not supply them)
 static size_t qws_bytes(int N, bool own_tree) {
-    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 6 * al256(4 * (size_t)N);
+    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 3 * al256(4 * (size_t)N);
     if (own_tree) b += al256(8 * (size_t)N) + 3 * al256(4 * (size_t)N);
     return b;
 }
@@ -495,10 +513,7 @@ static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi
     };
     w.ctl = (Ctl *)take(sizeof(Ctl));
     w.st = (unsigned char *)take((size_t)N);
-    w.open[0] = (int *)take(4 * (size_t)N);
-    w.open[1] = (int *)take(4 * (size_t)N);
-    w.glist[0] = (int *)take(4 * (size_t)N);
-    w.glist[1] = (int *)take(4 * (size_t)N);
+    w.glist = (int *)take(4 * (size_t)N);
     w.clist = (int *)take(4 * (size_t)N);
     w.hits = (int *)take(4 * (size_t)N);
     w.cost = cost ? cost : (double *)take(8 * (size_t)N);
@@ -678,24 +693,32 @@ static int num_cus() {
     return g_num_cu;
 }
 
-// LDS bytes of the plan kernel: boxes, plus the state bytes when kept in LDS
+// LDS bytes of the plan kernel: boxes, plus the state bytes and counters
+// when kept in LDS
 static size_t plan_lds(int box_words, int nmax, bool lds_st) {
     size_t b = (size_t)((std::max(box_words, 1) + 3) & ~3) * sizeof(int);
-    if (lds_st) b += (size_t)((nmax + 1 + 3) & ~3);
+    if (lds_st) b += (size_t)((nmax + 1 + 15) & ~15) + sizeof(Ctl);
     return b;
 }
 
 static const size_t kLdsStateLimit = 48 * 1024;
 
-static const void *plan_kernel(int kind, bool lds_st) {
-    if (kind == GMT_COST_EUCLIDEAN) return lds_st ? (const void *)k_plan<0, true> : (const void *)k_plan<0, false>;
-    return lds_st ? (const void *)k_plan<1, true> : (const void *)k_plan<1, false>;
+template <int K, bool L>
+static const void *plan_kernel_cl(int cl) {
+    return cl == 8 ? (const void *)k_plan<K, L, 8> : (const void *)k_plan<K, L, 16>;
 }
+
+static const void *plan_kernel(int kind, bool lds_st, int cl) {
+    if (kind == GMT_COST_EUCLIDEAN) return lds_st ? plan_kernel_cl<0, true>(cl) : plan_kernel_cl<0, false>(cl);
+    return lds_st ? plan_kernel_cl<1, true>(cl) : plan_kernel_cl<1, false>(cl);
+}
+
+static int lanes_of(int lanes) { return lanes == 8 ? 8 : 16; }
 
 // Launch init + persistent planning over staged queries [first, first+count)
 // of one cost kind; queue counter `qslot` of the staging header.
 static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int nmax,
-                                   int teams, int team_wgs, int box_words, int qslot, bool prof,
+                                   int teams, int team_wgs, int box_words, int qslot, int cl, bool prof,
                                    hipStream_t s) {
     char *sd = (char *)w->stage_d.p;
     int *queue = (int *)sd + qslot;
@@ -721,11 +744,12 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
         HIPCHK(hipEventRecord(e0, s));
     }
     dim3 grid(teams * team_wgs), block(256);
-    void *args[] = {&probs, &count, &boxes, &box_words, &queue, &tctl, &team_wgs, &res};
+    int st_bytes = nmax + 1;
+    void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
     if (team_wgs > 1)
-        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, false), grid, block, args, (unsigned)plds, s));
+        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, false, cl), grid, block, args, (unsigned)plds, s));
     else
-        HIPCHK(hipLaunchKernel(plan_kernel(kind, lds_st), grid, block, args, plds, s));
+        HIPCHK(hipLaunchKernel(plan_kernel(kind, lds_st, cl), grid, block, args, plds, s));
     if (prof) {
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
@@ -740,9 +764,9 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
     return GMT_OK;
 }
 
-static int max_coop_wgs(size_t lds, int kind, bool lds_st = false) {
+static int max_coop_wgs(size_t lds, int kind, bool lds_st = false, int cl = 16) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, lds_st), 256, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, lds_st, cl), 256, lds) != hipSuccess ||
         per < 1)
         per = 1;
     return per * num_cus();
@@ -750,7 +774,7 @@ static int max_coop_wgs(size_t lds, int kind, bool lds_st = false) {
 
 // Stage-copy, launch per kind (queries sorted Euclidean first), read back.
 static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int nmax_e, int nmax_d, int teams,
-                              int team_wgs, int box_words, size_t stage_used, hipStream_t s) {
+                              int team_wgs, int box_words, int cl, size_t stage_used, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, stage_used, hipMemcpyHostToDevice, s));
     bool prof;
     {
@@ -759,10 +783,10 @@ static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int nmax_e, i
     }
     if (n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, n_euclid, count, nmax_e, std::min(teams, n_euclid),
-                             team_wgs, box_words, 0, prof, s));
+                             team_wgs, box_words, 0, cl, prof, s));
     if (count - n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, n_euclid, count - n_euclid, count, nmax_d,
-                             std::min(teams, count - n_euclid), team_wgs, box_words, 1, prof, s));
+                             std::min(teams, count - n_euclid), team_wgs, box_words, 1, cl, prof, s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return GMT_OK;
@@ -803,8 +827,9 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
     if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
     const int box_words = m * 2 * pd;
     const size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
+    const int cl = lanes_of(o.lanes);
     int team_wgs = o.team_wgs > 0 ? o.team_wgs : num_cus();
-    team_wgs = std::min(team_wgs, max_coop_wgs(lds, rm->kind));
+    team_wgs = std::min(team_wgs, max_coop_wgs(lds, rm->kind, false, cl));
     const int N = rm->n + 1;
     // the tree arrays are the caller's when all four are given
     const bool own = !(d_parent && d_cost && d_group_iter && d_added_iter);
@@ -828,7 +853,7 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
                 qws_carve((char *)w->mem.p, N, P->w, d_cost, d_parent, d_group_iter, d_added_iter);
             tree_parent = P->w.parent;
             const bool eu = rm->kind == GMT_COST_EUCLIDEAN;
-            st = launch_plan(w, 1, eu ? 1 : 0, eu ? rm->n : 0, eu ? 0 : rm->n, 1, team_wgs, box_words, used, s);
+            st = launch_plan(w, 1, eu ? 1 : 0, eu ? rm->n : 0, eu ? 0 : rm->n, 1, team_wgs, box_words, cl, used, s);
         }
     }
     if (st == GMT_OK && own && (d_parent || d_cost || d_group_iter || d_added_iter)) {
@@ -848,7 +873,7 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
             ws_reset_ctl(w, s);
             st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
         } else {
-            g_last_work = gmt_work{0, 0, 0, 0, 0, 0};
+            g_last_work = gmt_work{};
             work_add(g_last_work, r.work);
             if (path_len) *path_len = r.path_len;
             if (path_cost) *path_cost = r.path_cost;
@@ -913,7 +938,8 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
     const int nmax = std::max(nmax_e, nmax_d);
     const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
     const size_t lds = plan_lds(box_words, nmax, lds_st);
-    int resident = std::min(max_coop_wgs(lds, 0, lds_st), max_coop_wgs(lds, 1, lds_st));
+    const int cl = lanes_of(bo.plan.lanes);
+    int resident = std::min(max_coop_wgs(lds, 0, lds_st, cl), max_coop_wgs(lds, 1, lds_st, cl));
     int teams = bo.workgroups > 0 ? bo.workgroups / team_wgs : resident / team_wgs;
     teams = std::max(1, std::min(teams, count));
     if (team_wgs > 1) teams = std::max(1, std::min(teams, resident / team_wgs));
@@ -947,7 +973,7 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
                 qws_carve(base, pr.roadmap->n + 1, P[j].w, rr.d_cost, rr.d_parent, rr.d_group_iter, rr.d_added_iter);
             off += P[j].m * 2 * P[j].pd;
         }
-        if (st == GMT_OK) st = launch_plan(w, count, n_euclid, nmax_e, nmax_d, teams, team_wgs, box_words, used, s);
+        if (st == GMT_OK) st = launch_plan(w, count, n_euclid, nmax_e, nmax_d, teams, team_wgs, box_words, cl, used, s);
     }
     if (st == GMT_OK) {
         // partial tree requests: copy the requested arrays out
@@ -968,13 +994,13 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
     }
     if (st == GMT_OK) {
         bool fault = false;
-        g_last_work = gmt_work{0, 0, 0, 0, 0, 0};
+        g_last_work = gmt_work{};
         const ProbDev *P = (const ProbDev *)((char *)w->stage_h + 256);
         for (int j = 0; j < count; ++j) {
             const int k = order[j];
             const Result &r = w->res_h[j];
             gmt_result &o = results[k];
-            o.work = gmt_work{0, 0, 0, 0, 0, 0};
+            o.work = gmt_work{};
             work_add(o.work, r.work);
             work_add(g_last_work, r.work);
             if (r.abort || r.status == ST_FAULT) fault = true;

@@ -20,14 +20,15 @@
 // order or on the launch shape.
 //
 // Iteration i (Algorithm 1 lines 3-12), three phases split by team barriers:
-//   select  : close G_{i-1}, mark the open list open, split it into G_i (cost
-//             <= i*delta) and the rest (ballot compaction).  Empty groups are
-//             skipped by jumping i to the first threshold at or above the
-//             least open cost -- the iteration the literal loop reaches.
+//   select  : one pass over the state bytes closes G_{i-1} and splits the
+//             open nodes into G_i (cost <= i*delta, gathered by ballot
+//             compaction) and the rest.  Empty groups are skipped by jumping i
+//             to the first threshold at or above the least open cost -- the
+//             iteration the literal loop reaches.
 //   frontier: one wave per group member walks its out-row; each unexplored
 //             neighbour is claimed once per iteration (atomic OR of a claim
 //             bit in its state byte) and appended to the candidate list.
-//   connect : 16 lanes per candidate, four candidates per wave: lexicographic
+//   connect : CL lanes per candidate, 64/CL candidates per wave: lexicographic
 //             argmin of (cost[y] + c(y,x), y) over open in-neighbours (four
 //             independent loads in flight per lane), lazy check of that single
 //             edge, commit on success, else release the claim.
@@ -40,14 +41,18 @@
 
 #define GMT_PATH_INLINE 500
 
-// node state byte: low two bits the set, bit 2 the goal flag, bit 3 set while
-// the node is a candidate of the running iteration
-#define ST_UNEXPLORED 0
-#define ST_OPEN 1
-#define ST_TREE 2  // in the tree and not open: closed, or added this iteration
-#define ST_DEAD 3
-#define ST_GOAL 4
-#define ST_CLAIM 8
+// node state byte: bits 0-2 the set, bit 3 the goal flag, bit 4 set while
+// the node is a candidate of the running iteration.  OPEN and GROUP are the
+// only sets with (s & 3) == 1: the nodes open when an iteration begins.
+#define S_UNEXPLORED 0
+#define S_OPEN 1    // in the tree, open
+#define S_NEW 2     // added by the running iteration (open from the next one)
+#define S_CLOSED 3
+#define S_GROUP 5   // member of the running iteration's group: open, then closed
+#define S_DEAD 6    // inside an obstacle of this query
+#define S_SET 7
+#define S_GOAL 8
+#define S_CLAIM 16
 
 namespace gmt {
 
@@ -63,20 +68,24 @@ struct RoadmapDev {
     const int *out_col;
 };
 
-// per-query counters
+// per-query counters (double-buffered by iteration parity where a fast
+// thread of the next iteration could otherwise race a slow reader)
 struct Ctl {
-    int open_cnt[2];
-    int g_cnt[2];
-    int hit_cnt[2];
-    int c_cnt[2];
-    unsigned long long min_bits[2];
+    int g_cnt;       // group size
+    int c_cnt;       // candidates
+    int hit_cnt[2];  // goal nodes in the group
+    int rem_cnt[2];  // open nodes carried to the next iteration
+    int com_cnt[2];  // nodes added by the iteration
+    int pad[2];
+    unsigned long long min_bits[2];  // least cost over the next iteration's open set
 };
+// 64-bit LDS atomics need 8-byte alignment of these fields
+static_assert(offsetof(Ctl, min_bits) % 8 == 0, "Ctl layout");
 
 // per-query device workspace; cost/parent/gi/ai are the tree outputs
 struct QWs {
     unsigned char *st;  // (n+1) bytes, padded to a multiple of 4
-    int *open[2];
-    int *glist[2];
+    int *glist;
     int *clist;
     int *hits;
     Ctl *ctl;
@@ -99,9 +108,11 @@ struct ProbDev {
 };
 
 // work counters of one query (exact): out-edges walked, in-edges scanned,
-// candidates processed, nodes committed, open-list entries partitioned,
-// non-empty iterations
-enum { W_OUT = 0, W_IN = 1, W_CAND = 2, W_COMMIT = 3, W_OPEN = 4, W_ITERS = 5, W_COUNT = 6 };
+// candidates processed, nodes committed, open nodes partitioned, non-empty
+// iterations; then wall-clock ticks spent in setup / select / frontier /
+// connect (first thread's view)
+enum { W_OUT = 0, W_IN = 1, W_CAND = 2, W_COMMIT = 3, W_OPEN = 4, W_ITERS = 5,
+       W_T_SETUP = 6, W_T_SELECT = 7, W_T_FRONTIER = 8, W_T_CONNECT = 9, W_COUNT = 10 };
 
 struct Result {
     int status, iters, path_len, z;
@@ -121,7 +132,6 @@ struct TeamCtl {
 
 enum { ST_OK = 0, ST_NO_PATH = 1, ST_TIMEOUT = 2, ST_FAULT = -3 };
 
-#define CL_LANES 16  // lanes per candidate in the connect phase
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -217,7 +227,7 @@ __device__ bool di_edge_free_serial(const double *ys, const double *xs, double t
 template <int KIND>
 __global__ void __launch_bounds__(256) k_plan_init(const ProbDev *__restrict__ probs,
                                                    const int *__restrict__ boxes) {
-    extern __shared__ int lbox[];
+    extern __shared__ __align__(16) int lbox[];
     const ProbDev &P = probs[blockIdx.y];
     const RoadmapDev &R = P.rm;
     const int words = P.m * 2 * P.pd;
@@ -229,7 +239,7 @@ __global__ void __launch_bounds__(256) k_plan_init(const ProbDev *__restrict__ p
     const QWs &w = P.w;
     w.gi[v] = -1;
     if (v == root) {
-        w.st[v] = (unsigned char)(ST_TREE | (in_goal_q(P.x_q, P) ? ST_GOAL : 0));
+        w.st[v] = (unsigned char)(S_CLOSED | (in_goal_q(P.x_q, P) ? S_GOAL : 0));
         w.cost[v] = 0.0;
         w.parent[v] = -1;
         w.ai[v] = -1;
@@ -240,7 +250,7 @@ __global__ void __launch_bounds__(256) k_plan_init(const ProbDev *__restrict__ p
     for (int a = 0; a < R.dim; ++a) q[a] = (int)((double)R.s[(size_t)a * n + v] * GMT_QS);
     bool dead = false;
     for (int b = 0; b < P.m && !dead; ++b) dead = point_in_box_q(q, lbox + b * 2 * P.pd, P.pd);
-    unsigned char goal = in_goal_q(q, P) ? ST_GOAL : 0;
+    unsigned char goal = in_goal_q(q, P) ? S_GOAL : 0;
     double c = __longlong_as_double(COST_INF_BITS);
     bool join = false;
     if (!dead) {
@@ -268,18 +278,19 @@ __global__ void __launch_bounds__(256) k_plan_init(const ProbDev *__restrict__ p
             }
         }
     }
-    w.st[v] = (unsigned char)((dead ? ST_DEAD : (join ? ST_OPEN : ST_UNEXPLORED)) | goal);
+    w.st[v] = (unsigned char)((dead ? S_DEAD : (join ? S_OPEN : S_UNEXPLORED)) | goal);
     w.cost[v] = c;
     w.parent[v] = join ? root : -1;
     w.ai[v] = join ? 0 : -2;
 }
 
 // ---------------------------------------------------------------------------
-// connect phase helpers: 16-lane groups
+// connect phase helpers: groups of CL lanes
 // ---------------------------------------------------------------------------
+template <int CL>
 __device__ __forceinline__ void group_argmin(double &v, int &y, int &e) {
 #pragma unroll
-    for (int off = CL_LANES / 2; off > 0; off >>= 1) {
+    for (int off = CL / 2; off > 0; off >>= 1) {
         double ov = __shfl_xor(v, off);
         int oy = __shfl_xor(y, off);
         int oe = __shfl_xor(e, off);
@@ -291,40 +302,52 @@ __device__ __forceinline__ void group_argmin(double &v, int &y, int &e) {
     }
 }
 
-// lazy check of edge y -> x by the 16 lanes of a group; every lane of the
-// wave calls it; returns the verdict for this lane's group
+// End state of the candidate x (KIND 0: grid coordinates in xq; KIND 1: the
+// state in xs), loaded while its in-row is scanned.
+struct CandEnd {
+    int xq[3];
+    double xs[6];
+};
+
 template <int KIND>
-__device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, int y, int x, int e,
-                                                const int *lbox) {
+__device__ __forceinline__ void load_end(const RoadmapDev &R, int x, CandEnd &c) {
+    if (KIND == 0) {
+        for (int a = 0; a < 3; ++a) c.xq[a] = a < R.dim ? (int)((double)R.s[(size_t)a * R.n + x] * GMT_QS) : 0;
+    } else {
+        sample_d<6>(R, x, c.xs);
+    }
+}
+
+// lazy check of edge y -> x by the CL lanes of a group; every lane of the
+// wave calls it; returns the verdict for this lane's group
+template <int KIND, int CL>
+__device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, int y, const CandEnd &c,
+                                                int e, const int *lbox) {
     const RoadmapDev &R = P.rm;
-    const int l16 = lane_id() & (CL_LANES - 1);
+    const int lg = lane_id() & (CL - 1);
     bool hit = false;
     if (active) {
         if (KIND == 0) {
-            int yq[3] = {0, 0, 0}, xq[3] = {0, 0, 0};
-            for (int a = 0; a < R.dim; ++a) {
-                yq[a] = (int)((double)R.s[(size_t)a * R.n + y] * GMT_QS);
-                xq[a] = (int)((double)R.s[(size_t)a * R.n + x] * GMT_QS);
-            }
+            int yq[3] = {0, 0, 0};
+            for (int a = 0; a < R.dim; ++a) yq[a] = (int)((double)R.s[(size_t)a * R.n + y] * GMT_QS);
             long long d2 = 0;
             for (int a = 0; a < P.pd; ++a) {
-                long long dd = (long long)xq[a] - yq[a];
+                long long dd = (long long)c.xq[a] - yq[a];
                 d2 += dd * dd;
             }
             long long K1 = segment_parts(d2, P.step_q);
-            for (int b = l16; b < P.m; b += CL_LANES) {
+            for (int b = lg; b < P.m; b += CL) {
                 const int *lo = lbox + b * 2 * P.pd, *hi = lo + P.pd;
-                if (!aabb_disjoint(yq, xq, P.pd, lo, hi) && segment_hits_box(yq, xq, P.pd, K1, lo, hi))
+                if (!aabb_disjoint(yq, c.xq, P.pd, lo, hi) && segment_hits_box(yq, c.xq, P.pd, K1, lo, hi))
                     hit = true;
             }
         } else {
-            double ys[6], xs[6];
+            double ys[6];
             sample_d<6>(R, y, ys);
-            sample_d<6>(R, x, xs);
-            DiPair d = make_pair(ys, xs);
+            DiPair d = make_pair(ys, c.xs);
             const double tau = R.in_tau[e];
             const int K = P.traj_points;
-            for (int k = l16; k < K && !hit; k += CL_LANES) {
+            for (int k = lg; k < K && !hit; k += CL) {
                 double p[3];
                 di_point(ys, d, tau, (double)k / (double)(K - 1), p);
                 for (int b = -1; b < P.m; ++b)
@@ -336,8 +359,9 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, i
         }
     }
     uint64_t m = wave_ballot(hit);
-    const int sub = lane_id() / CL_LANES;
-    return ((m >> (sub * CL_LANES)) & 0xffffull) == 0;
+    const int sub = lane_id() / CL;
+    const uint64_t gm = (CL == 64) ? ~0ull : ((1ull << CL) - 1ull);
+    return ((m >> (sub * CL)) & gm) == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +371,7 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, i
 // claim x as a candidate of this iteration: true for exactly one caller
 __device__ __forceinline__ bool claim(unsigned char *st, int x) {
     unsigned int *wd = (unsigned int *)(st) + (x >> 2);
-    const unsigned int bit = (unsigned int)ST_CLAIM << ((x & 3) * 8);
+    const unsigned int bit = (unsigned int)S_CLAIM << ((x & 3) * 8);
     return (atomicOr(wd, bit) & bit) == 0u;
 }
 
@@ -355,7 +379,7 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 __device__ __forceinline__ void scan_edge(const unsigned char *st, const double *cost,
                                           const double *in_cost, int y, int f, double &best, int &by,
                                           int &be) {
-    if ((st[y] & 3) == ST_OPEN) {
+    if ((st[y] & 3) == 1) {  // open when the iteration began (S_OPEN or S_GROUP)
         const double v = cost[y] + in_cost[f];
         if (v < best || (v == best && y < by)) {
             best = v;
@@ -365,52 +389,69 @@ __device__ __forceinline__ void scan_edge(const unsigned char *st, const double 
     }
 }
 
-// LDS_ST: the node state bytes live in this workgroup's LDS (one-workgroup
-// teams); otherwise they stay in global memory, shared by the team
-template <int KIND, bool LDS_ST>
-__device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsigned char *lst,
+__device__ __forceinline__ int ld_cnt(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// add this wave's count of true predicates to *counter (no return value)
+__device__ __forceinline__ void wave_count(int *counter, bool pred) {
+    uint64_t m = wave_ballot(pred);
+    if (m && lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(counter, (int)__popcll(m));
+}
+
+__device__ __forceinline__ unsigned long long clock_ticks() { return wall_clock64(); }
+
+// LDS: node state bytes and counters live in this workgroup's LDS
+// (one-workgroup teams); otherwise in global memory, shared by the team.
+// CL: lanes per candidate in the connect phase.
+template <int KIND, bool LDS, int CL>
+__device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsigned char *lst, Ctl *lctl,
                           Result *res) {
     const RoadmapDev &R = P.rm;
     const QWs &w = P.w;
     const int n = R.n, N = n + 1, root = n;
-    Ctl *ctl = w.ctl;
-    unsigned char *st = LDS_ST ? lst : w.st;
+    unsigned char *st = LDS ? lst : w.st;
+    Ctl *ctl = LDS ? lctl : w.ctl;
     unsigned long long w_out = 0, w_in = 0, w_cand = 0, w_commit = 0, w_open = 0, w_iters = 0;
+    unsigned long long tk_setup = 0, tk_select = 0, tk_frontier = 0, tk_connect = 0;
+    unsigned long long tk = (t.rank == 0) ? clock_ticks() : 0;
 
     if (t.rank == 0) {
-        for (int k = 0; k < W_COUNT; ++k) res->work[k] = 0ull;
+        ctl->g_cnt = 0;
+        ctl->c_cnt = 0;
         for (int k = 0; k < 2; ++k) {
-            ctl->open_cnt[k] = 0;
-            ctl->g_cnt[k] = 0;
             ctl->hit_cnt[k] = 0;
-            ctl->c_cnt[k] = 0;
+            ctl->rem_cnt[k] = 0;
+            ctl->com_cnt[k] = 0;
             ctl->min_bits[k] = COST_INF_BITS;
         }
     }
-    if (LDS_ST) {
+    if (LDS) {
         const int words = (N + 3) >> 2;
         const unsigned int *src = (const unsigned int *)w.st;
         unsigned int *dst = (unsigned int *)lst;
         for (int k = t.rank; k < words; k += t.size) dst[k] = src[k];
     }
     team_sync(t);
-    // open list of iteration 1: the root's children (added by k_plan_init)
+    // open set of iteration 1: the root's children (added by k_plan_init)
     for (int v = t.rank; v < n; v += t.size) {
-        bool op = (st[v] & 3) == ST_OPEN;
-        int slot = wave_append(&ctl->open_cnt[1], op);
-        if (op) {
-            w.open[1][slot] = v;
-            atomic_min_cost(&ctl->min_bits[1], w.cost[v]);
-        }
+        const bool op = (st[v] & S_SET) == S_OPEN;
+        wave_count(&ctl->rem_cnt[1], op);
+        if (op) atomic_min_cost(&ctl->min_bits[1], w.cost[v]);
     }
     team_sync(t);
 
     int status = -1, iters = 0, z = -1, hit_parity = 0;
-    if (st[root] & ST_GOAL) {
+    if (st[root] & S_GOAL) {
         status = ST_OK;
         z = root;
-    } else if (ld_acquire(&ctl->open_cnt[1]) == 0) {
+    } else if (ld_cnt(&ctl->rem_cnt[1]) == 0) {
         status = ST_NO_PATH;
+    }
+    if (t.rank == 0) {
+        unsigned long long now = clock_ticks();
+        tk_setup += now - tk;
+        tk = now;
     }
 
     int i_prev = 0;
@@ -420,8 +461,9 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             break;
         }
         const int p = it & 1;
-        const int cnt = ld_acquire(&ctl->open_cnt[p]);
-        const double mn = __longlong_as_double((long long)ld_acquire_u64(&ctl->min_bits[p]));
+        const int open_n = ld_cnt(&ctl->rem_cnt[p]) + ld_cnt(&ctl->com_cnt[p]);
+        const double mn = __longlong_as_double(
+            (long long)__hip_atomic_load(&ctl->min_bits[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         // threshold index of this iteration (Algorithm 1 line 3)
         long long i = (long long)i_prev + 1;
         double thr;
@@ -449,51 +491,44 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         }
         const int ii = (int)i;
         if (t.rank == 0) {
-            w_open += (unsigned long long)cnt;
+            w_open += (unsigned long long)open_n;
             ++w_iters;
+            ctl->c_cnt = 0;  // read by the previous connect phase, before its barrier
         }
-        // ---- select ----
-        {
-            // the previous group closes (line 10 of the previous iteration)
-            const int gprev = it > 1 ? ld_acquire(&ctl->g_cnt[p ^ 1]) : 0;
-            for (int k = t.rank; k < gprev; k += t.size) {
-                const int g = w.glist[p ^ 1][k];
-                st[g] = (unsigned char)(ST_TREE | (st[g] & ST_GOAL));
+        // ---- select (line 3; line 10 of the previous iteration) ----
+        for (int v = t.rank; v < n; v += t.size) {
+            const unsigned char s = st[v];
+            const int set = s & S_SET;
+            const unsigned char goal = s & S_GOAL;
+            bool in_g = false, rem = false;
+            double c = 0.0;
+            if (set == S_GROUP) {
+                st[v] = (unsigned char)(S_CLOSED | goal);
+            } else if (set == S_OPEN || set == S_NEW) {
+                c = w.cost[v];
+                in_g = c <= thr;
+                rem = !in_g;
+                st[v] = (unsigned char)((in_g ? S_GROUP : S_OPEN) | goal);
+                if (in_g) w.gi[v] = ii;
             }
-            const int *cur = w.open[p];
-            int *nxt = w.open[p ^ 1];
-            for (int k = t.rank; k < cnt; k += t.size) {
-                const int y = cur[k];
-                const double c = w.cost[y];
-                const unsigned char s = st[y];
-                st[y] = (unsigned char)(ST_OPEN | (s & ST_GOAL));
-                const bool in_g = c <= thr;
-                if (in_g) w.gi[y] = ii;
-                int sg = wave_append(&ctl->g_cnt[p], in_g);
-                if (in_g) w.glist[p][sg] = y;
-                const bool hit = in_g && (s & ST_GOAL);
-                int sh = wave_append(&ctl->hit_cnt[p], hit);
-                if (hit) w.hits[sh] = y;
-                int so = wave_append(&ctl->open_cnt[p ^ 1], !in_g);
-                if (!in_g) {
-                    nxt[so] = y;
-                    atomic_min_cost(&ctl->min_bits[p ^ 1], c);
-                }
-            }
+            const int sg = wave_append(&ctl->g_cnt, in_g);
+            if (in_g) w.glist[sg] = v;
+            const bool hit = in_g && goal;
+            const int sh = wave_append(&ctl->hit_cnt[p], hit);
+            if (hit) w.hits[sh] = v;
+            wave_count(&ctl->rem_cnt[p ^ 1], rem);
+            if (rem) atomic_min_cost(&ctl->min_bits[p ^ 1], c);
         }
         team_sync(t);
-        // ---- frontier (line 4) ----
-        // next iteration's counters: every thread read them before the select
-        // barrier, and nothing else writes them in this iteration
         if (t.rank == 0) {
-            ctl->open_cnt[p] = 0;
-            ctl->min_bits[p] = COST_INF_BITS;
-            ctl->hit_cnt[p ^ 1] = 0;
-            ctl->c_cnt[p ^ 1] = 0;
+            unsigned long long now = clock_ticks();
+            tk_select += now - tk;
+            tk = now;
         }
-        const int gc = ld_acquire(&ctl->g_cnt[p]);
+        // ---- frontier (line 4) ----
+        const int gc = ld_cnt(&ctl->g_cnt);
         for (int gk = t.wave; gk < gc; gk += t.nwaves) {
-            const int g = w.glist[p][gk];
+            const int g = w.glist[gk];
             const int ob = R.out_ptr[g], oe = R.out_ptr[g + 1];
             if (t.lane == 0) w_out += (unsigned long long)(oe - ob);
             for (int e0 = ob; e0 < oe; e0 += GMT_WAVE) {
@@ -503,20 +538,30 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 if (e < oe) {
                     x = R.out_col[e];
                     const unsigned char s = st[x];
-                    if ((s & 3) == ST_UNEXPLORED && !(s & ST_CLAIM)) cand = claim(st, x);
+                    if ((s & S_SET) == S_UNEXPLORED && !(s & S_CLAIM)) cand = claim(st, x);
                 }
-                int slot = wave_append(&ctl->c_cnt[p], cand);
+                const int slot = wave_append(&ctl->c_cnt, cand);
                 if (cand) w.clist[slot] = x;
             }
         }
         team_sync(t);
+        if (t.rank == 0) {
+            unsigned long long now = clock_ticks();
+            tk_frontier += now - tk;
+            tk = now;
+            // next iteration's counters: their last readers finished before
+            // the select barrier
+            ctl->g_cnt = 0;
+            ctl->rem_cnt[p] = 0;
+            ctl->com_cnt[p] = 0;
+            ctl->min_bits[p] = COST_INF_BITS;
+            ctl->hit_cnt[p ^ 1] = 0;
+        }
         // ---- connect (lines 5-9) ----
-        if (t.rank == 0) ctl->g_cnt[p ^ 1] = 0;  // read by the select phase above
         {
-            int *nxt = w.open[p ^ 1];
-            const int cc = ld_acquire(&ctl->c_cnt[p]);
-            const int sub = t.lane / CL_LANES, l16 = t.lane & (CL_LANES - 1);
-            const int per_wave = GMT_WAVE / CL_LANES;
+            const int cc = ld_cnt(&ctl->c_cnt);
+            const int sub = t.lane / CL, lg = t.lane & (CL - 1);
+            constexpr int per_wave = GMT_WAVE / CL;
             const int *__restrict__ in_col = R.in_col;
             const double *__restrict__ in_cost = R.in_cost;
             const double *__restrict__ cost = w.cost;
@@ -526,56 +571,60 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 const int x = active ? w.clist[k] : 0;
                 double best = __longlong_as_double(COST_INF_BITS);
                 int by = 0x7fffffff, be = -1;
+                CandEnd ce;
                 if (active) {
                     const int ib = R.in_ptr[x], ie = R.in_ptr[x + 1];
-                    if (l16 == 0) {
+                    load_end<KIND>(R, x, ce);
+                    if (lg == 0) {
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    int f = ib + l16;
+                    int f = ib + lg;
                     // four independent rows of loads in flight per lane
-                    for (; f + 3 * CL_LANES < ie; f += 4 * CL_LANES) {
-                        const int y0 = in_col[f], y1 = in_col[f + CL_LANES];
-                        const int y2 = in_col[f + 2 * CL_LANES], y3 = in_col[f + 3 * CL_LANES];
+                    for (; f + 3 * CL < ie; f += 4 * CL) {
+                        const int y0 = in_col[f], y1 = in_col[f + CL];
+                        const int y2 = in_col[f + 2 * CL], y3 = in_col[f + 3 * CL];
                         scan_edge(st, cost, in_cost, y0, f, best, by, be);
-                        scan_edge(st, cost, in_cost, y1, f + CL_LANES, best, by, be);
-                        scan_edge(st, cost, in_cost, y2, f + 2 * CL_LANES, best, by, be);
-                        scan_edge(st, cost, in_cost, y3, f + 3 * CL_LANES, best, by, be);
+                        scan_edge(st, cost, in_cost, y1, f + CL, best, by, be);
+                        scan_edge(st, cost, in_cost, y2, f + 2 * CL, best, by, be);
+                        scan_edge(st, cost, in_cost, y3, f + 3 * CL, best, by, be);
                     }
-                    for (; f < ie; f += CL_LANES) scan_edge(st, cost, in_cost, in_col[f], f, best, by, be);
+                    for (; f < ie; f += CL) scan_edge(st, cost, in_cost, in_col[f], f, best, by, be);
                 }
-                group_argmin(best, by, be);
+                group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
-                const bool free_edge = group_edge_free<KIND>(P, ok, ok ? by : 0, x, be, lbox);
-                const bool commit = ok && free_edge && l16 == 0;
-                if (active && l16 == 0) {
-                    // commit (line 8-9) or release the claim (x stays unexplored)
-                    const unsigned char g = st[x] & ST_GOAL;
-                    st[x] = (unsigned char)(commit ? (ST_TREE | g) : (ST_UNEXPLORED | g));
+                const bool free_edge = group_edge_free<KIND, CL>(P, ok, ok ? by : 0, ce, be, lbox);
+                const bool commit = ok && free_edge && lg == 0;
+                if (active && lg == 0) {
+                    // commit (lines 8-9), or release the claim: x stays unexplored
+                    const unsigned char goal = st[x] & S_GOAL;
+                    st[x] = (unsigned char)((commit ? S_NEW : S_UNEXPLORED) | goal);
                 }
                 if (commit) {
                     w.cost[x] = best;
                     w.parent[x] = by;
                     w.ai[x] = ii;
                     ++w_commit;
-                }
-                int slot = wave_append(&ctl->open_cnt[p ^ 1], commit);
-                if (commit) {
-                    nxt[slot] = x;
                     atomic_min_cost(&ctl->min_bits[p ^ 1], best);
                 }
+                wave_count(&ctl->com_cnt[p ^ 1], commit);
             }
         }
         team_sync(t);
+        if (t.rank == 0) {
+            unsigned long long now = clock_ticks();
+            tk_connect += now - tk;
+            tk = now;
+        }
         iters = ii;
         i_prev = ii;
         // ---- termination (line 12) ----
-        if (ld_acquire(&ctl->hit_cnt[p]) > 0) {
+        if (ld_cnt(&ctl->hit_cnt[p]) > 0) {
             status = ST_OK;
             hit_parity = p;
             break;
         }
-        if (ld_acquire(&ctl->open_cnt[p ^ 1]) == 0) {
+        if (ld_cnt(&ctl->rem_cnt[p ^ 1]) + ld_cnt(&ctl->com_cnt[p ^ 1]) == 0) {
             status = ST_NO_PATH;
             break;
         }
@@ -587,7 +636,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         double pc = __longlong_as_double(COST_INF_BITS);
         if (status == ST_OK) {
             if (z < 0) {
-                const int hc = ld_acquire(&ctl->hit_cnt[hit_parity]);
+                const int hc = ld_cnt(&ctl->hit_cnt[hit_parity]);
                 for (int k = 0; k < hc; ++k) {
                     int v = w.hits[k];
                     double c = w.cost[v];
@@ -609,11 +658,15 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         res->z = z;
         res->path_cost = pc;
         res->abort = (t.nwg > 1) ? ld_acquire(t.abort) : 0;
+        res->work[W_T_SETUP] = tk_setup;
+        res->work[W_T_SELECT] = tk_select;
+        res->work[W_T_FRONTIER] = tk_frontier;
+        res->work[W_T_CONNECT] = tk_connect;
     }
     // ---- work counters: one atomic per wave and counter ----
     {
-        unsigned long long wv[W_COUNT] = {w_out, w_in, w_cand, w_commit, w_open, w_iters};
-        for (int k = 0; k < W_COUNT; ++k) {
+        unsigned long long wv[6] = {w_out, w_in, w_cand, w_commit, w_open, w_iters};
+        for (int k = 0; k < 6; ++k) {
             unsigned long long v = wv[k];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -626,16 +679,19 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // ---------------------------------------------------------------------------
 // persistent kernel: teams of `team_wgs` workgroups pull queries of one
 // cost kind (KIND 0 Euclidean, 1 double integrator).  LDS holds the query's
-// boxes (box_words ints) and, for LDS_ST, its node state bytes after them.
+// boxes (box_words ints) and, for LDS, its node state bytes and counters;
+// the dynamic region is 16-byte aligned (it follows the static s_job), which
+// the 64-bit counter fields require.
 // ---------------------------------------------------------------------------
-template <int KIND, bool LDS_ST>
+template <int KIND, bool LDS, int CL>
 __global__ void __launch_bounds__(256) k_plan(const ProbDev *__restrict__ probs, int count,
-                                              const int *__restrict__ boxes, int box_words,
+                                              const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
                                               int team_wgs, Result *__restrict__ res) {
-    extern __shared__ int lbox[];
+    extern __shared__ __align__(16) int lbox[];
     __shared__ int s_job;
     unsigned char *lst = (unsigned char *)(lbox + ((box_words + 3) & ~3));
+    Ctl *lctl = (Ctl *)(lst + ((st_bytes + 15) & ~15));
     Team t;
     const int team = blockIdx.x / team_wgs;
     const int wg = blockIdx.x % team_wgs;
@@ -667,7 +723,7 @@ __global__ void __launch_bounds__(256) k_plan(const ProbDev *__restrict__ probs,
         const int words = P.m * 2 * P.pd;
         for (int k = threadIdx.x; k < words && k < box_words; k += blockDim.x) lbox[k] = boxes[P.box_off + k];
         __syncthreads();
-        run_query<KIND, LDS_ST>(t, P, lbox, lst, res + job);
+        run_query<KIND, LDS, CL>(t, P, lbox, lst, lctl, res + job);
         if (t.nwg > 1 && ld_acquire(t.abort)) return;
     }
 }

@@ -93,7 +93,9 @@ class gmt_problem(C.Structure):
 
 class gmt_work(C.Structure):
     _fields_ = [("out_edges", C.c_int64), ("in_edges", C.c_int64), ("candidates", C.c_int64),
-                ("commits", C.c_int64), ("open_entries", C.c_int64), ("iterations", C.c_int64)]
+                ("commits", C.c_int64), ("open_entries", C.c_int64), ("iterations", C.c_int64),
+                ("setup_ns", C.c_int64), ("select_ns", C.c_int64), ("frontier_ns", C.c_int64),
+                ("connect_ns", C.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
