@@ -500,7 +500,7 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // bytes of one query's workspace over N nodes (tree arrays included when the
 // caller does not supply them)
 static size_t qws_bytes(int N, bool own_tree) {
-    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 3 * al256(4 * (size_t)N);
+    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 2 * al256(4 * (size_t)N) + al256(16 * (size_t)N);
     if (own_tree) b += al256(8 * (size_t)N) + 3 * al256(4 * (size_t)N);
     return b;
 }
@@ -514,7 +514,7 @@ static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi
     w.ctl = (Ctl *)take(sizeof(Ctl));
     w.st = (unsigned char *)take((size_t)N);
     w.glist = (int *)take(4 * (size_t)N);
-    w.clist = (int *)take(4 * (size_t)N);
+    w.clist = (int4 *)take(16 * (size_t)N);
     w.hits = (int *)take(4 * (size_t)N);
     w.cost = cost ? cost : (double *)take(8 * (size_t)N);
     w.parent = parent ? parent : (int *)take(4 * (size_t)N);
@@ -715,18 +715,24 @@ static const void *plan_kernel(int kind, bool lds_st, int cl) {
 
 static int lanes_of(int lanes) { return lanes == 8 ? 8 : 16; }
 
+// 32-bit words of boxes the plan kernel stages in LDS (doubles for the
+// double integrator)
+static int plan_box_words(int kind, int words) { return kind == GMT_COST_EUCLIDEAN ? words : 2 * words; }
+
 // Launch init + persistent planning over staged queries [first, first+count)
 // of one cost kind; queue counter `qslot` of the staging header.
 static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int nmax,
-                                   int teams, int team_wgs, int box_words, int qslot, int cl, bool prof,
+                                   int teams, int team_wgs, int box_words_in, int qslot, int cl, bool prof,
                                    hipStream_t s) {
+    // the plan kernel stages double-integrator boxes as doubles (2 words each)
+    int box_words = plan_box_words(kind, box_words_in);
     char *sd = (char *)w->stage_d.p;
     int *queue = (int *)sd + qslot;
     const ProbDev *probs = (const ProbDev *)(sd + 256) + first;
     const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
     TeamCtl *tctl = (TeamCtl *)w->tctl.p;
     Result *res = (Result *)w->res_d.p + first;
-    size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
+    size_t lds = (size_t)std::max(box_words_in, 1) * sizeof(int);
     const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
     const size_t plds = plan_lds(box_words, nmax, lds_st);
     for (int c0 = 0; c0 < count; c0 += 65535) {
@@ -826,7 +832,7 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
     const int pd = pdim_of(rm->kind, rm->dim);
     if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
     const int box_words = m * 2 * pd;
-    const size_t lds = (size_t)std::max(box_words, 1) * sizeof(int);
+    const size_t lds = plan_lds(plan_box_words(rm->kind, box_words), rm->n, false);
     const int cl = lanes_of(o.lanes);
     int team_wgs = o.team_wgs > 0 ? o.team_wgs : num_cus();
     team_wgs = std::min(team_wgs, max_coop_wgs(lds, rm->kind, false, cl));
@@ -936,8 +942,9 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
     }
     int team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
     const int nmax = std::max(nmax_e, nmax_d);
-    const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
-    const size_t lds = plan_lds(box_words, nmax, lds_st);
+    const int pbw = plan_box_words(nmax_d > 0 ? GMT_COST_DOUBLE_INTEGRATOR : GMT_COST_EUCLIDEAN, box_words);
+    const bool lds_st = team_wgs == 1 && plan_lds(pbw, nmax, true) <= kLdsStateLimit;
+    const size_t lds = plan_lds(pbw, nmax, lds_st);
     const int cl = lanes_of(bo.plan.lanes);
     int resident = std::min(max_coop_wgs(lds, 0, lds_st, cl), max_coop_wgs(lds, 1, lds_st, cl));
     int teams = bo.workgroups > 0 ? bo.workgroups / team_wgs : resident / team_wgs;

@@ -29,9 +29,9 @@
 //             neighbour is claimed once per iteration (atomic OR of a claim
 //             bit in its state byte) and appended to the candidate list.
 //   connect : CL lanes per candidate, 64/CL candidates per wave: lexicographic
-//             argmin of (cost[y] + c(y,x), y) over open in-neighbours (four
-//             independent loads in flight per lane), lazy check of that single
-//             edge, commit on success, else release the claim.
+//             argmin of (cost[y] + c(y,x), y) over open in-neighbours (loads
+//             issued in independent stages), lazy check of that single edge,
+//             commit on success, else release the claim.
 //   then    : a goal node in G_i ends the run (least (cost, index) goal node);
 //             an empty open list reports failure.
 #pragma once
@@ -86,7 +86,7 @@ static_assert(offsetof(Ctl, min_bits) % 8 == 0, "Ctl layout");
 struct QWs {
     unsigned char *st;  // (n+1) bytes, padded to a multiple of 4
     int *glist;
-    int *clist;
+    int4 *clist;        // candidate x with its in-row [begin, end)
     int *hits;
     Ctl *ctl;
     double *cost;
@@ -169,7 +169,8 @@ __device__ __forceinline__ bool in_goal_q(const int *q, const ProbDev &P) {
     return (double)s <= P.goal_r2q;
 }
 
-// does a trajectory point lie in box b (b = -1: outside [0,1]^3)?
+// does a trajectory point lie in box b (b = -1: outside [0,1]^3)?  Boxes as
+// grid integers (k_plan_init) ...
 __device__ __forceinline__ bool di_point_hits(const double *p, int b, const int *lbox) {
     if (b < 0) return p[0] < 0.0 || p[0] > 1.0 || p[1] < 0.0 || p[1] > 1.0 || p[2] < 0.0 || p[2] > 1.0;
     const int *bx = lbox + b * 6;
@@ -179,6 +180,13 @@ __device__ __forceinline__ bool di_point_hits(const double *p, int b, const int 
         if (p[a] < lo || p[a] > hi) return false;
     }
     return true;
+}
+
+// ... or as exact doubles (k_plan stages them once per query)
+__device__ __forceinline__ bool di_point_hits_d(const double *p, int b, const double *dbox) {
+    if (b < 0) return p[0] < 0.0 || p[0] > 1.0 || p[1] < 0.0 || p[1] > 1.0 || p[2] < 0.0 || p[2] > 1.0;
+    const double *bx = dbox + b * 6;
+    return p[0] >= bx[0] && p[0] <= bx[3] && p[1] >= bx[1] && p[1] <= bx[4] && p[2] >= bx[2] && p[2] <= bx[5];
 }
 
 __device__ __forceinline__ DiPair make_pair(const double *src, const double *dst) {
@@ -342,16 +350,18 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, i
                     hit = true;
             }
         } else {
+            const double *dbox = (const double *)lbox;
             double ys[6];
             sample_d<6>(R, y, ys);
             DiPair d = make_pair(ys, c.xs);
             const double tau = R.in_tau[e];
             const int K = P.traj_points;
+            const double inv = 1.0 / (double)(K - 1);
             for (int k = lg; k < K && !hit; k += CL) {
                 double p[3];
-                di_point(ys, d, tau, (double)k / (double)(K - 1), p);
+                di_point(ys, d, tau, (double)k * inv, p);
                 for (int b = -1; b < P.m; ++b)
-                    if (di_point_hits(p, b, lbox)) {
+                    if (di_point_hits_d(p, b, dbox)) {
                         hit = true;
                         break;
                     }
@@ -375,16 +385,42 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
     return (atomicOr(wd, bit) & bit) == 0u;
 }
 
-// fold one scanned in-edge into the running lexicographic minimum
-__device__ __forceinline__ void scan_edge(const unsigned char *st, const double *cost,
-                                          const double *in_cost, int y, int f, double &best, int &by,
-                                          int &be) {
-    if ((st[y] & 3) == 1) {  // open when the iteration began (S_OPEN or S_GROUP)
-        const double v = cost[y] + in_cost[f];
-        if (v < best || (v == best && y < by)) {
-            best = v;
-            by = y;
-            be = f;
+// Scan the in-row [ib, ie) of candidate x with the CL lanes of a group for
+// the lexicographic minimum of (cost[y] + c(y, x), y) over open y.  Loads are
+// issued in stages of SCAN_U edges per lane -- indices, then state bytes,
+// then both costs -- so a lane keeps SCAN_U independent loads in flight per
+// stage instead of one dependent chain per edge.  Lanes whose edge is absent
+// or not open read fixed valid addresses (in_col[ib], cost[x], in_cost[ib])
+// and ignore the values.
+#define SCAN_U 8
+template <int CL>
+__device__ __forceinline__ void scan_row(const unsigned char *st, const double *__restrict__ cost,
+                                         const int *__restrict__ in_col, const double *__restrict__ in_cost,
+                                         int x, int ib, int ie, int lg, double &best, int &by, int &be) {
+    for (int f0 = ib + lg; f0 < ie; f0 += SCAN_U * CL) {
+        int y[SCAN_U];
+        bool op[SCAN_U];
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const int f = f0 + u * CL;
+            y[u] = in_col[f < ie ? f : ib];
+        }
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
+        double c[SCAN_U], ic[SCAN_U];
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            c[u] = cost[op[u] ? y[u] : x];
+            ic[u] = in_cost[op[u] ? f0 + u * CL : ib];
+        }
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const double v = c[u] + ic[u];
+            if (op[u] && (v < best || (v == best && y[u] < by))) {
+                best = v;
+                by = y[u];
+                be = f0 + u * CL;
+            }
         }
     }
 }
@@ -525,23 +561,29 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             tk_select += now - tk;
             tk = now;
         }
-        // ---- frontier (line 4) ----
-        const int gc = ld_cnt(&ctl->g_cnt);
-        for (int gk = t.wave; gk < gc; gk += t.nwaves) {
-            const int g = w.glist[gk];
-            const int ob = R.out_ptr[g], oe = R.out_ptr[g + 1];
-            if (t.lane == 0) w_out += (unsigned long long)(oe - ob);
-            for (int e0 = ob; e0 < oe; e0 += GMT_WAVE) {
-                const int e = e0 + t.lane;
-                int x = -1;
-                bool cand = false;
-                if (e < oe) {
-                    x = R.out_col[e];
-                    const unsigned char s = st[x];
-                    if ((s & S_SET) == S_UNEXPLORED && !(s & S_CLAIM)) cand = claim(st, x);
+        // ---- frontier (line 4): CL lanes per group member ----
+        {
+            const int gc = ld_cnt(&ctl->g_cnt);
+            const int sub = t.lane / CL, lg = t.lane & (CL - 1);
+            constexpr int per_wave = GMT_WAVE / CL;
+            for (int gb = t.wave * per_wave; gb < gc; gb += t.nwaves * per_wave) {
+                const int gk = gb + sub;
+                int ob = 0, oe = 0;
+                if (gk < gc) {
+                    const int g = w.glist[gk];
+                    ob = R.out_ptr[g];
+                    oe = R.out_ptr[g + 1];
+                    if (lg == 0) w_out += (unsigned long long)(oe - ob);
                 }
-                const int slot = wave_append(&ctl->c_cnt, cand);
-                if (cand) w.clist[slot] = x;
+                for (int e = ob + lg; e < oe; e += CL) {
+                    const int x = R.out_col[e];
+                    const unsigned char s = st[x];
+                    bool cand = false;
+                    if ((s & S_SET) == S_UNEXPLORED && !(s & S_CLAIM)) cand = claim(st, x);
+                    const int4 ent = make_int4(x, R.in_ptr[x], R.in_ptr[x + 1], 0);
+                    const int slot = wave_append(&ctl->c_cnt, cand);
+                    if (cand) w.clist[slot] = ent;
+                }
             }
         }
         team_sync(t);
@@ -568,28 +610,19 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             for (int base = t.wave * per_wave; base < cc; base += t.nwaves * per_wave) {
                 const int k = base + sub;
                 const bool active = k < cc;
-                const int x = active ? w.clist[k] : 0;
+                const int4 ent = active ? w.clist[k] : make_int4(0, 0, 0, 0);
+                const int x = ent.x;
                 double best = __longlong_as_double(COST_INF_BITS);
                 int by = 0x7fffffff, be = -1;
                 CandEnd ce;
                 if (active) {
-                    const int ib = R.in_ptr[x], ie = R.in_ptr[x + 1];
+                    const int ib = ent.y, ie = ent.z;
                     load_end<KIND>(R, x, ce);
                     if (lg == 0) {
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    int f = ib + lg;
-                    // four independent rows of loads in flight per lane
-                    for (; f + 3 * CL < ie; f += 4 * CL) {
-                        const int y0 = in_col[f], y1 = in_col[f + CL];
-                        const int y2 = in_col[f + 2 * CL], y3 = in_col[f + 3 * CL];
-                        scan_edge(st, cost, in_cost, y0, f, best, by, be);
-                        scan_edge(st, cost, in_cost, y1, f + CL, best, by, be);
-                        scan_edge(st, cost, in_cost, y2, f + 2 * CL, best, by, be);
-                        scan_edge(st, cost, in_cost, y3, f + 3 * CL, best, by, be);
-                    }
-                    for (; f < ie; f += CL) scan_edge(st, cost, in_cost, in_col[f], f, best, by, be);
+                    scan_row<CL>(st, cost, in_col, in_cost, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
@@ -679,7 +712,9 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // ---------------------------------------------------------------------------
 // persistent kernel: teams of `team_wgs` workgroups pull queries of one
 // cost kind (KIND 0 Euclidean, 1 double integrator).  LDS holds the query's
-// boxes (box_words ints) and, for LDS, its node state bytes and counters;
+// boxes (box_words 32-bit words: grid integers for KIND 0, doubles for KIND
+// 1, which take two words per coordinate) and, for LDS, its node state bytes
+// and counters;
 // the dynamic region is 16-byte aligned (it follows the static s_job), which
 // the 64-bit counter fields require.
 // ---------------------------------------------------------------------------
@@ -721,7 +756,14 @@ __global__ void __launch_bounds__(256) k_plan(const ProbDev *__restrict__ probs,
         if (job >= count) return;
         const ProbDev &P = probs[job];
         const int words = P.m * 2 * P.pd;
-        for (int k = threadIdx.x; k < words && k < box_words; k += blockDim.x) lbox[k] = boxes[P.box_off + k];
+        if (KIND == 0) {
+            for (int k = threadIdx.x; k < words && k < box_words; k += blockDim.x) lbox[k] = boxes[P.box_off + k];
+        } else {
+            // exact doubles: grid integer * 2^-20
+            double *dbox = (double *)lbox;
+            for (int k = threadIdx.x; k < words && 2 * k < box_words; k += blockDim.x)
+                dbox[k] = (double)boxes[P.box_off + k] * GMT_INV_QS;
+        }
         __syncthreads();
         run_query<KIND, LDS, CL>(t, P, lbox, lst, lctl, res + job);
         if (t.nwg > 1 && ld_acquire(t.abort)) return;
