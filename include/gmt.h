@@ -90,9 +90,13 @@ typedef struct {
  *  traj_points double integrator: the optimal trajectory is checked at
  *              traj_points times t_k = k tau/(traj_points-1) (>= 2).
  *  max_iters   cap on the threshold index i of Algorithm 1 (<= 0: none).
- *  team_wgs    workgroups cooperating on one plan (0: library choice).
- *  lanes       lanes per candidate in the parent search: 0 (library choice,
- *              16) or 8.  Results do not depend on it.  */
+ *  team_wgs    workgroups cooperating on one plan (0: library choice: the
+ *              autotuned value for the workload's shape if one is cached,
+ *              else the whole co-resident grid for gmt_plan and one
+ *              workgroup per query for batches).
+ *  lanes       lanes per candidate in the parent search: 4, 8, 16 or 32, or
+ *              0 (library choice: autotuned if cached, else 16).
+ *  Results do not depend on team_wgs or lanes.  */
 typedef struct {
     double edge_step;
     int32_t traj_points;
@@ -231,6 +235,8 @@ typedef struct {
     int32_t *d_group_iter;
     int32_t *d_added_iter;
     gmt_work work;
+    int64_t submit_ns; /* engine only: host steady-clock time of submit ... */
+    int64_t done_ns;   /* ... and of the worker seeing the batch complete */
 } gmt_result;
 
 /* Batch options: the plan options shared by every query, and the launch
@@ -252,11 +258,110 @@ typedef struct {
 gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count, const gmt_batch_opts *opts,
                           gmt_result *results, void *stream);
 
+/* ---- replanning engine: continuous batching ----------------------------
+ * Requests are queued on submit; a worker thread forms batches from the
+ * queue whenever one of `slots` streams is free and the per-query device
+ * memory of the in-flight batches stays within the budget (admission by
+ * footprint), and launches them asynchronously, so batches overlap on the
+ * device while new requests keep arriving.  Each result equals what gmt_plan
+ * returns for the same query.  Roadmaps are the caller's and must stay alive
+ * until their requests complete.  Thread-safe. */
+typedef struct gmt_engine *gmt_engine_t;
+
+typedef struct {
+    size_t budget_bytes;  /* device bytes for in-flight per-query workspaces */
+    int32_t slots;        /* concurrent batches (streams), 1..16 */
+    int32_t max_batch;    /* queries per batch */
+    int32_t queue_cap;    /* queued requests before GMT_EBUSY (0: unbounded) */
+    int32_t workgroups;   /* persistent workgroups per batch (0: fill the GPU) */
+    gmt_plan_opts plan;   /* shared plan options */
+} gmt_engine_opts;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, rejected, batches;
+    int64_t queued;                  /* waiting for admission now */
+    int64_t inflight_bytes;          /* admitted now */
+    int64_t peak_inflight_bytes;
+    int64_t peak_inflight_requests;
+} gmt_engine_stats;
+
+gmt_status gmt_engine_create(const gmt_engine_opts *opts, gmt_engine_t *out);
+
+/* Queue one query (copied); `path_cap` nodes of path are kept for the result.
+ * GMT_EBUSY when the queue is full. */
+gmt_status gmt_engine_submit(gmt_engine_t e, const gmt_problem *problem, int32_t path_cap, int64_t *ticket);
+
+/* Wait up to wait_us microseconds (< 0: forever, 0: no wait) for a ticket.
+ * GMT_OK: `out` holds the result (out->status is the query's status) and the
+ * ticket is retired; GMT_EBUSY: not finished yet.  A query whose workspace can
+ * never fit the budget completes with status GMT_ENOMEM. */
+gmt_status gmt_engine_poll(gmt_engine_t e, int64_t ticket, int32_t wait_us, gmt_result *out, int32_t *path,
+                           int32_t path_cap);
+
+/* Withdraw a queued request (GMT_EBUSY once it is running). */
+gmt_status gmt_engine_cancel(gmt_engine_t e, int64_t ticket);
+
+/* Change the device-memory budget for in-flight queries. */
+gmt_status gmt_engine_set_budget(gmt_engine_t e, size_t budget_bytes);
+
+gmt_status gmt_engine_get_stats(gmt_engine_t e, gmt_engine_stats *out);
+
+/* Finish in-flight batches, drop queued requests, free the engine. */
+gmt_status gmt_engine_destroy(gmt_engine_t e);
+
+/* ---- autotuner ----------------------------------------------------------
+ * The launch knobs -- lanes per candidate, workgroups per query (team_wgs)
+ * and persistent workgroups per batch -- change speed, never results.  The
+ * tuner times every candidate configuration on a caller-supplied workload,
+ * checks that each gives exactly the results of the default configuration
+ * (status, iterations, path, path cost bits), and caches the fastest under
+ * the workload's shape bucket: (cost kind, dim, ceil log2 n, ceil log2 (m+1),
+ * mode, ceil log2 batch).  Plan calls whose options leave a knob at 0 use the
+ * cached value for their shape.  The cache is per process, thread-safe, and
+ * can be saved to / loaded from a text file. */
+typedef struct {
+    int32_t kind, dim;   /* cost kind and state dimension */
+    int32_t n, m;        /* samples (largest in a batch), boxes (largest) */
+    int32_t batch;       /* 0: single plan (gmt_plan); k >= 1: batches of k */
+} gmt_tune_shape;
+
+typedef struct {
+    int32_t lanes, team_wgs, workgroups; /* the chosen knobs (0: none cached) */
+    double ms;           /* median wall time of one call with them */
+    double default_ms;   /* the same with the library defaults */
+    int32_t candidates;  /* configurations timed (0 for a cache lookup) */
+} gmt_tune_choice;
+
+/* Tune on `count` queries: count == 1 with `single` != 0 tunes gmt_plan
+ * (the whole GPU on one query), otherwise gmt_plan_batch over all of them.
+ * `opts` supplies edge_step / traj_points / max_iters; its knobs are ignored.
+ * Each candidate runs once untimed, then `reps` (>= 1) timed calls.
+ * GMT_EDEVICE if any candidate's results differ from the default's. */
+gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, int32_t single, const gmt_plan_opts *opts,
+                        int32_t reps, gmt_tune_choice *out, void *stream);
+
+/* Cached choice for a shape (all zero when none). */
+gmt_status gmt_tune_lookup(const gmt_tune_shape *shape, gmt_tune_choice *out);
+
+/* Store a choice for a shape (validated like plan options). */
+gmt_status gmt_tune_store(const gmt_tune_shape *shape, const gmt_tune_choice *choice);
+
+/* Forget every cached choice. */
+gmt_status gmt_tune_clear(void);
+
+/* Write / read the cache as text, one bucket per line.  Loading merges into
+ * the cache; a malformed line gives GMT_EINVAL and loads nothing. */
+gmt_status gmt_tune_save(const char *path);
+gmt_status gmt_tune_load(const char *path);
+
 /* Thread-local message describing the last error on this thread. */
 const char *gmt_last_error(void);
 
 /* Library version string. */
 const char *gmt_version(void);
+
+/* Host steady clock in nanoseconds (the clock of gmt_result.submit_ns). */
+int64_t gmt_steady_ns(void);
 
 #ifdef __cplusplus
 }

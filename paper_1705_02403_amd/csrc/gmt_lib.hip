@@ -10,12 +10,19 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
 #include "../../include/gmt.h"
+#include "gmt_host.hpp"
 #include "gmt_build.hpp"
 #include "gmt_dev.hpp"
 #include "gmt_plan.hpp"
@@ -23,11 +30,15 @@
 using namespace gmt;
 
 // ---------------------------------------------------------------------------
-// errors
+// errors and device buffers (declared in gmt_host.hpp)
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
+static std::mutex g_alloc_mu;
+static gmt_allocator g_alloc = {nullptr, nullptr, nullptr};
 
-static gmt_status fail(gmt_status st, const char *fmt, ...) {
+namespace gmt_host {
+
+gmt_status fail(gmt_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -37,26 +48,7 @@ static gmt_status fail(gmt_status st, const char *fmt, ...) {
     return st;
 }
 
-#define HIPCHK(expr)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(GMT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// allocator
-// ---------------------------------------------------------------------------
-static std::mutex g_alloc_mu;
-static gmt_allocator g_alloc = {nullptr, nullptr, nullptr};
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    gmt_allocator a{nullptr, nullptr, nullptr};
-};
-
-static gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
+gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
     gmt_allocator a;
     {
         std::lock_guard<std::mutex> lk(g_alloc_mu);
@@ -76,7 +68,7 @@ static gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
     return GMT_OK;
 }
 
-static void dev_free(DevBuf &b, hipStream_t s) {
+void dev_free(DevBuf &b, hipStream_t s) {
     if (!b.p) return;
     if (b.a.free)
         b.a.free(b.p, b.a.ctx, (void *)s);
@@ -84,6 +76,13 @@ static void dev_free(DevBuf &b, hipStream_t s) {
         (void)hipFree(b.p);
     b.p = nullptr;
 }
+
+}  // namespace gmt_host
+
+using gmt_host::DevBuf;
+using gmt_host::dev_alloc;
+using gmt_host::dev_free;
+using gmt_host::fail;
 
 extern "C" gmt_status gmt_set_allocator(const gmt_allocator *allocator) {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
@@ -152,6 +151,8 @@ static void work_add(gmt_work &w, const unsigned long long *c) {
 }
 extern "C" const char *gmt_version(void) { return "gmt-mi355x 0.1 (gfx950)"; }
 
+extern "C" int64_t gmt_steady_ns(void);
+
 // ---------------------------------------------------------------------------
 // roadmap
 // ---------------------------------------------------------------------------
@@ -195,11 +196,6 @@ static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
     }
 }
 
-#define TRY(expr)                        \
-    do {                                 \
-        gmt_status st_ = (expr);         \
-        if (st_ != GMT_OK) return st_;   \
-    } while (0)
 
 static inline unsigned blocks_for(long long threads, int per) { return (unsigned)((threads + per - 1) / per); }
 
@@ -705,7 +701,12 @@ static const size_t kLdsStateLimit = 48 * 1024;
 
 template <int K, bool L>
 static const void *plan_kernel_cl(int cl) {
-    return cl == 8 ? (const void *)k_plan<K, L, 8> : (const void *)k_plan<K, L, 16>;
+    switch (cl) {
+    case 4: return (const void *)k_plan<K, L, 4>;
+    case 8: return (const void *)k_plan<K, L, 8>;
+    case 32: return (const void *)k_plan<K, L, 32>;
+    default: return (const void *)k_plan<K, L, 16>;
+    }
 }
 
 static const void *plan_kernel(int kind, bool lds_st, int cl) {
@@ -713,18 +714,107 @@ static const void *plan_kernel(int kind, bool lds_st, int cl) {
     return lds_st ? plan_kernel_cl<1, true>(cl) : plan_kernel_cl<1, false>(cl);
 }
 
-static int lanes_of(int lanes) { return lanes == 8 ? 8 : 16; }
+static bool lanes_valid(int lanes) { return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32; }
+static int lanes_of(int lanes) { return lanes_valid(lanes) && lanes ? lanes : 16; }
 
-// 32-bit words of boxes the plan kernel stages in LDS (doubles for the
-// double integrator)
-static int plan_box_words(int kind, int words) { return kind == GMT_COST_EUCLIDEAN ? words : 2 * words; }
+// 32-bit words of boxes the plan kernel stages in LDS
+static int plan_box_words(int kind, int words) {
+    (void)kind;
+    return words;
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuner cache: launch knobs per workload shape bucket
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int kind, dim, nlog, mlog, mode, blog;
+    bool operator<(const TuneKey &o) const {
+        const int a[6] = {kind, dim, nlog, mlog, mode, blog}, b[6] = {o.kind, o.dim, o.nlog, o.mlog, o.mode, o.blog};
+        return std::lexicographical_compare(a, a + 6, b, b + 6);
+    }
+};
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, gmt_tune_choice> g_tune;
+static thread_local bool g_tune_bypass = false;  // set while the tuner runs candidates
+
+static int ceil_log2(long long v) {
+    int k = 0;
+    while ((1LL << k) < v) ++k;
+    return k;
+}
+
+static TuneKey tune_key(const gmt_tune_shape &sh) {
+    return TuneKey{sh.kind, sh.dim, ceil_log2(std::max(sh.n, 1)), ceil_log2((long long)std::max(sh.m, 0) + 1),
+                   sh.batch > 0 ? 1 : 0, sh.batch > 0 ? ceil_log2(sh.batch) : 0};
+}
+
+// shape of a call: the double integrator dominates a mixed batch
+static gmt_tune_shape tune_shape(const gmt_problem *problems, int count, bool single) {
+    gmt_tune_shape sh{GMT_COST_EUCLIDEAN, 0, 0, 0, single ? 0 : count};
+    for (int k = 0; k < count; ++k)
+        if (problems[k].roadmap && problems[k].roadmap->kind == GMT_COST_DOUBLE_INTEGRATOR)
+            sh.kind = GMT_COST_DOUBLE_INTEGRATOR;
+    for (int k = 0; k < count; ++k) {
+        const gmt_roadmap *rm = problems[k].roadmap;
+        if (!rm || rm->kind != sh.kind) continue;
+        sh.dim = std::max(sh.dim, rm->dim);
+        sh.n = std::max(sh.n, rm->n);
+        sh.m = std::max(sh.m, problems[k].m);
+    }
+    return sh;
+}
+
+static bool tune_choice_valid(const gmt_tune_choice &c) {
+    return lanes_valid(c.lanes) && c.team_wgs >= 0 && c.workgroups >= 0;
+}
+
+// fill the knobs the caller left at 0 from the cache
+static void tune_apply(const gmt_problem *problems, int count, bool single, gmt_batch_opts &bo) {
+    if (g_tune_bypass) return;
+    const gmt_tune_shape sh = tune_shape(problems, count, single);
+    gmt_tune_choice c;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune.empty()) return;
+        auto it = g_tune.find(tune_key(sh));
+        if (it == g_tune.end()) return;
+        c = it->second;
+    }
+    if (bo.plan.lanes == 0) bo.plan.lanes = c.lanes;
+    if (bo.plan.team_wgs == 0) bo.plan.team_wgs = c.team_wgs;
+    if (!single && bo.workgroups == 0) bo.workgroups = c.workgroups;
+}
+
+// A staged batch: queries copied into pinned memory in kernel order
+// (Euclidean first), their workspaces carved, ready to launch on a stream.
+struct BatchRun {
+    WsBlock *w = nullptr;
+    std::vector<int> order;  // kernel order -> caller index
+    int count = 0, n_euclid = 0, nmax_e = 0, nmax_d = 0;
+    int teams = 1, team_wgs = 1, box_words = 1, cl = 16;
+    size_t used = 0;
+    bool prof = false;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // kernel brackets x2, done
+};
+
+static void run_release(BatchRun &r) {
+    for (hipEvent_t &e : r.ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    if (r.w) ws_release(r.w);
+    r.w = nullptr;
+}
 
 // Launch init + persistent planning over staged queries [first, first+count)
-// of one cost kind; queue counter `qslot` of the staging header.
+// of one cost kind; queue counter `qslot` of the staging header.  Events e0 /
+// e1 (may be null) bracket the plan kernel.
 static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int nmax,
-                                   int teams, int team_wgs, int box_words_in, int qslot, int cl, bool prof,
-                                   hipStream_t s) {
-    // the plan kernel stages double-integrator boxes as doubles (2 words each)
+                                   int teams, int team_wgs, int box_words_in, int qslot, int cl,
+                                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
     int box_words = plan_box_words(kind, box_words_in);
     char *sd = (char *)w->stage_d.p;
     int *queue = (int *)sd + qslot;
@@ -743,12 +833,7 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
             k_plan_init<1><<<ig, 256, lds, s>>>(probs + c0, boxes);
     }
     HIPCHK(hipGetLastError());
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof) {
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        HIPCHK(hipEventRecord(e0, s));
-    }
+    if (e0) HIPCHK(hipEventRecord(e0, s));
     dim3 grid(teams * team_wgs), block(256);
     int st_bytes = nmax + 1;
     void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
@@ -756,17 +841,7 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
         HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, false, cl), grid, block, args, (unsigned)plds, s));
     else
         HIPCHK(hipLaunchKernel(plan_kernel(kind, lds_st, cl), grid, block, args, plds, s));
-    if (prof) {
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        g_prof_ms += ms;
-        g_prof_launches += 1;
-    }
+    if (e1) HIPCHK(hipEventRecord(e1, s));
     return GMT_OK;
 }
 
@@ -778,24 +853,41 @@ static int max_coop_wgs(size_t lds, int kind, bool lds_st = false, int cl = 16) 
     return per * num_cus();
 }
 
-// Stage-copy, launch per kind (queries sorted Euclidean first), read back.
-static gmt_status launch_plan(WsBlock *w, int count, int n_euclid, int nmax_e, int nmax_d, int teams,
-                              int team_wgs, int box_words, int cl, size_t stage_used, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, stage_used, hipMemcpyHostToDevice, s));
-    bool prof;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        prof = g_prof_on;
-    }
-    if (n_euclid > 0)
-        TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, n_euclid, count, nmax_e, std::min(teams, n_euclid),
-                             team_wgs, box_words, 0, cl, prof, s));
-    if (count - n_euclid > 0)
-        TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, n_euclid, count - n_euclid, count, nmax_d,
-                             std::min(teams, count - n_euclid), team_wgs, box_words, 1, cl, prof, s));
-    HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+// Copy the staged queries up, launch per kind, copy the results down and
+// record the completion event -- all asynchronous on `s`.
+static gmt_status batch_launch(BatchRun &r, hipStream_t s) {
+    WsBlock *w = r.w;
+    HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, r.used, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < 5; ++k)
+        if (!r.ev[k] && (k == 4 || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
+    if (r.n_euclid > 0)
+        TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, r.n_euclid, r.count, r.nmax_e, std::min(r.teams, r.n_euclid),
+                             r.team_wgs, r.box_words, 0, r.cl, r.ev[0], r.ev[1], s));
+    if (r.count - r.n_euclid > 0)
+        TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, r.n_euclid, r.count - r.n_euclid, r.count, r.nmax_d,
+                             std::min(r.teams, r.count - r.n_euclid), r.team_wgs, r.box_words, 1, r.cl, r.ev[2],
+                             r.ev[3], s));
+    HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(r.ev[4], s));
     return GMT_OK;
+}
+
+// after completion: fold kernel times into the profile
+static void batch_profile(BatchRun &r) {
+    if (!r.prof) return;
+    double ms = 0.0;
+    long long n = 0;
+    for (int k = 0; k < 4; k += 2) {
+        if ((k == 0 && r.n_euclid == 0) || (k == 2 && r.count - r.n_euclid == 0)) continue;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]) == hipSuccess) {
+            ms += t;
+            ++n;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_ms += ms;
+    g_prof_launches += n;
 }
 
 static gmt_status status_of(int st) {
@@ -818,6 +910,174 @@ static gmt_status long_path(const int *d_parent, int N, int z, int *path, int ca
     return GMT_OK;
 }
 
+// Stage `count` queries.  `single`: one query run by a cooperative team of
+// workgroups (latency); otherwise one-workgroup teams (throughput) unless
+// opts.plan.team_wgs says otherwise.  `results` may be null (no device tree
+// outputs); it is read only for the optional device arrays.
+static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_batch_opts &bo_in, bool single,
+                              const gmt_result *results, BatchRun &r, hipStream_t s) {
+    if (!lanes_valid(bo_in.plan.lanes)) return fail(GMT_EINVAL, "lanes must be 0, 4, 8, 16 or 32");
+    if (bo_in.plan.team_wgs < 0 || bo_in.workgroups < 0) return fail(GMT_EINVAL, "negative launch shape");
+    gmt_batch_opts bo = bo_in;
+    r.count = count;
+    r.order.clear();
+    r.order.reserve(count);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < count; ++k) {
+            const gmt_problem &pr = problems[k];
+            if (!pr.roadmap) return fail(GMT_EINVAL, "problem %d: null roadmap", k);
+            if ((pr.roadmap->kind == GMT_COST_EUCLIDEAN) == (pass == 0)) r.order.push_back(k);
+        }
+    size_t total_boxes = 0, ws_bytes = 0;
+    std::vector<size_t> ws_off(count);
+    r.n_euclid = r.nmax_e = r.nmax_d = 0;
+    r.box_words = 1;
+    for (int j = 0; j < count; ++j) {
+        const gmt_problem &pr = problems[r.order[j]];
+        if (pr.m < 0 || pr.m > GMT_MAX_BOXES)
+            return fail(GMT_EINVAL, "problem %d: box count %d outside [0, %d]", r.order[j], pr.m, GMT_MAX_BOXES);
+        if (pr.roadmap->kind == GMT_COST_EUCLIDEAN) {
+            ++r.n_euclid;
+            r.nmax_e = std::max(r.nmax_e, pr.roadmap->n);
+        } else {
+            r.nmax_d = std::max(r.nmax_d, pr.roadmap->n);
+        }
+        const int words = pr.m * 2 * pdim_of(pr.roadmap->kind, pr.roadmap->dim);
+        r.box_words = std::max(r.box_words, words);
+        total_boxes += (size_t)words;
+        const gmt_result *rr = results ? &results[r.order[j]] : nullptr;
+        const bool own = !(rr && rr->d_parent && rr->d_cost && rr->d_group_iter && rr->d_added_iter);
+        ws_off[j] = ws_bytes;
+        ws_bytes += qws_bytes(pr.roadmap->n + 1, own);
+    }
+    const int nmax = std::max(r.nmax_e, r.nmax_d);
+    const int kind0 = r.nmax_d > 0 ? GMT_COST_DOUBLE_INTEGRATOR : GMT_COST_EUCLIDEAN;
+    if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || (!single && bo.workgroups == 0))
+        tune_apply(problems, count, single, bo);
+    r.cl = lanes_of(bo.plan.lanes);
+    if (single) {
+        const size_t lds = plan_lds(plan_box_words(kind0, r.box_words), nmax, false);
+        r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : num_cus();
+        r.team_wgs = std::max(1, std::min(r.team_wgs, max_coop_wgs(lds, kind0, false, r.cl)));
+        r.teams = 1;
+    } else {
+        r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
+        const int pbw = plan_box_words(kind0, r.box_words);
+        const bool lds_st = r.team_wgs == 1 && plan_lds(pbw, nmax, true) <= kLdsStateLimit;
+        const size_t lds = plan_lds(pbw, nmax, lds_st);
+        const int resident = std::min(max_coop_wgs(lds, 0, lds_st, r.cl), max_coop_wgs(lds, 1, lds_st, r.cl));
+        int teams = bo.workgroups > 0 ? bo.workgroups / r.team_wgs : resident / r.team_wgs;
+        teams = std::max(1, std::min(teams, count));
+        if (r.team_wgs > 1) teams = std::max(1, std::min(teams, resident / r.team_wgs));
+        r.teams = teams;
+    }
+    TRY(ws_acquire(ws_bytes, r.teams, s, &r.w));
+    r.used = 256 + sizeof(ProbDev) * count + sizeof(int) * total_boxes;
+    gmt_status st = ws_stage(r.w, r.used, count, s);
+    if (st == GMT_OK) {
+        char *sh = (char *)r.w->stage_h;
+        ((int *)sh)[0] = 0;  // queue counters, one per cost kind
+        ((int *)sh)[1] = 0;
+        ProbDev *P = (ProbDev *)(sh + 256);
+        int *bx = (int *)(sh + 256 + sizeof(ProbDev) * count);
+        int off = 0;
+        for (int j = 0; j < count && st == GMT_OK; ++j) {
+            const int k = r.order[j];
+            const gmt_problem &pr = problems[k];
+            QueryIn q{pr.roadmap, pr.x_init, &pr.goal, pr.boxes, pr.m, pr.lambda};
+            st = stage_query(q, bo.plan, P[j], bx + off, off);
+            if (st != GMT_OK) {
+                std::string msg = g_last_error;
+                st = fail(st, "problem %d: %s", k, msg.c_str());
+                break;
+            }
+            const gmt_result *rr = results ? &results[k] : nullptr;
+            const bool own = !(rr && rr->d_parent && rr->d_cost && rr->d_group_iter && rr->d_added_iter);
+            char *base = (char *)r.w->mem.p + ws_off[j];
+            if (own)
+                qws_carve(base, pr.roadmap->n + 1, P[j].w, nullptr, nullptr, nullptr, nullptr);
+            else
+                qws_carve(base, pr.roadmap->n + 1, P[j].w, rr->d_cost, rr->d_parent, rr->d_group_iter, rr->d_added_iter);
+            off += P[j].m * 2 * P[j].pd;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        r.prof = g_prof_on;
+    }
+    if (st != GMT_OK) run_release(r);
+    return st;
+}
+
+// After the completion event: copy partially requested tree arrays, fill the
+// results (paths root first), report faults, release the workspace.
+static gmt_status batch_collect(BatchRun &r, const gmt_problem *problems, gmt_result *results, hipStream_t s) {
+    gmt_status st = GMT_OK;
+    const ProbDev *P = (const ProbDev *)((char *)r.w->stage_h + 256);
+    bool copied = false;
+    for (int j = 0; j < r.count && st == GMT_OK; ++j) {
+        const gmt_result &rr = results[r.order[j]];
+        const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
+        if (!own || !(rr.d_parent || rr.d_cost || rr.d_group_iter || rr.d_added_iter)) continue;
+        const size_t N = (size_t)P[j].rm.n + 1;
+        hipError_t e = hipSuccess;
+        if (rr.d_parent) e = hipMemcpyAsync(rr.d_parent, P[j].w.parent, 4 * N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && rr.d_cost) e = hipMemcpyAsync(rr.d_cost, P[j].w.cost, 8 * N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && rr.d_group_iter)
+            e = hipMemcpyAsync(rr.d_group_iter, P[j].w.gi, 4 * N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && rr.d_added_iter)
+            e = hipMemcpyAsync(rr.d_added_iter, P[j].w.ai, 4 * N, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "tree copy failed: %s", hipGetErrorString(e));
+        copied = true;
+    }
+    if (st == GMT_OK && copied && hipStreamSynchronize(s) != hipSuccess) st = fail(GMT_EDEVICE, "stream sync failed");
+    bool fault = false;
+    g_last_work = gmt_work{};
+    for (int j = 0; j < r.count && st == GMT_OK; ++j) {
+        const int k = r.order[j];
+        const Result &res = r.w->res_h[j];
+        gmt_result &o = results[k];
+        o.work = gmt_work{};
+        work_add(o.work, res.work);
+        work_add(g_last_work, res.work);
+        if (res.abort || res.status == ST_FAULT) fault = true;
+        o.status = (int)status_of(res.status);
+        o.iters = res.iters;
+        o.path_len = res.path_len;
+        o.path_cost = res.path_cost;
+        if (o.path && res.status == ST_OK) {
+            if (res.path_len <= GMT_PATH_INLINE) {
+                for (int i = 0; i < res.path_len && i < o.path_cap; ++i) o.path[i] = res.path[i];
+            } else {
+                gmt_status ls = long_path(P[j].w.parent, P[j].rm.n + 1, res.z, o.path, o.path_cap, s);
+                if (ls != GMT_OK) st = ls;
+            }
+        }
+    }
+    if (fault) {
+        ws_reset_ctl(r.w, s);
+        st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
+    }
+    batch_profile(r);
+    run_release(r);
+    (void)problems;
+    return st;
+}
+
+static gmt_status run_sync(const gmt_problem *problems, int count, const gmt_batch_opts &bo, bool single,
+                           gmt_result *results, hipStream_t s) {
+    BatchRun r;
+    TRY(batch_stage(problems, count, bo, single, results, r, s));
+    gmt_status st = batch_launch(r, s);
+    if (st == GMT_OK && hipEventSynchronize(r.ev[4]) != hipSuccess) st = fail(GMT_EDEVICE, "planning launch failed");
+    if (st != GMT_OK) {
+        (void)hipStreamSynchronize(s);
+        run_release(r);
+        return st;
+    }
+    return batch_collect(r, problems, results, s);
+}
+
 extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
                                const float *boxes, int32_t m, double lambda,
                                const gmt_plan_opts *opts_in, int32_t *d_parent, double *d_cost,
@@ -826,76 +1086,32 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
                                int32_t *iters, void *stream) {
     if (!rm) return fail(GMT_EINVAL, "null roadmap");
     if (path_cap > 0 && !path) return fail(GMT_EINVAL, "null path buffer");
-    gmt_plan_opts o = default_opts(opts_in);
     if (!opts_in && rm->kind == GMT_COST_EUCLIDEAN) return fail(GMT_EINVAL, "Euclidean plans need opts.edge_step");
-    hipStream_t s = (hipStream_t)stream;
-    const int pd = pdim_of(rm->kind, rm->dim);
-    if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
-    const int box_words = m * 2 * pd;
-    const size_t lds = plan_lds(plan_box_words(rm->kind, box_words), rm->n, false);
-    const int cl = lanes_of(o.lanes);
-    int team_wgs = o.team_wgs > 0 ? o.team_wgs : num_cus();
-    team_wgs = std::min(team_wgs, max_coop_wgs(lds, rm->kind, false, cl));
-    const int N = rm->n + 1;
-    // the tree arrays are the caller's when all four are given
-    const bool own = !(d_parent && d_cost && d_group_iter && d_added_iter);
-    WsBlock *w = nullptr;
-    TRY(ws_acquire(qws_bytes(N, true), 1, s, &w));
-    size_t used = 256 + sizeof(ProbDev) + sizeof(int) * (size_t)box_words;
-    gmt_status st = ws_stage(w, used, 1, s);
-    const int *tree_parent = nullptr;
-    if (st == GMT_OK) {
-        char *sh = (char *)w->stage_h;
-        ((int *)sh)[0] = 0;  // queue counters
-        ((int *)sh)[1] = 0;
-        ProbDev *P = (ProbDev *)(sh + 256);
-        int *bx = (int *)(sh + 256 + sizeof(ProbDev));
-        QueryIn q{rm, x_init, goal, boxes, m, lambda};
-        st = stage_query(q, o, *P, bx, 0);
-        if (st == GMT_OK) {
-            if (own)
-                qws_carve((char *)w->mem.p, N, P->w, nullptr, nullptr, nullptr, nullptr);
-            else
-                qws_carve((char *)w->mem.p, N, P->w, d_cost, d_parent, d_group_iter, d_added_iter);
-            tree_parent = P->w.parent;
-            const bool eu = rm->kind == GMT_COST_EUCLIDEAN;
-            st = launch_plan(w, 1, eu ? 1 : 0, eu ? rm->n : 0, eu ? 0 : rm->n, 1, team_wgs, box_words, cl, used, s);
-        }
-    }
-    if (st == GMT_OK && own && (d_parent || d_cost || d_group_iter || d_added_iter)) {
-        // some but not all tree arrays requested: copy those out
-        const QWs &qw = ((ProbDev *)((char *)w->stage_h + 256))->w;
-        hipError_t e = hipSuccess;
-        if (d_parent) e = hipMemcpyAsync(d_parent, qw.parent, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess && d_cost) e = hipMemcpyAsync(d_cost, qw.cost, 8 * (size_t)N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess && d_group_iter) e = hipMemcpyAsync(d_group_iter, qw.gi, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess && d_added_iter) e = hipMemcpyAsync(d_added_iter, qw.ai, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) st = fail(GMT_EDEVICE, "tree copy failed: %s", hipGetErrorString(e));
-    }
-    if (st == GMT_OK) {
-        const Result &r = w->res_h[0];
-        if (r.abort || r.status == ST_FAULT) {
-            ws_reset_ctl(w, s);
-            st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
-        } else {
-            g_last_work = gmt_work{};
-            work_add(g_last_work, r.work);
-            if (path_len) *path_len = r.path_len;
-            if (path_cost) *path_cost = r.path_cost;
-            if (iters) *iters = r.iters;
-            if (path && r.status == ST_OK) {
-                if (r.path_len <= GMT_PATH_INLINE) {
-                    for (int k = 0; k < r.path_len && k < path_cap; ++k) path[k] = r.path[k];
-                } else {
-                    st = long_path(tree_parent, N, r.z, path, path_cap, s);
-                }
-            }
-            if (st == GMT_OK) st = status_of(r.status);
-        }
-    }
-    ws_release(w);
-    return st;
+    if (!goal) return fail(GMT_EINVAL, "null goal");
+    gmt_batch_opts bo;
+    std::memset(&bo, 0, sizeof bo);
+    bo.plan = default_opts(opts_in);
+    gmt_problem pr;
+    pr.roadmap = rm;
+    pr.x_init = x_init;
+    pr.goal = *goal;
+    pr.boxes = boxes;
+    pr.m = m;
+    pr.lambda = lambda;
+    gmt_result res;
+    std::memset(&res, 0, sizeof res);
+    res.path = path;
+    res.path_cap = path_cap;
+    res.d_parent = d_parent;
+    res.d_cost = d_cost;
+    res.d_group_iter = d_group_iter;
+    res.d_added_iter = d_added_iter;
+    gmt_status st = run_sync(&pr, 1, bo, true, &res, (hipStream_t)stream);
+    if (st != GMT_OK) return st;
+    if (path_len) *path_len = res.path_len;
+    if (path_cost) *path_cost = res.path_cost;
+    if (iters) *iters = res.iters;
+    return (gmt_status)res.status;
 }
 
 extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
@@ -908,127 +1124,516 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
         std::memset(&bo, 0, sizeof bo);
         bo.plan.traj_points = 16;
     }
+    return run_sync(problems, count, bo, false, results, (hipStream_t)stream);
+}
+
+static int64_t steady_ns() {
+    return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time every launch configuration, keep the fastest that gives
+// exactly the default configuration's results
+// ---------------------------------------------------------------------------
+struct TuneRun {
+    std::vector<gmt_result> res;
+    std::vector<std::vector<int>> paths;
+};
+
+static gmt_status tune_call(const gmt_problem *problems, int count, bool single, const gmt_batch_opts &bo,
+                            TuneRun &out, hipStream_t s) {
+    const int cap = 256;
+    out.res.assign(count, gmt_result{});
+    out.paths.assign(count, std::vector<int>(cap, -1));
+    for (int k = 0; k < count; ++k) {
+        out.res[k].path = out.paths[k].data();
+        out.res[k].path_cap = cap;
+    }
+    return run_sync(problems, count, bo, single, out.res.data(), s);
+}
+
+static bool tune_same(const TuneRun &a, const TuneRun &b) {
+    for (size_t k = 0; k < a.res.size(); ++k) {
+        const gmt_result &x = a.res[k], &y = b.res[k];
+        uint64_t cx, cy;
+        std::memcpy(&cx, &x.path_cost, 8);
+        std::memcpy(&cy, &y.path_cost, 8);
+        if (x.status != y.status || x.iters != y.iters || x.path_len != y.path_len || cx != cy) return false;
+        if (a.paths[k] != b.paths[k]) return false;
+    }
+    return true;
+}
+
+struct BypassTune {
+    bool prev;
+    BypassTune() : prev(g_tune_bypass) { g_tune_bypass = true; }
+    ~BypassTune() { g_tune_bypass = prev; }
+};
+
+extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, int32_t single_in,
+                                   const gmt_plan_opts *opts, int32_t reps, gmt_tune_choice *out, void *stream) {
+    if (count < 1 || !problems || !out) return fail(GMT_EINVAL, "bad autotune arguments");
+    if (reps < 1) return fail(GMT_EINVAL, "reps must be >= 1");
+    const bool single = single_in != 0;
+    if (single && count != 1) return fail(GMT_EINVAL, "single-plan tuning takes one query");
+    for (int k = 0; k < count; ++k)
+        if (!problems[k].roadmap) return fail(GMT_EINVAL, "problem %d: null roadmap", k);
     hipStream_t s = (hipStream_t)stream;
-    int box_words = 1, nmax_e = 0, nmax_d = 0;
-    size_t total_boxes = 0, ws_bytes = 0;
-    // Euclidean queries are staged first, double-integrator ones after
-    std::vector<int> order;
-    order.reserve(count);
-    for (int pass = 0; pass < 2; ++pass)
-        for (int k = 0; k < count; ++k) {
-            const gmt_problem &pr = problems[k];
-            if (!pr.roadmap) return fail(GMT_EINVAL, "problem %d: null roadmap", k);
-            if ((pr.roadmap->kind == GMT_COST_EUCLIDEAN) == (pass == 0)) order.push_back(k);
-        }
-    std::vector<size_t> ws_off(count);
-    int n_euclid = 0;
-    for (int j = 0; j < count; ++j) {
-        const gmt_problem &pr = problems[order[j]];
-        const gmt_result &rr = results[order[j]];
-        const bool eu = pr.roadmap->kind == GMT_COST_EUCLIDEAN;
-        if (eu) {
-            ++n_euclid;
-            nmax_e = std::max(nmax_e, pr.roadmap->n);
-        } else {
-            nmax_d = std::max(nmax_d, pr.roadmap->n);
-        }
-        if (pr.m < 0 || pr.m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "problem %d: box count out of range", order[j]);
-        int words = pr.m * 2 * pdim_of(pr.roadmap->kind, pr.roadmap->dim);
-        box_words = std::max(box_words, words);
-        total_boxes += (size_t)words;
-        const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
-        ws_off[j] = ws_bytes;
-        ws_bytes += qws_bytes(pr.roadmap->n + 1, own);
-    }
-    int team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
-    const int nmax = std::max(nmax_e, nmax_d);
-    const int pbw = plan_box_words(nmax_d > 0 ? GMT_COST_DOUBLE_INTEGRATOR : GMT_COST_EUCLIDEAN, box_words);
-    const bool lds_st = team_wgs == 1 && plan_lds(pbw, nmax, true) <= kLdsStateLimit;
-    const size_t lds = plan_lds(pbw, nmax, lds_st);
-    const int cl = lanes_of(bo.plan.lanes);
-    int resident = std::min(max_coop_wgs(lds, 0, lds_st, cl), max_coop_wgs(lds, 1, lds_st, cl));
-    int teams = bo.workgroups > 0 ? bo.workgroups / team_wgs : resident / team_wgs;
-    teams = std::max(1, std::min(teams, count));
-    if (team_wgs > 1) teams = std::max(1, std::min(teams, resident / team_wgs));
-    WsBlock *w = nullptr;
-    TRY(ws_acquire(ws_bytes, teams, s, &w));
-    size_t used = 256 + sizeof(ProbDev) * count + sizeof(int) * total_boxes;
-    gmt_status st = ws_stage(w, used, count, s);
-    if (st == GMT_OK) {
-        char *sh = (char *)w->stage_h;
-        ((int *)sh)[0] = 0;
-        ((int *)sh)[1] = 0;
-        ProbDev *P = (ProbDev *)(sh + 256);
-        int *bx = (int *)(sh + 256 + sizeof(ProbDev) * count);
-        int off = 0;
-        for (int j = 0; j < count && st == GMT_OK; ++j) {
-            const int k = order[j];
-            const gmt_problem &pr = problems[k];
-            QueryIn q{pr.roadmap, pr.x_init, &pr.goal, pr.boxes, pr.m, pr.lambda};
-            st = stage_query(q, bo.plan, P[j], bx + off, off);
-            if (st != GMT_OK) {
-                std::string msg = g_last_error;
-                st = fail(st, "problem %d: %s", k, msg.c_str());
-                break;
+    BypassTune bypass;
+    gmt_batch_opts base;
+    std::memset(&base, 0, sizeof base);
+    base.plan = default_opts(opts);
+    base.plan.lanes = 16;
+    base.plan.team_wgs = 0;
+    base.workgroups = 0;
+    // candidate knobs; the first is the library default
+    std::vector<gmt_batch_opts> cands;
+    const int lanes[4] = {16, 8, 4, 32};
+    const gmt_tune_shape sh = tune_shape(problems, count, single);
+    if (single) {
+        // team sizes up to the co-resident grid
+        int bw = 1;
+        for (int k = 0; k < count; ++k)
+            bw = std::max(bw, problems[k].m * 2 * pdim_of(problems[k].roadmap->kind, problems[k].roadmap->dim));
+        std::vector<int> teams = {num_cus()};
+        for (int t = 32; t < num_cus(); t *= 2) teams.push_back(t);
+        for (int l : lanes) {
+            const int cap = max_coop_wgs(plan_lds(bw, sh.n, false), sh.kind, false, l);
+            for (int t : teams) {
+                gmt_batch_opts b = base;
+                b.plan.lanes = l;
+                b.plan.team_wgs = std::min(t, cap);
+                bool dup = false;
+                for (const gmt_batch_opts &c : cands)
+                    dup |= c.plan.lanes == l && c.plan.team_wgs == b.plan.team_wgs;
+                if (!dup) cands.push_back(b);
             }
-            const gmt_result &rr = results[k];
-            const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
-            char *base = (char *)w->mem.p + ws_off[j];
-            if (own)
-                qws_carve(base, pr.roadmap->n + 1, P[j].w, nullptr, nullptr, nullptr, nullptr);
-            else
-                qws_carve(base, pr.roadmap->n + 1, P[j].w, rr.d_cost, rr.d_parent, rr.d_group_iter, rr.d_added_iter);
-            off += P[j].m * 2 * P[j].pd;
         }
-        if (st == GMT_OK) st = launch_plan(w, count, n_euclid, nmax_e, nmax_d, teams, team_wgs, box_words, cl, used, s);
-    }
-    if (st == GMT_OK) {
-        // partial tree requests: copy the requested arrays out
-        const ProbDev *P = (const ProbDev *)((char *)w->stage_h + 256);
-        for (int j = 0; j < count && st == GMT_OK; ++j) {
-            const gmt_result &rr = results[order[j]];
-            const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
-            if (!own || !(rr.d_parent || rr.d_cost || rr.d_group_iter || rr.d_added_iter)) continue;
-            const size_t N = (size_t)P[j].rm.n + 1;
-            hipError_t e = hipSuccess;
-            if (rr.d_parent) e = hipMemcpyAsync(rr.d_parent, P[j].w.parent, 4 * N, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess && rr.d_cost) e = hipMemcpyAsync(rr.d_cost, P[j].w.cost, 8 * N, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess && rr.d_group_iter) e = hipMemcpyAsync(rr.d_group_iter, P[j].w.gi, 4 * N, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess && rr.d_added_iter) e = hipMemcpyAsync(rr.d_added_iter, P[j].w.ai, 4 * N, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) st = fail(GMT_EDEVICE, "tree copy failed: %s", hipGetErrorString(e));
-        }
-        if (st == GMT_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(GMT_EDEVICE, "stream sync failed");
-    }
-    if (st == GMT_OK) {
-        bool fault = false;
-        g_last_work = gmt_work{};
-        const ProbDev *P = (const ProbDev *)((char *)w->stage_h + 256);
-        for (int j = 0; j < count; ++j) {
-            const int k = order[j];
-            const Result &r = w->res_h[j];
-            gmt_result &o = results[k];
-            o.work = gmt_work{};
-            work_add(o.work, r.work);
-            work_add(g_last_work, r.work);
-            if (r.abort || r.status == ST_FAULT) fault = true;
-            o.status = (int)status_of(r.status);
-            o.iters = r.iters;
-            o.path_len = r.path_len;
-            o.path_cost = r.path_cost;
-            if (o.path && r.status == ST_OK) {
-                if (r.path_len <= GMT_PATH_INLINE) {
-                    for (int i = 0; i < r.path_len && i < o.path_cap; ++i) o.path[i] = r.path[i];
-                } else {
-                    gmt_status ls = long_path(P[j].w.parent, P[j].rm.n + 1, r.z, o.path, o.path_cap, s);
-                    if (ls != GMT_OK) st = ls;
+    } else {
+        const int wgs_half = num_cus() * 2;  // half of the usual co-resident grid
+        for (int l : lanes)
+            for (int t : {1, 2, 4})
+                for (int wg : {0, wgs_half}) {
+                    gmt_batch_opts b = base;
+                    b.plan.lanes = l;
+                    b.plan.team_wgs = t;
+                    b.workgroups = wg;
+                    cands.push_back(b);
                 }
-            }
+    }
+    TuneRun ref, cur;
+    double best_ms = 0.0, default_ms = 0.0;
+    int best = -1;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        TRY(tune_call(problems, count, single, cands[c], cur, s));  // untimed: warms workspaces
+        if (c == 0) ref = cur;
+        else if (!tune_same(ref, cur))
+            return fail(GMT_EDEVICE, "launch configuration lanes=%d team_wgs=%d workgroups=%d changed the results",
+                        cands[c].plan.lanes, cands[c].plan.team_wgs, cands[c].workgroups);
+        std::vector<double> t(reps);
+        for (int k = 0; k < reps; ++k) {
+            const int64_t t0 = steady_ns();
+            TRY(tune_call(problems, count, single, cands[c], cur, s));
+            t[k] = (double)(steady_ns() - t0) * 1e-6;
         }
-        if (fault) {
-            ws_reset_ctl(w, s);
-            st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
+        std::sort(t.begin(), t.end());
+        const double med = t[reps / 2];
+        if (c == 0) default_ms = med;
+        if (best < 0 || med < best_ms) {
+            best = (int)c;
+            best_ms = med;
         }
     }
-    ws_release(w);
-    return st;
+    gmt_tune_choice ch{};
+    ch.lanes = cands[best].plan.lanes;
+    ch.team_wgs = cands[best].plan.team_wgs;
+    ch.workgroups = cands[best].workgroups;
+    ch.ms = best_ms;
+    ch.default_ms = default_ms;
+    ch.candidates = (int)cands.size();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(sh)] = ch;
+    }
+    *out = ch;
+    return GMT_OK;
+}
+
+static bool tune_shape_valid(const gmt_tune_shape &sh) {
+    return (sh.kind == GMT_COST_EUCLIDEAN || sh.kind == GMT_COST_DOUBLE_INTEGRATOR) && sh.dim >= 1 &&
+           sh.dim <= GMT_MAX_DIM && sh.n >= 1 && sh.m >= 0 && sh.batch >= 0;
+}
+
+extern "C" gmt_status gmt_tune_lookup(const gmt_tune_shape *shape, gmt_tune_choice *out) {
+    if (!shape || !out || !tune_shape_valid(*shape)) return fail(GMT_EINVAL, "bad tune shape");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(*shape));
+    if (it == g_tune.end()) {
+        std::memset(out, 0, sizeof *out);
+    } else {
+        *out = it->second;
+        out->candidates = 0;
+    }
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_tune_store(const gmt_tune_shape *shape, const gmt_tune_choice *choice) {
+    if (!shape || !choice || !tune_shape_valid(*shape)) return fail(GMT_EINVAL, "bad tune shape");
+    if (!tune_choice_valid(*choice)) return fail(GMT_EINVAL, "bad tune choice");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(*shape)] = *choice;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return GMT_OK;
+}
+
+static const char *kTuneHeader = "# gmt tune v1: kind dim nlog mlog mode blog lanes team_wgs workgroups ms default_ms";
+
+extern "C" gmt_status gmt_tune_save(const char *path) {
+    if (!path) return fail(GMT_EINVAL, "null path");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(GMT_EINVAL, "cannot open %s for writing", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::fprintf(f, "%s\n", kTuneHeader);
+    for (const auto &kv : g_tune) {
+        const TuneKey &k = kv.first;
+        const gmt_tune_choice &c = kv.second;
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f %.6f\n", k.kind, k.dim, k.nlog, k.mlog, k.mode, k.blog,
+                     c.lanes, c.team_wgs, c.workgroups, c.ms, c.default_ms);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? GMT_OK : fail(GMT_EINVAL, "write to %s failed", path);
+}
+
+extern "C" gmt_status gmt_tune_load(const char *path) {
+    if (!path) return fail(GMT_EINVAL, "null path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(GMT_EINVAL, "cannot open %s", path);
+    std::map<TuneKey, gmt_tune_choice> got;
+    char line[512];
+    int lineno = 0;
+    gmt_status st = GMT_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        TuneKey k{};
+        gmt_tune_choice c{};
+        char tail = 0;
+        const int got_n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %lf %lf %c", &k.kind, &k.dim, &k.nlog, &k.mlog,
+                                      &k.mode, &k.blog, &c.lanes, &c.team_wgs, &c.workgroups, &c.ms, &c.default_ms,
+                                      &tail);
+        const bool key_ok = (k.kind == GMT_COST_EUCLIDEAN || k.kind == GMT_COST_DOUBLE_INTEGRATOR) && k.dim >= 1 &&
+                            k.dim <= GMT_MAX_DIM && k.nlog >= 0 && k.nlog <= 31 && k.mlog >= 0 && k.mlog <= 31 &&
+                            (k.mode == 0 || k.mode == 1) && k.blog >= 0 && k.blog <= 31;
+        if (got_n != 11 || !key_ok || !tune_choice_valid(c)) {
+            st = fail(GMT_EINVAL, "%s:%d: malformed tune line", path, lineno);
+            break;
+        }
+        got[k] = c;
+    }
+    std::fclose(f);
+    if (st != GMT_OK) return st;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    return GMT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// replanning engine: continuous batching over several streams
+// ---------------------------------------------------------------------------
+extern "C" int64_t gmt_steady_ns(void) { return steady_ns(); }
+
+struct EngineReq {
+    int64_t id = 0;
+    int64_t t_submit = 0;
+    gmt_problem prob{};
+    std::vector<float> x_init, boxes;
+    std::vector<int> path;
+    gmt_result res{};
+    size_t bytes = 0;
+    int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
+};
+
+struct EngineSlot {
+    hipStream_t stream = nullptr;
+    BatchRun run;
+    std::vector<EngineReq *> reqs;
+    std::vector<gmt_problem> probs;
+    std::vector<gmt_result> results;
+    size_t bytes = 0;
+    bool busy = false;
+};
+
+struct gmt_engine {
+    gmt_engine_opts o{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<EngineReq *> queue;
+    std::unordered_map<int64_t, EngineReq *> reqs;
+    std::vector<EngineSlot> slots;
+    size_t inflight = 0, budget = 0;
+    int64_t next_id = 1;
+    bool stop = false;
+    std::thread worker;
+    std::string error;
+    gmt_engine_stats st{};
+};
+
+static size_t engine_req_bytes(const gmt_problem &p) {
+    const int pd = pdim_of(p.roadmap->kind, p.roadmap->dim);
+    return qws_bytes(p.roadmap->n + 1, true) + sizeof(ProbDev) + sizeof(Result) + 4 * (size_t)p.m * 2 * pd;
+}
+
+static void engine_loop(gmt_engine *E) {
+    (void)hipSetDevice(E->device);
+    std::unique_lock<std::mutex> lk(E->mu);
+    while (!E->stop) {
+        bool progressed = false;
+        // completions
+        for (EngineSlot &sl : E->slots) {
+            if (!sl.busy) continue;
+            hipError_t q = hipEventQuery(sl.run.ev[4]);
+            if (q == hipErrorNotReady) continue;
+            lk.unlock();
+            gmt_status cs = (q == hipSuccess) ? batch_collect(sl.run, sl.probs.data(), sl.results.data(), sl.stream)
+                                              : fail(GMT_EDEVICE, "engine batch failed: %s", hipGetErrorString(q));
+            if (q != hipSuccess) {
+                (void)hipStreamSynchronize(sl.stream);
+                run_release(sl.run);
+            }
+            lk.lock();
+            const int64_t now = steady_ns();
+            for (size_t k = 0; k < sl.reqs.size(); ++k) {
+                EngineReq *r = sl.reqs[k];
+                r->res = sl.results[k];
+                if (cs != GMT_OK) r->res.status = cs;
+                r->res.path = nullptr;
+                r->res.submit_ns = r->t_submit;
+                r->res.done_ns = now;
+                r->state = 2;
+                E->st.completed += 1;
+            }
+            E->inflight -= sl.bytes;
+            E->st.batches += 1;
+            sl.reqs.clear();
+            sl.busy = false;
+            progressed = true;
+        }
+        // admission: fill a free slot with queued requests that fit the budget
+        for (EngineSlot &sl : E->slots) {
+            if (sl.busy || E->queue.empty()) continue;
+            sl.reqs.clear();
+            size_t bytes = 0;
+            while (!E->queue.empty() && (int)sl.reqs.size() < E->o.max_batch) {
+                EngineReq *r = E->queue.front();
+                if (r->state == 3) {  // cancelled while queued
+                    E->queue.pop_front();
+                    continue;
+                }
+                if (E->inflight + bytes + r->bytes > E->budget) {
+                    if (E->inflight == 0 && sl.reqs.empty() && r->bytes > E->budget) {
+                        E->queue.pop_front();  // can never fit
+                        r->res.status = GMT_ENOMEM;
+                        r->state = 2;
+                        E->st.rejected += 1;
+                        continue;
+                    }
+                    break;
+                }
+                E->queue.pop_front();
+                bytes += r->bytes;
+                r->state = 1;
+                sl.reqs.push_back(r);
+            }
+            if (sl.reqs.empty()) break;
+            sl.probs.resize(sl.reqs.size());
+            sl.results.assign(sl.reqs.size(), gmt_result{});
+            for (size_t k = 0; k < sl.reqs.size(); ++k) {
+                sl.probs[k] = sl.reqs[k]->prob;
+                sl.results[k].path = sl.reqs[k]->path.data();
+                sl.results[k].path_cap = (int)sl.reqs[k]->path.size();
+            }
+            E->inflight += bytes;
+            sl.bytes = bytes;
+            sl.busy = true;
+            E->st.peak_inflight_bytes = std::max<int64_t>(E->st.peak_inflight_bytes, (int64_t)E->inflight);
+            lk.unlock();
+            gmt_batch_opts bo;
+            std::memset(&bo, 0, sizeof bo);
+            bo.plan = E->o.plan;
+            bo.workgroups = E->o.workgroups;
+            gmt_status ss = batch_stage(sl.probs.data(), (int)sl.probs.size(), bo, false, nullptr, sl.run, sl.stream);
+            if (ss == GMT_OK) ss = batch_launch(sl.run, sl.stream);
+            lk.lock();
+            if (ss != GMT_OK) {
+                (void)hipStreamSynchronize(sl.stream);
+                if (sl.run.w) run_release(sl.run);
+                for (EngineReq *r : sl.reqs) {
+                    r->res.status = ss;
+                    r->state = 2;
+                }
+                E->error = g_last_error;
+                E->inflight -= sl.bytes;
+                sl.reqs.clear();
+                sl.busy = false;
+            } else {
+                int64_t running = 0;
+                for (const EngineSlot &x : E->slots)
+                    if (x.busy) running += (int64_t)x.reqs.size();
+                E->st.peak_inflight_requests = std::max(E->st.peak_inflight_requests, running);
+            }
+            progressed = true;
+        }
+        if (progressed) E->cv_done.notify_all();
+        bool busy = false;
+        for (const EngineSlot &sl : E->slots) busy = busy || sl.busy;
+        if (!progressed) {
+            if (busy)
+                E->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            else
+                E->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+extern "C" gmt_status gmt_engine_create(const gmt_engine_opts *opts, gmt_engine_t *out) {
+    if (!opts || !out) return fail(GMT_EINVAL, "null argument");
+    if (opts->slots < 1 || opts->slots > 16) return fail(GMT_EINVAL, "slots must lie in [1, 16]");
+    if (opts->max_batch < 1) return fail(GMT_EINVAL, "max_batch must be >= 1");
+    if (opts->budget_bytes == 0) return fail(GMT_EINVAL, "budget must be > 0");
+    gmt_engine *E = new gmt_engine;
+    E->o = *opts;
+    E->budget = opts->budget_bytes;
+    (void)hipGetDevice(&E->device);
+    E->slots.resize(opts->slots);
+    for (EngineSlot &sl : E->slots)
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
+            for (EngineSlot &x : E->slots)
+                if (x.stream) (void)hipStreamDestroy(x.stream);
+            delete E;
+            return fail(GMT_EDEVICE, "stream creation failed");
+        }
+    E->worker = std::thread(engine_loop, E);
+    *out = E;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_submit(gmt_engine_t E, const gmt_problem *p, int32_t path_cap, int64_t *ticket) {
+    if (!E || !p || !ticket || !p->roadmap || !p->x_init) return fail(GMT_EINVAL, "null argument");
+    if (p->m < 0 || p->m > GMT_MAX_BOXES || (p->m > 0 && !p->boxes)) return fail(GMT_EINVAL, "bad box list");
+    EngineReq *r = new EngineReq;
+    const int pd = pdim_of(p->roadmap->kind, p->roadmap->dim);
+    r->x_init.assign(p->x_init, p->x_init + p->roadmap->dim);
+    if (p->m > 0) r->boxes.assign(p->boxes, p->boxes + (size_t)p->m * 2 * pd);
+    r->prob = *p;
+    r->prob.x_init = r->x_init.data();
+    r->prob.boxes = p->m > 0 ? r->boxes.data() : nullptr;
+    r->path.assign((size_t)std::max(path_cap, 0), 0);
+    r->bytes = engine_req_bytes(*p);
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        if (E->o.queue_cap > 0 && (int)E->queue.size() >= E->o.queue_cap) {
+            delete r;
+            return fail(GMT_EBUSY, "engine queue full");
+        }
+        r->id = E->next_id++;
+        r->t_submit = steady_ns();
+        E->reqs[r->id] = r;
+        E->queue.push_back(r);
+        E->st.submitted += 1;
+    }
+    E->cv_work.notify_one();
+    *ticket = r->id;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_poll(gmt_engine_t E, int64_t ticket, int32_t wait_us, gmt_result *out,
+                                      int32_t *path, int32_t path_cap) {
+    if (!E || !out) return fail(GMT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto it = E->reqs.find(ticket);
+    if (it == E->reqs.end()) return fail(GMT_EINVAL, "unknown ticket %lld", (long long)ticket);
+    EngineReq *r = it->second;
+    if (r->state < 2 && wait_us != 0) {
+        auto pred = [&] { return r->state >= 2; };
+        if (wait_us < 0)
+            E->cv_done.wait(lk, pred);
+        else
+            E->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), pred);
+    }
+    if (r->state < 2) return GMT_EBUSY;
+    *out = r->res;
+    out->path = path;
+    out->path_cap = path_cap;
+    if (path && r->res.status == GMT_OK)
+        for (int k = 0; k < r->res.path_len && k < path_cap && k < (int)r->path.size(); ++k) path[k] = r->path[k];
+    E->reqs.erase(it);
+    delete r;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_cancel(gmt_engine_t E, int64_t ticket) {
+    if (!E) return fail(GMT_EINVAL, "null engine");
+    std::lock_guard<std::mutex> lk(E->mu);
+    auto it = E->reqs.find(ticket);
+    if (it == E->reqs.end()) return fail(GMT_EINVAL, "unknown ticket");
+    EngineReq *r = it->second;
+    if (r->state != 0) return fail(GMT_EBUSY, "request already running or done");
+    r->state = 3;
+    r->res.status = GMT_EBUSY;
+    E->reqs.erase(it);
+    for (auto q = E->queue.begin(); q != E->queue.end(); ++q)
+        if (*q == r) {
+            E->queue.erase(q);
+            break;
+        }
+    E->st.cancelled += 1;
+    delete r;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_set_budget(gmt_engine_t E, size_t budget_bytes) {
+    if (!E || budget_bytes == 0) return fail(GMT_EINVAL, "bad arguments");
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        E->budget = budget_bytes;
+    }
+    E->cv_work.notify_one();
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_get_stats(gmt_engine_t E, gmt_engine_stats *out) {
+    if (!E || !out) return fail(GMT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(E->mu);
+    *out = E->st;
+    out->queued = (int64_t)E->queue.size();
+    out->inflight_bytes = (int64_t)E->inflight;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_destroy(gmt_engine_t E) {
+    if (!E) return GMT_OK;
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        E->stop = true;
+    }
+    E->cv_work.notify_all();
+    if (E->worker.joinable()) E->worker.join();
+    for (EngineSlot &sl : E->slots) {
+        if (sl.busy) {
+            (void)hipStreamSynchronize(sl.stream);
+            run_release(sl.run);
+        }
+        (void)hipStreamDestroy(sl.stream);
+    }
+    for (auto &kv : E->reqs) delete kv.second;
+    delete E;
+    return GMT_OK;
 }

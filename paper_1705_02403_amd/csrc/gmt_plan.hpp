@@ -350,21 +350,73 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, i
                     hit = true;
             }
         } else {
-            const double *dbox = (const double *)lbox;
+            const float *fbox = (const float *)lbox;
             double ys[6];
             sample_d<6>(R, y, ys);
             DiPair d = make_pair(ys, c.xs);
             const double tau = R.in_tau[e];
             const int K = P.traj_points;
             const double inv = 1.0 / (double)(K - 1);
-            for (int k = lg; k < K && !hit; k += CL) {
-                double p[3];
-                di_point(ys, d, tau, (double)k * inv, p);
-                for (int b = -1; b < P.m; ++b)
-                    if (di_point_hits_d(p, b, dbox)) {
-                        hit = true;
-                        break;
+            if (K <= 2 * CL) {
+                // this lane's trajectory points (k = lg, lg + CL), kept in registers
+                double p0[3], p1[3];
+                const bool h0 = lg < K, h1 = lg + CL < K;
+                di_point(ys, d, tau, (double)lg * inv, p0);
+                di_point(ys, d, tau, (double)(lg + CL) * inv, p1);
+                // leaving [0,1]^3 is a collision
+                hit = (h0 && di_point_hits_d(p0, -1, nullptr)) || (h1 && di_point_hits_d(p1, -1, nullptr));
+                // conservative float box of the group's points (slack 1e-6 covers
+                // the FP64 -> FP32 rounding of coordinates within [-4, 4])
+                float lo[3], hi[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    float v0 = (float)p0[a], v1 = (float)p1[a];
+                    lo[a] = fminf(h0 ? v0 : 1e30f, h1 ? v1 : 1e30f) - 1e-6f;
+                    hi[a] = fmaxf(h0 ? v0 : -1e30f, h1 ? v1 : -1e30f) + 1e-6f;
+                }
+#pragma unroll
+                for (int off = CL / 2; off > 0; off >>= 1)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
+                        hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off));
                     }
+                // boxes overlapping that box, one per lane; then every lane tests
+                // its points exactly against each of them
+                for (int b0 = 0; b0 < P.m; b0 += CL) {
+                    const int b = b0 + lg;
+                    bool ov = false;
+                    if (b < P.m) {
+                        const float *bx = fbox + b * 6;
+                        ov = bx[0] <= hi[0] && bx[3] >= lo[0] && bx[1] <= hi[1] && bx[4] >= lo[1] &&
+                             bx[2] <= hi[2] && bx[5] >= lo[2];
+                    }
+                    uint64_t om = wave_ballot(ov);
+                    const int sub = lane_id() / CL;
+                    uint64_t gm = (CL == 64) ? om : ((om >> (sub * CL)) & ((1ull << CL) - 1ull));
+                    while (gm) {
+                        const int bb = b0 + __ffsll((unsigned long long)gm) - 1;
+                        gm &= gm - 1ull;
+                        const float *bx = fbox + bb * 6;
+                        double dbx[6];
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) dbx[q] = (double)bx[q];
+                        if (h0 && di_point_hits_d(p0, 0, dbx)) hit = true;
+                        if (h1 && di_point_hits_d(p1, 0, dbx)) hit = true;
+                    }
+                }
+            } else {
+                for (int k = lg; k < K && !hit; k += CL) {
+                    double p[3];
+                    di_point(ys, d, tau, (double)k * inv, p);
+                    if (di_point_hits_d(p, -1, nullptr)) hit = true;
+                    for (int b = 0; b < P.m && !hit; ++b) {
+                        const float *bx = fbox + b * 6;
+                        double dbx[6];
+                        for (int q = 0; q < 6; ++q) dbx[q] = (double)bx[q];
+                        if (di_point_hits_d(p, 0, dbx)) hit = true;
+                    }
+                }
             }
         }
     }
@@ -712,14 +764,13 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // ---------------------------------------------------------------------------
 // persistent kernel: teams of `team_wgs` workgroups pull queries of one
 // cost kind (KIND 0 Euclidean, 1 double integrator).  LDS holds the query's
-// boxes (box_words 32-bit words: grid integers for KIND 0, doubles for KIND
-// 1, which take two words per coordinate) and, for LDS, its node state bytes
-// and counters;
+// boxes (box_words 32-bit words: grid integers for KIND 0, exact floats for
+// KIND 1) and, for LDS, its node state bytes and counters;
 // the dynamic region is 16-byte aligned (it follows the static s_job), which
 // the 64-bit counter fields require.
 // ---------------------------------------------------------------------------
 template <int KIND, bool LDS, int CL>
-__global__ void __launch_bounds__(256) k_plan(const ProbDev *__restrict__ probs, int count,
+__global__ void __launch_bounds__(256, 4) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
                                               int team_wgs, Result *__restrict__ res) {
@@ -759,10 +810,10 @@ __global__ void __launch_bounds__(256) k_plan(const ProbDev *__restrict__ probs,
         if (KIND == 0) {
             for (int k = threadIdx.x; k < words && k < box_words; k += blockDim.x) lbox[k] = boxes[P.box_off + k];
         } else {
-            // exact doubles: grid integer * 2^-20
-            double *dbox = (double *)lbox;
-            for (int k = threadIdx.x; k < words && 2 * k < box_words; k += blockDim.x)
-                dbox[k] = (double)boxes[P.box_off + k] * GMT_INV_QS;
+            // exact floats: grid integer * 2^-20
+            float *fbox = (float *)lbox;
+            for (int k = threadIdx.x; k < words && k < box_words; k += blockDim.x)
+                fbox[k] = (float)((double)boxes[P.box_off + k] * GMT_INV_QS);
         }
         __syncthreads();
         run_query<KIND, LDS, CL>(t, P, lbox, lst, lctl, res + job);

@@ -40,7 +40,10 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_batch",
            "gmt_last_work", "gmt_profile_enable", "gmt_profile_read",
-           "gmt_last_error", "gmt_version"]
+           "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_cancel",
+           "gmt_engine_set_budget", "gmt_engine_get_stats", "gmt_engine_destroy",
+           "gmt_autotune", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
+           "gmt_tune_load", "gmt_last_error", "gmt_version", "gmt_steady_ns"]
 
 
 class GmtError(RuntimeError):
@@ -51,7 +54,7 @@ class GmtError(RuntimeError):
 
 def sources() -> List[str]:
     return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))
-            if f.endswith((".hip", ".hpp"))] + [os.path.join(INCLUDE, "gmt.h")]
+            if f.endswith((".hip", ".hpp"))] + [os.path.join(INCLUDE, f) for f in ("gmt.h", "gmt_sampler.h")]
 
 
 def build_library(force: bool = True) -> str:
@@ -62,7 +65,8 @@ def build_library(force: bool = True) -> str:
         if os.path.getmtime(LIB_PATH) >= newest:
             return LIB_PATH
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp, os.path.join(CSRC, "gmt_lib.hip")]
+    units = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp] + units
     subprocess.check_call(cmd)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -105,16 +109,44 @@ class gmt_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("path_len", C.c_int32),
                 ("path_cap", C.c_int32), ("path_cost", C.c_double),
                 ("path", C.POINTER(C.c_int32)), ("d_parent", C.c_void_p), ("d_cost", C.c_void_p),
-                ("d_group_iter", C.c_void_p), ("d_added_iter", C.c_void_p), ("work", gmt_work)]
+                ("d_group_iter", C.c_void_p), ("d_added_iter", C.c_void_p), ("work", gmt_work),
+                ("submit_ns", C.c_int64), ("done_ns", C.c_int64)]
 
 
 class gmt_batch_opts(C.Structure):
     _fields_ = [("plan", gmt_plan_opts), ("workgroups", C.c_int32), ("threads", C.c_int32)]
 
 
+class gmt_engine_opts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_size_t), ("slots", C.c_int32), ("max_batch", C.c_int32),
+                ("queue_cap", C.c_int32), ("workgroups", C.c_int32), ("plan", gmt_plan_opts)]
+
+
+class gmt_engine_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "cancelled", "rejected", "batches",
+                                         "queued", "inflight_bytes", "peak_inflight_bytes",
+                                         "peak_inflight_requests")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _lock = threading.Lock()
 _lib = None
 _alloc_keep = None
+
+
+class gmt_tune_shape(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n", C.c_int32), ("m", C.c_int32),
+                ("batch", C.c_int32)]
+
+
+class gmt_tune_choice(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("team_wgs", C.c_int32), ("workgroups", C.c_int32),
+                ("ms", C.c_double), ("default_ms", C.c_double), ("candidates", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def lib():
@@ -142,10 +174,25 @@ def lib():
             L.gmt_last_work.argtypes = [C.POINTER(gmt_work)]
             L.gmt_profile_enable.argtypes = [i32]
             L.gmt_profile_read.argtypes = [C.POINTER(f64), C.POINTER(i64)]
+            L.gmt_engine_create.argtypes = [C.POINTER(gmt_engine_opts), C.POINTER(P)]
+            L.gmt_engine_submit.argtypes = [P, C.POINTER(gmt_problem), i32, C.POINTER(i64)]
+            L.gmt_engine_poll.argtypes = [P, i64, i32, C.POINTER(gmt_result), P, i32]
+            L.gmt_engine_cancel.argtypes = [P, i64]
+            L.gmt_engine_set_budget.argtypes = [P, C.c_size_t]
+            L.gmt_engine_get_stats.argtypes = [P, C.POINTER(gmt_engine_stats)]
+            L.gmt_engine_destroy.argtypes = [P]
+            L.gmt_autotune.argtypes = [C.POINTER(gmt_problem), i32, i32, C.POINTER(gmt_plan_opts), i32,
+                                       C.POINTER(gmt_tune_choice), P]
+            L.gmt_tune_lookup.argtypes = [C.POINTER(gmt_tune_shape), C.POINTER(gmt_tune_choice)]
+            L.gmt_tune_store.argtypes = [C.POINTER(gmt_tune_shape), C.POINTER(gmt_tune_choice)]
+            L.gmt_tune_clear.argtypes = []
+            L.gmt_tune_save.argtypes = [C.c_char_p]
+            L.gmt_tune_load.argtypes = [C.c_char_p]
             L.gmt_last_error.restype = C.c_char_p
             L.gmt_version.restype = C.c_char_p
+            L.gmt_steady_ns.restype = i64
             for name in EXPORTS:
-                if name not in ("gmt_last_error", "gmt_version"):
+                if name not in ("gmt_last_error", "gmt_version", "gmt_steady_ns"):
                     getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -366,48 +413,185 @@ class BatchQuery:
     lam: float
 
 
+class PreparedBatch:
+    """Queries marshalled once into ABI structs; ``run()`` solves them with one
+    ``gmt_plan_batch`` call and can be repeated without re-marshalling."""
+
+    def __init__(self, queries: Sequence[BatchQuery], opts: gmt_plan_opts, workgroups: int = 0,
+                 outputs: bool = False, path_cap: int = 1024):
+        import torch
+        k = len(queries)
+        self.k = k
+        self.probs = (gmt_problem * k)()
+        self.res = (gmt_result * k)()
+        self.keep = []
+        self.paths = []
+        self.outs = []
+        dev = torch.device("cuda", torch.cuda.current_device())
+        for j, q in enumerate(queries):
+            xi = _host_f32(q.x_init)
+            bx = _host_f32(q.boxes).reshape(-1)
+            pd = 3 if q.roadmap.kind == GMT_COST_DOUBLE_INTEGRATOR else q.roadmap.dim
+            m = int(bx.size // (2 * pd)) if bx.size else 0
+            path = np.zeros(path_cap, np.int32)
+            self.keep += [xi, bx]
+            self.paths.append(path)
+            self.probs[j].roadmap = q.roadmap.handle
+            self.probs[j].x_init = xi.ctypes.data_as(C.POINTER(C.c_float))
+            self.probs[j].goal = q.goal
+            self.probs[j].boxes = bx.ctypes.data_as(C.POINTER(C.c_float)) if m else None
+            self.probs[j].m = m
+            self.probs[j].lambda_ = float(q.lam)
+            self.res[j].path = path.ctypes.data_as(C.POINTER(C.c_int32))
+            self.res[j].path_cap = path_cap
+            o = [None] * 4
+            if outputs:
+                N = q.roadmap.n + 1
+                o = [torch.empty(N, dtype=torch.int32, device=dev),
+                     torch.empty(N, dtype=torch.float64, device=dev),
+                     torch.empty(N, dtype=torch.int32, device=dev),
+                     torch.empty(N, dtype=torch.int32, device=dev)]
+                self.res[j].d_parent, self.res[j].d_cost = o[0].data_ptr(), o[1].data_ptr()
+                self.res[j].d_group_iter, self.res[j].d_added_iter = o[2].data_ptr(), o[3].data_ptr()
+            self.outs.append(o)
+        self.bo = gmt_batch_opts(opts, int(workgroups), 0)
+        self.path_cap = path_cap
+
+    def run(self, stream=None) -> None:
+        _check(lib().gmt_plan_batch(self.probs, self.k, C.byref(self.bo), self.res, _stream(stream)),
+               "gmt_plan_batch")
+
+    def statuses(self) -> np.ndarray:
+        return np.array([self.res[j].status for j in range(self.k)], np.int32)
+
+    def results(self) -> List[PlanResult]:
+        out = []
+        for j in range(self.k):
+            r = self.res[j]
+            L = int(r.path_len) if r.status == GMT_OK else 0
+            out.append(PlanResult(int(r.status), self.paths[j][:min(L, self.path_cap)].copy(),
+                                  float(r.path_cost), int(r.iters), *self.outs[j],
+                                  work=r.work.as_dict()))
+        return out
+
+
 def gmt_plan_batch(queries: Sequence[BatchQuery], opts: gmt_plan_opts, workgroups: int = 0,
-                   outputs: bool = False, stream=None, path_cap: int = 1024):
+                   outputs: bool = False, stream=None, path_cap: int = 1024) -> List[PlanResult]:
     """Solve queries in one persistent launch; returns a list of PlanResult."""
-    import torch
-    k = len(queries)
-    probs = (gmt_problem * k)()
-    res = (gmt_result * k)()
-    keep = []
-    outs = []
-    dev = torch.device("cuda", torch.cuda.current_device())
-    for j, q in enumerate(queries):
+    pb = PreparedBatch(queries, opts, workgroups, outputs, path_cap)
+    pb.run(stream)
+    return pb.results()
+
+
+# ---------------------------------------------------------------------------
+# autotuner
+# ---------------------------------------------------------------------------
+def gmt_autotune(queries: Sequence[BatchQuery], opts: gmt_plan_opts, single: bool = False,
+                 reps: int = 3, stream=None) -> dict:
+    """Time every launch configuration on ``queries`` and cache the fastest
+    for their shape bucket (see gmt_autotune in the header)."""
+    pb = PreparedBatch(queries, opts)
+    out = gmt_tune_choice()
+    _check(lib().gmt_autotune(pb.probs, pb.k, int(bool(single)), C.byref(opts), int(reps), C.byref(out),
+                              _stream(stream)), "gmt_autotune")
+    return out.as_dict()
+
+
+def tune_shape(kind: int, dim: int, n: int, m: int, batch: int) -> gmt_tune_shape:
+    return gmt_tune_shape(int(kind), int(dim), int(n), int(m), int(batch))
+
+
+def gmt_tune_lookup(shape: gmt_tune_shape) -> dict:
+    out = gmt_tune_choice()
+    _check(lib().gmt_tune_lookup(C.byref(shape), C.byref(out)), "gmt_tune_lookup")
+    return out.as_dict()
+
+
+def gmt_tune_store(shape: gmt_tune_shape, lanes: int, team_wgs: int, workgroups: int = 0) -> None:
+    c = gmt_tune_choice(int(lanes), int(team_wgs), int(workgroups), 0.0, 0.0, 0)
+    _check(lib().gmt_tune_store(C.byref(shape), C.byref(c)), "gmt_tune_store")
+
+
+def gmt_tune_clear() -> None:
+    _check(lib().gmt_tune_clear(), "gmt_tune_clear")
+
+
+def gmt_tune_save(path: str) -> None:
+    _check(lib().gmt_tune_save(os.fsencode(path)), "gmt_tune_save")
+
+
+def gmt_tune_load(path: str) -> None:
+    _check(lib().gmt_tune_load(os.fsencode(path)), "gmt_tune_load")
+
+
+# ---------------------------------------------------------------------------
+# replanning engine
+# ---------------------------------------------------------------------------
+def gmt_steady_ns() -> int:
+    return int(lib().gmt_steady_ns())
+
+
+class Engine:
+    """Continuous-batching engine (``gmt_engine_*``)."""
+
+    def __init__(self, budget_bytes: int, opts: gmt_plan_opts, slots: int = 4, max_batch: int = 256,
+                 queue_cap: int = 0, workgroups: int = 0):
+        eo = gmt_engine_opts(int(budget_bytes), int(slots), int(max_batch), int(queue_cap),
+                             int(workgroups), opts)
+        h = C.c_void_p()
+        _check(lib().gmt_engine_create(C.byref(eo), C.byref(h)), "gmt_engine_create")
+        self.handle = h
+
+    def submit(self, q: BatchQuery, path_cap: int = 512) -> int:
         xi = _host_f32(q.x_init)
         bx = _host_f32(q.boxes).reshape(-1)
         pd = 3 if q.roadmap.kind == GMT_COST_DOUBLE_INTEGRATOR else q.roadmap.dim
         m = int(bx.size // (2 * pd)) if bx.size else 0
+        p = gmt_problem()
+        p.roadmap = q.roadmap.handle
+        p.x_init = xi.ctypes.data_as(C.POINTER(C.c_float))
+        p.goal = q.goal
+        p.boxes = bx.ctypes.data_as(C.POINTER(C.c_float)) if m else None
+        p.m = m
+        p.lambda_ = float(q.lam)
+        t = C.c_int64()
+        _check(lib().gmt_engine_submit(self.handle, C.byref(p), int(path_cap), C.byref(t)),
+               "gmt_engine_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int, wait_us: int = 0, path_cap: int = 512):
+        """PlanResult (with submit_ns/done_ns in .work) or None if not done."""
+        r = gmt_result()
         path = np.zeros(path_cap, np.int32)
-        keep += [xi, bx, path]
-        probs[j].roadmap = q.roadmap.handle
-        probs[j].x_init = xi.ctypes.data_as(C.POINTER(C.c_float))
-        probs[j].goal = q.goal
-        probs[j].boxes = bx.ctypes.data_as(C.POINTER(C.c_float)) if m else None
-        probs[j].m = m
-        probs[j].lambda_ = float(q.lam)
-        res[j].path = path.ctypes.data_as(C.POINTER(C.c_int32))
-        res[j].path_cap = path_cap
-        o = [None] * 4
-        if outputs:
-            N = q.roadmap.n + 1
-            o = [torch.empty(N, dtype=torch.int32, device=dev),
-                 torch.empty(N, dtype=torch.float64, device=dev),
-                 torch.empty(N, dtype=torch.int32, device=dev),
-                 torch.empty(N, dtype=torch.int32, device=dev)]
-            res[j].d_parent, res[j].d_cost = o[0].data_ptr(), o[1].data_ptr()
-            res[j].d_group_iter, res[j].d_added_iter = o[2].data_ptr(), o[3].data_ptr()
-        outs.append((path, o))
-    bo = gmt_batch_opts(opts, int(workgroups), 0)
-    _check(lib().gmt_plan_batch(probs, k, C.byref(bo), res, _stream(stream)), "gmt_plan_batch")
-    out = []
-    for j in range(k):
-        path, o = outs[j]
-        L = int(res[j].path_len) if res[j].status == GMT_OK else 0
-        out.append(PlanResult(int(res[j].status), path[:min(L, path_cap)].copy(),
-                              float(res[j].path_cost), int(res[j].iters), *o,
-                              work=res[j].work.as_dict()))
-    return out
+        st = lib().gmt_engine_poll(self.handle, int(ticket), int(wait_us), C.byref(r), path.ctypes.data,
+                                   path_cap)
+        if st == GMT_EBUSY:
+            return None
+        _check(st, "gmt_engine_poll")
+        L = int(r.path_len) if r.status == GMT_OK else 0
+        w = r.work.as_dict()
+        w["submit_ns"], w["done_ns"] = int(r.submit_ns), int(r.done_ns)
+        return PlanResult(int(r.status), path[:min(L, path_cap)].copy(), float(r.path_cost),
+                          int(r.iters), work=w)
+
+    def cancel(self, ticket: int) -> bool:
+        return lib().gmt_engine_cancel(self.handle, int(ticket)) == GMT_OK
+
+    def set_budget(self, budget_bytes: int) -> None:
+        _check(lib().gmt_engine_set_budget(self.handle, int(budget_bytes)), "gmt_engine_set_budget")
+
+    def stats(self) -> dict:
+        s = gmt_engine_stats()
+        _check(lib().gmt_engine_get_stats(self.handle, C.byref(s)), "gmt_engine_get_stats")
+        return s.as_dict()
+
+    def close(self) -> None:
+        if self.handle:
+            lib().gmt_engine_destroy(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

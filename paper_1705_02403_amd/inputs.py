@@ -288,3 +288,48 @@ def tiny_problem(seed: int, dim: int, n: int, m: int, lam: float, step: float = 
                  smin: float = 0.1, smax: float = 0.3) -> Problem:
     """Small Euclidean instance for brute-force cross-checks."""
     return geometric_problem(seed, dim, n, m, smin, smax, lam=lam, step=step)
+
+
+# ---------------------------------------------------------------------------
+# learned sampler: parameter initialisation and random draws (both sides use
+# these; the method's arithmetic is not here)
+# ---------------------------------------------------------------------------
+SAMPLER_IN, SAMPLER_HID, SAMPLER_OUT, SAMPLER_COND = 416, 256, 16, 396
+SAMPLER_NET = (SAMPLER_HID * SAMPLER_IN + SAMPLER_HID + SAMPLER_HID * SAMPLER_HID + SAMPLER_HID
+               + SAMPLER_OUT * SAMPLER_HID + SAMPLER_OUT)
+SAMPLER_PARAMS = 2 * SAMPLER_NET
+
+
+def bf16_round(x) -> np.ndarray:
+    """FP32 values rounded to the nearest BF16 value (ties to even), as FP32."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def sampler_params(seed: int, out_scale: float = 0.1) -> np.ndarray:
+    """Initial parameters of the encoder and decoder (flat FP32, layout of
+    include/gmt_sampler.h), BF16-representable.  Uniform He-style weights
+    on the 402 real input columns, zero on the padding columns, zero biases,
+    output rows beyond the used ones (12 encoder, 6 decoder) zero."""
+    rng = np.random.default_rng(30_000_001 + int(seed))
+    H, IN, OUT = SAMPLER_HID, SAMPLER_IN, SAMPLER_OUT
+    parts = []
+    for used in (12, 6):
+        a1 = np.sqrt(6.0 / 402.0)
+        W1 = rng.uniform(-a1, a1, size=(H, IN))
+        W1[:, 6:8] = 0.0
+        W1[:, 404:] = 0.0
+        a2 = np.sqrt(6.0 / H)
+        W2 = rng.uniform(-a2, a2, size=(H, H))
+        W3 = np.zeros((OUT, H))
+        W3[:used] = rng.uniform(-a2, a2, size=(used, H)) * out_scale
+        parts += [W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(), np.zeros(OUT)]
+    return bf16_round(np.concatenate(parts).astype(np.float32))
+
+
+def normal_draws(seed: int, count: int, dim: int = 6) -> np.ndarray:
+    """Standard normal draws [count][dim] (FP32) for the sampler's noise."""
+    rng = np.random.default_rng(40_000_003 + int(seed))
+    return rng.standard_normal(size=(count, dim)).astype(np.float32)

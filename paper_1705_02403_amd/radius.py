@@ -47,3 +47,10 @@ def problem_radius(prob) -> float:
     if prob.r is not None:
         return float(prob.r)
     return theorem1_radius(prob.dim, free_volume(prob.pdim, prob.boxes), prob.n, prob.r_factor)
+
+
+def di_radius(n: int) -> float:
+    """Connection radius of the double integrator at n samples: r = 1.75 at
+    n = 16384, scaled by (16384 / n)^(1/6) so that the mean in-degree stays
+    near its value at n = 16384 as n changes."""
+    return 1.75 * (16384.0 / float(n)) ** (1.0 / 6.0)

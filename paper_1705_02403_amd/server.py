@@ -1,0 +1,194 @@
+"""Replanning server: continuous batching over resident roadmaps.
+
+Requests arrive over time; each names a sample set (dim, n, sample seed) and
+a query (start, goal, boxes, lambda).  Roadmaps stay resident on the device
+in an LRU cache under a byte budget (a roadmap with requests in flight is
+never evicted); the native engine (``gmt_engine_*``) admits queries by the
+device memory of their workspaces, forms batches from whatever is queued
+when a stream frees up, and overlaps batches on the device.  Latency is
+arrival to completion; throughput is completed queries over the makespan.
+"""
+
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, Hashable, List, Optional
+
+import numpy as np
+
+from . import gmt
+
+
+def roadmap_bytes(n: int, dim: int, kind: int, nnz: int) -> int:
+    """Device bytes of a roadmap: samples, row pointers and the in/out tables."""
+    b = 4 * dim * n + 4 * (n + 1) + 12 * nnz
+    if kind == gmt.GMT_COST_DOUBLE_INTEGRATOR:
+        b += 8 * nnz + 4 * (n + 1) + 4 * nnz  # arrival times + transposed table
+    return b
+
+
+class RoadmapCache:
+    """LRU of resident roadmaps under ``budget`` bytes, with pin counts."""
+
+    def __init__(self, budget: int, build: Callable[[Hashable], "gmt.Roadmap"],
+                 size_of: Callable[["gmt.Roadmap"], int] = None):
+        self.budget = int(budget)
+        self.build = build
+        self.size_of = size_of or (lambda rm: roadmap_bytes(rm.n, rm.dim, rm.kind, rm.nnz))
+        self.items: "collections.OrderedDict[Hashable, list]" = collections.OrderedDict()
+        self.bytes = 0
+        self.hits = 0
+        self.misses = 0
+        self.evictions = 0
+        self.lock = threading.Lock()
+
+    def acquire(self, key: Hashable):
+        """Roadmap for ``key``, pinned until ``release(key)``."""
+        with self.lock:
+            it = self.items.get(key)
+            if it is not None:
+                self.items.move_to_end(key)
+                it[2] += 1
+                self.hits += 1
+                return it[0]
+            self.misses += 1
+        rm = self.build(key)
+        size = self.size_of(rm)
+        with self.lock:
+            self._evict(size)
+            self.items[key] = [rm, size, 1]
+            self.bytes += size
+        return rm
+
+    def release(self, key: Hashable) -> None:
+        with self.lock:
+            self.items[key][2] -= 1
+
+    def _evict(self, need: int) -> None:
+        for k in list(self.items.keys()):
+            if self.bytes + need <= self.budget:
+                return
+            rm, size, pins = self.items[k]
+            if pins > 0:
+                continue
+            del self.items[k]
+            self.bytes -= size
+            self.evictions += 1
+            if hasattr(rm, "free"):
+                rm.free()
+
+    def clear(self) -> None:
+        with self.lock:
+            for rm, _, _ in self.items.values():
+                if hasattr(rm, "free"):
+                    rm.free()
+            self.items.clear()
+            self.bytes = 0
+
+
+@dataclass
+class Request:
+    arrival_s: float
+    key: Hashable                      # roadmap key
+    make_query: Callable[["gmt.Roadmap"], "gmt.BatchQuery"]
+    tag: object = None
+
+
+@dataclass
+class Served:
+    tag: object
+    status: int
+    path: np.ndarray
+    path_cost: float
+    latency_ms: float
+    queue_wait_ms: float
+
+
+@dataclass
+class ServeReport:
+    served: List[Served]
+    makespan_s: float
+    plans_per_s: float
+    p50_ms: float
+    p99_ms: float
+    engine: dict = field(default_factory=dict)
+    cache: dict = field(default_factory=dict)
+
+
+class ReplanServer:
+    def __init__(self, build_roadmap: Callable[[Hashable], "gmt.Roadmap"], opts: "gmt.gmt_plan_opts",
+                 engine_budget: int, roadmap_budget: int, slots: int = 4, max_batch: int = 256,
+                 workgroups: int = 0, path_cap: int = 512):
+        self.cache = RoadmapCache(roadmap_budget, build_roadmap)
+        self.engine = gmt.Engine(engine_budget, opts, slots=slots, max_batch=max_batch,
+                                 workgroups=workgroups)
+        self.path_cap = path_cap
+
+    def serve(self, requests: List[Request], realtime: bool = True) -> ServeReport:
+        """Replay ``requests`` at their arrival times (``realtime``) or all at
+        once, and collect every result."""
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        t0 = gmt.gmt_steady_ns() + 2_000_000  # start 2 ms from now
+        tickets: Dict[int, tuple] = {}
+        lock = threading.Lock()
+        submitted = threading.Event()
+
+        def submitter():
+            for r in reqs:
+                at = t0 + int(r.arrival_s * 1e9) if realtime else t0
+                while True:
+                    now = gmt.gmt_steady_ns()
+                    if now >= at:
+                        break
+                    if at - now > 200_000:
+                        time.sleep((at - now - 100_000) / 1e9)
+                rm = self.cache.acquire(r.key)
+                tk = self.engine.submit(r.make_query(rm), self.path_cap)
+                with lock:
+                    tickets[tk] = (r, at)
+            submitted.set()
+
+        th = threading.Thread(target=submitter, daemon=True)
+        th.start()
+        served: List[Served] = []
+        last_done = t0
+        while True:
+            with lock:
+                pending = list(tickets.items())
+            if not pending:
+                if submitted.is_set():
+                    with lock:
+                        if not tickets:
+                            break
+                time.sleep(50e-6)
+                continue
+            progressed = False
+            for tk, (r, at) in pending:
+                res = self.engine.poll(tk, 0, self.path_cap)
+                if res is None:
+                    continue
+                progressed = True
+                with lock:
+                    del tickets[tk]
+                self.cache.release(r.key)
+                done = res.work["done_ns"]
+                last_done = max(last_done, done)
+                served.append(Served(r.tag, res.status, res.path, res.path_cost, (done - at) / 1e6,
+                                     (res.work["submit_ns"] - at) / 1e6))
+            if not progressed:
+                time.sleep(50e-6)
+        th.join()
+        lat = np.array([s.latency_ms for s in served]) if served else np.zeros(1)
+        first = t0
+        span = max(last_done - first, 1) / 1e9
+        return ServeReport(served, span, len(served) / span, float(np.percentile(lat, 50)),
+                           float(np.percentile(lat, 99)), self.engine.stats(),
+                           {"hits": self.cache.hits, "misses": self.cache.misses,
+                            "evictions": self.cache.evictions, "bytes": self.cache.bytes})
+
+    def close(self) -> None:
+        self.engine.close()
+        self.cache.clear()

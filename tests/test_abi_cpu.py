@@ -8,27 +8,28 @@ import re
 import numpy as np
 import pytest
 
-from paper_1705_02403_amd import gmt, inputs, radius
+from paper_1705_02403_amd import gmt, inputs, radius, sampler
 from oracle import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "gmt.h")).read()
+def header_functions(name="gmt.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gmt_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gmt_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_lists_the_bound_symbols():
     assert header_functions() == sorted(gmt.EXPORTS)
+    assert header_functions("gmt_sampler.h") == sorted(sampler.EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(gmt.LIB_PATH):
         gmt.build_library()
     L = ctypes.CDLL(gmt.LIB_PATH)
-    for name in header_functions():
+    for name in header_functions() + header_functions("gmt_sampler.h"):
         assert hasattr(L, name), name
     assert "gfx950" in gmt.gmt_version()
 
@@ -41,6 +42,10 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.gmt_plan(None, None, None, None, 0, 0.5, None, None, None, None, None, None, 0,
                       None, None, None, None) == gmt.GMT_EINVAL
     assert "null" in gmt.last_error()
+    S = sampler.lib()
+    assert S.gmt_gemm_bf16(0, 1, 64, 64, 12, None, 16, None, 16, None, 0, None, None, 64, None) == gmt.GMT_EINVAL
+    assert S.gmt_sampler_create(None, ctypes.byref(h)) == gmt.GMT_EINVAL
+    assert S.gmt_sampler_finish(None, 6, 0, None, 0, None, 0, None, 0, None, None) == gmt.GMT_EINVAL
     bad = gmt.gmt_allocator()
     assert L.gmt_set_allocator(ctypes.byref(bad)) == gmt.GMT_EINVAL
     assert L.gmt_set_allocator(None) == gmt.GMT_OK

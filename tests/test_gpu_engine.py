@@ -1,0 +1,128 @@
+"""Continuous-batching engine on the GPU: every result equals the same query
+solved alone; admission keeps in-flight workspaces under the budget."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1705_02403_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1705_02403_amd import gmt, server
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def world():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    gmt.use_torch_allocator()
+    rms = {}
+    probs = []
+    for seed in range(6):
+        p = I.problem_2d(seed, lam=0.5)
+        r = O.euclid_radius(p)
+        rms[("2d", seed)] = gmt.gmt_build_neighbors(torch.from_numpy(p.samples).cuda(), gmt.GMT_COST_EUCLIDEAN, r)
+        probs.append((("2d", seed), p))
+    s = I.di_samples(0, 4096)
+    rdi = 1.75 * 4.0 ** (1.0 / 6.0)
+    rms[("di", 0)] = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, rdi)
+    for seed in range(10):
+        probs.append((("di", 0), I.di_problem(seed, s, r=rdi)))
+    yield rms, probs
+    for rm in rms.values():
+        rm.free()
+
+
+def query(rms, key, p):
+    return gmt.BatchQuery(rms[key], p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, p.pdim), p.boxes, p.lam)
+
+
+def opts():
+    return gmt.make_opts(edge_step=0.005, traj_points=16)
+
+
+def alone(rms, key, p):
+    return gmt.gmt_plan(rms[key], p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, p.pdim), p.boxes,
+                        p.lam, opts(), outputs=False)
+
+
+def test_engine_results_equal_alone(world):
+    say("engine: mixed stream equals alone")
+    rms, probs = world
+    ref = [alone(rms, k, p) for k, p in probs]
+    eng = gmt.Engine(1 << 30, opts(), slots=3, max_batch=4)
+    order = list(range(len(probs))) * 2
+    tickets = [eng.submit(query(rms, *probs[j])) for j in order]
+    for j, tk in zip(order, tickets):
+        res = eng.poll(tk, -1)
+        assert res.status == ref[j].status
+        assert list(res.path) == list(ref[j].path)
+        assert res.path_cost == ref[j].path_cost
+        assert res.work["done_ns"] >= res.work["submit_ns"] > 0
+    st = eng.stats()
+    assert st["completed"] == len(order) and st["batches"] >= len(order) // 4
+    eng.close()
+
+
+def test_engine_budget_admission(world):
+    say("engine: small budget")
+    rms, probs = world
+    # a DI query at n = 4096 holds about 190 kB of workspace: at most two fit
+    budget = 400_000
+    eng = gmt.Engine(budget, opts(), slots=4, max_batch=64)
+    tickets = [eng.submit(query(rms, *probs[j % len(probs)])) for j in range(24)]
+    outs = [eng.poll(t, -1) for t in tickets]
+    st = eng.stats()
+    assert 0 < st["peak_inflight_bytes"] <= budget
+    assert st["peak_inflight_requests"] >= 2
+    assert st["completed"] == 24
+    ref = [alone(rms, *probs[j % len(probs)]) for j in range(24)]
+    for a, b in zip(outs, ref):
+        assert a.status == b.status and a.path_cost == b.path_cost
+    eng.close()
+
+
+def test_engine_rejects_what_never_fits_and_cancels(world):
+    say("engine: enomem and cancel")
+    rms, probs = world
+    eng = gmt.Engine(1000, opts(), slots=1, max_batch=1)
+    tk = eng.submit(query(rms, *probs[0]))
+    res = eng.poll(tk, -1)
+    assert res.status == gmt.GMT_ENOMEM
+    eng.close()
+    eng = gmt.Engine(1 << 30, opts(), slots=1, max_batch=1)
+    tks = [eng.submit(query(rms, *probs[-1])) for _ in range(8)]
+    cancelled = [t for t in tks[2:] if eng.cancel(t)]
+    for t in tks:
+        if t in cancelled:
+            continue
+        assert eng.poll(t, -1).status in (gmt.GMT_OK, gmt.GMT_NO_PATH)
+    eng.close()
+
+
+def test_server_poisson_stream(world):
+    say("server: poisson stream")
+    rms, probs = world
+    arrivals = I.poisson_arrivals(40, 2000.0, seed=7)
+    reqs = []
+    for k, t in enumerate(arrivals):
+        key, p = probs[k % len(probs)]
+        reqs.append(server.Request(float(t), key, (lambda p: lambda rm: gmt.BatchQuery(
+            rm, p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, p.pdim), p.boxes, p.lam))(p), tag=k))
+    srv = server.ReplanServer(lambda key: rms[key], opts(), engine_budget=1 << 30, roadmap_budget=1 << 40,
+                              slots=4, max_batch=32)
+    rep = srv.serve(reqs)
+    srv.engine.close()
+    assert len(rep.served) == 40
+    ref = {k: alone(rms, *probs[k % len(probs)]) for k in range(40)}
+    for s in rep.served:
+        assert s.status == ref[s.tag].status and s.path_cost == ref[s.tag].path_cost
+    assert rep.p99_ms >= rep.p50_ms > 0
