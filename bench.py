@@ -37,6 +37,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--server-requests", type=int, default=4096)
     ap.add_argument("--server-rate", type=float, default=20000.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB buffer 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the learned sampler and compare it with plain GMT* at n=32768")
+    ap.add_argument("--learned-train", type=int, default=20000)
+    ap.add_argument("--learned-steps", type=int, default=3000)
+    ap.add_argument("--learned-test", type=int, default=200)
     return ap.parse_args()
 
 
@@ -46,6 +53,105 @@ def plan_bytes(w):
     edge cost 8 + node state 16), 16 B per node added, 12 B per open-list
     entry partitioned."""
     return (4 * w["out_edges"] + 28 * w["in_edges"] + 16 * w["commits"] + 12 * w["open_entries"])
+
+
+def learned_report(args, torch, gmt, I):
+    """Learned sampler (configuration 5): train on waypoints of plain GMT*
+    paths at n=32768, then compare the 50/50 learned mix at n in {2k, 4k, 8k}
+    with plain GMT* at n=32768 on held-out queries."""
+    from paper_1705_02403_amd import radius, sampler as S
+    dev = torch.device("cuda", 0)
+    opts = gmt.make_opts(traj_points=16)
+    n_big = 32768
+    r_big = radius.di_radius(n_big)
+    sets = 8
+    samples, rms, build_ms = {}, {}, []
+    for ss in range(sets):
+        samples[ss] = I.di_samples(ss, n_big)
+        d = torch.from_numpy(samples[ss]).to(dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rms[ss] = gmt.gmt_build_neighbors(d, gmt.GMT_COST_DOUBLE_INTEGRATOR, r_big)
+        torch.cuda.synchronize()
+        build_ms.append((time.perf_counter() - t) * 1e3)
+    t = time.perf_counter()
+    train_probs = [I.di_problem(1_000_000 + k, samples[k % sets], r=r_big, sample_seed=k % sets)
+                   for k in range(args.learned_train)]
+    data = S.path_dataset(train_probs, rms, samples, opts)
+    data_s = time.perf_counter() - t
+    smp = S.Sampler(I.sampler_params(0))
+    t = time.perf_counter()
+    hist = S.train(smp, data, steps=args.learned_steps, batch=1024, seed=0,
+                   opts=S.train_opts(lr=1e-3, kl_weight=0.5), log_every=max(args.learned_steps // 10, 1))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3
+
+    tests = [I.di_problem(2_000_000 + k, samples[k % sets], r=r_big, sample_seed=k % sets)
+             for k in range(args.learned_test)]
+    ref_cost, ref_ms = [], []
+    for p in tests:
+        res, ms = timed(lambda: gmt.gmt_plan(rms[p.sample_seed], p.x_init,
+                                             gmt.make_goal(p.goal_center, p.goal_radius, 3), p.boxes, p.lam,
+                                             opts, outputs=False))
+        ref_cost.append(res.path_cost if res.status == gmt.GMT_OK else np.inf)
+        ref_ms.append(ms)
+    ref_cost = np.array(ref_cost)
+    rows = {}
+    for n in (2048, 4096, 8192):
+        r_n = radius.di_radius(n)
+        n_l = n // 2
+        uni = torch.from_numpy(I.di_samples(777, n - n_l)).to(dev)
+        fb = torch.from_numpy(I.di_samples(778, n_l)).to(dev)
+        eps = torch.from_numpy(I.normal_draws(779, n_l)).to(dev)
+        uni_full = torch.from_numpy(I.di_samples(777, n)).to(dev)
+        for learned in (True, False):
+            costs, lat, rej = [], [], 0
+            for p in tests:
+                goal = gmt.make_goal(p.goal_center, p.goal_radius, 3)
+
+                def run():
+                    if learned:
+                        x, rj = S.mixed_samples(smp, p, n, 0, True, uniform=uni, fallback=fb, eps=eps)
+                    else:
+                        x, rj = uni_full, 0
+                    rm = gmt.gmt_build_neighbors(x, gmt.GMT_COST_DOUBLE_INTEGRATOR, r_n)
+                    res = gmt.gmt_plan(rm, p.x_init, goal, p.boxes, p.lam, opts, outputs=False)
+                    rm.free()
+                    return res, rj
+                (res, rj), ms = timed(run)
+                rej += rj
+                costs.append(res.path_cost if res.status == gmt.GMT_OK else np.inf)
+                lat.append(ms)
+            costs = np.array(costs)
+            both = np.isfinite(costs) & np.isfinite(ref_cost)
+            ratio = costs[both] / ref_cost[both]
+            rows["%s_n%d" % ("learned" if learned else "uniform", n)] = {
+                "solved": int(np.isfinite(costs).sum()),
+                "median_cost_ratio_vs_plain_n32768": round(float(np.median(ratio)), 4) if both.any() else None,
+                "mean_cost_ratio_vs_plain_n32768": round(float(np.mean(ratio)), 4) if both.any() else None,
+                "p50_ms_end_to_end": round(float(np.percentile(lat, 50)), 3),
+                "rejected_per_query": round(rej / len(tests), 1)}
+    for rm in rms.values():
+        rm.free()
+    smp.close()
+    return {"train_problems": args.learned_train, "train_solved": data.solved,
+            "waypoints": int(data.targets.shape[0]), "dataset_s": round(data_s, 1),
+            "train_steps": args.learned_steps, "train_s": round(train_s, 2),
+            "loss_first_last": [[round(v, 4) for v in hist[0][1:]], [round(v, 4) for v in hist[-1][1:]]],
+            "test_problems": len(tests),
+            "plain_n32768": {"solved": int(np.isfinite(ref_cost).sum()),
+                             "p50_ms_plan_resident": round(float(np.percentile(ref_ms, 50)), 3),
+                             "build_ms": round(float(np.median(build_ms)), 3)},
+            "mixes": rows,
+            "note": "end-to-end = sampler inference + neighbour build + plan; uniform halves, "
+                    "fallbacks and noise are query-independent and resident"}
 
 
 def main():
@@ -58,6 +164,14 @@ def main():
     from paper_1705_02403_amd import gmt, inputs as I
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_copy": 1 << 30, "copies": 5}), flush=True)
+        return
     gmt.use_torch_allocator()
     stream = torch.cuda.current_stream()
     n = args.n
@@ -162,6 +276,8 @@ def main():
                   "ms": round(bt, 3),
                   "GB_per_s_out": round(12.0 * e3 / (bt * 1e-3) / 1e9, 1)}
 
+    learned = learned_report(args, torch, gmt, I) if args.learned else None
+
     # ---- cost against the FP64 oracle (sample set 0) and CPU baseline ----
     check = {}
     cpu = None
@@ -237,6 +353,7 @@ def main():
         "oracle_check": check,
         "server": srv_line,
         "euclid_build": build_line,
+        "learned": learned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_plan<1> (one launch per batch)",

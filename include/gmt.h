@@ -185,7 +185,8 @@ gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
  * scanned for parents (lines 5-6), candidates processed, nodes added (lines
  * 8-9), open nodes partitioned (line 3), non-empty iterations; then the
  * time the query's team spent in setup and in the select / frontier /
- * connect phases (device wall clock, first thread's view, nanoseconds). */
+ * connect phases (device wall clock, first thread's view, nanoseconds), and
+ * the part of connect that the first wavefront spent in lazy checks. */
 typedef struct {
     int64_t out_edges;
     int64_t in_edges;
@@ -197,6 +198,7 @@ typedef struct {
     int64_t select_ns;
     int64_t frontier_ns;
     int64_t connect_ns;
+    int64_t check_ns;
 } gmt_work;
 
 /* Work of the last gmt_plan / gmt_plan_batch call on this thread. */
@@ -258,6 +260,24 @@ typedef struct {
 gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count, const gmt_batch_opts *opts,
                           gmt_result *results, void *stream);
 
+/* ---- prepared batches ---------------------------------------------------
+ * Stage `count` queries once (inputs are copied; roadmaps must stay alive and
+ * unchanged) and capture their launch sequence -- upload of the staged
+ * queries, initialisation, the persistent planning kernel, download of the
+ * results -- as a HIP graph; gmt_batch_run replays it and fills `results`
+ * (statuses, paths, costs; device tree arrays are copied out when all four or
+ * some of d_parent / d_cost / d_group_iter / d_added_iter are given).  Each
+ * replay gives the results gmt_plan_batch gives for the same queries.  Launch
+ * shapes with team_wgs > 1 (cooperative) are not captured and are replayed as
+ * direct launches.  A prepared batch holds its workspace until freed; runs of
+ * one prepared batch must not overlap. */
+typedef struct gmt_batch *gmt_batch_t;
+
+gmt_status gmt_batch_prepare(const gmt_problem *problems, int32_t count, const gmt_batch_opts *opts,
+                             gmt_batch_t *out, void *stream);
+gmt_status gmt_batch_run(gmt_batch_t batch, gmt_result *results, void *stream);
+gmt_status gmt_batch_free(gmt_batch_t batch);
+
 /* ---- replanning engine: continuous batching ----------------------------
  * Requests are queued on submit; a worker thread forms batches from the
  * queue whenever one of `slots` streams is free and the per-query device
@@ -306,7 +326,8 @@ gmt_status gmt_engine_set_budget(gmt_engine_t e, size_t budget_bytes);
 
 gmt_status gmt_engine_get_stats(gmt_engine_t e, gmt_engine_stats *out);
 
-/* Finish in-flight batches, drop queued requests, free the engine. */
+/* Finish in-flight batches, drop queued requests, free the engine.  No other
+ * call on the engine may be in progress (a poll must have returned). */
 gmt_status gmt_engine_destroy(gmt_engine_t e);
 
 /* ---- autotuner ----------------------------------------------------------

@@ -148,6 +148,7 @@ static void work_add(gmt_work &w, const unsigned long long *c) {
     w.select_ns += (int64_t)((double)c[7] * ns);
     w.frontier_ns += (int64_t)((double)c[8] * ns);
     w.connect_ns += (int64_t)((double)c[9] * ns);
+    w.check_ns += (int64_t)((double)c[10] * ns);
 }
 extern "C" const char *gmt_version(void) { return "gmt-mi355x 0.1 (gfx950)"; }
 
@@ -796,6 +797,7 @@ struct BatchRun {
     int teams = 1, team_wgs = 1, box_words = 1, cl = 16;
     size_t used = 0;
     bool prof = false;
+    bool own_all = false;  // tree arrays always in the workspace (prepared batches)
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // kernel brackets x2, done
 };
 
@@ -855,10 +857,11 @@ static int max_coop_wgs(size_t lds, int kind, bool lds_st = false, int cl = 16) 
 
 // Copy the staged queries up, launch per kind, copy the results down and
 // record the completion event -- all asynchronous on `s`.
-static gmt_status batch_launch(BatchRun &r, hipStream_t s) {
+// `events` false (graph capture): no event records.
+static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true) {
     WsBlock *w = r.w;
     HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, r.used, hipMemcpyHostToDevice, s));
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 5 && events; ++k)
         if (!r.ev[k] && (k == 4 || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
     if (r.n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, r.n_euclid, r.count, r.nmax_e, std::min(r.teams, r.n_euclid),
@@ -868,7 +871,7 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s) {
                              std::min(r.teams, r.count - r.n_euclid), r.team_wgs, r.box_words, 1, r.cl, r.ev[2],
                              r.ev[3], s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipEventRecord(r.ev[4], s));
+    if (events) HIPCHK(hipEventRecord(r.ev[4], s));
     return GMT_OK;
 }
 
@@ -1010,14 +1013,14 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
 }
 
 // After the completion event: copy partially requested tree arrays, fill the
-// results (paths root first), report faults, release the workspace.
-static gmt_status batch_collect(BatchRun &r, const gmt_problem *problems, gmt_result *results, hipStream_t s) {
+// results (paths root first), report faults; the workspace stays held.
+static gmt_status collect_results(BatchRun &r, gmt_result *results, hipStream_t s) {
     gmt_status st = GMT_OK;
     const ProbDev *P = (const ProbDev *)((char *)r.w->stage_h + 256);
     bool copied = false;
     for (int j = 0; j < r.count && st == GMT_OK; ++j) {
         const gmt_result &rr = results[r.order[j]];
-        const bool own = !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
+        const bool own = r.own_all || !(rr.d_parent && rr.d_cost && rr.d_group_iter && rr.d_added_iter);
         if (!own || !(rr.d_parent || rr.d_cost || rr.d_group_iter || rr.d_added_iter)) continue;
         const size_t N = (size_t)P[j].rm.n + 1;
         hipError_t e = hipSuccess;
@@ -1058,9 +1061,14 @@ static gmt_status batch_collect(BatchRun &r, const gmt_problem *problems, gmt_re
         ws_reset_ctl(r.w, s);
         st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
     }
+    return st;
+}
+
+// collect, fold kernel times into the profile, release the workspace
+static gmt_status batch_collect(BatchRun &r, gmt_result *results, hipStream_t s) {
+    gmt_status st = collect_results(r, results, s);
     batch_profile(r);
     run_release(r);
-    (void)problems;
     return st;
 }
 
@@ -1075,7 +1083,7 @@ static gmt_status run_sync(const gmt_problem *problems, int count, const gmt_bat
         run_release(r);
         return st;
     }
-    return batch_collect(r, problems, results, s);
+    return batch_collect(r, results, s);
 }
 
 extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
@@ -1131,6 +1139,84 @@ static int64_t steady_ns() {
     return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
+}
+
+// ---------------------------------------------------------------------------
+// prepared batches: staged once, launch sequence captured as a HIP graph
+// ---------------------------------------------------------------------------
+struct gmt_batch {
+    BatchRun run;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<gmt_problem> probs;
+    std::vector<float> inputs;  // copies of x_init and boxes the problems point to
+};
+
+extern "C" gmt_status gmt_batch_prepare(const gmt_problem *problems, int32_t count, const gmt_batch_opts *bopts,
+                                        gmt_batch_t *out, void *stream) {
+    if (count < 1 || !problems || !out) return fail(GMT_EINVAL, "bad batch arguments");
+    hipStream_t s = (hipStream_t)stream;
+    gmt_batch_opts bo;
+    if (bopts) bo = *bopts;
+    else {
+        std::memset(&bo, 0, sizeof bo);
+        bo.plan.traj_points = 16;
+    }
+    gmt_batch *b = new gmt_batch();
+    gmt_status st = batch_stage(problems, count, bo, false, nullptr, b->run, s);
+    if (st != GMT_OK) {
+        delete b;
+        return st;
+    }
+    b->run.own_all = true;
+    b->run.prof = false;
+    b->probs.assign(problems, problems + count);
+    // cooperative launches (team_wgs > 1) cannot be captured: those batches
+    // are replayed as direct launches
+    if (b->run.team_wgs == 1) {
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            gmt_status ls = batch_launch(b->run, cs, false);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cs, &g);
+            b->graph = g;
+            if (ls != GMT_OK && e == hipSuccess) e = hipErrorUnknown;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            st = fail(GMT_EDEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+            gmt_batch_free(b);
+            return st;
+        }
+    }
+    *out = b;
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_batch_run(gmt_batch_t b, gmt_result *results, void *stream) {
+    if (!b || !results) return fail(GMT_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) {
+        HIPCHK(hipGraphLaunch(b->exec, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        TRY(batch_launch(b->run, s));
+        HIPCHK(hipEventSynchronize(b->run.ev[4]));
+    }
+    return collect_results(b->run, results, s);
+}
+
+extern "C" gmt_status gmt_batch_free(gmt_batch_t b) {
+    if (!b) return GMT_OK;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    run_release(b->run);
+    delete b;
+    return GMT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1402,7 +1488,7 @@ static void engine_loop(gmt_engine *E) {
             hipError_t q = hipEventQuery(sl.run.ev[4]);
             if (q == hipErrorNotReady) continue;
             lk.unlock();
-            gmt_status cs = (q == hipSuccess) ? batch_collect(sl.run, sl.probs.data(), sl.results.data(), sl.stream)
+            gmt_status cs = (q == hipSuccess) ? batch_collect(sl.run, sl.results.data(), sl.stream)
                                               : fail(GMT_EDEVICE, "engine batch failed: %s", hipGetErrorString(q));
             if (q != hipSuccess) {
                 (void)hipStreamSynchronize(sl.stream);
@@ -1443,6 +1529,7 @@ static void engine_loop(gmt_engine *E) {
                         r->res.status = GMT_ENOMEM;
                         r->state = 2;
                         E->st.rejected += 1;
+                        progressed = true;  // wakes a poller waiting on it
                         continue;
                     }
                     break;

@@ -110,9 +110,10 @@ struct ProbDev {
 // work counters of one query (exact): out-edges walked, in-edges scanned,
 // candidates processed, nodes committed, open nodes partitioned, non-empty
 // iterations; then wall-clock ticks spent in setup / select / frontier /
-// connect (first thread's view)
+// connect (first thread's view), and the part of connect the first wave
+// spent in lazy checks
 enum { W_OUT = 0, W_IN = 1, W_CAND = 2, W_COMMIT = 3, W_OPEN = 4, W_ITERS = 5,
-       W_T_SETUP = 6, W_T_SELECT = 7, W_T_FRONTIER = 8, W_T_CONNECT = 9, W_COUNT = 10 };
+       W_T_SETUP = 6, W_T_SELECT = 7, W_T_FRONTIER = 8, W_T_CONNECT = 9, W_T_CHECK = 10, W_COUNT = 11 };
 
 struct Result {
     int status, iters, path_len, z;
@@ -359,10 +360,10 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, i
             const double inv = 1.0 / (double)(K - 1);
             if (K <= 2 * CL) {
                 // this lane's trajectory points (k = lg, lg + CL), kept in registers
-                double p0[3], p1[3];
+                double p0[3], p1[3] = {0.0, 0.0, 0.0};
                 const bool h0 = lg < K, h1 = lg + CL < K;
                 di_point(ys, d, tau, (double)lg * inv, p0);
-                di_point(ys, d, tau, (double)(lg + CL) * inv, p1);
+                if (K > CL) di_point(ys, d, tau, (double)(lg + CL) * inv, p1);  // second point only when needed
                 // leaving [0,1]^3 is a collision
                 hit = (h0 && di_point_hits_d(p0, -1, nullptr)) || (h1 && di_point_hits_d(p1, -1, nullptr));
                 // conservative float box of the group's points (slack 1e-6 covers
@@ -501,7 +502,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     unsigned char *st = LDS ? lst : w.st;
     Ctl *ctl = LDS ? lctl : w.ctl;
     unsigned long long w_out = 0, w_in = 0, w_cand = 0, w_commit = 0, w_open = 0, w_iters = 0;
-    unsigned long long tk_setup = 0, tk_select = 0, tk_frontier = 0, tk_connect = 0;
+    unsigned long long tk_setup = 0, tk_select = 0, tk_frontier = 0, tk_connect = 0, tk_check = 0;
     unsigned long long tk = (t.rank == 0) ? clock_ticks() : 0;
 
     if (t.rank == 0) {
@@ -678,7 +679,9 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
+                const unsigned long long c0 = (t.wave == 0) ? clock_ticks() : 0;
                 const bool free_edge = group_edge_free<KIND, CL>(P, ok, ok ? by : 0, ce, be, lbox);
+                if (t.wave == 0) tk_check += clock_ticks() - c0;
                 const bool commit = ok && free_edge && lg == 0;
                 if (active && lg == 0) {
                     // commit (lines 8-9), or release the claim: x stays unexplored
@@ -747,6 +750,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         res->work[W_T_SELECT] = tk_select;
         res->work[W_T_FRONTIER] = tk_frontier;
         res->work[W_T_CONNECT] = tk_connect;
+        res->work[W_T_CHECK] = tk_check;
     }
     // ---- work counters: one atomic per wave and counter ----
     {
@@ -769,8 +773,13 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // the dynamic region is 16-byte aligned (it follows the static s_job), which
 // the 64-bit counter fields require.
 // ---------------------------------------------------------------------------
+// workgroups per CU the register allocation is sized for
+#ifndef GMT_PLAN_OCC
+#define GMT_PLAN_OCC 4
+#endif
+
 template <int KIND, bool LDS, int CL>
-__global__ void __launch_bounds__(256, 4) k_plan(const ProbDev *__restrict__ probs, int count,
+__global__ void __launch_bounds__(256, GMT_PLAN_OCC) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
                                               int team_wgs, Result *__restrict__ res) {

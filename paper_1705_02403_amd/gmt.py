@@ -42,6 +42,7 @@ EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "
            "gmt_last_work", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_cancel",
            "gmt_engine_set_budget", "gmt_engine_get_stats", "gmt_engine_destroy",
+           "gmt_batch_prepare", "gmt_batch_run", "gmt_batch_free",
            "gmt_autotune", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
            "gmt_tune_load", "gmt_last_error", "gmt_version", "gmt_steady_ns"]
 
@@ -99,7 +100,7 @@ class gmt_work(C.Structure):
     _fields_ = [("out_edges", C.c_int64), ("in_edges", C.c_int64), ("candidates", C.c_int64),
                 ("commits", C.c_int64), ("open_entries", C.c_int64), ("iterations", C.c_int64),
                 ("setup_ns", C.c_int64), ("select_ns", C.c_int64), ("frontier_ns", C.c_int64),
-                ("connect_ns", C.c_int64)]
+                ("connect_ns", C.c_int64), ("check_ns", C.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -181,6 +182,10 @@ def lib():
             L.gmt_engine_set_budget.argtypes = [P, C.c_size_t]
             L.gmt_engine_get_stats.argtypes = [P, C.POINTER(gmt_engine_stats)]
             L.gmt_engine_destroy.argtypes = [P]
+            L.gmt_batch_prepare.argtypes = [C.POINTER(gmt_problem), i32, C.POINTER(gmt_batch_opts), C.POINTER(P),
+                                            P]
+            L.gmt_batch_run.argtypes = [P, C.POINTER(gmt_result), P]
+            L.gmt_batch_free.argtypes = [P]
             L.gmt_autotune.argtypes = [C.POINTER(gmt_problem), i32, i32, C.POINTER(gmt_plan_opts), i32,
                                        C.POINTER(gmt_tune_choice), P]
             L.gmt_tune_lookup.argtypes = [C.POINTER(gmt_tune_shape), C.POINTER(gmt_tune_choice)]
@@ -473,6 +478,35 @@ class PreparedBatch:
                                   float(r.path_cost), int(r.iters), *self.outs[j],
                                   work=r.work.as_dict()))
         return out
+
+
+class GraphBatch(PreparedBatch):
+    """Queries staged once by the library (gmt_batch_prepare) with their launch
+    captured as a HIP graph; ``run()`` replays it (gmt_batch_run)."""
+
+    def __init__(self, queries: Sequence[BatchQuery], opts: gmt_plan_opts, workgroups: int = 0,
+                 path_cap: int = 1024, team_wgs: int = 0, stream=None):
+        super().__init__(queries, opts, workgroups, False, path_cap)
+        if team_wgs:
+            self.bo.plan.team_wgs = int(team_wgs)
+        h = C.c_void_p()
+        _check(lib().gmt_batch_prepare(self.probs, self.k, C.byref(self.bo), C.byref(h), _stream(stream)),
+               "gmt_batch_prepare")
+        self.handle = h
+
+    def run(self, stream=None) -> None:
+        _check(lib().gmt_batch_run(self.handle, self.res, _stream(stream)), "gmt_batch_run")
+
+    def close(self) -> None:
+        if self.handle:
+            lib().gmt_batch_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gmt_plan_batch(queries: Sequence[BatchQuery], opts: gmt_plan_opts, workgroups: int = 0,

@@ -256,21 +256,28 @@ def train(sampler: Sampler, data: TrainingSet, steps: int, batch: int = 1024, se
     return hist
 
 
-def mixed_samples(sampler: Sampler, prob, n: int, seed: int, learned: bool = True):
+def mixed_samples(sampler: Sampler, prob, n: int, seed: int, learned: bool = True, uniform=None,
+                  fallback=None, eps=None):
     """Sample set of one query as a CUDA SoA [6][n] tensor: the first n - n/2
     uniform (with a goal sample), the rest from the network (rejected ones
-    replaced by uniform draws) -- or all uniform when ``learned`` is false.
-    Returns (samples, rejected)."""
+    replaced by uniform fallback draws) -- or all uniform when ``learned`` is
+    false.  ``uniform`` [6][n - n/2], ``fallback`` [6][n/2] and ``eps``
+    [n/2][6] may be supplied as resident CUDA tensors (they do not depend on
+    the query); otherwise they are drawn from ``seed``.  Returns
+    (samples, rejected)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     n_l = n // 2 if learned else 0
     n_u = n - n_l
-    uni = I.di_samples(1_000 + seed, n_u)
     out = torch.empty((6, n), dtype=torch.float32, device=dev)
-    out[:, :n_u] = torch.from_numpy(uni).to(dev)
+    if uniform is None:
+        uniform = torch.from_numpy(I.di_samples(1_000 + seed, n_u)).to(dev)
+    out[:, :n_u] = uniform
     rej = 0
     if n_l:
-        fb = torch.from_numpy(I.di_samples(2_000_000 + seed, n_l)).to(dev)
-        eps = torch.from_numpy(I.normal_draws(3_000_000 + seed, n_l)).to(dev)
-        rej = sampler.generate(condition(prob), eps, prob.boxes, fb, out[:, n_u:])
+        if fallback is None:
+            fallback = torch.from_numpy(I.di_samples(2_000_000 + seed, n_l)).to(dev)
+        if eps is None:
+            eps = torch.from_numpy(I.normal_draws(3_000_000 + seed, n_l)).to(dev)
+        rej = sampler.generate(condition(prob), eps, prob.boxes, fallback, out[:, n_u:])
     return out, rej

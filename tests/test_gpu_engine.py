@@ -126,3 +126,28 @@ def test_server_poisson_stream(world):
     for s in rep.served:
         assert s.status == ref[s.tag].status and s.path_cost == ref[s.tag].path_cost
     assert rep.p99_ms >= rep.p50_ms > 0
+
+
+def test_graph_batch_replays_equal_eager(world):
+    """A prepared batch replays its captured HIP graph; every replay, with
+    eager planning work between replays, equals gmt_plan_batch."""
+    say("graph batch: replays")
+    rms, probs = world
+    qs = [query(rms, *kp) for kp in probs]
+    eager = gmt.gmt_plan_batch(qs, opts())
+    gb = gmt.GraphBatch(qs, opts())
+    for rep in range(4):
+        gb.run()
+        got = gb.results()
+        for a, b in zip(got, eager):
+            assert a.status == b.status and a.path_cost == b.path_cost and list(a.path) == list(b.path), rep
+        other = gmt.gmt_plan_batch(qs[::-1], opts())  # eager work between replays
+        assert other[-1].path_cost == eager[0].path_cost
+    gb.close()
+    # cooperative shape: not captured, replayed as direct launches
+    gc = gmt.GraphBatch(qs[:3], opts(), team_wgs=2)
+    for _ in range(2):
+        gc.run()
+        for a, b in zip(gc.results(), eager[:3]):
+            assert a.status == b.status and a.path_cost == b.path_cost
+    gc.close()
