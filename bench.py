@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--server-requests", type=int, default=4096)
     ap.add_argument("--server-rate", type=float, default=20000.0)
+    ap.add_argument("--only-throughput", action="store_true",
+                    help="time the batches only (for counter runs): no latency, server, build or oracle sections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 5 times (calibrates HBM byte counters)")
     ap.add_argument("--learned", action="store_true",
@@ -227,18 +229,19 @@ def main():
 
     # ---- latency: single queries, the whole GPU on one plan ----
     lat = []
-    for k in range(args.latency_warmup + args.latency_samples):
+    n_lat = 0 if args.only_throughput else args.latency_warmup + args.latency_samples
+    for k in range(n_lat):
         p = probs[k % len(probs)]
         torch.cuda.synchronize()
         t = time.perf_counter()
         res = gmt.gmt_plan(rms[p.sample_seed], p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, 3),
                            p.boxes, p.lam, opts, outputs=False)
         lat.append((time.perf_counter() - t) * 1e3)
-    lat = np.array(lat[args.latency_warmup:])
+    lat = np.array(lat[args.latency_warmup:]) if len(lat) > args.latency_warmup else None
 
     # ---- replanning server: Poisson arrivals through the continuous-batching engine ----
     srv_line = None
-    if args.server_requests > 0:
+    if args.server_requests > 0 and not args.only_throughput:
         from paper_1705_02403_amd import server
         arr = I.poisson_arrivals(args.server_requests, args.server_rate, seed=11)
         reqs = [server.Request(float(t), probs[k % len(probs)].sample_seed,
@@ -258,30 +261,32 @@ def main():
                     "identical_to_batch": "%d/%d" % (same, len(rep.served))}
 
     # ---- Euclidean neighbour table build, 3D n=16384 (config 2 workload) ----
-    p3 = I.problem_3d(0)
-    from paper_1705_02403_amd import radius as RAD
-    r3 = RAD.problem_radius(p3)
-    d3 = torch.from_numpy(p3.samples).cuda()
-    bt = []
-    for k in range(6):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
-        torch.cuda.synchronize()
-        bt.append((time.perf_counter() - t) * 1e3)
-        e3 = rm3.nnz
-        rm3.free()
-    bt = float(np.median(bt[1:]))
-    build_line = {"workload": "3D Euclidean n=16384, r=%.4f" % r3, "edges": int(e3),
-                  "ms": round(bt, 3),
-                  "GB_per_s_out": round(12.0 * e3 / (bt * 1e-3) / 1e9, 1)}
+    build_line = None
+    if not args.only_throughput:
+        p3 = I.problem_3d(0)
+        from paper_1705_02403_amd import radius as RAD
+        r3 = RAD.problem_radius(p3)
+        d3 = torch.from_numpy(p3.samples).cuda()
+        bt = []
+        for k in range(6):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
+            torch.cuda.synchronize()
+            bt.append((time.perf_counter() - t) * 1e3)
+            e3 = rm3.nnz
+            rm3.free()
+        bt = float(np.median(bt[1:]))
+        build_line = {"workload": "3D Euclidean n=16384, r=%.4f" % r3, "edges": int(e3),
+                      "ms": round(bt, 3),
+                      "GB_per_s_out": round(12.0 * e3 / (bt * 1e-3) / 1e9, 1)}
 
     learned = learned_report(args, torch, gmt, I) if args.learned else None
 
     # ---- cost against the FP64 oracle (sample set 0) and CPU baseline ----
     check = {}
     cpu = None
-    if args.oracle_checks > 0 or not args.no_cpu:
+    if (args.oracle_checks > 0 or not args.no_cpu) and not args.only_throughput:
         from oracle import oracle as O
         t = time.perf_counter()
         tab = O.neighbors(samples[0], O.DI, r)
@@ -344,8 +349,8 @@ def main():
         "config": {"workload": "6D double integrator, n=16384 samples, 40 boxes U[0.05,0.2], "
                                "lambda=0.5, r=1.75, 16 trajectory points",
                    "batch_queries": args.batch, "sample_sets": args.sample_sets},
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat is not None else None,
+        "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat is not None else None,
         "solved": "%d/%d" % (ok, args.batch),
         "roadmap_build_ms": round(float(np.median(build_ms)), 3),
         "roadmap_nnz": int(np.median(nnz)),

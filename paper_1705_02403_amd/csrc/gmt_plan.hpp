@@ -445,8 +445,13 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 // stage instead of one dependent chain per edge.  Lanes whose edge is absent
 // or not open read fixed valid addresses (in_col[ib], cost[x], in_cost[ib])
 // and ignore the values.
+//
+// EAGER (state bytes in global memory): the costs are loaded together with
+// the state bytes rather than after them, one dependent round trip fewer;
+// values of nodes that are not open are read and ignored (a node committed
+// by this iteration may be written meanwhile; it is not open either way).
 #define SCAN_U 8
-template <int CL>
+template <int CL, bool EAGER>
 __device__ __forceinline__ void scan_row(const unsigned char *st, const double *__restrict__ cost,
                                          const int *__restrict__ in_col, const double *__restrict__ in_cost,
                                          int x, int ib, int ie, int lg, double &best, int &by, int &be) {
@@ -458,13 +463,23 @@ __device__ __forceinline__ void scan_row(const unsigned char *st, const double *
             const int f = f0 + u * CL;
             y[u] = in_col[f < ie ? f : ib];
         }
-#pragma unroll
-        for (int u = 0; u < SCAN_U; ++u) op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
         double c[SCAN_U], ic[SCAN_U];
+        if (EAGER) {
 #pragma unroll
-        for (int u = 0; u < SCAN_U; ++u) {
-            c[u] = cost[op[u] ? y[u] : x];
-            ic[u] = in_cost[op[u] ? f0 + u * CL : ib];
+            for (int u = 0; u < SCAN_U; ++u) {
+                const bool in_row = f0 + u * CL < ie;
+                c[u] = cost[y[u]];
+                ic[u] = in_cost[in_row ? f0 + u * CL : ib];
+                op[u] = in_row && ((st[y[u]] & 3) == 1);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                c[u] = cost[op[u] ? y[u] : x];
+                ic[u] = in_cost[op[u] ? f0 + u * CL : ib];
+            }
         }
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
@@ -660,10 +675,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             const int *__restrict__ in_col = R.in_col;
             const double *__restrict__ in_cost = R.in_cost;
             const double *__restrict__ cost = w.cost;
-            for (int base = t.wave * per_wave; base < cc; base += t.nwaves * per_wave) {
+            const int stride = t.nwaves * per_wave;
+            // the next round's candidate entry is loaded one round ahead
+            int4 ent_next = (t.wave * per_wave + sub < cc) ? w.clist[t.wave * per_wave + sub] : make_int4(0, 0, 0, 0);
+            for (int base = t.wave * per_wave; base < cc; base += stride) {
                 const int k = base + sub;
                 const bool active = k < cc;
-                const int4 ent = active ? w.clist[k] : make_int4(0, 0, 0, 0);
+                const int4 ent = ent_next;
+                ent_next = (k + stride < cc) ? w.clist[k + stride] : make_int4(0, 0, 0, 0);
                 const int x = ent.x;
                 double best = __longlong_as_double(COST_INF_BITS);
                 int by = 0x7fffffff, be = -1;
@@ -675,7 +694,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    scan_row<CL>(st, cost, in_col, in_cost, x, ib, ie, lg, best, by, be);
+                    scan_row<CL, !LDS>(st, cost, in_col, in_cost, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
