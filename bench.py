@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--server-requests", type=int, default=4096)
     ap.add_argument("--server-rate", type=float, default=20000.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shape instead of tuning it first")
     ap.add_argument("--only-throughput", action="store_true",
                     help="time the batches only (for counter runs): no latency, server, build or oracle sections")
     ap.add_argument("--copy-probe", action="store_true",
@@ -200,6 +202,12 @@ def main():
 
     queries = [query(p) for p in probs]
     opts = gmt.make_opts(traj_points=16)
+    # launch shape: the autotuner times every candidate on this batch and on
+    # one single query, checks they give identical results, caches the fastest
+    tuned = None
+    if not args.no_autotune:
+        tuned = {"batch": gmt.gmt_autotune(queries, opts, single=False, reps=2),
+                 "single": gmt.gmt_autotune(queries[:1], opts, single=True, reps=3)}
     # queries marshalled into ABI structs once; a step is one gmt_plan_batch call
     batch = gmt.PreparedBatch(queries, opts)
 
@@ -219,6 +227,19 @@ def main():
     gmt.gmt_profile_enable(False)
     work = gmt.gmt_last_work()
     out = batch.results()
+    # the same batch replayed from a captured HIP graph (staging done once)
+    graph_ms = None
+    if not args.only_throughput:
+        gb = gmt.GraphBatch(queries, opts)
+        gb.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            gb.run()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t) * 1e3 / args.steps
+        assert all(a.path_cost == b.path_cost for a, b in zip(gb.results(), out))
+        gb.close()
     ok = sum(o.status == gmt.GMT_OK for o in out)
     plans = args.steps * args.batch
     value = plans / elapsed
@@ -352,6 +373,8 @@ def main():
         "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat is not None else None,
         "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat is not None else None,
         "solved": "%d/%d" % (ok, args.batch),
+        "graph_replay_ms_per_step": round(graph_ms, 3) if graph_ms else None,
+        "launch_shape": tuned,
         "roadmap_build_ms": round(float(np.median(build_ms)), 3),
         "roadmap_nnz": int(np.median(nnz)),
         "work_per_plan": {k: round(v / args.batch, 1) for k, v in work.items()},

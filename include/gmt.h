@@ -318,6 +318,12 @@ gmt_status gmt_engine_submit(gmt_engine_t e, const gmt_problem *problem, int32_t
 gmt_status gmt_engine_poll(gmt_engine_t e, int64_t ticket, int32_t wait_us, gmt_result *out, int32_t *path,
                            int32_t path_cap);
 
+/* Wait up to wait_us microseconds (< 0: forever, 0: no wait) for any
+ * finished ticket, in completion order.  GMT_OK: *ticket names it and `out`
+ * holds its result (the ticket is retired); GMT_EBUSY: none finished. */
+gmt_status gmt_engine_poll_any(gmt_engine_t e, int32_t wait_us, int64_t *ticket, gmt_result *out, int32_t *path,
+                               int32_t path_cap);
+
 /* Withdraw a queued request (GMT_EBUSY once it is running). */
 gmt_status gmt_engine_cancel(gmt_engine_t e, int64_t ticket);
 

@@ -497,7 +497,8 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // bytes of one query's workspace over N nodes (tree arrays included when the
 // caller does not supply them)
 static size_t qws_bytes(int N, bool own_tree) {
-    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 2 * al256(4 * (size_t)N) + al256(16 * (size_t)N);
+    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 2 * al256(4 * (size_t)N) + al256(16 * (size_t)N) +
+               al256(8 * (size_t)N);
     if (own_tree) b += al256(8 * (size_t)N) + 3 * al256(4 * (size_t)N);
     return b;
 }
@@ -513,6 +514,7 @@ static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi
     w.glist = (int *)take(4 * (size_t)N);
     w.clist = (int4 *)take(16 * (size_t)N);
     w.hits = (int *)take(4 * (size_t)N);
+    w.aux = (double *)take(8 * (size_t)N);
     w.cost = cost ? cost : (double *)take(8 * (size_t)N);
     w.parent = parent ? parent : (int *)take(4 * (size_t)N);
     w.gi = gi ? gi : (int *)take(4 * (size_t)N);
@@ -824,17 +826,8 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
     const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
     TeamCtl *tctl = (TeamCtl *)w->tctl.p;
     Result *res = (Result *)w->res_d.p + first;
-    size_t lds = (size_t)std::max(box_words_in, 1) * sizeof(int);
     const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
     const size_t plds = plan_lds(box_words, nmax, lds_st);
-    for (int c0 = 0; c0 < count; c0 += 65535) {
-        dim3 ig(blocks_for((long long)nmax + 1, 256), std::min(65535, count - c0));
-        if (kind == GMT_COST_EUCLIDEAN)
-            k_plan_init<0><<<ig, 256, lds, s>>>(probs + c0, boxes);
-        else
-            k_plan_init<1><<<ig, 256, lds, s>>>(probs + c0, boxes);
-    }
-    HIPCHK(hipGetLastError());
     if (e0) HIPCHK(hipEventRecord(e0, s));
     dim3 grid(teams * team_wgs), block(256);
     int st_bytes = nmax + 1;
@@ -1462,6 +1455,7 @@ struct gmt_engine {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<EngineReq *> queue;
+    std::deque<int64_t> done;  // finished tickets in completion order (poll_any)
     std::unordered_map<int64_t, EngineReq *> reqs;
     std::vector<EngineSlot> slots;
     size_t inflight = 0, budget = 0;
@@ -1504,6 +1498,7 @@ static void engine_loop(gmt_engine *E) {
                 r->res.submit_ns = r->t_submit;
                 r->res.done_ns = now;
                 r->state = 2;
+                E->done.push_back(r->id);
                 E->st.completed += 1;
             }
             E->inflight -= sl.bytes;
@@ -1528,6 +1523,7 @@ static void engine_loop(gmt_engine *E) {
                         E->queue.pop_front();  // can never fit
                         r->res.status = GMT_ENOMEM;
                         r->state = 2;
+                        E->done.push_back(r->id);
                         E->st.rejected += 1;
                         progressed = true;  // wakes a poller waiting on it
                         continue;
@@ -1565,6 +1561,7 @@ static void engine_loop(gmt_engine *E) {
                 for (EngineReq *r : sl.reqs) {
                     r->res.status = ss;
                     r->state = 2;
+                    E->done.push_back(r->id);
                 }
                 E->error = g_last_error;
                 E->inflight -= sl.bytes;
@@ -1641,6 +1638,19 @@ extern "C" gmt_status gmt_engine_submit(gmt_engine_t E, const gmt_problem *p, in
     return GMT_OK;
 }
 
+// copy a finished request's result out and forget the request (lock held)
+static void engine_retire(gmt_engine *E, std::unordered_map<int64_t, EngineReq *>::iterator it, gmt_result *out,
+                          int32_t *path, int32_t path_cap) {
+    EngineReq *r = it->second;
+    *out = r->res;
+    out->path = path;
+    out->path_cap = path_cap;
+    if (path && r->res.status == GMT_OK)
+        for (int k = 0; k < r->res.path_len && k < path_cap && k < (int)r->path.size(); ++k) path[k] = r->path[k];
+    E->reqs.erase(it);
+    delete r;
+}
+
 extern "C" gmt_status gmt_engine_poll(gmt_engine_t E, int64_t ticket, int32_t wait_us, gmt_result *out,
                                       int32_t *path, int32_t path_cap) {
     if (!E || !out) return fail(GMT_EINVAL, "null argument");
@@ -1656,13 +1666,29 @@ extern "C" gmt_status gmt_engine_poll(gmt_engine_t E, int64_t ticket, int32_t wa
             E->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), pred);
     }
     if (r->state < 2) return GMT_EBUSY;
-    *out = r->res;
-    out->path = path;
-    out->path_cap = path_cap;
-    if (path && r->res.status == GMT_OK)
-        for (int k = 0; k < r->res.path_len && k < path_cap && k < (int)r->path.size(); ++k) path[k] = r->path[k];
-    E->reqs.erase(it);
-    delete r;
+    engine_retire(E, it, out, path, path_cap);
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_engine_poll_any(gmt_engine_t E, int32_t wait_us, int64_t *ticket, gmt_result *out,
+                                          int32_t *path, int32_t path_cap) {
+    if (!E || !out || !ticket) return fail(GMT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto ready = [&] {
+        while (!E->done.empty() && !E->reqs.count(E->done.front())) E->done.pop_front();  // retired by poll
+        return !E->done.empty();
+    };
+    if (!ready() && wait_us != 0) {
+        if (wait_us < 0)
+            E->cv_done.wait(lk, ready);
+        else
+            E->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), ready);
+    }
+    if (!ready()) return GMT_EBUSY;
+    const int64_t id = E->done.front();
+    E->done.pop_front();
+    *ticket = id;
+    engine_retire(E, E->reqs.find(id), out, path, path_cap);
     return GMT_OK;
 }
 

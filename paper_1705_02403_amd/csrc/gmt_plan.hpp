@@ -1,15 +1,14 @@
 // gmt_plan.hpp -- Algorithm 1 (GMT*) on the GPU.
 //
-// k_plan_init: one thread per (query, node).  Marks samples inside the
-//   query's boxes dead, flags goal samples, and performs iteration 0: the
-//   root x_init is the only open node, so every sample within r of it whose
-//   edge passes the lazy check joins the tree (Algorithm 1 lines 1-9 for
-//   i = 0).  Runs at full GPU width and keeps the root-edge solver out of the
-//   persistent kernel.
-//
 // k_plan: persistent.  A team of workgroups runs one query at a time and
 //   pulls the next from a device counter, so one kernel serves a single plan
 //   (team = the whole co-resident grid) and a batch (team = one workgroup).
+//   A query starts with iteration 0 (Algorithm 1 lines 1-9 with the root as
+//   the only open node): one pass over the nodes marks samples inside the
+//   boxes dead, flags goal samples and lists those that may lie within r of
+//   x_init; their root-edge costs are solved one per lane, and the edges
+//   below r are checked by groups of lanes -- dense work instead of a few
+//   busy lanes per wavefront.
 //
 // Sets (Section IV: each sample is in exactly one of unexplored / open /
 // closed) live in one byte per node -- in LDS for one-workgroup teams, in
@@ -93,6 +92,7 @@ struct QWs {
     int *parent;
     int *gi;
     int *ai;
+    double *aux;        // per node: arrival time of the root edge (iteration 0)
 };
 
 struct ProbDev {
@@ -161,6 +161,20 @@ __device__ __forceinline__ bool point_in_box_q(const int *q, const int *box, int
     return true;
 }
 
+// grid point inside staged box b: grid integers (KIND 0) or exact floats
+// (KIND 1, position only)
+template <int KIND>
+__device__ __forceinline__ bool in_staged_box(const int *q, const int *lbox, int b, int pd) {
+    if (KIND == 0) return point_in_box_q(q, lbox + b * 2 * pd, pd);
+    const float *bx = (const float *)lbox + b * 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double v = (double)q[a] * GMT_INV_QS;
+        if (v < (double)bx[a] || v > (double)bx[3 + a]) return false;
+    }
+    return true;
+}
+
 __device__ __forceinline__ bool in_goal_q(const int *q, const ProbDev &P) {
     long long s = 0;
     for (int a = 0; a < P.goal_dims; ++a) {
@@ -171,19 +185,7 @@ __device__ __forceinline__ bool in_goal_q(const int *q, const ProbDev &P) {
 }
 
 // does a trajectory point lie in box b (b = -1: outside [0,1]^3)?  Boxes as
-// grid integers (k_plan_init) ...
-__device__ __forceinline__ bool di_point_hits(const double *p, int b, const int *lbox) {
-    if (b < 0) return p[0] < 0.0 || p[0] > 1.0 || p[1] < 0.0 || p[1] > 1.0 || p[2] < 0.0 || p[2] > 1.0;
-    const int *bx = lbox + b * 6;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double lo = (double)bx[a] * GMT_INV_QS, hi = (double)bx[3 + a] * GMT_INV_QS;
-        if (p[a] < lo || p[a] > hi) return false;
-    }
-    return true;
-}
-
-// ... or as exact doubles (k_plan stages them once per query)
+// exact doubles.
 __device__ __forceinline__ bool di_point_hits_d(const double *p, int b, const double *dbox) {
     if (b < 0) return p[0] < 0.0 || p[0] > 1.0 || p[1] < 0.0 || p[1] > 1.0 || p[2] < 0.0 || p[2] > 1.0;
     const double *bx = dbox + b * 6;
@@ -201,96 +203,13 @@ __device__ __forceinline__ DiPair make_pair(const double *src, const double *dst
     return d;
 }
 
-// serial lazy checks (one thread per edge; the root's edges)
-__device__ bool eu_edge_free_serial(const int *yq, const int *xq, const ProbDev &P, const int *lbox) {
-    long long d2 = 0;
-    for (int a = 0; a < P.pd; ++a) {
-        long long dd = (long long)xq[a] - yq[a];
-        d2 += dd * dd;
-    }
-    long long K1 = segment_parts(d2, P.step_q);
-    for (int b = 0; b < P.m; ++b) {
-        const int *lo = lbox + b * 2 * P.pd, *hi = lo + P.pd;
-        if (aabb_disjoint(yq, xq, P.pd, lo, hi)) continue;
-        if (segment_hits_box(yq, xq, P.pd, K1, lo, hi)) return false;
-    }
-    return true;
-}
-
-__device__ bool di_edge_free_serial(const double *ys, const double *xs, double tau, const ProbDev &P,
-                                    const int *lbox) {
-    DiPair d = make_pair(ys, xs);
-    const int K = P.traj_points;
-    for (int k = 0; k < K; ++k) {
-        double p[3];
-        di_point(ys, d, tau, (double)k / (double)(K - 1), p);
-        for (int b = -1; b < P.m; ++b)
-            if (di_point_hits(p, b, lbox)) return false;
-    }
-    return true;
-}
-
-// ---------------------------------------------------------------------------
-// init: masks and iteration 0
-// ---------------------------------------------------------------------------
-template <int KIND>
-__global__ void __launch_bounds__(256) k_plan_init(const ProbDev *__restrict__ probs,
-                                                   const int *__restrict__ boxes) {
-    extern __shared__ __align__(16) int lbox[];
-    const ProbDev &P = probs[blockIdx.y];
-    const RoadmapDev &R = P.rm;
-    const int words = P.m * 2 * P.pd;
-    for (int k = threadIdx.x; k < words; k += blockDim.x) lbox[k] = boxes[P.box_off + k];
-    __syncthreads();
-    const int n = R.n, root = n;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v > n) return;
-    const QWs &w = P.w;
-    w.gi[v] = -1;
-    if (v == root) {
-        w.st[v] = (unsigned char)(S_CLOSED | (in_goal_q(P.x_q, P) ? S_GOAL : 0));
-        w.cost[v] = 0.0;
-        w.parent[v] = -1;
-        w.ai[v] = -1;
-        w.gi[v] = 0;
-        return;
-    }
-    int q[6] = {0, 0, 0, 0, 0, 0};
-    for (int a = 0; a < R.dim; ++a) q[a] = (int)((double)R.s[(size_t)a * n + v] * GMT_QS);
-    bool dead = false;
-    for (int b = 0; b < P.m && !dead; ++b) dead = point_in_box_q(q, lbox + b * 2 * P.pd, P.pd);
-    unsigned char goal = in_goal_q(q, P) ? S_GOAL : 0;
-    double c = __longlong_as_double(COST_INF_BITS);
-    bool join = false;
-    if (!dead) {
-        if (KIND == 0) {
-            long long d2 = 0;
-            for (int a = 0; a < R.dim; ++a) {
-                long long dd = (long long)q[a] - P.x_q[a];
-                d2 += dd * dd;
-            }
-            if ((double)d2 < R.R2 && eu_edge_free_serial(P.x_q, q, P, lbox)) {
-                join = true;
-                c = sqrt((double)d2) * GMT_INV_QS;
-            }
-        } else {
-            double xs[6];
-            sample_d<6>(R, v, xs);
-            DiPair d = make_pair(P.x_d, xs);
-            if (di_may_connect(d, R.r)) {
-                double J = 0.0, tau = 0.0;
-                di_cost(d, J, tau);
-                if (J < R.r && di_edge_free_serial(P.x_d, xs, tau, P, lbox)) {
-                    join = true;
-                    c = J;
-                }
-            }
-        }
-    }
-    w.st[v] = (unsigned char)((dead ? S_DEAD : (join ? S_OPEN : S_UNEXPLORED)) | goal);
-    w.cost[v] = c;
-    w.parent[v] = join ? root : -1;
-    w.ai[v] = join ? 0 : -2;
+// double-integrator cost of the root edge x_init -> v.  Kept out of line:
+// it runs once per query, and inlined its registers would crowd the
+// allocation of the expansion loop.
+__device__ __noinline__ void root_edge_cost(const ProbDev &P, int v, double &J, double &tau) {
+    double xs[6];
+    sample_d<6>(P.rm, v, xs);
+    di_cost(make_pair(P.x_d, xs), J, tau);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,17 +247,16 @@ __device__ __forceinline__ void load_end(const RoadmapDev &R, int x, CandEnd &c)
 }
 
 // lazy check of edge y -> x by the CL lanes of a group; every lane of the
-// wave calls it; returns the verdict for this lane's group
+// wave calls it; returns the verdict for this lane's group.  y is given by
+// its grid coordinates yq (KIND 0) or its state ys and the edge's arrival
+// time tau (KIND 1).
 template <int KIND, int CL>
-__device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, int y, const CandEnd &c,
-                                                int e, const int *lbox) {
-    const RoadmapDev &R = P.rm;
+__device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, const int *yq, const double *ys,
+                                                double tau, const CandEnd &c, const int *lbox) {
     const int lg = lane_id() & (CL - 1);
     bool hit = false;
     if (active) {
         if (KIND == 0) {
-            int yq[3] = {0, 0, 0};
-            for (int a = 0; a < R.dim; ++a) yq[a] = (int)((double)R.s[(size_t)a * R.n + y] * GMT_QS);
             long long d2 = 0;
             for (int a = 0; a < P.pd; ++a) {
                 long long dd = (long long)c.xq[a] - yq[a];
@@ -352,10 +270,7 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, i
             }
         } else {
             const float *fbox = (const float *)lbox;
-            double ys[6];
-            sample_d<6>(R, y, ys);
             DiPair d = make_pair(ys, c.xs);
-            const double tau = R.in_tau[e];
             const int K = P.traj_points;
             const double inv = 1.0 / (double)(K - 1);
             if (K <= 2 * CL) {
@@ -521,6 +436,9 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     unsigned long long tk = (t.rank == 0) ? clock_ticks() : 0;
 
     if (t.rank == 0) {
+        // work counters are summed by atomics at the end: start them at zero
+        // (the result block is reused across launches)
+        for (int k = 0; k < W_COUNT; ++k) res->work[k] = 0ull;
         ctl->g_cnt = 0;
         ctl->c_cnt = 0;
         for (int k = 0; k < 2; ++k) {
@@ -530,14 +448,115 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             ctl->min_bits[k] = COST_INF_BITS;
         }
     }
-    if (LDS) {
-        const int words = (N + 3) >> 2;
-        const unsigned int *src = (const unsigned int *)w.st;
-        unsigned int *dst = (unsigned int *)lst;
-        for (int k = t.rank; k < words; k += t.size) dst[k] = src[k];
+    team_sync(t);  // counters are zero before the appends below
+
+    // ---- iteration 0: the root x_init is the only open node (lines 1-9) ----
+    // (a) every node: obstacle and goal bits, tree arrays reset; samples that
+    //     may lie within r of the root are listed (exact test for the
+    //     Euclidean cost, the lower bound on J for the double integrator)
+    const int wbase = t.rank - t.lane;
+    for (int v0 = wbase; v0 < N; v0 += t.size) {
+        const int v = v0 + t.lane;
+        bool cand = false;
+        if (v == root) {
+            st[v] = (unsigned char)(S_CLOSED | (in_goal_q(P.x_q, P) ? S_GOAL : 0));
+            w.cost[v] = 0.0;
+            w.parent[v] = -1;
+            w.gi[v] = 0;
+            w.ai[v] = -1;
+        } else if (v < n) {
+            int q[6] = {0, 0, 0, 0, 0, 0};
+            for (int a = 0; a < R.dim; ++a) q[a] = (int)((double)R.s[(size_t)a * n + v] * GMT_QS);
+            bool dead = false;
+            for (int b = 0; b < P.m && !dead; ++b) dead = in_staged_box<KIND>(q, lbox, b, P.pd);
+            st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
+            w.cost[v] = __longlong_as_double(COST_INF_BITS);
+            w.parent[v] = -1;
+            w.gi[v] = -1;
+            w.ai[v] = -2;
+            if (!dead) {
+                if (KIND == 0) {
+                    long long d2 = 0;
+                    for (int a = 0; a < R.dim; ++a) {
+                        const long long dd = (long long)q[a] - P.x_q[a];
+                        d2 += dd * dd;
+                    }
+                    cand = (double)d2 < R.R2;
+                } else {
+                    double xs[6];
+                    sample_d<6>(R, v, xs);
+                    cand = di_may_connect(make_pair(P.x_d, xs), R.r);
+                }
+            }
+        }
+        const int slot = wave_append(&ctl->c_cnt, cand);
+        if (cand) w.clist[slot] = make_int4(v, 0, 0, 0);
     }
     team_sync(t);
-    // open set of iteration 1: the root's children (added by k_plan_init)
+    // (b) edge cost from the root, one candidate per lane; those below r are
+    //     compacted for the lazy check
+    {
+        const int cc0 = ld_cnt(&ctl->c_cnt);
+        for (int k0 = wbase; k0 < cc0; k0 += t.size) {
+            const int k = k0 + t.lane;
+            bool ok = false;
+            int v = 0;
+            if (k < cc0) {
+                v = w.clist[k].x;
+                if (KIND == 0) {
+                    long long d2 = 0;
+                    for (int a = 0; a < R.dim; ++a) {
+                        const long long dd = (long long)((double)R.s[(size_t)a * n + v] * GMT_QS) - P.x_q[a];
+                        d2 += dd * dd;
+                    }
+                    w.cost[v] = sqrt((double)d2) * GMT_INV_QS;
+                    ok = true;
+                } else {
+                    double J = 0.0, tau = 0.0;
+                    root_edge_cost(P, v, J, tau);
+                    ok = J < R.r;
+                    if (ok) {
+                        w.cost[v] = J;
+                        w.aux[v] = tau;
+                    }
+                }
+            }
+            const int slot = wave_append(&ctl->g_cnt, ok);
+            if (ok) w.glist[slot] = v;
+        }
+    }
+    team_sync(t);
+    // (c) lazy check of each root edge by CL lanes; a free edge adds the node
+    //     (parent root, added at iteration 0), otherwise it stays unexplored
+    {
+        const int gc0 = ld_cnt(&ctl->g_cnt);
+        const int sub = t.lane / CL, lg = t.lane & (CL - 1);
+        constexpr int per_wave = GMT_WAVE / CL;
+        for (int base = t.wave * per_wave; base < gc0; base += t.nwaves * per_wave) {
+            const int k = base + sub;
+            const bool active = k < gc0;
+            const int v = active ? w.glist[k] : 0;
+            CandEnd ce;
+            if (active) load_end<KIND>(R, v, ce);
+            const double tau = (KIND == 1 && active) ? w.aux[v] : 0.0;
+            const bool free_edge = group_edge_free<KIND, CL>(P, active, P.x_q, P.x_d, tau, ce, lbox);
+            if (active && lg == 0) {
+                if (free_edge) {
+                    st[v] = (unsigned char)(S_OPEN | (st[v] & S_GOAL));
+                    w.parent[v] = root;
+                    w.ai[v] = 0;
+                } else {
+                    w.cost[v] = __longlong_as_double(COST_INF_BITS);
+                }
+            }
+        }
+    }
+    team_sync(t);
+    if (t.rank == 0) {
+        ctl->g_cnt = 0;  // first read by the select phase, after the next barrier
+        ctl->c_cnt = 0;
+    }
+    // open set of iteration 1: the root's children
     for (int v = t.rank; v < n; v += t.size) {
         const bool op = (st[v] & S_SET) == S_OPEN;
         wave_count(&ctl->rem_cnt[1], op);
@@ -699,7 +718,17 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
                 const unsigned long long c0 = (t.wave == 0) ? clock_ticks() : 0;
-                const bool free_edge = group_edge_free<KIND, CL>(P, ok, ok ? by : 0, ce, be, lbox);
+                int yq[3] = {0, 0, 0};
+                double ys[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, tau = 0.0;
+                if (ok) {
+                    if (KIND == 0) {
+                        for (int a = 0; a < R.dim; ++a) yq[a] = (int)((double)R.s[(size_t)a * n + by] * GMT_QS);
+                    } else {
+                        sample_d<6>(R, by, ys);
+                        tau = R.in_tau[be];
+                    }
+                }
+                const bool free_edge = group_edge_free<KIND, CL>(P, ok, yq, ys, tau, ce, lbox);
                 if (t.wave == 0) tk_check += clock_ticks() - c0;
                 const bool commit = ok && free_edge && lg == 0;
                 if (active && lg == 0) {

@@ -40,7 +40,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_batch",
            "gmt_last_work", "gmt_profile_enable", "gmt_profile_read",
-           "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_cancel",
+           "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
            "gmt_engine_set_budget", "gmt_engine_get_stats", "gmt_engine_destroy",
            "gmt_batch_prepare", "gmt_batch_run", "gmt_batch_free",
            "gmt_autotune", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
@@ -178,6 +178,7 @@ def lib():
             L.gmt_engine_create.argtypes = [C.POINTER(gmt_engine_opts), C.POINTER(P)]
             L.gmt_engine_submit.argtypes = [P, C.POINTER(gmt_problem), i32, C.POINTER(i64)]
             L.gmt_engine_poll.argtypes = [P, i64, i32, C.POINTER(gmt_result), P, i32]
+            L.gmt_engine_poll_any.argtypes = [P, i32, C.POINTER(i64), C.POINTER(gmt_result), P, i32]
             L.gmt_engine_cancel.argtypes = [P, i64]
             L.gmt_engine_set_budget.argtypes = [P, C.c_size_t]
             L.gmt_engine_get_stats.argtypes = [P, C.POINTER(gmt_engine_stats)]
@@ -607,6 +608,22 @@ class Engine:
         w["submit_ns"], w["done_ns"] = int(r.submit_ns), int(r.done_ns)
         return PlanResult(int(r.status), path[:min(L, path_cap)].copy(), float(r.path_cost),
                           int(r.iters), work=w)
+
+    def poll_any(self, wait_us: int = 0, path_cap: int = 512):
+        """(ticket, PlanResult) of the next finished request, or None."""
+        r = gmt_result()
+        t = C.c_int64()
+        path = np.zeros(path_cap, np.int32)
+        st = lib().gmt_engine_poll_any(self.handle, int(wait_us), C.byref(t), C.byref(r), path.ctypes.data,
+                                       path_cap)
+        if st == GMT_EBUSY:
+            return None
+        _check(st, "gmt_engine_poll_any")
+        L = int(r.path_len) if r.status == GMT_OK else 0
+        w = r.work.as_dict()
+        w["submit_ns"], w["done_ns"] = int(r.submit_ns), int(r.done_ns)
+        return int(t.value), PlanResult(int(r.status), path[:min(L, path_cap)].copy(), float(r.path_cost),
+                                        int(r.iters), work=w)
 
     def cancel(self, ticket: int) -> bool:
         return lib().gmt_engine_cancel(self.handle, int(ticket)) == GMT_OK

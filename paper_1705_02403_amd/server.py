@@ -134,9 +134,16 @@ class ReplanServer:
         t0 = gmt.gmt_steady_ns() + 2_000_000  # start 2 ms from now
         tickets: Dict[int, tuple] = {}
         lock = threading.Lock()
-        submitted = threading.Event()
+
+        errors: List[BaseException] = []
 
         def submitter():
+            try:
+                submit_all()
+            except BaseException as e:  # surfaced by the collector
+                errors.append(e)
+
+        def submit_all():
             for r in reqs:
                 at = t0 + int(r.arrival_s * 1e9) if realtime else t0
                 while True:
@@ -149,37 +156,30 @@ class ReplanServer:
                 tk = self.engine.submit(r.make_query(rm), self.path_cap)
                 with lock:
                     tickets[tk] = (r, at)
-            submitted.set()
 
         th = threading.Thread(target=submitter, daemon=True)
         th.start()
         served: List[Served] = []
         last_done = t0
-        while True:
-            with lock:
-                pending = list(tickets.items())
-            if not pending:
-                if submitted.is_set():
-                    with lock:
-                        if not tickets:
-                            break
-                time.sleep(50e-6)
+        while len(served) < len(reqs):
+            got = self.engine.poll_any(2000, self.path_cap)  # completion order; releases the GIL while waiting
+            if got is None:
+                if errors and not th.is_alive():
+                    raise errors[0]
                 continue
-            progressed = False
-            for tk, (r, at) in pending:
-                res = self.engine.poll(tk, 0, self.path_cap)
-                if res is None:
-                    continue
-                progressed = True
+            tk, res = got
+            while True:  # the submitter records a ticket just after submit returns it
                 with lock:
-                    del tickets[tk]
-                self.cache.release(r.key)
-                done = res.work["done_ns"]
-                last_done = max(last_done, done)
-                served.append(Served(r.tag, res.status, res.path, res.path_cost, (done - at) / 1e6,
-                                     (res.work["submit_ns"] - at) / 1e6))
-            if not progressed:
-                time.sleep(50e-6)
+                    entry = tickets.pop(tk, None)
+                if entry is not None:
+                    break
+                time.sleep(0)
+            r, at = entry
+            self.cache.release(r.key)
+            done = res.work["done_ns"]
+            last_done = max(last_done, done)
+            served.append(Served(r.tag, res.status, res.path, res.path_cost, (done - at) / 1e6,
+                                 (res.work["submit_ns"] - at) / 1e6))
         th.join()
         lat = np.array([s.latency_ms for s in served]) if served else np.zeros(1)
         first = t0
