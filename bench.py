@@ -27,7 +27,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--sample-sets", type=int, default=8)
     ap.add_argument("--latency-samples", type=int, default=200)
@@ -37,8 +37,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--server-requests", type=int, default=4096)
     ap.add_argument("--server-rate", type=float, default=20000.0)
+    ap.add_argument("--server-slots", type=int, default=4)
+    ap.add_argument("--server-max-batch", type=int, default=256)
+    ap.add_argument("--server-threads", type=int, default=0,
+                    help="threads per workgroup for the server's batches (0: library choice)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape instead of tuning it first")
+    ap.add_argument("--lanes", type=int, default=0, help="force lanes per candidate (skips tuning)")
+    ap.add_argument("--threads", type=int, default=0, help="force threads per workgroup (skips tuning)")
     ap.add_argument("--only-throughput", action="store_true",
                     help="time the batches only (for counter runs): no latency, server, build or oracle sections")
     ap.add_argument("--copy-probe", action="store_true",
@@ -201,7 +207,9 @@ def main():
                               gmt.make_goal(p.goal_center, p.goal_radius, 3), p.boxes, p.lam)
 
     queries = [query(p) for p in probs]
-    opts = gmt.make_opts(traj_points=16)
+    opts = gmt.make_opts(traj_points=16, lanes=args.lanes, threads=args.threads)
+    if args.lanes or args.threads:
+        args.no_autotune = True
     # launch shape: the autotuner times every candidate on this batch and on
     # one single query, checks they give identical results, caches the fastest
     tuned = None
@@ -268,14 +276,18 @@ def main():
         reqs = [server.Request(float(t), probs[k % len(probs)].sample_seed,
                                (lambda q: lambda rm: q)(queries[k % len(queries)]), tag=k)
                 for k, t in enumerate(arr)]
-        srv = server.ReplanServer(lambda key: rms[key], opts, engine_budget=8 << 30,
-                                  roadmap_budget=1 << 40, slots=4, max_batch=256)
+        sopts = gmt.make_opts(traj_points=16, threads=args.server_threads)
+        srv = server.ReplanServer(lambda key: rms[key], sopts, engine_budget=8 << 30,
+                                  roadmap_budget=1 << 40, slots=args.server_slots,
+                                  max_batch=args.server_max_batch)
         srv.serve(reqs[:256])  # warm the streams and workspaces
         rep = srv.serve(reqs)
         srv.engine.close()
         by_tag = {s.tag: s for s in rep.served}
         same = sum(by_tag[k].path_cost == out[k % len(out)].path_cost for k in by_tag)
         srv_line = {"arrival_rate_hz": args.server_rate, "requests": len(rep.served),
+                    "slots": args.server_slots, "max_batch": args.server_max_batch,
+                    "threads": args.server_threads,
                     "plans_per_s": round(rep.plans_per_s, 1), "p50_ms": round(rep.p50_ms, 3),
                     "p99_ms": round(rep.p99_ms, 3), "batches": rep.engine.get("batches"),
                     "peak_inflight_requests": rep.engine.get("peak_inflight_requests"),

@@ -92,17 +92,21 @@ typedef struct {
  *  max_iters   cap on the threshold index i of Algorithm 1 (<= 0: none).
  *  team_wgs    workgroups cooperating on one plan (0: library choice: the
  *              autotuned value for the workload's shape if one is cached,
- *              else the whole co-resident grid for gmt_plan and one
- *              workgroup per query for batches).
+ *              else CUs/8 workgroups of 1024 threads (one per CU for smaller
+ *              workgroups) for gmt_plan and one workgroup per query for
+ *              batches).
  *  lanes       lanes per candidate in the parent search: 4, 8, 16 or 32, or
  *              0 (library choice: autotuned if cached, else 16).
- *  Results do not depend on team_wgs or lanes.  */
+ *  threads     threads per workgroup: 256, 512 or 1024, or 0 (library
+ *              choice: autotuned if cached, else 1024).
+ *  Results do not depend on team_wgs, lanes or threads.  */
 typedef struct {
     double edge_step;
     int32_t traj_points;
     int32_t max_iters;
     int32_t team_wgs;
     int32_t lanes;
+    int32_t threads;
 } gmt_plan_opts;
 
 /* Install the device allocator (NULL restores hipMalloc/hipFree).  Affects
@@ -248,7 +252,6 @@ typedef struct {
 typedef struct {
     gmt_plan_opts plan;
     int32_t workgroups;
-    int32_t threads;
 } gmt_batch_opts;
 
 /* Solve `count` independent queries (possibly on different roadmaps, of
@@ -337,8 +340,9 @@ gmt_status gmt_engine_get_stats(gmt_engine_t e, gmt_engine_stats *out);
 gmt_status gmt_engine_destroy(gmt_engine_t e);
 
 /* ---- autotuner ----------------------------------------------------------
- * The launch knobs -- lanes per candidate, workgroups per query (team_wgs)
- * and persistent workgroups per batch -- change speed, never results.  The
+ * The launch knobs -- lanes per candidate, workgroups per query (team_wgs),
+ * threads per workgroup and persistent workgroups per batch -- change speed,
+ * never results.  The
  * tuner times every candidate configuration on a caller-supplied workload,
  * checks that each gives exactly the results of the default configuration
  * (status, iterations, path, path cost bits), and caches the fastest under
@@ -353,7 +357,7 @@ typedef struct {
 } gmt_tune_shape;
 
 typedef struct {
-    int32_t lanes, team_wgs, workgroups; /* the chosen knobs (0: none cached) */
+    int32_t lanes, team_wgs, workgroups, threads; /* the chosen knobs (0: none cached) */
     double ms;           /* median wall time of one call with them */
     double default_ms;   /* the same with the library defaults */
     int32_t candidates;  /* configurations timed (0 for a cache lookup) */

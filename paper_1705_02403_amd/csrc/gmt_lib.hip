@@ -677,6 +677,7 @@ static gmt_plan_opts default_opts(const gmt_plan_opts *o) {
     d.max_iters = 0;
     d.team_wgs = 0;
     d.lanes = 0;
+    d.threads = 0;
     return d;
 }
 
@@ -719,6 +720,10 @@ static const void *plan_kernel(int kind, bool lds_st, int cl) {
 
 static bool lanes_valid(int lanes) { return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32; }
 static int lanes_of(int lanes) { return lanes_valid(lanes) && lanes ? lanes : 16; }
+static bool threads_valid(int t) { return t == 0 || t == 256 || t == 512 || t == 1024; }
+// library default: 1024-thread workgroups (16 waves on one query per CU)
+static const int kDefaultThreads = 1024;
+static int threads_of(int t) { return threads_valid(t) && t ? t : kDefaultThreads; }
 
 // 32-bit words of boxes the plan kernel stages in LDS
 static int plan_box_words(int kind, int words) {
@@ -770,7 +775,7 @@ static gmt_tune_shape tune_shape(const gmt_problem *problems, int count, bool si
 }
 
 static bool tune_choice_valid(const gmt_tune_choice &c) {
-    return lanes_valid(c.lanes) && c.team_wgs >= 0 && c.workgroups >= 0;
+    return lanes_valid(c.lanes) && threads_valid(c.threads) && c.team_wgs >= 0 && c.workgroups >= 0;
 }
 
 // fill the knobs the caller left at 0 from the cache
@@ -787,6 +792,7 @@ static void tune_apply(const gmt_problem *problems, int count, bool single, gmt_
     }
     if (bo.plan.lanes == 0) bo.plan.lanes = c.lanes;
     if (bo.plan.team_wgs == 0) bo.plan.team_wgs = c.team_wgs;
+    if (bo.plan.threads == 0) bo.plan.threads = c.threads;
     if (!single && bo.workgroups == 0) bo.workgroups = c.workgroups;
 }
 
@@ -796,7 +802,7 @@ struct BatchRun {
     WsBlock *w = nullptr;
     std::vector<int> order;  // kernel order -> caller index
     int count = 0, n_euclid = 0, nmax_e = 0, nmax_d = 0;
-    int teams = 1, team_wgs = 1, box_words = 1, cl = 16;
+    int teams = 1, team_wgs = 1, box_words = 1, cl = 16, threads = 256;
     size_t used = 0;
     bool prof = false;
     bool own_all = false;  // tree arrays always in the workspace (prepared batches)
@@ -817,7 +823,7 @@ static void run_release(BatchRun &r) {
 // of one cost kind; queue counter `qslot` of the staging header.  Events e0 /
 // e1 (may be null) bracket the plan kernel.
 static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int nmax,
-                                   int teams, int team_wgs, int box_words_in, int qslot, int cl,
+                                   int teams, int team_wgs, int box_words_in, int qslot, int cl, int threads,
                                    hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
     int box_words = plan_box_words(kind, box_words_in);
     char *sd = (char *)w->stage_d.p;
@@ -829,7 +835,7 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
     const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
     const size_t plds = plan_lds(box_words, nmax, lds_st);
     if (e0) HIPCHK(hipEventRecord(e0, s));
-    dim3 grid(teams * team_wgs), block(256);
+    dim3 grid(teams * team_wgs), block(threads);
     int st_bytes = nmax + 1;
     void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
     if (team_wgs > 1)
@@ -840,9 +846,13 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
     return GMT_OK;
 }
 
-static int max_coop_wgs(size_t lds, int kind, bool lds_st = false, int cl = 16) {
+// default team of a single plan: an eighth of the CUs' worth of 1024-thread
+// workgroups (measured fastest at n = 16384), or one per CU for smaller ones
+static int default_team_wgs(int threads) { return threads >= 1024 ? std::max(1, num_cus() / 8) : num_cus(); }
+
+static int max_coop_wgs(size_t lds, int kind, bool lds_st = false, int cl = 16, int threads = 256) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, lds_st, cl), 256, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, lds_st, cl), threads, lds) != hipSuccess ||
         per < 1)
         per = 1;
     return per * num_cus();
@@ -858,10 +868,11 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true) {
         if (!r.ev[k] && (k == 4 || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
     if (r.n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, r.n_euclid, r.count, r.nmax_e, std::min(r.teams, r.n_euclid),
-                             r.team_wgs, r.box_words, 0, r.cl, r.ev[0], r.ev[1], s));
+                             r.team_wgs, r.box_words, 0, r.cl, r.threads, r.ev[0], r.ev[1], s));
     if (r.count - r.n_euclid > 0)
         TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, r.n_euclid, r.count - r.n_euclid, r.count, r.nmax_d,
-                             std::min(r.teams, r.count - r.n_euclid), r.team_wgs, r.box_words, 1, r.cl, r.ev[2],
+                             std::min(r.teams, r.count - r.n_euclid), r.team_wgs, r.box_words, 1, r.cl, r.threads,
+                             r.ev[2],
                              r.ev[3], s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
     if (events) HIPCHK(hipEventRecord(r.ev[4], s));
@@ -913,6 +924,7 @@ static gmt_status long_path(const int *d_parent, int N, int z, int *path, int ca
 static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_batch_opts &bo_in, bool single,
                               const gmt_result *results, BatchRun &r, hipStream_t s) {
     if (!lanes_valid(bo_in.plan.lanes)) return fail(GMT_EINVAL, "lanes must be 0, 4, 8, 16 or 32");
+    if (!threads_valid(bo_in.plan.threads)) return fail(GMT_EINVAL, "threads must be 0, 256, 512 or 1024");
     if (bo_in.plan.team_wgs < 0 || bo_in.workgroups < 0) return fail(GMT_EINVAL, "negative launch shape");
     gmt_batch_opts bo = bo_in;
     r.count = count;
@@ -948,20 +960,22 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     }
     const int nmax = std::max(r.nmax_e, r.nmax_d);
     const int kind0 = r.nmax_d > 0 ? GMT_COST_DOUBLE_INTEGRATOR : GMT_COST_EUCLIDEAN;
-    if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || (!single && bo.workgroups == 0))
+    if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || bo.plan.threads == 0 || (!single && bo.workgroups == 0))
         tune_apply(problems, count, single, bo);
     r.cl = lanes_of(bo.plan.lanes);
+    r.threads = threads_of(bo.plan.threads);
     if (single) {
         const size_t lds = plan_lds(plan_box_words(kind0, r.box_words), nmax, false);
-        r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : num_cus();
-        r.team_wgs = std::max(1, std::min(r.team_wgs, max_coop_wgs(lds, kind0, false, r.cl)));
+        r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : default_team_wgs(r.threads);
+        r.team_wgs = std::max(1, std::min(r.team_wgs, max_coop_wgs(lds, kind0, false, r.cl, r.threads)));
         r.teams = 1;
     } else {
         r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
         const int pbw = plan_box_words(kind0, r.box_words);
         const bool lds_st = r.team_wgs == 1 && plan_lds(pbw, nmax, true) <= kLdsStateLimit;
         const size_t lds = plan_lds(pbw, nmax, lds_st);
-        const int resident = std::min(max_coop_wgs(lds, 0, lds_st, r.cl), max_coop_wgs(lds, 1, lds_st, r.cl));
+        const int resident = std::min(max_coop_wgs(lds, 0, lds_st, r.cl, r.threads),
+                                      max_coop_wgs(lds, 1, lds_st, r.cl, r.threads));
         int teams = bo.workgroups > 0 ? bo.workgroups / r.team_wgs : resident / r.team_wgs;
         teams = std::max(1, std::min(teams, count));
         if (r.team_wgs > 1) teams = std::max(1, std::min(teams, resident / r.team_wgs));
@@ -1266,41 +1280,55 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
     base.plan = default_opts(opts);
     base.plan.lanes = 16;
     base.plan.team_wgs = 0;
+    base.plan.threads = kDefaultThreads;
     base.workgroups = 0;
     // candidate knobs; the first is the library default
     std::vector<gmt_batch_opts> cands;
     const int lanes[4] = {16, 8, 4, 32};
     const gmt_tune_shape sh = tune_shape(problems, count, single);
+    auto add = [&](int l, int team, int wg, int threads) {
+        for (const gmt_batch_opts &c : cands)
+            if (c.plan.lanes == l && c.plan.team_wgs == team && c.workgroups == wg && c.plan.threads == threads)
+                return;
+        gmt_batch_opts b = base;
+        b.plan.lanes = l;
+        b.plan.team_wgs = team;
+        b.plan.threads = threads;
+        b.workgroups = wg;
+        cands.push_back(b);
+    };
     if (single) {
-        // team sizes up to the co-resident grid
+        // team sizes up to the co-resident grid, for 256- and 1024-thread workgroups
         int bw = 1;
         for (int k = 0; k < count; ++k)
             bw = std::max(bw, problems[k].m * 2 * pdim_of(problems[k].roadmap->kind, problems[k].roadmap->dim));
-        std::vector<int> teams = {num_cus()};
-        for (int t = 32; t < num_cus(); t *= 2) teams.push_back(t);
-        for (int l : lanes) {
-            const int cap = max_coop_wgs(plan_lds(bw, sh.n, false), sh.kind, false, l);
-            for (int t : teams) {
-                gmt_batch_opts b = base;
-                b.plan.lanes = l;
-                b.plan.team_wgs = std::min(t, cap);
-                bool dup = false;
-                for (const gmt_batch_opts &c : cands)
-                    dup |= c.plan.lanes == l && c.plan.team_wgs == b.plan.team_wgs;
-                if (!dup) cands.push_back(b);
+        for (int threads : {256, 1024}) {
+            const int per_cu = 1024 / threads;  // workgroups per CU at the kernel's register budget
+            std::vector<int> teams = {num_cus() * per_cu};
+            for (int t = 8 * per_cu; t < num_cus() * per_cu; t *= 2) teams.push_back(t);
+            if (threads == 1024) teams = {num_cus() / 8, num_cus() / 4, num_cus() / 2, num_cus()};
+            for (int l : lanes) {
+                const int cap = max_coop_wgs(plan_lds(bw, sh.n, false), sh.kind, false, l, threads);
+                for (int t : teams)
+                    if (t >= 1) add(l, std::min(t, cap), 0, threads);
             }
         }
+        // the library default first
+        const int dteam = std::min(default_team_wgs(kDefaultThreads),
+                                   max_coop_wgs(plan_lds(bw, sh.n, false), sh.kind, false, 16, kDefaultThreads));
+        add(16, dteam, 0, kDefaultThreads);
+        for (size_t k = 0; k < cands.size(); ++k)
+            if (cands[k].plan.lanes == 16 && cands[k].plan.team_wgs == dteam && cands[k].plan.threads == kDefaultThreads)
+                std::swap(cands[0], cands[k]);
     } else {
-        const int wgs_half = num_cus() * 2;  // half of the usual co-resident grid
-        for (int l : lanes)
+        const int wgs_half = num_cus() * 2;  // half of the usual co-resident grid of 256-thread workgroups
+        for (int l : lanes) {
+            add(l, 1, 0, 1024);  // the library default (for lanes 16) first
+            add(l, 1, num_cus() / 2, 1024);
+            add(l, 1, 0, 512);
             for (int t : {1, 2, 4})
-                for (int wg : {0, wgs_half}) {
-                    gmt_batch_opts b = base;
-                    b.plan.lanes = l;
-                    b.plan.team_wgs = t;
-                    b.workgroups = wg;
-                    cands.push_back(b);
-                }
+                for (int wg : {0, wgs_half}) add(l, t, wg, 256);
+        }
     }
     TuneRun ref, cur;
     double best_ms = 0.0, default_ms = 0.0;
@@ -1309,8 +1337,9 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
         TRY(tune_call(problems, count, single, cands[c], cur, s));  // untimed: warms workspaces
         if (c == 0) ref = cur;
         else if (!tune_same(ref, cur))
-            return fail(GMT_EDEVICE, "launch configuration lanes=%d team_wgs=%d workgroups=%d changed the results",
-                        cands[c].plan.lanes, cands[c].plan.team_wgs, cands[c].workgroups);
+            return fail(GMT_EDEVICE,
+                        "launch configuration lanes=%d team_wgs=%d threads=%d workgroups=%d changed the results",
+                        cands[c].plan.lanes, cands[c].plan.team_wgs, cands[c].plan.threads, cands[c].workgroups);
         std::vector<double> t(reps);
         for (int k = 0; k < reps; ++k) {
             const int64_t t0 = steady_ns();
@@ -1329,6 +1358,7 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
     ch.lanes = cands[best].plan.lanes;
     ch.team_wgs = cands[best].plan.team_wgs;
     ch.workgroups = cands[best].workgroups;
+    ch.threads = cands[best].plan.threads;
     ch.ms = best_ms;
     ch.default_ms = default_ms;
     ch.candidates = (int)cands.size();
@@ -1372,7 +1402,8 @@ extern "C" gmt_status gmt_tune_clear(void) {
     return GMT_OK;
 }
 
-static const char *kTuneHeader = "# gmt tune v1: kind dim nlog mlog mode blog lanes team_wgs workgroups ms default_ms";
+static const char *kTuneHeader =
+    "# gmt tune v2: kind dim nlog mlog mode blog lanes team_wgs workgroups threads ms default_ms";
 
 extern "C" gmt_status gmt_tune_save(const char *path) {
     if (!path) return fail(GMT_EINVAL, "null path");
@@ -1383,8 +1414,8 @@ extern "C" gmt_status gmt_tune_save(const char *path) {
     for (const auto &kv : g_tune) {
         const TuneKey &k = kv.first;
         const gmt_tune_choice &c = kv.second;
-        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f %.6f\n", k.kind, k.dim, k.nlog, k.mlog, k.mode, k.blog,
-                     c.lanes, c.team_wgs, c.workgroups, c.ms, c.default_ms);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.6f %.6f\n", k.kind, k.dim, k.nlog, k.mlog, k.mode, k.blog,
+                     c.lanes, c.team_wgs, c.workgroups, c.threads, c.ms, c.default_ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? GMT_OK : fail(GMT_EINVAL, "write to %s failed", path);
@@ -1404,13 +1435,13 @@ extern "C" gmt_status gmt_tune_load(const char *path) {
         TuneKey k{};
         gmt_tune_choice c{};
         char tail = 0;
-        const int got_n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %lf %lf %c", &k.kind, &k.dim, &k.nlog, &k.mlog,
-                                      &k.mode, &k.blog, &c.lanes, &c.team_wgs, &c.workgroups, &c.ms, &c.default_ms,
-                                      &tail);
+        const int got_n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %lf %lf %c", &k.kind, &k.dim, &k.nlog,
+                                      &k.mlog, &k.mode, &k.blog, &c.lanes, &c.team_wgs, &c.workgroups, &c.threads,
+                                      &c.ms, &c.default_ms, &tail);
         const bool key_ok = (k.kind == GMT_COST_EUCLIDEAN || k.kind == GMT_COST_DOUBLE_INTEGRATOR) && k.dim >= 1 &&
                             k.dim <= GMT_MAX_DIM && k.nlog >= 0 && k.nlog <= 31 && k.mlog >= 0 && k.mlog <= 31 &&
                             (k.mode == 0 || k.mode == 1) && k.blog >= 0 && k.blog <= 31;
-        if (got_n != 11 || !key_ok || !tune_choice_valid(c)) {
+        if (got_n != 12 || !key_ok || !tune_choice_valid(c)) {
             st = fail(GMT_EINVAL, "%s:%d: malformed tune line", path, lineno);
             break;
         }

@@ -821,13 +821,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // the dynamic region is 16-byte aligned (it follows the static s_job), which
 // the 64-bit counter fields require.
 // ---------------------------------------------------------------------------
-// workgroups per CU the register allocation is sized for
-#ifndef GMT_PLAN_OCC
-#define GMT_PLAN_OCC 4
-#endif
-
+// Workgroups of 256, 512 or 1024 threads; registers are sized for 16 waves
+// per CU (four 256-thread workgroups or one of 1024 threads).
 template <int KIND, bool LDS, int CL>
-__global__ void __launch_bounds__(256, GMT_PLAN_OCC) k_plan(const ProbDev *__restrict__ probs, int count,
+__global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
                                               int team_wgs, Result *__restrict__ res) {

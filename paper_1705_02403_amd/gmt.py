@@ -88,7 +88,7 @@ class gmt_goal(C.Structure):
 
 class gmt_plan_opts(C.Structure):
     _fields_ = [("edge_step", C.c_double), ("traj_points", C.c_int32), ("max_iters", C.c_int32),
-                ("team_wgs", C.c_int32), ("lanes", C.c_int32)]
+                ("team_wgs", C.c_int32), ("lanes", C.c_int32), ("threads", C.c_int32)]
 
 
 class gmt_problem(C.Structure):
@@ -115,7 +115,7 @@ class gmt_result(C.Structure):
 
 
 class gmt_batch_opts(C.Structure):
-    _fields_ = [("plan", gmt_plan_opts), ("workgroups", C.c_int32), ("threads", C.c_int32)]
+    _fields_ = [("plan", gmt_plan_opts), ("workgroups", C.c_int32)]
 
 
 class gmt_engine_opts(C.Structure):
@@ -144,7 +144,8 @@ class gmt_tune_shape(C.Structure):
 
 class gmt_tune_choice(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("team_wgs", C.c_int32), ("workgroups", C.c_int32),
-                ("ms", C.c_double), ("default_ms", C.c_double), ("candidates", C.c_int32)]
+                ("threads", C.c_int32), ("ms", C.c_double), ("default_ms", C.c_double),
+                ("candidates", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -375,9 +376,9 @@ def make_goal(center: Sequence[float], radius: float, ndims: int) -> gmt_goal:
 
 
 def make_opts(edge_step: float = 0.0, traj_points: int = 16, max_iters: int = 0,
-              team_wgs: int = 0, lanes: int = 0) -> gmt_plan_opts:
+              team_wgs: int = 0, lanes: int = 0, threads: int = 0) -> gmt_plan_opts:
     return gmt_plan_opts(float(edge_step), int(traj_points), int(max_iters), int(team_wgs),
-                         int(lanes))
+                         int(lanes), int(threads))
 
 
 def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_plan_opts,
@@ -460,7 +461,7 @@ class PreparedBatch:
                 self.res[j].d_parent, self.res[j].d_cost = o[0].data_ptr(), o[1].data_ptr()
                 self.res[j].d_group_iter, self.res[j].d_added_iter = o[2].data_ptr(), o[3].data_ptr()
             self.outs.append(o)
-        self.bo = gmt_batch_opts(opts, int(workgroups), 0)
+        self.bo = gmt_batch_opts(opts, int(workgroups))
         self.path_cap = path_cap
 
     def run(self, stream=None) -> None:
@@ -542,8 +543,9 @@ def gmt_tune_lookup(shape: gmt_tune_shape) -> dict:
     return out.as_dict()
 
 
-def gmt_tune_store(shape: gmt_tune_shape, lanes: int, team_wgs: int, workgroups: int = 0) -> None:
-    c = gmt_tune_choice(int(lanes), int(team_wgs), int(workgroups), 0.0, 0.0, 0)
+def gmt_tune_store(shape: gmt_tune_shape, lanes: int, team_wgs: int, workgroups: int = 0,
+                   threads: int = 256) -> None:
+    c = gmt_tune_choice(int(lanes), int(team_wgs), int(workgroups), int(threads), 0.0, 0.0, 0)
     _check(lib().gmt_tune_store(C.byref(shape), C.byref(c)), "gmt_tune_store")
 
 

@@ -150,13 +150,15 @@ def test_plan_3d_full_size_bit_exact(seed):
     rm.free()
 
 
-@pytest.mark.parametrize("team_wgs", [1, 3, 16, 0])
-def test_launch_shape_does_not_change_results(team_wgs):
-    say("team shape %d" % team_wgs)
+@pytest.mark.parametrize("team_wgs,threads", [(1, 256), (3, 256), (16, 256), (0, 0), (1, 1024), (4, 512),
+                                              (8, 1024)])
+def test_launch_shape_does_not_change_results(team_wgs, threads):
+    say("team shape %d x %d threads" % (team_wgs, threads))
     prob = I.problem_2d(7, lam=0.5)
     r = O.euclid_radius(prob)
     rm = build(prob, r)
-    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5, opts_of(prob, team_wgs=team_wgs))
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5,
+                       opts_of(prob, team_wgs=team_wgs, threads=threads))
     compare_tree(res, O.plan(prob, r))
     rm.free()
 

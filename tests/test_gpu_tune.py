@@ -48,10 +48,12 @@ def test_batch_tuning_keeps_results(setup):
     opts = gmt.make_opts(edge_step=0.005)
     ref = gmt.gmt_plan_batch(qs, gmt.make_opts(edge_step=0.005, lanes=16, team_wgs=1))
     ch = gmt.gmt_autotune(qs, opts, single=False, reps=1)
-    assert ch["candidates"] == 24 and ch["lanes"] in (4, 8, 16, 32) and ch["team_wgs"] in (1, 2, 4)
+    assert ch["candidates"] == 36 and ch["lanes"] in (4, 8, 16, 32) and ch["team_wgs"] in (1, 2, 4)
+    assert ch["threads"] in (256, 512, 1024)
     assert ch["ms"] <= ch["default_ms"]
     hit = gmt.gmt_tune_lookup(gmt.tune_shape(gmt.GMT_COST_EUCLIDEAN, 2, 2000, 20, 8))
-    assert (hit["lanes"], hit["team_wgs"], hit["workgroups"]) == (ch["lanes"], ch["team_wgs"], ch["workgroups"])
+    assert (hit["lanes"], hit["team_wgs"], hit["workgroups"], hit["threads"]) == \
+        (ch["lanes"], ch["team_wgs"], ch["workgroups"], ch["threads"])
     got = gmt.gmt_plan_batch(qs, opts)  # knobs at 0: the tuned choice
     for a, b in zip(got, ref):
         assert a.status == b.status and a.path_cost == b.path_cost and list(a.path) == list(b.path)
@@ -68,8 +70,8 @@ def test_single_tuning_double_integrator(setup):
     q = gmt.BatchQuery(rm, p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, 3), p.boxes, p.lam)
     opts = gmt.make_opts(traj_points=16)
     ch = gmt.gmt_autotune([q], opts, single=True, reps=1)
-    assert ch["candidates"] >= 8 and ch["lanes"] in (4, 8, 16, 32) and ch["team_wgs"] >= 1
-    alone = gmt.gmt_plan(rm, p.x_init, q.goal, p.boxes, p.lam, gmt.make_opts(traj_points=16, lanes=16),
+    assert ch["candidates"] >= 16 and ch["lanes"] in (4, 8, 16, 32) and ch["team_wgs"] >= 1
+    alone = gmt.gmt_plan(rm, p.x_init, q.goal, p.boxes, p.lam, gmt.make_opts(traj_points=16, lanes=16, threads=256),
                          outputs=False)
     tuned = gmt.gmt_plan(rm, p.x_init, q.goal, p.boxes, p.lam, opts, outputs=False)
     assert tuned.status == alone.status and tuned.path_cost == alone.path_cost

@@ -15,10 +15,10 @@ def clean_cache():
 
 
 def test_store_lookup_by_bucket():
-    gmt.gmt_tune_store(gmt.tune_shape(DI, 6, 16384, 40, 1024), lanes=8, team_wgs=2, workgroups=512)
+    gmt.gmt_tune_store(gmt.tune_shape(DI, 6, 16384, 40, 1024), lanes=8, team_wgs=2, workgroups=512, threads=512)
     # same bucket: n in (8192, 16384], m in [32, 63], batch in (512, 1024]
     hit = gmt.gmt_tune_lookup(gmt.tune_shape(DI, 6, 9000, 33, 600))
-    assert (hit["lanes"], hit["team_wgs"], hit["workgroups"]) == (8, 2, 512)
+    assert (hit["lanes"], hit["team_wgs"], hit["workgroups"], hit["threads"]) == (8, 2, 512, 512)
     for other in [gmt.tune_shape(DI, 6, 16385, 40, 1024),   # next n bucket
                   gmt.tune_shape(DI, 6, 16384, 64, 1024),   # next m bucket
                   gmt.tune_shape(DI, 6, 16384, 40, 0),      # single-plan mode
@@ -30,7 +30,7 @@ def test_store_lookup_by_bucket():
 def test_save_load_round_trip(tmp_path):
     a = gmt.tune_shape(E, 2, 2000, 20, 0)
     b = gmt.tune_shape(DI, 6, 16384, 40, 256)
-    gmt.gmt_tune_store(a, 32, 128)
+    gmt.gmt_tune_store(a, 32, 128, threads=1024)
     gmt.gmt_tune_store(b, 4, 1, 0)
     f = tmp_path / "tune.txt"
     gmt.gmt_tune_save(str(f))
@@ -38,18 +38,20 @@ def test_save_load_round_trip(tmp_path):
     assert gmt.gmt_tune_lookup(a)["lanes"] == 0
     gmt.gmt_tune_load(str(f))
     assert (gmt.gmt_tune_lookup(a)["lanes"], gmt.gmt_tune_lookup(a)["team_wgs"]) == (32, 128)
+    assert gmt.gmt_tune_lookup(a)["threads"] == 1024
     assert gmt.gmt_tune_lookup(b)["lanes"] == 4
 
 
 @pytest.mark.parametrize("line", [
-    "0 2 11 5 0 0 12 64 0 1.0 1.0",      # lanes 12 is not a kernel variant
-    "0 2 11 5 0 0 16 64 0 1.0",          # missing field
-    "7 2 11 5 0 0 16 64 0 1.0 1.0",      # unknown cost kind
-    "0 2 11 5 0 0 16 -1 0 1.0 1.0",      # negative team size
-    "0 2 11 5 0 0 16 64 0 1.0 1.0 x",    # trailing text
+    "0 2 11 5 0 0 12 64 0 256 1.0 1.0",      # lanes 12 is not a kernel variant
+    "0 2 11 5 0 0 16 64 0 256 1.0",          # missing field
+    "7 2 11 5 0 0 16 64 0 256 1.0 1.0",      # unknown cost kind
+    "0 2 11 5 0 0 16 -1 0 256 1.0 1.0",      # negative team size
+    "0 2 11 5 0 0 16 64 0 300 1.0 1.0",      # no 300-thread workgroups
+    "0 2 11 5 0 0 16 64 0 256 1.0 1.0 x",    # trailing text
 ])
 def test_malformed_file_loads_nothing(tmp_path, line):
-    good = "0 2 11 5 0 0 16 64 0 1.0 1.0"
+    good = "0 2 11 5 0 0 16 64 0 256 1.0 1.0"
     f = tmp_path / "bad.txt"
     f.write_text("# header\n" + good.replace(" 2 11", " 3 11") + "\n" + line + "\n")
     with pytest.raises(gmt.GmtError):
