@@ -693,17 +693,39 @@ static int num_cus() {
     return g_num_cu;
 }
 
-// LDS bytes of the plan kernel: boxes, plus the state bytes and counters
-// when kept in LDS
-static size_t plan_lds(int box_words, int nmax, bool lds_st) {
+// LDS bytes of the plan kernel: boxes, plus for level >= 1 the state bytes
+// and counters, plus for level 2 the costs-to-come
+static size_t plan_lds(int box_words, int nmax, int level) {
     size_t b = (size_t)((std::max(box_words, 1) + 3) & ~3) * sizeof(int);
-    if (lds_st) b += (size_t)((nmax + 1 + 15) & ~15) + sizeof(Ctl);
+    if (level >= 1) b += (size_t)((nmax + 1 + 15) & ~15) + ((sizeof(Ctl) + 15) & ~(size_t)15);
+    if (level >= 2) b += 8 * (size_t)(nmax + 1);
     return b;
 }
 
 static const size_t kLdsStateLimit = 48 * 1024;
 
-template <int K, bool L>
+static size_t g_lds_max = 0;
+static size_t lds_max() {
+    if (g_lds_max == 0) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        g_lds_max = (size_t)v;
+    }
+    return g_lds_max;
+}
+
+// Where a query's state lives (see run_query): level 2 (costs in LDS too) for
+// one 1024-thread workgroup per query when it fits, level 1 for other
+// one-workgroup teams up to kLdsStateLimit, else global memory.
+static int plan_level(int team_wgs, int threads, int box_words, int nmax) {
+    if (team_wgs != 1) return 0;
+    if (threads == 1024 && plan_lds(box_words, nmax, 2) <= lds_max()) return 2;
+    return plan_lds(box_words, nmax, 1) <= kLdsStateLimit ? 1 : 0;
+}
+
+template <int K, int L>
 static const void *plan_kernel_cl(int cl) {
     switch (cl) {
     case 4: return (const void *)k_plan<K, L, 4>;
@@ -713,9 +735,13 @@ static const void *plan_kernel_cl(int cl) {
     }
 }
 
-static const void *plan_kernel(int kind, bool lds_st, int cl) {
-    if (kind == GMT_COST_EUCLIDEAN) return lds_st ? plan_kernel_cl<0, true>(cl) : plan_kernel_cl<0, false>(cl);
-    return lds_st ? plan_kernel_cl<1, true>(cl) : plan_kernel_cl<1, false>(cl);
+template <int K>
+static const void *plan_kernel_k(int level, int cl) {
+    return level == 2 ? plan_kernel_cl<K, 2>(cl) : level == 1 ? plan_kernel_cl<K, 1>(cl) : plan_kernel_cl<K, 0>(cl);
+}
+
+static const void *plan_kernel(int kind, int level, int cl) {
+    return kind == GMT_COST_EUCLIDEAN ? plan_kernel_k<0>(level, cl) : plan_kernel_k<1>(level, cl);
 }
 
 static bool lanes_valid(int lanes) { return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32; }
@@ -832,16 +858,18 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
     const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
     TeamCtl *tctl = (TeamCtl *)w->tctl.p;
     Result *res = (Result *)w->res_d.p + first;
-    const bool lds_st = team_wgs == 1 && plan_lds(box_words, nmax, true) <= kLdsStateLimit;
-    const size_t plds = plan_lds(box_words, nmax, lds_st);
+    const int level = plan_level(team_wgs, threads, box_words, nmax);
+    const size_t plds = plan_lds(box_words, nmax, level);
+    if (plds > 64 * 1024)
+        (void)hipFuncSetAttribute(plan_kernel(kind, level, cl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
     if (e0) HIPCHK(hipEventRecord(e0, s));
     dim3 grid(teams * team_wgs), block(threads);
     int st_bytes = nmax + 1;
     void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
     if (team_wgs > 1)
-        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, false, cl), grid, block, args, (unsigned)plds, s));
+        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, 0, cl), grid, block, args, (unsigned)plds, s));
     else
-        HIPCHK(hipLaunchKernel(plan_kernel(kind, lds_st, cl), grid, block, args, plds, s));
+        HIPCHK(hipLaunchKernel(plan_kernel(kind, level, cl), grid, block, args, plds, s));
     if (e1) HIPCHK(hipEventRecord(e1, s));
     return GMT_OK;
 }
@@ -850,9 +878,9 @@ static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, i
 // workgroups (measured fastest at n = 16384), or one per CU for smaller ones
 static int default_team_wgs(int threads) { return threads >= 1024 ? std::max(1, num_cus() / 8) : num_cus(); }
 
-static int max_coop_wgs(size_t lds, int kind, bool lds_st = false, int cl = 16, int threads = 256) {
+static int max_coop_wgs(size_t lds, int kind, int level = 0, int cl = 16, int threads = 256) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, lds_st, cl), threads, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, level, cl), threads, lds) != hipSuccess ||
         per < 1)
         per = 1;
     return per * num_cus();
@@ -965,17 +993,17 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     r.cl = lanes_of(bo.plan.lanes);
     r.threads = threads_of(bo.plan.threads);
     if (single) {
-        const size_t lds = plan_lds(plan_box_words(kind0, r.box_words), nmax, false);
+        const size_t lds = plan_lds(plan_box_words(kind0, r.box_words), nmax, 0);
         r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : default_team_wgs(r.threads);
-        r.team_wgs = std::max(1, std::min(r.team_wgs, max_coop_wgs(lds, kind0, false, r.cl, r.threads)));
+        r.team_wgs = std::max(1, std::min(r.team_wgs, max_coop_wgs(lds, kind0, 0, r.cl, r.threads)));
         r.teams = 1;
     } else {
         r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
         const int pbw = plan_box_words(kind0, r.box_words);
-        const bool lds_st = r.team_wgs == 1 && plan_lds(pbw, nmax, true) <= kLdsStateLimit;
-        const size_t lds = plan_lds(pbw, nmax, lds_st);
-        const int resident = std::min(max_coop_wgs(lds, 0, lds_st, r.cl, r.threads),
-                                      max_coop_wgs(lds, 1, lds_st, r.cl, r.threads));
+        const int level = plan_level(r.team_wgs, r.threads, pbw, nmax);
+        const size_t lds = plan_lds(pbw, nmax, level);
+        const int resident = std::min(max_coop_wgs(lds, 0, level, r.cl, r.threads),
+                                      max_coop_wgs(lds, 1, level, r.cl, r.threads));
         int teams = bo.workgroups > 0 ? bo.workgroups / r.team_wgs : resident / r.team_wgs;
         teams = std::max(1, std::min(teams, count));
         if (r.team_wgs > 1) teams = std::max(1, std::min(teams, resident / r.team_wgs));
@@ -1308,14 +1336,14 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
             for (int t = 8 * per_cu; t < num_cus() * per_cu; t *= 2) teams.push_back(t);
             if (threads == 1024) teams = {num_cus() / 8, num_cus() / 4, num_cus() / 2, num_cus()};
             for (int l : lanes) {
-                const int cap = max_coop_wgs(plan_lds(bw, sh.n, false), sh.kind, false, l, threads);
+                const int cap = max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, l, threads);
                 for (int t : teams)
                     if (t >= 1) add(l, std::min(t, cap), 0, threads);
             }
         }
         // the library default first
         const int dteam = std::min(default_team_wgs(kDefaultThreads),
-                                   max_coop_wgs(plan_lds(bw, sh.n, false), sh.kind, false, 16, kDefaultThreads));
+                                   max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, 16, kDefaultThreads));
         add(16, dteam, 0, kDefaultThreads);
         for (size_t k = 0; k < cands.size(); ++k)
             if (cands[k].plan.lanes == 16 && cands[k].plan.team_wgs == dteam && cands[k].plan.threads == kDefaultThreads)

@@ -420,17 +420,23 @@ __device__ __forceinline__ void wave_count(int *counter, bool pred) {
 
 __device__ __forceinline__ unsigned long long clock_ticks() { return wall_clock64(); }
 
-// LDS: node state bytes and counters live in this workgroup's LDS
-// (one-workgroup teams); otherwise in global memory, shared by the team.
+// LDS (placement of the per-query state; levels 1 and 2 need a
+// one-workgroup team):
+//   0: node state bytes, counters and costs-to-come in global memory, shared
+//      by the team;
+//   1: state bytes and counters in this workgroup's LDS;
+//   2: also the costs-to-come, copied out to the tree output at the end --
+//      every cost gather of the parent search is then an LDS read.
 // CL: lanes per candidate in the connect phase.
-template <int KIND, bool LDS, int CL>
+template <int KIND, int LDS, int CL>
 __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsigned char *lst, Ctl *lctl,
-                          Result *res) {
+                          double *lcost, Result *res) {
     const RoadmapDev &R = P.rm;
     const QWs &w = P.w;
     const int n = R.n, N = n + 1, root = n;
     unsigned char *st = LDS ? lst : w.st;
     Ctl *ctl = LDS ? lctl : w.ctl;
+    double *cost = (LDS >= 2) ? lcost : w.cost;
     unsigned long long w_out = 0, w_in = 0, w_cand = 0, w_commit = 0, w_open = 0, w_iters = 0;
     unsigned long long tk_setup = 0, tk_select = 0, tk_frontier = 0, tk_connect = 0, tk_check = 0;
     unsigned long long tk = (t.rank == 0) ? clock_ticks() : 0;
@@ -460,7 +466,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         bool cand = false;
         if (v == root) {
             st[v] = (unsigned char)(S_CLOSED | (in_goal_q(P.x_q, P) ? S_GOAL : 0));
-            w.cost[v] = 0.0;
+            cost[v] = 0.0;
             w.parent[v] = -1;
             w.gi[v] = 0;
             w.ai[v] = -1;
@@ -470,7 +476,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             bool dead = false;
             for (int b = 0; b < P.m && !dead; ++b) dead = in_staged_box<KIND>(q, lbox, b, P.pd);
             st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
-            w.cost[v] = __longlong_as_double(COST_INF_BITS);
+            cost[v] = __longlong_as_double(COST_INF_BITS);
             w.parent[v] = -1;
             w.gi[v] = -1;
             w.ai[v] = -2;
@@ -509,14 +515,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         const long long dd = (long long)((double)R.s[(size_t)a * n + v] * GMT_QS) - P.x_q[a];
                         d2 += dd * dd;
                     }
-                    w.cost[v] = sqrt((double)d2) * GMT_INV_QS;
+                    cost[v] = sqrt((double)d2) * GMT_INV_QS;
                     ok = true;
                 } else {
                     double J = 0.0, tau = 0.0;
                     root_edge_cost(P, v, J, tau);
                     ok = J < R.r;
                     if (ok) {
-                        w.cost[v] = J;
+                        cost[v] = J;
                         w.aux[v] = tau;
                     }
                 }
@@ -546,7 +552,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     w.parent[v] = root;
                     w.ai[v] = 0;
                 } else {
-                    w.cost[v] = __longlong_as_double(COST_INF_BITS);
+                    cost[v] = __longlong_as_double(COST_INF_BITS);
                 }
             }
         }
@@ -560,7 +566,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     for (int v = t.rank; v < n; v += t.size) {
         const bool op = (st[v] & S_SET) == S_OPEN;
         wave_count(&ctl->rem_cnt[1], op);
-        if (op) atomic_min_cost(&ctl->min_bits[1], w.cost[v]);
+        if (op) atomic_min_cost(&ctl->min_bits[1], cost[v]);
     }
     team_sync(t);
 
@@ -628,7 +634,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             if (set == S_GROUP) {
                 st[v] = (unsigned char)(S_CLOSED | goal);
             } else if (set == S_OPEN || set == S_NEW) {
-                c = w.cost[v];
+                c = cost[v];
                 in_g = c <= thr;
                 rem = !in_g;
                 st[v] = (unsigned char)((in_g ? S_GROUP : S_OPEN) | goal);
@@ -693,7 +699,6 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             constexpr int per_wave = GMT_WAVE / CL;
             const int *__restrict__ in_col = R.in_col;
             const double *__restrict__ in_cost = R.in_cost;
-            const double *__restrict__ cost = w.cost;
             const int stride = t.nwaves * per_wave;
             // the next round's candidate entry is loaded one round ahead
             int4 ent_next = (t.wave * per_wave + sub < cc) ? w.clist[t.wave * per_wave + sub] : make_int4(0, 0, 0, 0);
@@ -713,7 +718,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    scan_row<CL, !LDS>(st, cost, in_col, in_cost, x, ib, ie, lg, best, by, be);
+                    scan_row<CL, LDS == 0>(st, cost, in_col, in_cost, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
@@ -737,7 +742,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     st[x] = (unsigned char)((commit ? S_NEW : S_UNEXPLORED) | goal);
                 }
                 if (commit) {
-                    w.cost[x] = best;
+                    cost[x] = best;
                     w.parent[x] = by;
                     w.ai[x] = ii;
                     ++w_commit;
@@ -775,14 +780,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 const int hc = ld_cnt(&ctl->hit_cnt[hit_parity]);
                 for (int k = 0; k < hc; ++k) {
                     int v = w.hits[k];
-                    double c = w.cost[v];
+                    double c = cost[v];
                     if (z < 0 || c < pc || (c == pc && v < z)) {
                         z = v;
                         pc = c;
                     }
                 }
             }
-            pc = w.cost[z];
+            pc = cost[z];
             for (int v = z; v >= 0 && plen <= N; v = w.parent[v]) ++plen;
             int pos = plen - 1;
             for (int v = z; v >= 0 && pos >= 0; v = w.parent[v], --pos)
@@ -810,6 +815,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             if (t.lane == 0 && v) atomicAdd(&res->work[k], v);
         }
     }
+    if (LDS >= 2) {
+        team_sync(t);  // the path walk above has read the costs
+        for (int v = t.rank; v < N; v += t.size) w.cost[v] = cost[v];
+    }
     team_sync(t);
 }
 
@@ -817,13 +826,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // persistent kernel: teams of `team_wgs` workgroups pull queries of one
 // cost kind (KIND 0 Euclidean, 1 double integrator).  LDS holds the query's
 // boxes (box_words 32-bit words: grid integers for KIND 0, exact floats for
-// KIND 1) and, for LDS, its node state bytes and counters;
+// KIND 1), for LDS >= 1 its node state bytes and counters, and for LDS 2 its
+// costs-to-come;
 // the dynamic region is 16-byte aligned (it follows the static s_job), which
 // the 64-bit counter fields require.
 // ---------------------------------------------------------------------------
 // Workgroups of 256, 512 or 1024 threads; registers are sized for 16 waves
 // per CU (four 256-thread workgroups or one of 1024 threads).
-template <int KIND, bool LDS, int CL>
+template <int KIND, int LDS, int CL>
 __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
@@ -832,6 +842,7 @@ __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ pr
     __shared__ int s_job;
     unsigned char *lst = (unsigned char *)(lbox + ((box_words + 3) & ~3));
     Ctl *lctl = (Ctl *)(lst + ((st_bytes + 15) & ~15));
+    double *lcost = (double *)((char *)lctl + ((sizeof(Ctl) + 15) & ~15));
     Team t;
     const int team = blockIdx.x / team_wgs;
     const int wg = blockIdx.x % team_wgs;
@@ -870,7 +881,7 @@ __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ pr
                 fbox[k] = (float)((double)boxes[P.box_off + k] * GMT_INV_QS);
         }
         __syncthreads();
-        run_query<KIND, LDS, CL>(t, P, lbox, lst, lctl, res + job);
+        run_query<KIND, LDS, CL>(t, P, lbox, lst, lctl, lcost, res + job);
         if (t.nwg > 1 && ld_acquire(t.abort)) return;
     }
 }
