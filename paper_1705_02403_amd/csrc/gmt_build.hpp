@@ -88,6 +88,18 @@ __global__ void k_check_samples(const float *__restrict__ s, int n, int dim, int
     if (bad) atomicOr(&flags[0], 1);
 }
 
+// in-table records for the parent search: (column, edge cost) as three
+// 32-bit words per edge, so one load brings both
+__global__ void k_pack_rec(long long E, const int *__restrict__ col, const double *__restrict__ cost,
+                           unsigned int *__restrict__ rec) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(cost[e]);
+    rec[3 * e] = (unsigned int)col[e];
+    rec[3 * e + 1] = (unsigned int)(b & 0xffffffffull);
+    rec[3 * e + 2] = (unsigned int)(b >> 32);
+}
+
 // ---------------------------------------------------------------------------
 // Euclidean table
 // ---------------------------------------------------------------------------

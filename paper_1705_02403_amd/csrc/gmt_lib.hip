@@ -162,6 +162,7 @@ struct gmt_roadmap {
     double r = 0.0;
     long long nnz = 0;
     DevBuf s, in_ptr, in_col, in_cost, in_tau, out_ptr, out_col;
+    DevBuf in_rec;  // (column, edge cost) records of the in-table, 12 bytes per edge
     bool out_shared = false;
 };
 
@@ -191,6 +192,7 @@ static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
     dev_free(rm->in_col, s);
     dev_free(rm->in_cost, s);
     dev_free(rm->in_tau, s);
+    dev_free(rm->in_rec, s);
     if (!rm->out_shared) {
         dev_free(rm->out_ptr, s);
         dev_free(rm->out_col, s);
@@ -230,6 +232,17 @@ static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
     dev_free(cursor, s);
     dev_free(flags, s);
     if (hf) return fail(GMT_EINVAL, "a node has more than 4096 out-neighbours: radius too large");
+    return GMT_OK;
+}
+
+// records of the finished in-table (column, edge cost)
+static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
+    const long long E = rm->nnz;
+    TRY(dev_alloc(rm->in_rec, 12 * (size_t)std::max<long long>(E, 1), s));
+    if (E > 0)
+        k_pack_rec<<<blocks_for(E, 256), 256, 0, s>>>(E, (const int *)rm->in_col.p, (const double *)rm->in_cost.p,
+                                                      (unsigned int *)rm->in_rec.p);
+    HIPCHK(hipGetLastError());
     return GMT_OK;
 }
 
@@ -306,7 +319,7 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     rm->out_ptr = rm->in_ptr;
     rm->out_col = rm->in_col;
     rm->out_shared = true;
-    return GMT_OK;
+    return pack_records(rm, s);
 }
 
 static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
@@ -348,6 +361,7 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     }
     dev_free(deg, s);
     if (st == GMT_OK) st = build_out_table(rm, s);
+    if (st == GMT_OK) st = pack_records(rm, s);
     dev_free(scal, s);
     return st;
 }
@@ -430,6 +444,7 @@ extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int3
     (void)e1;
     if (kind == GMT_COST_DOUBLE_INTEGRATOR) up(rm->in_tau, tau, sizeof(double) * rm->nnz);
     if (st == GMT_OK) st = build_out_table(rm, s);
+    if (st == GMT_OK) st = pack_records(rm, s);
     if (st != GMT_OK) {
         (void)hipStreamSynchronize(s);
         roadmap_release(rm, s);
@@ -618,8 +633,7 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
     P.rm.R2 = rm->r * rm->r * GMT_Q2;
     P.rm.s = (const float *)rm->s.p;
     P.rm.in_ptr = (const int *)rm->in_ptr.p;
-    P.rm.in_col = (const int *)rm->in_col.p;
-    P.rm.in_cost = (const double *)rm->in_cost.p;
+    P.rm.in_rec = (const unsigned int *)rm->in_rec.p;
     P.rm.in_tau = (const double *)rm->in_tau.p;
     P.rm.out_ptr = (const int *)rm->out_ptr.p;
     P.rm.out_col = (const int *)rm->out_col.p;

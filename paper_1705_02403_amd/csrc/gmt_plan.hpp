@@ -60,8 +60,7 @@ struct RoadmapDev {
     double r, R2;
     const float *s;  // SoA [dim][n]
     const int *in_ptr;
-    const int *in_col;
-    const double *in_cost;
+    const unsigned int *in_rec;  // per in-edge: column, edge cost (low, high words)
     const double *in_tau;  // double integrator only
     const int *out_ptr;
     const int *out_col;
@@ -355,11 +354,11 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 
 // Scan the in-row [ib, ie) of candidate x with the CL lanes of a group for
 // the lexicographic minimum of (cost[y] + c(y, x), y) over open y.  Loads are
-// issued in stages of SCAN_U edges per lane -- indices, then state bytes,
-// then both costs -- so a lane keeps SCAN_U independent loads in flight per
-// stage instead of one dependent chain per edge.  Lanes whose edge is absent
-// or not open read fixed valid addresses (in_col[ib], cost[x], in_cost[ib])
-// and ignore the values.
+// issued in stages of SCAN_U edges per lane -- the (column, edge cost)
+// records, then the state bytes, then the costs-to-come -- so a lane keeps
+// SCAN_U independent loads in flight per stage instead of one dependent
+// chain per edge.  Lanes whose edge is absent or not open read a fixed valid
+// address (cost[x]) and ignore the value.
 //
 // EAGER (state bytes in global memory): the costs are loaded together with
 // the state bytes rather than after them, one dependent round trip fewer;
@@ -368,33 +367,31 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 #define SCAN_U 8
 template <int CL, bool EAGER>
 __device__ __forceinline__ void scan_row(const unsigned char *st, const double *__restrict__ cost,
-                                         const int *__restrict__ in_col, const double *__restrict__ in_cost,
-                                         int x, int ib, int ie, int lg, double &best, int &by, int &be) {
+                                         const unsigned int *__restrict__ rec, int x, int ib, int ie, int lg,
+                                         double &best, int &by, int &be) {
     for (int f0 = ib + lg; f0 < ie; f0 += SCAN_U * CL) {
         int y[SCAN_U];
         bool op[SCAN_U];
+        double ic[SCAN_U];
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
             const int f = f0 + u * CL;
-            y[u] = in_col[f < ie ? f : ib];
+            const unsigned int *r = rec + 3 * (size_t)(f < ie ? f : ib);
+            y[u] = (int)r[0];
+            ic[u] = __hiloint2double((int)r[2], (int)r[1]);
         }
-        double c[SCAN_U], ic[SCAN_U];
+        double c[SCAN_U];
         if (EAGER) {
 #pragma unroll
             for (int u = 0; u < SCAN_U; ++u) {
-                const bool in_row = f0 + u * CL < ie;
                 c[u] = cost[y[u]];
-                ic[u] = in_cost[in_row ? f0 + u * CL : ib];
-                op[u] = in_row && ((st[y[u]] & 3) == 1);
+                op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
             }
         } else {
 #pragma unroll
             for (int u = 0; u < SCAN_U; ++u) op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
 #pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) {
-                c[u] = cost[op[u] ? y[u] : x];
-                ic[u] = in_cost[op[u] ? f0 + u * CL : ib];
-            }
+            for (int u = 0; u < SCAN_U; ++u) c[u] = cost[op[u] ? y[u] : x];
         }
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
@@ -697,8 +694,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             const int cc = ld_cnt(&ctl->c_cnt);
             const int sub = t.lane / CL, lg = t.lane & (CL - 1);
             constexpr int per_wave = GMT_WAVE / CL;
-            const int *__restrict__ in_col = R.in_col;
-            const double *__restrict__ in_cost = R.in_cost;
+            const unsigned int *__restrict__ in_rec = R.in_rec;
             const int stride = t.nwaves * per_wave;
             // the next round's candidate entry is loaded one round ahead
             int4 ent_next = (t.wave * per_wave + sub < cc) ? w.clist[t.wave * per_wave + sub] : make_int4(0, 0, 0, 0);
@@ -718,7 +714,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    scan_row<CL, LDS == 0>(st, cost, in_col, in_cost, x, ib, ie, lg, best, by, be);
+                    scan_row<CL, LDS == 0>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
