@@ -365,6 +365,7 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 // values of nodes that are not open are read and ignored (a node committed
 // by this iteration may be written meanwhile; it is not open either way).
 #define SCAN_U 8
+#define FRONT_U 4
 template <int CL, bool EAGER>
 __device__ __forceinline__ void scan_row(const unsigned char *st, const double *__restrict__ cost,
                                          const unsigned int *__restrict__ rec, int x, int ib, int ie, int lg,
@@ -471,7 +472,15 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             int q[6] = {0, 0, 0, 0, 0, 0};
             for (int a = 0; a < R.dim; ++a) q[a] = (int)((double)R.s[(size_t)a * n + v] * GMT_QS);
             bool dead = false;
-            for (int b = 0; b < P.m && !dead; ++b) dead = in_staged_box<KIND>(q, lbox, b, P.pd);
+            if (KIND == 0) {
+                for (int b = 0; b < P.m && !dead; ++b) dead = point_in_box_q(q, lbox + b * 2 * P.pd, P.pd);
+            } else {
+                // grid coordinates are exact in FP32, as are the staged boxes
+                const float p0 = R.s[v], p1 = R.s[(size_t)n + v], p2 = R.s[2 * (size_t)n + v];
+                const float *fb = (const float *)lbox;
+                for (int b = 0; b < P.m && !dead; ++b, fb += 6)
+                    dead = p0 >= fb[0] && p0 <= fb[3] && p1 >= fb[1] && p1 <= fb[4] && p2 >= fb[2] && p2 <= fb[5];
+            }
             st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
             cost[v] = __longlong_as_double(COST_INF_BITS);
             w.parent[v] = -1;
@@ -543,27 +552,25 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             if (active) load_end<KIND>(R, v, ce);
             const double tau = (KIND == 1 && active) ? w.aux[v] : 0.0;
             const bool free_edge = group_edge_free<KIND, CL>(P, active, P.x_q, P.x_d, tau, ce, lbox);
+            const bool joined = active && lg == 0 && free_edge;
             if (active && lg == 0) {
                 if (free_edge) {
                     st[v] = (unsigned char)(S_OPEN | (st[v] & S_GOAL));
                     w.parent[v] = root;
                     w.ai[v] = 0;
+                    // the open set of iteration 1 is the root's children
+                    atomic_min_cost(&ctl->min_bits[1], cost[v]);
                 } else {
                     cost[v] = __longlong_as_double(COST_INF_BITS);
                 }
             }
+            wave_count(&ctl->rem_cnt[1], joined);
         }
     }
     team_sync(t);
     if (t.rank == 0) {
-        ctl->g_cnt = 0;  // first read by the select phase, after the next barrier
+        ctl->g_cnt = 0;  // compaction counters of iteration 0, reused by the select phase
         ctl->c_cnt = 0;
-    }
-    // open set of iteration 1: the root's children
-    for (int v = t.rank; v < n; v += t.size) {
-        const bool op = (st[v] & S_SET) == S_OPEN;
-        wave_count(&ctl->rem_cnt[1], op);
-        if (op) atomic_min_cost(&ctl->min_bits[1], cost[v]);
     }
     team_sync(t);
 
@@ -665,14 +672,35 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     oe = R.out_ptr[g + 1];
                     if (lg == 0) w_out += (unsigned long long)(oe - ob);
                 }
-                for (int e = ob + lg; e < oe; e += CL) {
-                    const int x = R.out_col[e];
-                    const unsigned char s = st[x];
-                    bool cand = false;
-                    if ((s & S_SET) == S_UNEXPLORED && !(s & S_CLAIM)) cand = claim(st, x);
-                    const int4 ent = make_int4(x, R.in_ptr[x], R.in_ptr[x + 1], 0);
-                    const int slot = wave_append(&ctl->c_cnt, cand);
-                    if (cand) w.clist[slot] = ent;
+                // FRONT_U out-edges per lane per step: their loads are issued
+                // together; row extents are read for claimed nodes only
+                for (int e0 = ob + lg; e0 < oe; e0 += FRONT_U * CL) {
+                    int xs[FRONT_U];
+#pragma unroll
+                    for (int u = 0; u < FRONT_U; ++u) {
+                        const int e = e0 + u * CL;
+                        xs[u] = e < oe ? R.out_col[e] : -1;
+                    }
+                    bool cand[FRONT_U];
+#pragma unroll
+                    for (int u = 0; u < FRONT_U; ++u) {
+                        cand[u] = false;
+                        if (xs[u] >= 0) {
+                            const unsigned char sx = st[xs[u]];
+                            if ((sx & S_SET) == S_UNEXPLORED && !(sx & S_CLAIM)) cand[u] = claim(st, xs[u]);
+                        }
+                    }
+                    int ib[FRONT_U], ie[FRONT_U];
+#pragma unroll
+                    for (int u = 0; u < FRONT_U; ++u) {
+                        ib[u] = cand[u] ? R.in_ptr[xs[u]] : 0;
+                        ie[u] = cand[u] ? R.in_ptr[xs[u] + 1] : 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < FRONT_U; ++u) {
+                        const int slot = wave_append(&ctl->c_cnt, cand[u]);
+                        if (cand[u]) w.clist[slot] = make_int4(xs[u], ib[u], ie[u], 0);
+                    }
                 }
             }
         }
