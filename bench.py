@@ -130,9 +130,17 @@ def learned_report(args, torch, gmt, I):
         ref_ms.append(ms)
     ref_cost = np.array(ref_cost)
     rows = {}
+    tuned_single = {}
     for n in (2048, 4096, 8192):
         r_n = radius.di_radius(n)
         n_l = n // 2
+        # single-plan launch shape for this n, tuned on one uniform sample set
+        rm_t = gmt.gmt_build_neighbors(torch.from_numpy(I.di_samples(7_000, n)).to(dev),
+                                       gmt.GMT_COST_DOUBLE_INTEGRATOR, r_n)
+        p0 = tests[0]
+        tuned_single[n] = gmt.gmt_autotune([gmt.BatchQuery(rm_t, p0.x_init, gmt.make_goal(p0.goal_center,
+                                            p0.goal_radius, 3), p0.boxes, p0.lam)], opts, single=True, reps=3)
+        rm_t.free()
         # query-independent draws stay resident: `sets` pools, query k uses pool k % sets
         uni = [torch.from_numpy(I.di_samples(7_000 + ss, n - n_l)).to(dev) for ss in range(sets)]
         fb = [torch.from_numpy(I.di_samples(8_000 + ss, n_l)).to(dev) for ss in range(sets)]
@@ -178,6 +186,8 @@ def learned_report(args, torch, gmt, I):
                              "p50_ms_plan_resident": round(float(np.percentile(ref_ms, 50)), 3),
                              "build_ms": round(float(np.median(build_ms)), 3)},
             "mixes": rows,
+            "single_plan_shape": {str(k): {kk: v[kk] for kk in ("lanes", "team_wgs", "threads", "ms", "default_ms")}
+                                  for k, v in tuned_single.items()},
             "note": "end-to-end = sampler inference + neighbour build + plan; uniform draws, "
                     "fallbacks and noise are query-independent and resident (8 pools per n); "
                     "r(n) = 1.75 (16384/n)^(1/6) for every n"}

@@ -332,45 +332,25 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
 // ---------------------------------------------------------------------------
 // transpose (out-neighbour table) with rows sorted by target
 // ---------------------------------------------------------------------------
-__global__ void k_out_count(const int *__restrict__ in_ptr, const int *__restrict__ in_col, int n,
-                            int *__restrict__ out_deg) {
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
+// transpose of the in-table: one wave per in-row x, lanes over its edges, so
+// the row is read coalesced and the atomics of a wave go out together
+__global__ void __launch_bounds__(256) k_out_count(const int *__restrict__ in_ptr, const int *__restrict__ in_col,
+                                                   int n, int *__restrict__ out_deg) {
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
     if (x >= n) return;
-    for (int e = in_ptr[x]; e < in_ptr[x + 1]; ++e) atomicAdd(&out_deg[in_col[e]], 1);
+    const int b = in_ptr[x], e = in_ptr[x + 1];
+    for (int k = b + lane_id(); k < e; k += GMT_WAVE) atomicAdd(&out_deg[in_col[k]], 1);
 }
 
-__global__ void k_out_place(const int *__restrict__ in_ptr, const int *__restrict__ in_col, int n,
-                            const int *__restrict__ out_ptr, int *__restrict__ cursor,
-                            int *__restrict__ out_col) {
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_out_place(const int *__restrict__ in_ptr, const int *__restrict__ in_col,
+                                                   int n, const int *__restrict__ out_ptr, int *__restrict__ cursor,
+                                                   int *__restrict__ out_col) {
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
     if (x >= n) return;
-    for (int e = in_ptr[x]; e < in_ptr[x + 1]; ++e) {
-        int y = in_col[e];
+    const int b = in_ptr[x], e = in_ptr[x + 1];
+    for (int k = b + lane_id(); k < e; k += GMT_WAVE) {
+        const int y = in_col[k];
         out_col[out_ptr[y] + atomicAdd(&cursor[y], 1)] = x;
-    }
-}
-
-// sort each out-row ascending (one wave per row, rank sort through LDS);
-// rows longer than `cap` are left unsorted and flagged in flags[0]
-__global__ void __launch_bounds__(256) k_rows_sort(const int *__restrict__ ptr, int n, int cap,
-                                                   int *__restrict__ col, int *__restrict__ flags) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int wl = threadIdx.x / GMT_WAVE;
-    int *buf = (int *)lds_raw + (size_t)wl * cap;
-    int row = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
-    if (row >= n) return;
-    int b = ptr[row], e = ptr[row + 1], cnt = e - b;
-    if (cnt > cap) {
-        if (lane_id() == 0) atomicOr(&flags[0], 2);
-        return;
-    }
-    for (int k = lane_id(); k < cnt; k += GMT_WAVE) buf[k] = col[b + k];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    for (int k = lane_id(); k < cnt; k += GMT_WAVE) {
-        int key = buf[k], rank = 0;
-        for (int k2 = 0; k2 < cnt; ++k2) rank += (buf[k2] < key) ? 1 : 0;
-        col[b + rank] = key;
     }
 }
 

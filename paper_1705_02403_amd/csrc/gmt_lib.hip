@@ -205,33 +205,24 @@ static inline unsigned blocks_for(long long threads, int per) { return (unsigned
 // out-neighbour table by transposing the in-table, rows sorted
 static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n;
-    DevBuf deg, cursor, flags;
+    DevBuf deg, cursor;
     TRY(dev_alloc(rm->out_ptr, sizeof(int) * (n + 1), s));
     TRY(dev_alloc(rm->out_col, sizeof(int) * std::max<long long>(rm->nnz, 1), s));
     rm->out_shared = false;
     TRY(dev_alloc(deg, sizeof(int) * n, s));
     TRY(dev_alloc(cursor, sizeof(int) * n, s));
-    TRY(dev_alloc(flags, 64, s));
-    k_fill_int<<<1, 64, 0, s>>>((int *)flags.p, 16, 0);
     k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)deg.p, n, 0);
     k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)cursor.p, n, 0);
-    k_out_count<<<blocks_for(n, 256), 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
-                                                   (int *)deg.p);
+    const unsigned wave_blocks = blocks_for((long long)n * GMT_WAVE, 256);
+    k_out_count<<<wave_blocks, 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n, (int *)deg.p);
     k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->out_ptr.p, nullptr);
-    k_out_place<<<blocks_for(n, 256), 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
-                                                   (const int *)rm->out_ptr.p, (int *)cursor.p,
-                                                   (int *)rm->out_col.p);
-    // rows of up to 4096 entries sorted in LDS by one wave each
-    k_rows_sort<<<blocks_for((long long)n * GMT_WAVE, 64), 64, 4096 * sizeof(int), s>>>(
-        (const int *)rm->out_ptr.p, n, 4096, (int *)rm->out_col.p, (int *)flags.p);
+    k_out_place<<<wave_blocks, 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
+                                            (const int *)rm->out_ptr.p, (int *)cursor.p, (int *)rm->out_col.p);
+    // out-rows stay in placement order: the frontier's candidate order does not
+    // affect any decision of an iteration
     HIPCHK(hipGetLastError());
-    int hf = 0;
-    HIPCHK(hipMemcpyAsync(&hf, flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     dev_free(deg, s);
     dev_free(cursor, s);
-    dev_free(flags, s);
-    if (hf) return fail(GMT_EINVAL, "a node has more than 4096 out-neighbours: radius too large");
     return GMT_OK;
 }
 
