@@ -123,12 +123,14 @@ gmt_status gmt_set_allocator(const gmt_allocator *allocator);
  *             threshold on J.
  *  out        receives the roadmap; free with gmt_roadmap_free.
  * The table holds, for every sample x, its in-neighbours y (c(y -> x) < r)
- * in ascending order with FP64 costs (and FP64 arrival times for the double
- * integrator), plus the out-neighbour table; for the symmetric Euclidean cost
- * one table serves both.  Synchronises `stream` once (to size the table).
+ * with FP64 costs (and FP64 arrival times for the double integrator), plus
+ * the out-neighbour table; for the symmetric Euclidean cost one table serves
+ * both.  Row order on the device is unspecified (gmt_roadmap_export returns
+ * ascending rows).  Synchronises `stream` (to size the table, and on return:
+ * the table is complete).
  * Errors: GMT_EINVAL for n < 1, a bad dim/kind pair, r_n <= 0 or non-finite,
- * samples off the grid or outside the state space, or a row of more than
- * 4096 neighbours; GMT_ENOMEM; GMT_EDEVICE. */
+ * samples off the grid or outside the state space, or more than 2^31-1
+ * edges; GMT_ENOMEM; GMT_EDEVICE. */
 gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim, gmt_cost_kind kind,
                                double r_n, void *stream, gmt_roadmap_t *out);
 
@@ -147,7 +149,8 @@ gmt_status gmt_roadmap_info(gmt_roadmap_t rm, int32_t *n, int32_t *dim, int32_t 
                             int64_t *nnz);
 
 /* Copy the in-neighbour table to host arrays: row_ptr [n+1], col [nnz],
- * cost [nnz], tau [nnz] (any of col/cost/tau may be NULL). */
+ * cost [nnz], tau [nnz] (any of row_ptr/col/cost/tau may be NULL), each row
+ * ascending by column.  Synchronises `stream`. */
 gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int32_t *col, double *cost,
                               double *tau, void *stream);
 

@@ -142,99 +142,109 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
     for (int a = 0; a < g.dim; ++a) sq[(size_t)a * n + pos] = (int)((double)s[(size_t)a * n + i] * GMT_QS);
 }
 
-// Visit every member j of the 3^d cells around sorted position t; calls
-// f(j, d2, is_nbr) per lane-chunk with wave-uniform control flow.
-template <typename F>
-__device__ __forceinline__ void eu_scan_row(int t, int n, const EuGrid &g, const int *__restrict__ sq,
-                                            const int *__restrict__ perm,
-                                            const int *__restrict__ cell_start, double R2, F &&f) {
-    const int lane = lane_id();
-    int qi[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
-    for (int a = 0; a < g.dim; ++a) {
-        qi[a] = sq[(size_t)a * n + t];
-        int ca = (int)(((long long)qi[a] * g.G) >> 20);
-        ci[a] = ca >= g.G ? g.G - 1 : ca;
-    }
-    const int self = perm[t];
-    const int zr = g.dim == 3 ? 1 : 0;
-    for (int dz = -zr; dz <= zr; ++dz) {
-        int cz = ci[2] + dz;
-        if (cz < 0 || cz >= (g.dim == 3 ? g.G : 1)) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            int cy = ci[1] + dy;
-            if (cy < 0 || cy >= g.G) continue;
-            // cells along x are contiguous in the sorted order: one span
-            int cx0 = ci[0] - 1 < 0 ? 0 : ci[0] - 1;
-            int cx1 = ci[0] + 1 >= g.G ? g.G - 1 : ci[0] + 1;
-            int rowc = (cz * g.G + cy) * g.G;
-            int b = cell_start[rowc + cx0], e = cell_start[rowc + cx1 + 1];
-            for (int p0 = b; p0 < e; p0 += GMT_WAVE) {
-                int p = p0 + lane;
-                bool ok = false;
-                long long d2 = 0;
-                int j = -1;
-                if (p < e) {
-                    for (int a = 0; a < g.dim; ++a) {
-                        long long dd = (long long)sq[(size_t)a * n + p] - qi[a];
-                        d2 += dd * dd;
+// Rows of the Euclidean table.  Cells have edge >= r/2 (G per axis) and the
+// samples are sorted by cell (perm, grid coordinates sq).  One 256-thread
+// workgroup per cell stages the samples of the 5^d cells around it in LDS,
+// in chunks of EU_CHUNK, and each wave takes rows of the cell in turn and
+// tests all staged samples, 64 at a time.  Grid coordinates differ by less
+// than 2^21, so d2 = |q_i - q_j|^2 is exact in FP64 (each square below 2^42,
+// the sum below 2^53).  COUNT: row lengths; otherwise the rows are written
+// (in staging order: the parent search does not depend on it) with costs
+// sqrt(d2) * 2^-20, rounded once.
+#define EU_CHUNK 1024
+#define EU_ROWS 1024
+
+template <bool COUNT>
+__global__ void __launch_bounds__(256) k_eu_rows(int n, EuGrid g, const int *__restrict__ sq,
+                                                 const int *__restrict__ perm, const int *__restrict__ cell_start,
+                                                 double R2, int *__restrict__ deg, int *__restrict__ maxdeg,
+                                                 const int *__restrict__ row_ptr, int *__restrict__ col,
+                                                 double *__restrict__ cost) {
+    __shared__ int cq[3][EU_CHUNK];
+    __shared__ int cj[EU_CHUNK];
+    __shared__ int rcnt[EU_ROWS];
+    __shared__ int sb[25], soff[26];
+    const int c = blockIdx.x;
+    const int G = g.G;
+    const int cx = c % G, cy = (c / G) % G, cz = g.dim == 3 ? c / (G * G) : 0;
+    const int p0 = cell_start[c], p1 = cell_start[c + 1];
+    const int tid = threadIdx.x, wave = tid / GMT_WAVE, lane = lane_id();
+    const int zr = g.dim == 3 ? 2 : 0;
+    for (int rb = p0; rb < p1; rb += EU_ROWS) {  // blocks of rows of this cell
+        const int nr = min(EU_ROWS, p1 - rb);
+        for (int i = tid; i < nr; i += 256) rcnt[i] = 0;
+        // test the rows of this block against staged samples [0, cnt)
+        auto process = [&](int cnt) {
+            __syncthreads();
+            for (int ri = wave; ri < nr; ri += 4) {
+                const int p = rb + ri;
+                const int self = perm[p];
+                const int q0 = sq[p], q1 = sq[(size_t)n + p], q2 = g.dim == 3 ? sq[2 * (size_t)n + p] : 0;
+                int run = 0;
+                const int base = COUNT ? 0 : row_ptr[self] + rcnt[ri];
+                for (int k0 = 0; k0 < cnt; k0 += GMT_WAVE) {
+                    const int k = k0 + lane;
+                    bool ok = false;
+                    double d2 = 0.0;
+                    if (k < cnt) {
+                        const double d0 = (double)(cq[0][k] - q0), d1 = (double)(cq[1][k] - q1),
+                                     dz = (double)(cq[2][k] - q2);
+                        d2 = d0 * d0 + d1 * d1 + dz * dz;
+                        ok = cj[k] != self && d2 < R2;
                     }
-                    j = perm[p];
-                    ok = (j != self) && ((double)d2 < R2);
+                    const uint64_t m = wave_ballot(ok);
+                    if (!COUNT && ok) {
+                        const int slot = base + run + lanes_below(m);
+                        col[slot] = cj[k];
+                        cost[slot] = sqrt(d2) * GMT_INV_QS;
+                    }
+                    run += (int)__popcll(m);
                 }
-                f(j, d2, ok);
+                if (lane == 0) rcnt[ri] += run;
             }
+            __syncthreads();
+        };
+        // the neighbourhood as at most 25 spans of the sorted order (cells
+        // along x are contiguous): bounds read in parallel, then flattened
+        const int nspan = (2 * zr + 1) * 5;
+        if (tid < nspan) {
+            const int z = cz + tid / 5 - zr, y = cy + tid % 5 - 2;
+            int b = 0, e = 0;
+            if (z >= 0 && z < (g.dim == 3 ? G : 1) && y >= 0 && y < G) {
+                const int rowc = (z * G + y) * G;
+                b = cell_start[rowc + max(cx - 2, 0)];
+                e = cell_start[rowc + min(cx + 2, G - 1) + 1];
+            }
+            sb[tid] = b;
+            soff[tid + 1] = e - b;
         }
-    }
-}
-
-// degree of every row; rows visited in sorted order, one wave per row
-__global__ void __launch_bounds__(256) k_eu_count(int n, EuGrid g, const int *__restrict__ sq,
-                                                  const int *__restrict__ perm,
-                                                  const int *__restrict__ cell_start, double R2,
-                                                  int *__restrict__ deg, int *__restrict__ maxdeg) {
-    int t = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
-    if (t >= n) return;
-    int cnt = 0;
-    eu_scan_row(t, n, g, sq, perm, cell_start, R2, [&](int, long long, bool ok) {
-        cnt += (int)__popcll(wave_ballot(ok));
-    });
-    if (lane_id() == 0) {
-        deg[perm[t]] = cnt;
-        atomicMax(maxdeg, cnt);
-    }
-}
-
-// rows written sorted by neighbour index; cap = LDS entries per wave
-__global__ void __launch_bounds__(256) k_eu_fill(int n, EuGrid g, const int *__restrict__ sq,
-                                                 const int *__restrict__ perm,
-                                                 const int *__restrict__ cell_start, double R2,
-                                                 const int *__restrict__ row_ptr, int cap,
-                                                 int *__restrict__ col, double *__restrict__ cost) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int wl = threadIdx.x / GMT_WAVE;
-    int *bj = (int *)lds_raw + (size_t)wl * cap * 3;
-    long long *bd = (long long *)(bj + cap);  // 8-byte aligned: cap*4 bytes offset, cap even
-    int t = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
-    if (t >= n) return;
-    int cnt = 0;
-    eu_scan_row(t, n, g, sq, perm, cell_start, R2, [&](int j, long long d2, bool ok) {
-        uint64_t m = wave_ballot(ok);
-        if (ok) {
-            int slot = cnt + lanes_below(m);
-            bj[slot] = j;
-            bd[slot] = d2;
+        __syncthreads();
+        if (tid == 0) {
+            soff[0] = 0;
+            for (int k = 1; k <= nspan; ++k) soff[k] += soff[k - 1];
         }
-        cnt += (int)__popcll(m);
-    });
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    const int base = row_ptr[perm[t]];
-    for (int k = lane_id(); k < cnt; k += GMT_WAVE) {
-        int key = bj[k];
-        int rank = 0;
-        for (int k2 = 0; k2 < cnt; ++k2) rank += (bj[k2] < key) ? 1 : 0;
-        col[base + rank] = key;
-        cost[base + rank] = sqrt((double)bd[k]) * GMT_INV_QS;
+        __syncthreads();
+        const int total = soff[nspan];
+        for (int c0 = 0; c0 < total; c0 += EU_CHUNK) {
+            const int cnt = min(EU_CHUNK, total - c0);
+            for (int k = tid; k < cnt; k += 256) {
+                const int f = c0 + k;
+                int sp = 0;
+                while (soff[sp + 1] <= f) ++sp;
+                const int src = sb[sp] + (f - soff[sp]);
+                cq[0][k] = sq[src];
+                cq[1][k] = sq[(size_t)n + src];
+                cq[2][k] = g.dim == 3 ? sq[2 * (size_t)n + src] : 0;
+                cj[k] = perm[src];
+            }
+            process(cnt);
+        }
+        if (COUNT)
+            for (int i = tid; i < nr; i += 256) {
+                deg[perm[rb + i]] = rcnt[i];
+                atomicMax(maxdeg, rcnt[i]);
+            }
+        __syncthreads();
     }
 }
 

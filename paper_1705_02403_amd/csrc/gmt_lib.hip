@@ -242,9 +242,12 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     const double R2 = rm->r * rm->r * GMT_Q2;
     EuGrid g;
     g.dim = dim;
-    double inv = 1.0 / rm->r;
-    int Gmax = dim == 2 ? 2048 : 160;
-    g.G = inv >= Gmax ? Gmax : std::max(1, (int)std::floor(inv));
+    // cells of edge >= r/2 (the 5^d cells around a sample cover its r-ball),
+    // at most about one cell per sample
+    const double per_axis = std::floor(2.0 / rm->r);
+    const int Gmax = dim == 2 ? 2048 : 160;
+    const int Gn = (int)std::floor(std::pow((double)n, 1.0 / dim)) + 1;
+    g.G = (int)std::max(1.0, std::min({per_axis, (double)Gmax, (double)Gn}));
     g.ncell = 1;
     for (int a = 0; a < dim; ++a) g.ncell *= g.G;
     DevBuf cell_of, cell_cnt, cell_start, cursor, perm, sq, deg, scal;
@@ -269,8 +272,8 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     k_eu_scatter<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (const int *)cell_of.p,
                                                    (const int *)cell_start.p, (int *)cursor.p,
                                                    (int *)perm.p, (int *)sq.p);
-    k_eu_count<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
-        n, g, (const int *)sq.p, (const int *)perm.p, (const int *)cell_start.p, R2, (int *)deg.p, maxdeg);
+    k_eu_rows<true><<<g.ncell, 256, 0, s>>>(n, g, (const int *)sq.p, (const int *)perm.p, (const int *)cell_start.p,
+                                            R2, (int *)deg.p, maxdeg, nullptr, nullptr, nullptr);
     k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
     HIPCHK(hipGetLastError());
     int hs[4];
@@ -280,7 +283,6 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     std::memcpy(&E, hs + 2, sizeof E);
     gmt_status st = GMT_OK;
     if (hs[0]) st = fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
-    else if (hs[1] > 4096) st = fail(GMT_EINVAL, "a row has %d neighbours (limit 4096): radius too large", hs[1]);
     else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
     if (st == GMT_OK) {
         rm->nnz = E;
@@ -288,14 +290,11 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
         if (st == GMT_OK) st = dev_alloc(rm->in_cost, sizeof(double) * std::max<long long>(E, 1), s);
     }
     if (st == GMT_OK) {
-        int cap = std::max(64, (hs[1] + 63) / 64 * 64);
-        int threads = (cap * 12 * 4 <= 64 * 1024) ? 256 : 64;
-        size_t lds = (size_t)(threads / GMT_WAVE) * cap * 12;
-        k_eu_fill<<<blocks_for((long long)n * GMT_WAVE, threads), threads, lds, s>>>(
-            n, g, (const int *)sq.p, (const int *)perm.p, (const int *)cell_start.p, R2,
-            (const int *)rm->in_ptr.p, cap, (int *)rm->in_col.p, (double *)rm->in_cost.p);
+        k_eu_rows<false><<<g.ncell, 256, 0, s>>>(n, g, (const int *)sq.p, (const int *)perm.p,
+                                                 (const int *)cell_start.p, R2, nullptr, nullptr,
+                                                 (const int *)rm->in_ptr.p, (int *)rm->in_col.p,
+                                                 (double *)rm->in_cost.p);
         hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
     }
     dev_free(cell_of, s);
@@ -334,7 +333,6 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     std::memcpy(&E, hs + 2, sizeof E);
     gmt_status st = GMT_OK;
     if (hs[0]) st = fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, on the 2^-20 grid");
-    else if (hs[1] > 4096) st = fail(GMT_EINVAL, "a row has %d neighbours (limit 4096): radius too large", hs[1]);
     else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
     if (st == GMT_OK) {
         rm->nnz = E;
@@ -376,6 +374,8 @@ extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int
         if (e != hipSuccess) st = fail(GMT_EDEVICE, "sample copy failed: %s", hipGetErrorString(e));
     }
     if (st == GMT_OK) st = (kind == GMT_COST_EUCLIDEAN) ? build_euclid(rm, s) : build_di(rm, s);
+    // the table is complete on return, so any stream may plan on it
+    if (st == GMT_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(GMT_EDEVICE, "neighbour build failed");
     if (st != GMT_OK) {
         (void)hipStreamSynchronize(s);
         roadmap_release(rm, s);
@@ -460,12 +460,30 @@ extern "C" gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int
                                          double *cost, double *tau, void *stream) {
     if (!rm) return fail(GMT_EINVAL, "null roadmap");
     hipStream_t s = (hipStream_t)stream;
-    if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, rm->in_ptr.p, sizeof(int) * (rm->n + 1), hipMemcpyDeviceToHost, s));
-    if (col && rm->nnz) HIPCHK(hipMemcpyAsync(col, rm->in_col.p, sizeof(int) * rm->nnz, hipMemcpyDeviceToHost, s));
-    if (cost && rm->nnz) HIPCHK(hipMemcpyAsync(cost, rm->in_cost.p, sizeof(double) * rm->nnz, hipMemcpyDeviceToHost, s));
-    if (tau && rm->nnz && rm->in_tau.p)
-        HIPCHK(hipMemcpyAsync(tau, rm->in_tau.p, sizeof(double) * rm->nnz, hipMemcpyDeviceToHost, s));
+    const size_t E = (size_t)rm->nnz;
+    std::vector<int> rp(rm->n + 1), cl(E);
+    std::vector<double> cs(cost ? E : 0), ta(tau && rm->in_tau.p ? E : 0);
+    HIPCHK(hipMemcpyAsync(rp.data(), rm->in_ptr.p, sizeof(int) * (rm->n + 1), hipMemcpyDeviceToHost, s));
+    if (E) HIPCHK(hipMemcpyAsync(cl.data(), rm->in_col.p, sizeof(int) * E, hipMemcpyDeviceToHost, s));
+    if (E && !cs.empty()) HIPCHK(hipMemcpyAsync(cs.data(), rm->in_cost.p, sizeof(double) * E, hipMemcpyDeviceToHost, s));
+    if (E && !ta.empty()) HIPCHK(hipMemcpyAsync(ta.data(), rm->in_tau.p, sizeof(double) * E, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    // device rows may be in any order (the parent search does not depend on
+    // it); exported rows are ascending
+    std::vector<int> idx;
+    for (int x = 0; x < rm->n; ++x) {
+        const int b = rp[x], e = rp[x + 1];
+        idx.resize(e - b);
+        for (int k = b; k < e; ++k) idx[k - b] = k;
+        std::sort(idx.begin(), idx.end(), [&](int a, int c) { return cl[a] < cl[c]; });
+        for (int k = b; k < e; ++k) {
+            const int src = idx[k - b];
+            if (col) col[k] = cl[src];
+            if (cost) cost[k] = cs[src];
+            if (!ta.empty()) tau[k] = ta[src];
+        }
+    }
+    if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int) * (rm->n + 1));
     return GMT_OK;
 }
 
