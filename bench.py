@@ -65,6 +65,9 @@ def parse():
                     help="time the batches only (for counter runs): no latency, server, build or oracle sections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--mixed-requests", type=int, default=512,
+                    help="mixed 2D/3D/6D replanning stream (0: skip)")
+    ap.add_argument("--mixed-rate", type=float, default=2000.0)
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned sampler and compare it with plain GMT* at n=32768")
     ap.add_argument("--learned-train", type=int, default=20000)
@@ -191,6 +194,52 @@ def learned_report(args, torch, gmt, I):
             "note": "end-to-end = sampler inference + neighbour build + plan; uniform draws, "
                     "fallbacks and noise are query-independent and resident (8 pools per n); "
                     "r(n) = 1.75 (16384/n)^(1/6) for every n"}
+
+
+def mixed_report(args, torch, gmt, I):
+    """Batched replanning (configuration 4): mixed 2D/3D/6D queries, n
+    log-uniform in [1k, 32k], 10-100 boxes, on shared resident roadmaps keyed
+    by (dim, n, sample seed); Poisson arrivals, then all at once."""
+    from paper_1705_02403_amd import radius, server
+    dev = torch.device("cuda", 0)
+    specs = I.batch_specs(args.mixed_requests)
+    samples, rms = {}, {}
+    t = time.perf_counter()
+    for sp in specs:
+        key = (sp["dim"], sp["n"], sp["sample_seed"])
+        if key in rms:
+            continue
+        x = (I.di_samples(sp["sample_seed"], sp["n"]) if sp["dim"] == 6
+             else I.uniform_samples(sp["dim"], sp["n"], sp["sample_seed"]))
+        samples[key] = x
+        kind = gmt.GMT_COST_DOUBLE_INTEGRATOR if sp["dim"] == 6 else gmt.GMT_COST_EUCLIDEAN
+        rms[key] = gmt.gmt_build_neighbors(torch.from_numpy(x).to(dev), kind,
+                                           radius.shared_roadmap_radius(sp["dim"], sp["n"]))
+    build_s = time.perf_counter() - t
+    probs = [(sp, I.mixed_problem(sp, samples[(sp["dim"], sp["n"], sp["sample_seed"])])) for sp in specs]
+
+    def make(p):
+        return lambda rm: gmt.BatchQuery(rm, p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, p.pdim),
+                                         p.boxes, p.lam, p.step)
+
+    arr = I.poisson_arrivals(len(probs), args.mixed_rate, seed=7)
+    reqs = [server.Request(float(a), (sp["dim"], sp["n"], sp["sample_seed"]), make(p), tag=k)
+            for k, (a, (sp, p)) in enumerate(zip(arr, probs))]
+    srv = server.ReplanServer(lambda key: rms[key], gmt.make_opts(traj_points=16), engine_budget=16 << 30,
+                              roadmap_budget=1 << 40, slots=4, max_batch=256)
+    srv.serve(reqs[:64], realtime=False)  # warm streams and workspaces
+    rep = srv.serve(reqs)
+    sat = srv.serve(reqs, realtime=False)
+    srv.engine.close()
+    for rm in rms.values():
+        rm.free()
+    solved = sum(s.status == gmt.GMT_OK for s in rep.served)
+    return {"requests": len(reqs), "roadmaps": len(rms), "roadmap_build_s": round(build_s, 2),
+            "dims": {str(d): sum(sp["dim"] == d for sp in specs) for d in (2, 3, 6)},
+            "arrival_rate_hz": args.mixed_rate, "p50_ms": round(rep.p50_ms, 3), "p99_ms": round(rep.p99_ms, 3),
+            "plans_per_s": round(rep.plans_per_s, 1), "solved": solved,
+            "all_at_once_plans_per_s": round(sat.plans_per_s, 1),
+            "all_at_once_p50_ms": round(sat.p50_ms, 3), "batches": rep.engine.get("batches")}
 
 
 def main():
@@ -349,6 +398,8 @@ def main():
                       "GB_per_s_out": round(12.0 * e3 / (bt * 1e-3) / 1e9, 1)}
 
     learned = learned_report(args, torch, gmt, I) if args.learned else None
+    mixed = (mixed_report(args, torch, gmt, I)
+             if args.mixed_requests > 0 and not args.only_throughput else None)
 
     # ---- cost against the FP64 oracle (sample set 0) and CPU baseline ----
     check = {}
@@ -427,6 +478,7 @@ def main():
         "oracle_check": check,
         "server": srv_line,
         "euclid_build": build_line,
+        "mixed_stream": mixed,
         "learned": learned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

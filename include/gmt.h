@@ -218,7 +218,8 @@ gmt_status gmt_last_work(gmt_work *out);
 gmt_status gmt_profile_enable(int32_t enable);
 gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches);
 
-/* One query of a batch. */
+/* One query of a batch.  edge_step > 0 overrides the plan options' edge
+ * step for this query (Euclidean roadmaps; 0: use the options'). */
 typedef struct {
     gmt_roadmap_t roadmap;
     const float *x_init; /* host [dim] */
@@ -226,6 +227,7 @@ typedef struct {
     const float *boxes; /* host [m][2*pdim] */
     int32_t m;
     double lambda;
+    double edge_step;
 } gmt_problem;
 
 /* Result of one batched query: status, iteration index at termination, path

@@ -1046,7 +1046,9 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
             const int k = r.order[j];
             const gmt_problem &pr = problems[k];
             QueryIn q{pr.roadmap, pr.x_init, &pr.goal, pr.boxes, pr.m, pr.lambda};
-            st = stage_query(q, bo.plan, P[j], bx + off, off);
+            gmt_plan_opts po = bo.plan;
+            if (pr.edge_step > 0.0) po.edge_step = pr.edge_step;
+            st = stage_query(q, po, P[j], bx + off, off);
             if (st != GMT_OK) {
                 std::string msg = g_last_error;
                 st = fail(st, "problem %d: %s", k, msg.c_str());
@@ -1164,6 +1166,7 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
     pr.boxes = boxes;
     pr.m = m;
     pr.lambda = lambda;
+    pr.edge_step = 0.0;
     gmt_result res;
     std::memset(&res, 0, sizeof res);
     res.path = path;

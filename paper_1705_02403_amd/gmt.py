@@ -93,7 +93,8 @@ class gmt_plan_opts(C.Structure):
 
 class gmt_problem(C.Structure):
     _fields_ = [("roadmap", C.c_void_p), ("x_init", C.POINTER(C.c_float)), ("goal", gmt_goal),
-                ("boxes", C.POINTER(C.c_float)), ("m", C.c_int32), ("lambda_", C.c_double)]
+                ("boxes", C.POINTER(C.c_float)), ("m", C.c_int32), ("lambda_", C.c_double),
+                ("edge_step", C.c_double)]
 
 
 class gmt_work(C.Structure):
@@ -418,6 +419,7 @@ class BatchQuery:
     goal: gmt_goal
     boxes: np.ndarray
     lam: float
+    edge_step: float = 0.0  # > 0: this query's Euclidean edge step
 
 
 class PreparedBatch:
@@ -449,6 +451,7 @@ class PreparedBatch:
             self.probs[j].boxes = bx.ctypes.data_as(C.POINTER(C.c_float)) if m else None
             self.probs[j].m = m
             self.probs[j].lambda_ = float(q.lam)
+            self.probs[j].edge_step = float(q.edge_step)
             self.res[j].path = path.ctypes.data_as(C.POINTER(C.c_int32))
             self.res[j].path_cap = path_cap
             o = [None] * 4
@@ -591,6 +594,7 @@ class Engine:
         p.boxes = bx.ctypes.data_as(C.POINTER(C.c_float)) if m else None
         p.m = m
         p.lambda_ = float(q.lam)
+        p.edge_step = float(q.edge_step)
         t = C.c_int64()
         _check(lib().gmt_engine_submit(self.handle, C.byref(p), int(path_cap), C.byref(t)),
                "gmt_engine_submit")

@@ -284,6 +284,44 @@ def batch_specs(count: int = 512, seed: int = 7, sample_seeds: int = 4):
     return out
 
 
+def uniform_samples(dim: int, n: int, sample_seed: int, goal: float = 0.95,
+                    goal_radius: float = 0.05) -> np.ndarray:
+    """Obstacle-independent Euclidean sample set (SoA FP32 [dim][n], uniform on
+    the grid, at least one sample in the goal ball), shared by every box world
+    of a replanning stream; samples inside a query's boxes are dead for it."""
+    rng = np.random.default_rng(60_000_011 + 977 * int(dim) + int(sample_seed) * 131 + int(n))
+    pos = draw_positions(rng, n, dim)
+    _ensure_goal_sample(rng, pos, to_grid(np.full(dim, goal)), float(np.float32(goal_radius)), None)
+    return np.ascontiguousarray(from_grid(pos.T))
+
+
+def mixed_problem(spec: dict, samples: np.ndarray, lam: float = 0.5) -> Problem:
+    """Query of the mixed replanning stream on a shared sample set: `spec`
+    from batch_specs; 2D boxes with sides U[0.05, 0.15] (step 0.005), 3D and
+    6D with sides U[0.05, 0.2] (3D step 0.002); the Euclidean radius uses the
+    obstacle-free volume (r is a property of the shared roadmap)."""
+    dim, m, seed = spec["dim"], spec["m"], spec["problem_seed"]
+    if dim == 6:
+        return di_problem(seed, samples, m=m, lam=lam, r=di_radius_of(spec["n"]),
+                          sample_seed=spec["sample_seed"])
+    rng = np.random.default_rng(70_000_003 + int(seed))
+    smax, step = (0.15, 0.005) if dim == 2 else (0.2, 0.002)
+    start_q = to_grid(np.full(dim, 0.05))
+    goal_q = to_grid(np.full(dim, 0.95))
+    gr = float(np.float32(0.05))
+    boxes_q = draw_boxes(rng, m, dim, 0.05, smax, start_q, goal_q, gr)
+    return Problem(kind="euclid", dim=dim, pdim=dim, samples=samples, x_init=from_grid(start_q),
+                   goal_center=from_grid(goal_q), goal_radius=gr,
+                   boxes=np.ascontiguousarray(from_grid(boxes_q)), lam=float(lam), step=step,
+                   r=None, seed=int(seed), sample_seed=int(spec["sample_seed"]))
+
+
+def di_radius_of(n: int) -> float:
+    """Double-integrator radius at n samples: 1.75 at n = 16384, scaled by
+    (16384/n)^(1/6)."""
+    return DI_RADIUS * (16384.0 / float(n)) ** (1.0 / 6.0)
+
+
 def tiny_problem(seed: int, dim: int, n: int, m: int, lam: float, step: float = 0.01,
                  smin: float = 0.1, smax: float = 0.3) -> Problem:
     """Small Euclidean instance for brute-force cross-checks."""

@@ -53,4 +53,11 @@ def di_radius(n: int) -> float:
     """Connection radius of the double integrator at n samples: r = 1.75 at
     n = 16384, scaled by (16384 / n)^(1/6) so that the mean in-degree stays
     near its value at n = 16384 as n changes."""
-    return 1.75 * (16384.0 / float(n)) ** (1.0 / 6.0)
+    from .inputs import di_radius_of
+    return di_radius_of(n)
+
+
+def shared_roadmap_radius(dim: int, n: int, factor: float = 1.1) -> float:
+    """Radius of a roadmap shared by many box worlds: Theorem 1 with the
+    obstacle-free volume (Euclidean), or di_radius (double integrator)."""
+    return di_radius(n) if dim == 6 else theorem1_radius(dim, 1.0, n, factor)
