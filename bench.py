@@ -24,9 +24,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
 # with this digest and the launch shape named; reported only while both match
-TRAFFIC = {"sources_sha256": "a67cb3fb1fb2f18ccf98e156d4c707f2040c34782f8e55738372c55b68bc0771",
+TRAFFIC = {"sources_sha256": "cc5d775df7bf6df9bd3c961aa12f93836bbc6387ae46a15f34b8a183e335df9d",
            "batch": 4096, "lanes": 8, "threads": 1024,
-           "bytes_per_launch": int((2.0 * 65585970 + 5059144) * 1024)}
+           "bytes_per_launch": int((2.0 * 70667371 + 5053419) * 1024)}
 
 
 def kernel_digest():
