@@ -269,23 +269,39 @@ __device__ __forceinline__ DiPair di_pair(const double *src, const double *dst) 
     return d;
 }
 
-// One wave per target row x.  count_only: deg[x] only; else write the row.
-__global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, int n, double r,
-                                                 int count_only, const int *__restrict__ row_ptr,
-                                                 int *__restrict__ deg, int *__restrict__ maxdeg,
+// One wave per target row x (or per entry of `rows`: count rows[0], list
+// from rows[1]).  The sources y are scanned in increasing order, prefiltered
+// by a lower bound on J, queued in LDS, and solved one per lane, so each row
+// comes out ascending.  Modes:
+//   DI_FILL    write the row at row_ptr[x];
+//   DI_SCRATCH write the row into scratch slot x of `cap` entries (entries
+//              past cap are dropped and x is appended to `ovf`: count ovf[0],
+//              list from ovf[1]); deg[x] receives the full row length.
+enum { DI_FILL = 0, DI_SCRATCH = 2 };
+
+__global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, int n, double r, int mode,
+                                                 const int *__restrict__ rows, const int *__restrict__ row_ptr,
+                                                 int cap, int *__restrict__ deg, int *__restrict__ ovf,
                                                  int *__restrict__ col, double *__restrict__ cost,
                                                  double *__restrict__ tau) {
     __shared__ int queue[4][DI_QCAP];
     const int wl = threadIdx.x / GMT_WAVE;
     const int lane = lane_id();
-    int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
-    if (x >= n) return;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
+    int x;
+    if (rows) {
+        if (wid >= rows[0]) return;
+        x = rows[1 + wid];
+    } else {
+        if (wid >= n) return;
+        x = wid;
+    }
     int *qu = queue[wl];
     double xs[6];
     di_load(s, n, x, xs);
     int qn = 0;      // queued survivors (wave-uniform)
     int found = 0;   // neighbours emitted so far (wave-uniform)
-    const int base = count_only ? 0 : row_ptr[x];
+    const long long base = mode == DI_FILL ? (long long)row_ptr[x] : (long long)x * cap;
     auto drain = [&](int take) {
         // solve the first `take` queued sources, one per lane, in order
         bool hit = false;
@@ -300,11 +316,11 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
             hit = J < r;
         }
         uint64_t m = wave_ballot(hit);
-        if (!count_only && hit) {
-            int slot = base + found + lanes_below(m);
-            col[slot] = y;
-            cost[slot] = J;
-            tau[slot] = t;
+        const int k = found + lanes_below(m);
+        if (hit && (mode == DI_FILL || k < cap)) {
+            col[base + k] = y;
+            cost[base + k] = J;
+            tau[base + k] = t;
         }
         found += (int)__popcll(m);
         __builtin_amdgcn_wave_barrier();
@@ -333,9 +349,29 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         if (qn >= GMT_WAVE) drain(GMT_WAVE);
     }
     while (qn > 0) drain(qn < GMT_WAVE ? qn : GMT_WAVE);
-    if (lane == 0) {
+    if (lane == 0 && mode == DI_SCRATCH) {
         deg[x] = found;
-        if (count_only) atomicMax(maxdeg, found);
+        if (found > cap) ovf[1 + atomicAdd(&ovf[0], 1)] = x;
+    }
+}
+
+// scratch rows (cap entries each) -> CSR; rows longer than cap are left to
+// a DI_FILL pass over the overflow list.  One wave per row.
+__global__ void __launch_bounds__(256) k_di_compact(int n, int cap, const int *__restrict__ deg,
+                                                    const int *__restrict__ row_ptr, const int *__restrict__ scol,
+                                                    const double *__restrict__ scost, const double *__restrict__ stau,
+                                                    int *__restrict__ col, double *__restrict__ cost,
+                                                    double *__restrict__ tau) {
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
+    if (x >= n) return;
+    const int d = deg[x];
+    if (d > cap) return;
+    const size_t src = (size_t)x * cap;
+    const int dst = row_ptr[x];
+    for (int k = lane_id(); k < d; k += GMT_WAVE) {
+        col[dst + k] = scol[src + k];
+        cost[dst + k] = scost[src + k];
+        tau[dst + k] = stau[src + k];
     }
 }
 

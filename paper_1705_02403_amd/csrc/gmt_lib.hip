@@ -312,28 +312,45 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     return pack_records(rm, s);
 }
 
+// One pass over all ordered pairs writes each row into a scratch slot of
+// kDiScratchCap entries; the rows are then compacted into the CSR table, and
+// the few longer rows are recomputed straight into it.
+static const int kDiScratchCap = 384;
+
 static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n;
-    DevBuf deg, scal;
+    const int cap = kDiScratchCap;
+    DevBuf deg, scal, ovf, scol, scost, stau;
     TRY(dev_alloc(deg, sizeof(int) * n, s));
     TRY(dev_alloc(scal, 64, s));
+    TRY(dev_alloc(ovf, sizeof(int) * ((size_t)n + 1), s));
     TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
-    int *flags = (int *)scal.p, *maxdeg = flags + 1;
+    gmt_status st = dev_alloc(scol, sizeof(int) * (size_t)n * cap, s);
+    if (st == GMT_OK) st = dev_alloc(scost, sizeof(double) * (size_t)n * cap, s);
+    if (st == GMT_OK) st = dev_alloc(stau, sizeof(double) * (size_t)n * cap, s);
+    int *flags = (int *)scal.p;
     long long *total = (long long *)(flags + 2);
-    k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
-    k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
-    k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
-        (const float *)rm->s.p, n, rm->r, 1, nullptr, (int *)deg.p, maxdeg, nullptr, nullptr, nullptr);
-    k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
-    HIPCHK(hipGetLastError());
-    int hs[4];
-    HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    long long E;
+    int hs[4] = {0, 0, 0, 0}, novf = 0;
+    if (st == GMT_OK) {
+        k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
+        k_fill_int<<<1, 64, 0, s>>>((int *)ovf.p, 1, 0);
+        k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
+        k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
+            (const float *)rm->s.p, n, rm->r, DI_SCRATCH, nullptr, nullptr, cap, (int *)deg.p, (int *)ovf.p,
+            (int *)scol.p, (double *)scost.p, (double *)stau.p);
+        k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&novf, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour pass failed: %s", hipGetErrorString(e));
+    }
+    long long E = 0;
     std::memcpy(&E, hs + 2, sizeof E);
-    gmt_status st = GMT_OK;
-    if (hs[0]) st = fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, on the 2^-20 grid");
-    else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    if (st == GMT_OK) {
+        if (hs[0]) st = fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, on the 2^-20 grid");
+        else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    }
     if (st == GMT_OK) {
         rm->nnz = E;
         size_t e1 = (size_t)std::max<long long>(E, 1);
@@ -342,13 +359,17 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
         if (st == GMT_OK) st = dev_alloc(rm->in_tau, sizeof(double) * e1, s);
     }
     if (st == GMT_OK) {
-        k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
-            (const float *)rm->s.p, n, rm->r, 0, (const int *)rm->in_ptr.p, (int *)deg.p, maxdeg,
-            (int *)rm->in_col.p, (double *)rm->in_cost.p, (double *)rm->in_tau.p);
+        k_di_compact<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
+            n, cap, (const int *)deg.p, (const int *)rm->in_ptr.p, (const int *)scol.p, (const double *)scost.p,
+            (const double *)stau.p, (int *)rm->in_col.p, (double *)rm->in_cost.p, (double *)rm->in_tau.p);
+        if (novf > 0)
+            k_di_rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
+                (const float *)rm->s.p, n, rm->r, DI_FILL, (const int *)ovf.p, (const int *)rm->in_ptr.p, cap,
+                nullptr, nullptr, (int *)rm->in_col.p, (double *)rm->in_cost.p, (double *)rm->in_tau.p);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
     }
-    dev_free(deg, s);
+    for (DevBuf *b : {&deg, &ovf, &scol, &scost, &stau}) dev_free(*b, s);
     if (st == GMT_OK) st = build_out_table(rm, s);
     if (st == GMT_OK) st = pack_records(rm, s);
     dev_free(scal, s);

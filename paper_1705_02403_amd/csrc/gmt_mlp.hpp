@@ -297,15 +297,19 @@ __global__ void k_fill_f32(long long n, float *__restrict__ p, float v) {
 // inference
 // ---------------------------------------------------------------------------
 // first-layer pre-activation shared by every sample of one query: the
-// condition's part of W1 x + b1 (condition rounded to BF16 as in training)
-__global__ void k_cond_bias(int H, const unsigned short *__restrict__ W1, const float *__restrict__ b1,
-                            const float *__restrict__ cond, float *__restrict__ h0) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+// condition's part of W1 x + b1 (condition rounded to BF16 as in training).
+// One wave per output: lanes read the weight row coalesced, then reduce.
+__global__ void __launch_bounds__(256) k_cond_bias(int H, const unsigned short *__restrict__ W1,
+                                                   const float *__restrict__ b1, const float *__restrict__ cond,
+                                                   float *__restrict__ h0) {
+    const int n = (blockIdx.x * blockDim.x + threadIdx.x) / 64, lane = threadIdx.x & 63;
     if (n >= H) return;
     float s = 0.f;
-    for (int k = 0; k < MLP_COND; ++k)
+    for (int k = lane; k < MLP_COND; k += 64)
         s += bf2f(W1[(size_t)n * MLP_IN + MLP_COND0 + k]) * bf2f(f2bf(cond[k]));
-    h0[n] = s + b1[n];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) h0[n] = s + b1[n];
 }
 
 // prior draws z = eps as BF16 rows of 8

@@ -399,8 +399,8 @@ gmt_status decode_impl(gmt_sampler *s, const float *cond, const float *d_eps, in
     const NetOff o = net_off(1);
     const uint16_t *Wb = (const uint16_t *)s->Pb.p;
     const float *P = (const float *)s->P.p;
-    k_cond_bias<<<1, H, 0, st>>>(H, (const unsigned short *)(Wb + o.W1), P + o.b1, (const float *)s->icond.p,
-                                 (float *)s->h0.p);
+    k_cond_bias<<<blocks(64LL * H, 256), 256, 0, st>>>(H, (const unsigned short *)(Wb + o.W1), P + o.b1,
+                                                       (const float *)s->icond.p, (float *)s->h0.p);
     k_pack_z<<<blocks((long long)count * 8, 256), 256, 0, st>>>(count, d_eps, (unsigned short *)s->Z8.p);
     HIPCHK(hipGetLastError());
     // first layer over the z columns only: the condition's share is h0

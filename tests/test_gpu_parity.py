@@ -102,11 +102,12 @@ def test_euclid_table_tiny(n):
     rm.free()
 
 
-@pytest.mark.parametrize("seed,n", [(0, 1024), (1, 2048), (2, 777)])
-def test_di_table(seed, n):
+@pytest.mark.parametrize("seed,n,r", [(0, 1024, None), (1, 2048, None), (2, 777, None),
+                                      (3, 2048, 3.0)])  # rows of up to 699: past the scratch capacity
+def test_di_table(seed, n, r):
     say("di table seed %d n %d" % (seed, n))
     s = I.di_samples(seed, n)
-    r = 1.75 * (16384.0 / n) ** (1.0 / 6.0)
+    r = r or 1.75 * (16384.0 / n) ** (1.0 / 6.0)
     rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, r)
     rp, col, cost, tau = rm.export()
     ref = O.neighbors(s, O.DI, r)
