@@ -111,7 +111,8 @@ typedef struct {
 
 /* Install the device allocator (NULL restores hipMalloc/hipFree).  Affects
  * allocations made after the call; memory is returned to the allocator that
- * produced it. */
+ * produced it, so an allocator's callbacks must stay valid until everything
+ * it allocated has been freed. */
 gmt_status gmt_set_allocator(const gmt_allocator *allocator);
 
 /* Build the r-disk neighbour table over n samples on the GPU (the offline

@@ -259,24 +259,28 @@ def _host_f32(a) -> np.ndarray:
 
 
 def use_torch_allocator() -> None:
-    """Route the library's device allocations through torch's caching allocator."""
+    """Route the library's device allocations through torch's caching allocator.
+
+    The callbacks are created once and kept for the life of the process: every
+    device buffer remembers the allocator that produced it and calls its free
+    callback later, so the callbacks must outlive all buffers."""
     global _alloc_keep
     import torch
 
-    @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
-    def _alloc(nbytes, ctx, stream):
-        try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0) or None)
-        except Exception:
-            return None
+    if _alloc_keep is None:
+        @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+        def _alloc(nbytes, ctx, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0) or None)
+            except Exception:
+                return None
 
-    @C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
-    def _free(ptr, ctx, stream):
-        torch.cuda.caching_allocator_delete(int(ptr))
+        @C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+        def _free(ptr, ctx, stream):
+            torch.cuda.caching_allocator_delete(int(ptr))
 
-    a = gmt_allocator(_alloc, _free, None)
-    _alloc_keep = (a, _alloc, _free)
-    _check(lib().gmt_set_allocator(C.byref(a)), "gmt_set_allocator")
+        _alloc_keep = (gmt_allocator(_alloc, _free, None), _alloc, _free)
+    _check(lib().gmt_set_allocator(C.byref(_alloc_keep[0])), "gmt_set_allocator")
 
 
 # ---------------------------------------------------------------------------

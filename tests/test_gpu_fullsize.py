@@ -1,0 +1,145 @@
+"""Full-size parity (6D double integrator, n = 16384, r = 1.75) in the launch
+configurations the benchmark times, and host-forced failure paths.
+
+A batch of queries runs with one 1024-thread workgroup per query (state and
+costs-to-come in LDS, lanes 8); queries whose oracle run is decisive are
+compared tree for tree, and every tree of the batch is checked on sampled
+nodes against properties that hold at any size: each sampled node's cost is
+its parent's plus the oracle's cost of that edge, the edge passes the
+oracle's lazy check, and the parent was added earlier.  Single plans run
+with the default and the tuned team shapes."""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1705_02403_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1705_02403_amd import gmt
+
+N, R = 16384, 1.75
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def world():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    gmt.use_torch_allocator()
+    sets = {}
+    for ss in (0, 1):
+        s = I.di_samples(ss, N)
+        rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, R)
+        sets[ss] = (s, rm, O.neighbors(s, O.DI, R))
+    yield sets
+    for _, rm, _ in sets.values():
+        rm.free()
+
+
+def goal_of(p):
+    return gmt.make_goal(p.goal_center, p.goal_radius, 3)
+
+
+def check_tree_sampled(p, res, tab, rng, count=150):
+    par = res.parent.cpu().numpy()
+    cost = res.cost.cpu().numpy()
+    ai = res.added_iter.cpu().numpy()
+    n = p.n
+    in_tree = np.flatnonzero((par >= 0) & (np.arange(n + 1) < n))
+    assert np.all(np.isfinite(cost[in_tree]))
+    for x in rng.choice(in_tree, size=min(count, in_tree.size), replace=False):
+        y = int(par[x])
+        src = p.x_init if y == n else p.samples[:, y]
+        J, tau = O.di_cost(src, p.samples[:, x])
+        assert J < R
+        assert abs(cost[x] - (cost[y] + J)) <= 1e-12 * cost[x], (x, y)
+        free, _ = O.edge_free(p, y, int(x), tau)
+        assert free, (x, y)
+        assert ai[y] < ai[x] or y == n
+
+
+def test_batch_full_size_bench_shape(world):
+    say("full-size batch, lanes 8, 1024 threads")
+    rng = np.random.default_rng(0)
+    probs, qs = [], []
+    for k in range(48):
+        ss = k % 2
+        s, rm, _ = world[ss]
+        p = I.di_problem(5_000 + k, s, r=R, sample_seed=ss)
+        probs.append(p)
+        qs.append(gmt.BatchQuery(rm, p.x_init, goal_of(p), p.boxes, p.lam))
+    out = gmt.gmt_plan_batch(qs, gmt.make_opts(traj_points=16, lanes=8, threads=1024), outputs=True)
+    compared = 0
+    for p, res in zip(probs, out):
+        tab = world[p.sample_seed][2]
+        if compared < 6:
+            ref = O.plan(p, R, tab)
+            assert res.status == ref.status
+            if O.decisive(ref, O.DI, rel=1e-9, collide_abs=1e-9) and tab.margin > 1e-9:
+                np.testing.assert_array_equal(res.parent.cpu().numpy(), ref.parent)
+                np.testing.assert_array_equal(res.group_iter.cpu().numpy(), ref.group_iter)
+                np.testing.assert_allclose(res.cost.cpu().numpy()[np.isfinite(ref.cost)],
+                                           ref.cost[np.isfinite(ref.cost)], rtol=1e-12, atol=0)
+                compared += 1
+            elif ref.status == O.OK:
+                assert abs(res.path_cost - ref.path_cost) <= 1e-5 * ref.path_cost
+        if res.status == gmt.GMT_OK:
+            check_tree_sampled(p, res, tab, rng)
+    assert compared >= 3
+
+
+@pytest.mark.parametrize("team_wgs,threads,lanes", [(0, 0, 0), (64, 256, 32), (32, 1024, 32)])
+def test_single_full_size(world, team_wgs, threads, lanes):
+    say("full-size single plan %d x %d, lanes %d" % (team_wgs, threads, lanes))
+    s, rm, tab = world[1]
+    p = I.di_problem(6_001, s, r=R, sample_seed=1)
+    res = gmt.gmt_plan(rm, p.x_init, goal_of(p), p.boxes, p.lam,
+                       gmt.make_opts(traj_points=16, team_wgs=team_wgs, threads=threads, lanes=lanes))
+    ref = O.plan(p, R, tab)
+    assert res.status == ref.status
+    if ref.status == O.OK:
+        assert abs(res.path_cost - ref.path_cost) <= 1e-12 * ref.path_cost
+        check_tree_sampled(p, res, tab, np.random.default_rng(1))
+
+
+def test_forced_failures(world):
+    say("forced failures")
+    s, rm, _ = world[0]
+    p = I.di_problem(7_000, s, r=R)
+    o = gmt.make_opts(traj_points=16)
+    # non-finite start
+    bad = p.x_init.copy()
+    bad[0] = np.nan
+    with pytest.raises(gmt.GmtError) as e:
+        gmt.gmt_plan(rm, bad, goal_of(p), p.boxes, p.lam, o)
+    assert e.value.status == gmt.GMT_EINVAL
+    # an allocator that fails: the build reports GMT_ENOMEM and nothing leaks
+    @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+    def no_alloc(nbytes, ctx, stream):
+        return None
+
+    @C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+    def no_free(ptr, ctx, stream):
+        pass
+
+    a = gmt.gmt_allocator(no_alloc, no_free, None)
+    assert gmt.lib().gmt_set_allocator(C.byref(a)) == gmt.GMT_OK
+    try:
+        with pytest.raises(gmt.GmtError) as e:
+            gmt.gmt_build_neighbors(torch.from_numpy(s[:, :1024].copy()).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, 2.5)
+        assert e.value.status == gmt.GMT_ENOMEM
+    finally:
+        gmt.use_torch_allocator()
+    # the library still works afterwards
+    res = gmt.gmt_plan(rm, p.x_init, goal_of(p), p.boxes, p.lam, o, outputs=False)
+    assert res.status in (gmt.GMT_OK, gmt.GMT_NO_PATH)
