@@ -88,16 +88,19 @@ __global__ void k_check_samples(const float *__restrict__ s, int n, int dim, int
     if (bad) atomicOr(&flags[0], 1);
 }
 
-// in-table records for the parent search: (column, edge cost) as three
-// 32-bit words per edge, so one load brings both
-__global__ void k_pack_rec(long long E, const int *__restrict__ col, const double *__restrict__ cost,
-                           unsigned int *__restrict__ rec) {
+// in-table records for the parent search: (edge cost low word, high word,
+// column) as three 32-bit words per edge, so one load brings both and the
+// cost lands in an aligned register pair; records E .. total-1 are
+// padding (column 0, cost 0)
+__global__ void k_pack_rec(long long E, long long total, const int *__restrict__ col,
+                           const double *__restrict__ cost, unsigned int *__restrict__ rec) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    const unsigned long long b = (unsigned long long)__double_as_longlong(cost[e]);
-    rec[3 * e] = (unsigned int)col[e];
-    rec[3 * e + 1] = (unsigned int)(b & 0xffffffffull);
-    rec[3 * e + 2] = (unsigned int)(b >> 32);
+    if (e >= total) return;
+    const bool real = e < E;
+    const unsigned long long b = real ? (unsigned long long)__double_as_longlong(cost[e]) : 0ull;
+    rec[3 * e] = (unsigned int)(b & 0xffffffffull);
+    rec[3 * e + 1] = (unsigned int)(b >> 32);
+    rec[3 * e + 2] = real ? (unsigned int)col[e] : 0u;
 }
 
 // ---------------------------------------------------------------------------

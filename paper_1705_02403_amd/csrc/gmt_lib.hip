@@ -162,7 +162,7 @@ struct gmt_roadmap {
     double r = 0.0;
     long long nnz = 0;
     DevBuf s, in_ptr, in_col, in_cost, in_tau, out_ptr, out_col;
-    DevBuf in_rec;  // (column, edge cost) records of the in-table, 12 bytes per edge
+    DevBuf in_rec;  // (edge cost, column) records of the in-table, 12 bytes per edge
     bool out_shared = false;
 };
 
@@ -226,13 +226,14 @@ static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
     return GMT_OK;
 }
 
-// records of the finished in-table (column, edge cost)
+// records of the finished in-table (edge cost, column), followed by the
+// padding records the parent search may read past the last row
 static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
     const long long E = rm->nnz;
-    TRY(dev_alloc(rm->in_rec, 12 * (size_t)std::max<long long>(E, 1), s));
-    if (E > 0)
-        k_pack_rec<<<blocks_for(E, 256), 256, 0, s>>>(E, (const int *)rm->in_col.p, (const double *)rm->in_cost.p,
-                                                      (unsigned int *)rm->in_rec.p);
+    TRY(dev_alloc(rm->in_rec, 12 * (size_t)(E + GMT_REC_PAD), s));
+    k_pack_rec<<<blocks_for(E + GMT_REC_PAD, 256), 256, 0, s>>>(E, E + GMT_REC_PAD, (const int *)rm->in_col.p,
+                                                                (const double *)rm->in_cost.p,
+                                                                (unsigned int *)rm->in_rec.p);
     HIPCHK(hipGetLastError());
     return GMT_OK;
 }

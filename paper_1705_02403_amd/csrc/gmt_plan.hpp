@@ -60,7 +60,7 @@ struct RoadmapDev {
     double r, R2;
     const float *s;  // SoA [dim][n]
     const int *in_ptr;
-    const unsigned int *in_rec;  // per in-edge: column, edge cost (low, high words)
+    const unsigned int *in_rec;  // per in-edge: edge cost (low, high words), column
     const double *in_tau;  // double integrator only
     const int *out_ptr;
     const int *out_col;
@@ -354,54 +354,64 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 
 // Scan the in-row [ib, ie) of candidate x with the CL lanes of a group for
 // the lexicographic minimum of (cost[y] + c(y, x), y) over open y.  Loads are
-// issued in stages of SCAN_U edges per lane -- the (column, edge cost)
-// records, then the state bytes, then the costs-to-come -- so a lane keeps
-// SCAN_U independent loads in flight per stage instead of one dependent
-// chain per edge.  Lanes whose edge is absent or not open read a fixed valid
-// address (cost[x]) and ignore the value.
+// issued in stages of SCAN_U edges per lane -- the (edge cost, column)
+// records, then the state bytes (and costs), then the update -- so a lane
+// keeps SCAN_U independent loads in flight per stage instead of one dependent
+// chain per edge.  The body is branch-free: every read is issued unconditionally
+// (from valid addresses) and the minimum is updated by selects.
 //
-// EAGER (state bytes in global memory): the costs are loaded together with
-// the state bytes rather than after them, one dependent round trip fewer;
-// values of nodes that are not open are read and ignored (a node committed
-// by this iteration may be written meanwhile; it is not open either way).
+// The costs-to-come of all read slots are loaded unconditionally when they
+// live in LDS (COST_LDS) or when the state bytes are in global memory (EAGER:
+// one dependent round trip fewer; values of nodes that are not open are read
+// and ignored -- a node committed by this iteration may be written meanwhile,
+// and it is not open either way).  Otherwise (state in LDS, costs in global
+// memory) only open slots read their own cost, the others cost[x].
 #define SCAN_U 8
 #define FRONT_U 4
-template <int CL, bool EAGER>
+typedef __attribute__((address_space(1))) const unsigned int global_u32;
+// records past the end of the table, (column 0, cost 0), so that the slots of
+// a stage that run past the last row stay inside the allocation
+#define GMT_REC_PAD 256
+static_assert(SCAN_U * 32 <= GMT_REC_PAD, "record padding must cover one stage of the widest lane group");
+
+template <int CL, bool EAGER, bool COST_LDS>
 __device__ __forceinline__ void scan_row(const unsigned char *st, const double *__restrict__ cost,
-                                         const unsigned int *__restrict__ rec, int x, int ib, int ie, int lg,
+                                         const unsigned int *rec_in, int x, int ib, int ie, int lg,
                                          double &best, int &by, int &be) {
-    for (int f0 = ib + lg; f0 < ie; f0 += SCAN_U * CL) {
+    // slots past the row end read the records that follow it (other rows or
+    // the padding): valid columns, masked off below
+    global_u32 *rp = (global_u32 *)rec_in + 3 * (long long)(ib + lg);
+    for (int f0 = ib + lg; f0 < ie; f0 += SCAN_U * CL, rp += 3 * SCAN_U * CL) {
         int y[SCAN_U];
-        bool op[SCAN_U];
+        bool in_row[SCAN_U];
         double ic[SCAN_U];
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
-            const int f = f0 + u * CL;
-            const unsigned int *r = rec + 3 * (size_t)(f < ie ? f : ib);
-            y[u] = (int)r[0];
-            ic[u] = __hiloint2double((int)r[2], (int)r[1]);
+            in_row[u] = f0 + u * CL < ie;
+            ic[u] = __hiloint2double((int)rp[3 * u * CL + 1], (int)rp[3 * u * CL]);
+            y[u] = (int)rp[3 * u * CL + 2];
         }
+        unsigned int sv[SCAN_U];
         double c[SCAN_U];
-        if (EAGER) {
 #pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) {
-                c[u] = cost[y[u]];
-                op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
-            }
-        } else {
+        for (int u = 0; u < SCAN_U; ++u) {
+            sv[u] = st[y[u]];
+            if (EAGER || COST_LDS) c[u] = cost[y[u]];
+        }
+        bool op[SCAN_U];
 #pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) op[u] = (f0 + u * CL < ie) && ((st[y[u]] & 3) == 1);
+        for (int u = 0; u < SCAN_U; ++u) op[u] = in_row[u] & ((sv[u] & 3u) == 1u);
+        if (!(EAGER || COST_LDS)) {
 #pragma unroll
             for (int u = 0; u < SCAN_U; ++u) c[u] = cost[op[u] ? y[u] : x];
         }
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
             const double v = c[u] + ic[u];
-            if (op[u] && (v < best || (v == best && y[u] < by))) {
-                best = v;
-                by = y[u];
-                be = f0 + u * CL;
-            }
+            const bool better = op[u] & ((v < best) | ((v == best) & (y[u] < by)));
+            best = better ? v : best;
+            by = better ? y[u] : by;
+            be = better ? f0 + u * CL : be;
         }
     }
 }
@@ -742,7 +752,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    scan_row<CL, LDS == 0>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
+                    scan_row<CL, LDS == 0, LDS == 2>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && by != 0x7fffffff;
