@@ -25,46 +25,97 @@ namespace gmt {
 // generic helpers
 // ---------------------------------------------------------------------------
 
-// exclusive scan of in[0..count) into out[0..count] (out[count] = total) by
-// one workgroup of 1024 threads; returns nothing, total also in *total
-__global__ void __launch_bounds__(1024) k_scan_small(const int *__restrict__ in, int count,
-                                                     int *__restrict__ out, long long *total) {
-    __shared__ int wsum[16];
+// Exclusive scan of count ints of any length in three launches: each
+// 1024-thread workgroup scans a tile of SCAN_TILE elements (4 per thread) and
+// writes its total; one workgroup scans the totals (64-bit, so a sum beyond
+// the int32 range is seen by the caller); the tile offsets are added last,
+// and out[count] = total.  Partial sums are exact whenever the total fits in
+// int32, the only case in which the caller uses them.
+#define SCAN_TILE 4096
+
+__global__ void __launch_bounds__(1024) k_scan_tile(const int *__restrict__ in, int count, int *__restrict__ out,
+                                                    long long *__restrict__ tsum) {
+    __shared__ long long wsum[16];
+    const int t = threadIdx.x, lane = lane_id(), w = t / GMT_WAVE;
+    const long long base = (long long)blockIdx.x * SCAN_TILE + 4 * t;
+    int v[4];
+    if (base + 3 < count) {
+        const int4 q = *(const int4 *)(in + base);
+        v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = base + u < count ? in[base + u] : 0;
+    }
+    const long long s = (long long)v[0] + v[1] + v[2] + v[3];
+    long long x = s;
+#pragma unroll
+    for (int off = 1; off < GMT_WAVE; off <<= 1) {
+        const long long y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == GMT_WAVE - 1) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        long long a = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const long long y = __shfl_up(a, off);
+            if (lane >= off) a += y;
+        }
+        if (lane < 16) wsum[lane] = a;
+    }
+    __syncthreads();
+    long long e = x - s + (w > 0 ? wsum[w - 1] : 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (base + u < count) out[base + u] = (int)e;
+        e += v[u];
+    }
+    if (t == 0) tsum[blockIdx.x] = wsum[15];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(const long long *__restrict__ tsum, int nt,
+                                                   long long *__restrict__ toff, long long *__restrict__ total) {
+    __shared__ long long wsum[16];
     __shared__ long long carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     const int lane = lane_id(), w = threadIdx.x / GMT_WAVE;
-    for (int base = 0; base < count; base += 1024) {
-        int i = base + (int)threadIdx.x;
-        int v = i < count ? in[i] : 0;
-        int x = v;
+    for (int b = 0; b < nt; b += 1024) {
+        const int i = b + (int)threadIdx.x;
+        const long long v = i < nt ? tsum[i] : 0;
+        long long x = v;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            int y = __shfl_up(x, off);
+        for (int off = 1; off < GMT_WAVE; off <<= 1) {
+            const long long y = __shfl_up(x, off);
             if (lane >= off) x += y;
         }
-        if (lane == 63) wsum[w] = x;
+        if (lane == GMT_WAVE - 1) wsum[w] = x;
         __syncthreads();
         if (w == 0) {
-            int s = lane < 16 ? wsum[lane] : 0;
+            long long a = lane < 16 ? wsum[lane] : 0;
 #pragma unroll
             for (int off = 1; off < 16; off <<= 1) {
-                int y = __shfl_up(s, off);
-                if (lane >= off) s += y;
+                const long long y = __shfl_up(a, off);
+                if (lane >= off) a += y;
             }
-            if (lane < 16) wsum[lane] = s;
+            if (lane < 16) wsum[lane] = a;
         }
         __syncthreads();
-        long long excl = carry + (long long)(x - v) + (w > 0 ? wsum[w - 1] : 0);
-        if (i < count) out[i] = (int)excl;
+        const long long e = carry + x - v + (w > 0 ? wsum[w - 1] : 0);
+        if (i < nt) toff[i] = e;
         __syncthreads();
-        if (threadIdx.x == 1023) carry = excl + v;
+        if (threadIdx.x == 1023) carry = e + v;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out[count] = (int)carry;
-        if (total) *total = carry;
-    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int *__restrict__ out, int count, const long long *__restrict__ toff,
+                           const long long *__restrict__ total) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] += (int)toff[i / SCAN_TILE];
+    else if (i == count) out[count] = (int)*total;
 }
 
 __global__ void k_fill_int(int *p, int count, int v) {
@@ -103,6 +154,12 @@ __global__ void k_pack_rec(long long E, long long total, const int *__restrict__
     rec[3 * e + 2] = real ? (unsigned int)col[e] : 0u;
 }
 
+// the padding records (column 0, cost 0) after the E records of a table
+__global__ void k_rec_pad(unsigned int *__restrict__ rec, long long E) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < 3 * GMT_REC_PAD) rec[3 * E + k] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // Euclidean table
 // ---------------------------------------------------------------------------
@@ -133,121 +190,181 @@ __global__ void k_eu_bin(const float *__restrict__ s, int n, EuGrid g, int *__re
     atomicAdd(&cell_cnt[c], 1);
 }
 
-// cell-sorted copy: perm[pos] = sample, sq[a][pos] = grid coordinate
+// cell-sorted copy of the samples: pts[pos] = (grid coordinates, sample index)
 __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
                              const int *__restrict__ cell_of, const int *__restrict__ cell_start,
-                             int *__restrict__ cursor, int *__restrict__ perm, int *__restrict__ sq) {
+                             int *__restrict__ cursor, int4 *__restrict__ pts) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = cell_of[i];
     int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
-    perm[pos] = i;
-    for (int a = 0; a < g.dim; ++a) sq[(size_t)a * n + pos] = (int)((double)s[(size_t)a * n + i] * GMT_QS);
+    int q[3] = {0, 0, 0};
+    for (int a = 0; a < g.dim; ++a) q[a] = (int)((double)s[(size_t)a * n + i] * GMT_QS);
+    pts[pos] = make_int4(q[0], q[1], q[2], i);
 }
 
-// Rows of the Euclidean table.  Cells have edge >= r/2 (G per axis) and the
-// samples are sorted by cell (perm, grid coordinates sq).  One 256-thread
-// workgroup per cell stages the samples of the 5^d cells around it in LDS,
-// in chunks of EU_CHUNK, and each wave takes rows of the cell in turn and
-// tests all staged samples, 64 at a time.  Grid coordinates differ by less
-// than 2^21, so d2 = |q_i - q_j|^2 is exact in FP64 (each square below 2^42,
-// the sum below 2^53).  COUNT: row lengths; otherwise the rows are written
-// (in staging order: the parent search does not depend on it) with costs
-// sqrt(d2) * 2^-20, rounded once.
-#define EU_CHUNK 1024
-#define EU_ROWS 1024
+// Rows of the Euclidean table.  Cells have edge >= r/2 (G per axis), so the
+// r-ball of a sample lies in the 5^d cells around its own; the samples are
+// sorted by cell (pts).  One 256-thread workgroup takes EU_XB cells that
+// follow each other along x: it stages the samples of the cells within two
+// cells of them in LDS (at most 25 runs of the sorted order, cells along x
+// being contiguous) in chunks of EU_CHUNK, padded to a multiple of 128 with
+// samples far outside every r-ball, and each wave takes rows in turn and
+// tests the staged samples 128 at a time (two per lane, their LDS reads
+// issued together).  Grid coordinates differ by less than 2^30, so d2 =
+// |q_i - q_j|^2 is exact in FP64 for real pairs (each square below 2^42, the
+// sum below 2^53) and far above r^2 for the padding.
+// COUNT: row lengths.  Otherwise the rows are written, in staging order
+// (the parent search does not depend on it), as (cost, column) records plus
+// the column array: each wave gathers the staging slots of its row's edges
+// in an LDS buffer of EU_OBUF entries and writes them out in contiguous
+// runs, taking the cost sqrt(d2) * 2^-20 (rounded once) per written edge,
+// not per test.
+#ifndef EU_XB
+#define EU_XB 2
+#endif
+#define EU_CHUNK 1280
+#define EU_ROWS 512
+#define EU_OBUF 256
+#define EU_FAR (1 << 29)
+static_assert(EU_CHUNK % 256 == 0 && EU_CHUNK <= 65536 && EU_OBUF >= 128, "staging and output buffer shapes");
+
+__device__ __forceinline__ double eu_d2(const int4 &c, const int4 &q) {
+    const double d0 = (double)(c.x - q.x), d1 = (double)(c.y - q.y), d2 = (double)(c.z - q.z);
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
 
 template <bool COUNT>
-__global__ void __launch_bounds__(256) k_eu_rows(int n, EuGrid g, const int *__restrict__ sq,
-                                                 const int *__restrict__ perm, const int *__restrict__ cell_start,
-                                                 double R2, int *__restrict__ deg, int *__restrict__ maxdeg,
-                                                 const int *__restrict__ row_ptr, int *__restrict__ col,
-                                                 double *__restrict__ cost) {
-    __shared__ int cq[3][EU_CHUNK];
-    __shared__ int cj[EU_CHUNK];
+__global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restrict__ pts,
+                                                 const int *__restrict__ cell_start, double R2,
+                                                 int *__restrict__ deg, int *__restrict__ maxdeg,
+                                                 const int *__restrict__ row_ptr, unsigned int *__restrict__ rec,
+                                                 int *__restrict__ col) {
+    __shared__ int4 cand[EU_CHUNK];
+    // per wave: EU_OBUF slots, then one that lanes without an edge write to
+    __shared__ unsigned short oslot[COUNT ? 1 : 4 * (EU_OBUF + 2)];
     __shared__ int rcnt[EU_ROWS];
     __shared__ int sb[25], soff[26];
-    const int c = blockIdx.x;
     const int G = g.G;
-    const int cx = c % G, cy = (c / G) % G, cz = g.dim == 3 ? c / (G * G) : 0;
-    const int p0 = cell_start[c], p1 = cell_start[c + 1];
+    const int GX = (G + EU_XB - 1) / EU_XB;
+    const int bx = blockIdx.x % GX, yz = blockIdx.x / GX;
+    const int cy = yz % G, cz = g.dim == 3 ? yz / G : 0;
+    const int cx0 = bx * EU_XB, cx1 = min(cx0 + EU_XB, G) - 1;
+    const int rowc = (cz * G + cy) * G;
+    const int p0 = cell_start[rowc + cx0], p1 = cell_start[rowc + cx1 + 1];
+    if (p0 == p1) return;  // no rows: the whole workgroup leaves
     const int tid = threadIdx.x, wave = tid / GMT_WAVE, lane = lane_id();
     const int zr = g.dim == 3 ? 2 : 0;
-    for (int rb = p0; rb < p1; rb += EU_ROWS) {  // blocks of rows of this cell
+    const int nspan = (2 * zr + 1) * 5;
+    if (tid < nspan) {
+        const int z = cz + tid / 5 - zr, y = cy + tid % 5 - 2;
+        int b = 0, e = 0;
+        if (z >= 0 && z < (g.dim == 3 ? G : 1) && y >= 0 && y < G) {
+            const int rc = (z * G + y) * G;
+            b = cell_start[rc + max(cx0 - 2, 0)];
+            e = cell_start[rc + min(cx1 + 2, G - 1) + 1];
+        }
+        sb[tid] = b;
+        soff[tid + 1] = e - b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        soff[0] = 0;
+        for (int k = 1; k <= nspan; ++k) soff[k] += soff[k - 1];
+    }
+    __syncthreads();
+    const int total = soff[nspan];
+    unsigned short *wslot = oslot + (COUNT ? 0 : wave * (EU_OBUF + 2));
+    for (int rb = p0; rb < p1; rb += EU_ROWS) {  // blocks of rows
         const int nr = min(EU_ROWS, p1 - rb);
         for (int i = tid; i < nr; i += 256) rcnt[i] = 0;
-        // test the rows of this block against staged samples [0, cnt)
-        auto process = [&](int cnt) {
-            __syncthreads();
-            for (int ri = wave; ri < nr; ri += 4) {
-                const int p = rb + ri;
-                const int self = perm[p];
-                const int q0 = sq[p], q1 = sq[(size_t)n + p], q2 = g.dim == 3 ? sq[2 * (size_t)n + p] : 0;
-                int run = 0;
-                const int base = COUNT ? 0 : row_ptr[self] + rcnt[ri];
-                for (int k0 = 0; k0 < cnt; k0 += GMT_WAVE) {
-                    const int k = k0 + lane;
-                    bool ok = false;
-                    double d2 = 0.0;
-                    if (k < cnt) {
-                        const double d0 = (double)(cq[0][k] - q0), d1 = (double)(cq[1][k] - q1),
-                                     dz = (double)(cq[2][k] - q2);
-                        d2 = d0 * d0 + d1 * d1 + dz * dz;
-                        ok = cj[k] != self && d2 < R2;
-                    }
-                    const uint64_t m = wave_ballot(ok);
-                    if (!COUNT && ok) {
-                        const int slot = base + run + lanes_below(m);
-                        col[slot] = cj[k];
-                        cost[slot] = sqrt(d2) * GMT_INV_QS;
-                    }
-                    run += (int)__popcll(m);
-                }
-                if (lane == 0) rcnt[ri] += run;
-            }
-            __syncthreads();
-        };
-        // the neighbourhood as at most 25 spans of the sorted order (cells
-        // along x are contiguous): bounds read in parallel, then flattened
-        const int nspan = (2 * zr + 1) * 5;
-        if (tid < nspan) {
-            const int z = cz + tid / 5 - zr, y = cy + tid % 5 - 2;
-            int b = 0, e = 0;
-            if (z >= 0 && z < (g.dim == 3 ? G : 1) && y >= 0 && y < G) {
-                const int rowc = (z * G + y) * G;
-                b = cell_start[rowc + max(cx - 2, 0)];
-                e = cell_start[rowc + min(cx + 2, G - 1) + 1];
-            }
-            sb[tid] = b;
-            soff[tid + 1] = e - b;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            soff[0] = 0;
-            for (int k = 1; k <= nspan; ++k) soff[k] += soff[k - 1];
-        }
-        __syncthreads();
-        const int total = soff[nspan];
         for (int c0 = 0; c0 < total; c0 += EU_CHUNK) {
             const int cnt = min(EU_CHUNK, total - c0);
-            for (int k = tid; k < cnt; k += 256) {
-                const int f = c0 + k;
-                int sp = 0;
-                while (soff[sp + 1] <= f) ++sp;
-                const int src = sb[sp] + (f - soff[sp]);
-                cq[0][k] = sq[src];
-                cq[1][k] = sq[(size_t)n + src];
-                cq[2][k] = g.dim == 3 ? sq[2 * (size_t)n + src] : 0;
-                cj[k] = perm[src];
+            const int cntp = (cnt + 127) & ~127;
+            __syncthreads();  // the previous chunk is no longer read
+            // stage [c0, c0 + cnt) and the padding up to cntp: up to
+            // EU_CHUNK / 256 samples per thread, loads issued together
+            constexpr int SU = EU_CHUNK / 256;
+            int4 v[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int k = tid + u * 256;
+                v[u] = make_int4(EU_FAR, EU_FAR, EU_FAR, -1);
+                if (k < cnt) {
+                    const int f = c0 + k;
+                    int lo = 0, hi = nspan;  // soff[lo] <= f < soff[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (soff[mid] <= f) lo = mid;
+                        else hi = mid;
+                    }
+                    v[u] = pts[sb[lo] + (f - soff[lo])];
+                }
             }
-            process(cnt);
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                if (tid + u * 256 < cntp) cand[tid + u * 256] = v[u];
+            __syncthreads();
+            for (int ri = wave; ri < nr; ri += 4) {
+                const int4 q = pts[rb + ri];
+                int run = 0, fill = 0;
+                long long dst = COUNT ? 0 : (long long)row_ptr[q.w] + rcnt[ri];
+                // write the buffered entries of this row out
+                // (up to EU_OBUF / 64 entries per lane, their LDS reads issued together)
+                auto flush = [&]() {
+                    constexpr int FU = EU_OBUF / GMT_WAVE;
+                    __builtin_amdgcn_wave_barrier();
+                    int sl[FU];
+#pragma unroll
+                    for (int u = 0; u < FU; ++u) {
+                        const int raw = wslot[lane + u * GMT_WAVE];
+                        sl[u] = lane + u * GMT_WAVE < fill ? raw : 0;
+                    }
+                    int4 c[FU];
+#pragma unroll
+                    for (int u = 0; u < FU; ++u) c[u] = cand[sl[u]];
+                    unsigned int *r = rec + 3 * (dst + lane);
+                    int *cp = col + dst + lane;
+#pragma unroll
+                    for (int u = 0; u < FU; ++u) {
+                        if (lane + u * GMT_WAVE < fill) {
+                            const unsigned long long bits =
+                                (unsigned long long)__double_as_longlong(sqrt(eu_d2(c[u], q)) * GMT_INV_QS);
+                            r[3 * u * GMT_WAVE] = (unsigned int)(bits & 0xffffffffull);
+                            r[3 * u * GMT_WAVE + 1] = (unsigned int)(bits >> 32);
+                            r[3 * u * GMT_WAVE + 2] = (unsigned int)c[u].w;
+                            cp[u * GMT_WAVE] = c[u].w;
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    dst += fill;
+                    fill = 0;
+                };
+                for (int k0 = 0; k0 < cntp; k0 += 2 * GMT_WAVE) {
+                    const int4 ca = cand[k0 + lane], cb = cand[k0 + GMT_WAVE + lane];
+                    const double da = eu_d2(ca, q), db = eu_d2(cb, q);
+                    const uint64_t ma = wave_ballot(da < R2 && ca.w != q.w);
+                    const uint64_t mb = wave_ballot(db < R2 && cb.w != q.w);
+                    const bool oka = (ma >> lane) & 1ull, okb = (mb >> lane) & 1ull;
+                    const int pa = (int)__popcll(ma), pb = (int)__popcll(mb);
+                    if (!COUNT) {
+                        if (fill + pa + pb > EU_OBUF) flush();
+                        wslot[oka ? fill + lanes_below(ma) : EU_OBUF] = (unsigned short)(k0 + lane);
+                        wslot[okb ? fill + pa + lanes_below(mb) : EU_OBUF] = (unsigned short)(k0 + GMT_WAVE + lane);
+                        fill += pa + pb;
+                    }
+                    run += pa + pb;
+                }
+                if (!COUNT) flush();
+                if (lane == 0) rcnt[ri] += run;
+            }
         }
+        __syncthreads();
         if (COUNT)
             for (int i = tid; i < nr; i += 256) {
-                deg[perm[rb + i]] = rcnt[i];
+                deg[pts[rb + i].w] = rcnt[i];
                 atomicMax(maxdeg, rcnt[i]);
             }
-        __syncthreads();
     }
 }
 

@@ -14,6 +14,9 @@
 #define GMT_WAVE 64
 #define GMT_QS 1048576.0        // 2^20 grid units per unit length
 #define GMT_INV_QS (1.0 / 1048576.0)
+// records after the last one of an in-table, (cost 0, column 0), so that
+// the parent search may read a few slots past the end of the last row
+#define GMT_REC_PAD 256
 #define GMT_Q2 1099511627776.0  // 2^40
 
 // node bookkeeping values
@@ -43,7 +46,8 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return (uint64_t)__bal
 
 // number of set bits of `mask` below this lane
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
-    return (int)__popcll(mask & ((1ull << lane_id()) - 1ull));
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned int)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned int)mask, 0u));
 }
 
 // lexicographic (value, index) minimum across the wave, carried payload e

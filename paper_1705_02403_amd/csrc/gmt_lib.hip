@@ -84,6 +84,17 @@ using gmt_host::dev_alloc;
 using gmt_host::dev_free;
 using gmt_host::fail;
 
+// temporaries of a build, returned to their allocator on every exit
+struct Temps {
+    hipStream_t s;
+    std::vector<DevBuf *> list;
+    Temps(hipStream_t s_, std::initializer_list<DevBuf *> l) : s(s_), list(l) {}
+    ~Temps() {
+        for (DevBuf *b : list) gmt_host::dev_free(*b, s);
+    }
+};
+
+
 extern "C" gmt_status gmt_set_allocator(const gmt_allocator *allocator) {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     if (allocator && (!allocator->alloc || !allocator->free))
@@ -161,8 +172,9 @@ struct gmt_roadmap {
     int n = 0, dim = 0, kind = 0;
     double r = 0.0;
     long long nnz = 0;
-    DevBuf s, in_ptr, in_col, in_cost, in_tau, out_ptr, out_col;
-    DevBuf in_rec;  // (edge cost, column) records of the in-table, 12 bytes per edge
+    DevBuf s, in_ptr, in_col, in_tau, out_ptr, out_col;
+    DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
+    DevBuf in_rec;   // (edge cost, column) records of the in-table, 12 bytes per edge
     bool out_shared = false;
 };
 
@@ -202,10 +214,27 @@ static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
 
 static inline unsigned blocks_for(long long threads, int per) { return (unsigned)((threads + per - 1) / per); }
 
-// out-neighbour table by transposing the in-table, rows sorted
+// exclusive scan of in[0, count) into out[0, count], out[count] = total; the
+// 64-bit total also goes to *total when given (device memory)
+static gmt_status scan_ints(const int *in, int count, int *out, long long *total, hipStream_t s) {
+    const int nt = std::max(1, (int)(((long long)count + SCAN_TILE - 1) / SCAN_TILE));
+    DevBuf tb;
+    Temps keep(s, {&tb});
+    TRY(dev_alloc(tb, sizeof(long long) * (2 * (size_t)nt + 1), s));
+    long long *tsum = (long long *)tb.p, *toff = tsum + nt;
+    long long *tot = total ? total : toff + nt;
+    k_scan_tile<<<nt, 1024, 0, s>>>(in, count, out, tsum);
+    k_scan_top<<<1, 1024, 0, s>>>(tsum, nt, toff, tot);
+    k_scan_add<<<blocks_for((long long)count + 1, 256), 256, 0, s>>>(out, count, toff, tot);
+    HIPCHK(hipGetLastError());
+    return GMT_OK;
+}
+
+// out-neighbour table by transposing the in-table
 static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n;
     DevBuf deg, cursor;
+    Temps keep(s, {&deg, &cursor});
     TRY(dev_alloc(rm->out_ptr, sizeof(int) * (n + 1), s));
     TRY(dev_alloc(rm->out_col, sizeof(int) * std::max<long long>(rm->nnz, 1), s));
     rm->out_shared = false;
@@ -215,19 +244,18 @@ static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
     k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)cursor.p, n, 0);
     const unsigned wave_blocks = blocks_for((long long)n * GMT_WAVE, 256);
     k_out_count<<<wave_blocks, 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n, (int *)deg.p);
-    k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->out_ptr.p, nullptr);
+    TRY(scan_ints((const int *)deg.p, n, (int *)rm->out_ptr.p, nullptr, s));
     k_out_place<<<wave_blocks, 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
                                             (const int *)rm->out_ptr.p, (int *)cursor.p, (int *)rm->out_col.p);
     // out-rows stay in placement order: the frontier's candidate order does not
     // affect any decision of an iteration
     HIPCHK(hipGetLastError());
-    dev_free(deg, s);
-    dev_free(cursor, s);
     return GMT_OK;
 }
 
 // records of the finished in-table (edge cost, column), followed by the
-// padding records the parent search may read past the last row
+// padding records the parent search may read past the last row; the FP64
+// cost array is not kept once its values are in the records
 static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
     const long long E = rm->nnz;
     TRY(dev_alloc(rm->in_rec, 12 * (size_t)(E + GMT_REC_PAD), s));
@@ -235,12 +263,16 @@ static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
                                                                 (const double *)rm->in_cost.p,
                                                                 (unsigned int *)rm->in_rec.p);
     HIPCHK(hipGetLastError());
+    dev_free(rm->in_cost, s);
     return GMT_OK;
 }
 
 static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n, dim = rm->dim;
-    const double R2 = rm->r * rm->r * GMT_Q2;
+    // squared radius in grid units; every pair of the unit cube lies below
+    // 4 * 2^40, so a larger radius selects the same pairs (and the kernel's
+    // padding samples stay outside)
+    const double R2 = std::min(rm->r * rm->r * GMT_Q2, 4.0 * GMT_Q2);
     EuGrid g;
     g.dim = dim;
     // cells of edge >= r/2 (the 5^d cells around a sample cover its r-ball),
@@ -251,13 +283,13 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     g.G = (int)std::max(1.0, std::min({per_axis, (double)Gmax, (double)Gn}));
     g.ncell = 1;
     for (int a = 0; a < dim; ++a) g.ncell *= g.G;
-    DevBuf cell_of, cell_cnt, cell_start, cursor, perm, sq, deg, scal;
+    DevBuf cell_of, cell_cnt, cell_start, cursor, pts, deg, scal;
+    Temps keep(s, {&cell_of, &cell_cnt, &cell_start, &cursor, &pts, &deg, &scal});
     TRY(dev_alloc(cell_of, sizeof(int) * n, s));
     TRY(dev_alloc(cell_cnt, sizeof(int) * g.ncell, s));
     TRY(dev_alloc(cell_start, sizeof(int) * (g.ncell + 1), s));
     TRY(dev_alloc(cursor, sizeof(int) * g.ncell, s));
-    TRY(dev_alloc(perm, sizeof(int) * n, s));
-    TRY(dev_alloc(sq, sizeof(int) * (size_t)dim * n, s));
+    TRY(dev_alloc(pts, sizeof(int4) * (size_t)n, s));
     TRY(dev_alloc(deg, sizeof(int) * n, s));
     TRY(dev_alloc(scal, 64, s));  // [0] flags, [1] maxdeg, [2..3] total (long long)
     TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
@@ -269,48 +301,35 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, dim, 0, flags);
     k_eu_bin<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (int *)cell_of.p,
                                                (int *)cell_cnt.p);
-    k_scan_small<<<1, 1024, 0, s>>>((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr);
+    TRY(scan_ints((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr, s));
     k_eu_scatter<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (const int *)cell_of.p,
-                                                   (const int *)cell_start.p, (int *)cursor.p,
-                                                   (int *)perm.p, (int *)sq.p);
-    k_eu_rows<true><<<g.ncell, 256, 0, s>>>(n, g, (const int *)sq.p, (const int *)perm.p, (const int *)cell_start.p,
-                                            R2, (int *)deg.p, maxdeg, nullptr, nullptr, nullptr);
-    k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
-    HIPCHK(hipGetLastError());
+                                                   (const int *)cell_start.p, (int *)cursor.p, (int4 *)pts.p);
+    // one workgroup per EU_XB cells along x
+    const unsigned wgs = (unsigned)((g.G + EU_XB - 1) / EU_XB) * (unsigned)g.G * (unsigned)(dim == 3 ? g.G : 1);
+    k_eu_rows<true><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, (int *)deg.p,
+                                        maxdeg, nullptr, nullptr, nullptr);
+    TRY(scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s));
     int hs[4];
     HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     long long E;
     std::memcpy(&E, hs + 2, sizeof E);
-    gmt_status st = GMT_OK;
-    if (hs[0]) st = fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
-    else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
-    if (st == GMT_OK) {
-        rm->nnz = E;
-        st = dev_alloc(rm->in_col, sizeof(int) * std::max<long long>(E, 1), s);
-        if (st == GMT_OK) st = dev_alloc(rm->in_cost, sizeof(double) * std::max<long long>(E, 1), s);
-    }
-    if (st == GMT_OK) {
-        k_eu_rows<false><<<g.ncell, 256, 0, s>>>(n, g, (const int *)sq.p, (const int *)perm.p,
-                                                 (const int *)cell_start.p, R2, nullptr, nullptr,
-                                                 (const int *)rm->in_ptr.p, (int *)rm->in_col.p,
-                                                 (double *)rm->in_cost.p);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
-    }
-    dev_free(cell_of, s);
-    dev_free(cell_cnt, s);
-    dev_free(cell_start, s);
-    dev_free(cursor, s);
-    dev_free(perm, s);
-    dev_free(sq, s);
-    dev_free(deg, s);
-    dev_free(scal, s);
-    if (st != GMT_OK) return st;
+    if (hs[0]) return fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
+    if (E > 0x7fffffffLL) return fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    rm->nnz = E;
+    TRY(dev_alloc(rm->in_col, sizeof(int) * std::max<long long>(E, 1), s));
+    TRY(dev_alloc(rm->in_rec, 12 * (size_t)(E + GMT_REC_PAD), s));
+    k_eu_rows<false><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, nullptr, nullptr,
+                                         (const int *)rm->in_ptr.p, (unsigned int *)rm->in_rec.p,
+                                         (int *)rm->in_col.p);
+    k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>((unsigned int *)rm->in_rec.p, E);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
+    // the table is symmetric: the in-table serves as the out-table
     rm->out_ptr = rm->in_ptr;
     rm->out_col = rm->in_col;
     rm->out_shared = true;
-    return pack_records(rm, s);
+    return GMT_OK;
 }
 
 // One pass over all ordered pairs writes each row into a scratch slot of
@@ -322,6 +341,7 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n;
     const int cap = kDiScratchCap;
     DevBuf deg, scal, ovf, scol, scost, stau;
+    Temps keep(s, {&deg, &scal, &ovf, &scol, &scost, &stau});
     TRY(dev_alloc(deg, sizeof(int) * n, s));
     TRY(dev_alloc(scal, 64, s));
     TRY(dev_alloc(ovf, sizeof(int) * ((size_t)n + 1), s));
@@ -339,7 +359,9 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
         k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
             (const float *)rm->s.p, n, rm->r, DI_SCRATCH, nullptr, nullptr, cap, (int *)deg.p, (int *)ovf.p,
             (int *)scol.p, (double *)scost.p, (double *)stau.p);
-        k_scan_small<<<1, 1024, 0, s>>>((const int *)deg.p, n, (int *)rm->in_ptr.p, total);
+        st = scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s);
+    }
+    if (st == GMT_OK) {
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&novf, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -373,7 +395,6 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     for (DevBuf *b : {&deg, &ovf, &scol, &scost, &stau}) dev_free(*b, s);
     if (st == GMT_OK) st = build_out_table(rm, s);
     if (st == GMT_OK) st = pack_records(rm, s);
-    dev_free(scal, s);
     return st;
 }
 
@@ -484,12 +505,17 @@ extern "C" gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int
     hipStream_t s = (hipStream_t)stream;
     const size_t E = (size_t)rm->nnz;
     std::vector<int> rp(rm->n + 1), cl(E);
+    std::vector<unsigned int> rc(cost ? 3 * E : 0);
     std::vector<double> cs(cost ? E : 0), ta(tau && rm->in_tau.p ? E : 0);
     HIPCHK(hipMemcpyAsync(rp.data(), rm->in_ptr.p, sizeof(int) * (rm->n + 1), hipMemcpyDeviceToHost, s));
     if (E) HIPCHK(hipMemcpyAsync(cl.data(), rm->in_col.p, sizeof(int) * E, hipMemcpyDeviceToHost, s));
-    if (E && !cs.empty()) HIPCHK(hipMemcpyAsync(cs.data(), rm->in_cost.p, sizeof(double) * E, hipMemcpyDeviceToHost, s));
+    if (E && !rc.empty()) HIPCHK(hipMemcpyAsync(rc.data(), rm->in_rec.p, 12 * E, hipMemcpyDeviceToHost, s));
     if (E && !ta.empty()) HIPCHK(hipMemcpyAsync(ta.data(), rm->in_tau.p, sizeof(double) * E, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    for (size_t k = 0; k < cs.size(); ++k) {  // (cost low word, high word, column) records
+        const unsigned long long b = (unsigned long long)rc[3 * k] | ((unsigned long long)rc[3 * k + 1] << 32);
+        std::memcpy(&cs[k], &b, sizeof b);
+    }
     // device rows may be in any order (the parent search does not depend on
     // it); exported rows are ascending
     std::vector<int> idx;

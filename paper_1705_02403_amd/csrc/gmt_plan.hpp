@@ -357,24 +357,25 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 // issued in stages of SCAN_U edges per lane -- the (edge cost, column)
 // records, then the state bytes (and costs), then the update -- so a lane
 // keeps SCAN_U independent loads in flight per stage instead of one dependent
-// chain per edge.  The body is branch-free: every read is issued unconditionally
-// (from valid addresses) and the minimum is updated by selects.
+// chain per edge.  The body is branch-free: every read is issued
+// unconditionally (from valid addresses) and the minimum is updated by
+// selects.  A lane that finds no open in-neighbour ends with best = +inf.
 //
-// The costs-to-come of all read slots are loaded unconditionally when they
-// live in LDS (COST_LDS) or when the state bytes are in global memory (EAGER:
-// one dependent round trip fewer; values of nodes that are not open are read
-// and ignored -- a node committed by this iteration may be written meanwhile,
-// and it is not open either way).  Otherwise (state in LDS, costs in global
-// memory) only open slots read their own cost, the others cost[x].
+// OPEN_COST: `cost` holds the cost-to-come of the nodes open at the start of
+// the iteration and +inf for every other node, so the state bytes are not
+// read at all (non-open slots cannot improve on +inf; a tie at +inf may set
+// `by` but leaves best infinite).
+// EAGER (state bytes in global memory): the costs of all slots are loaded
+// with the state bytes, one dependent round trip fewer; values of nodes that
+// are not open are read and ignored -- a node committed by this iteration may
+// be written meanwhile, and it is not open either way.  Otherwise only open
+// slots read their own cost, the others cost[x].
 #define SCAN_U 8
 #define FRONT_U 4
 typedef __attribute__((address_space(1))) const unsigned int global_u32;
-// records past the end of the table, (column 0, cost 0), so that the slots of
-// a stage that run past the last row stay inside the allocation
-#define GMT_REC_PAD 256
 static_assert(SCAN_U * 32 <= GMT_REC_PAD, "record padding must cover one stage of the widest lane group");
 
-template <int CL, bool EAGER, bool COST_LDS>
+template <int CL, bool EAGER, bool OPEN_COST>
 __device__ __forceinline__ void scan_row(const unsigned char *st, const double *__restrict__ cost,
                                          const unsigned int *rec_in, int x, int ib, int ie, int lg,
                                          double &best, int &by, int &be) {
@@ -391,19 +392,27 @@ __device__ __forceinline__ void scan_row(const unsigned char *st, const double *
             ic[u] = __hiloint2double((int)rp[3 * u * CL + 1], (int)rp[3 * u * CL]);
             y[u] = (int)rp[3 * u * CL + 2];
         }
-        unsigned int sv[SCAN_U];
         double c[SCAN_U];
-#pragma unroll
-        for (int u = 0; u < SCAN_U; ++u) {
-            sv[u] = st[y[u]];
-            if (EAGER || COST_LDS) c[u] = cost[y[u]];
-        }
         bool op[SCAN_U];
+        if (OPEN_COST) {
 #pragma unroll
-        for (int u = 0; u < SCAN_U; ++u) op[u] = in_row[u] & ((sv[u] & 3u) == 1u);
-        if (!(EAGER || COST_LDS)) {
+            for (int u = 0; u < SCAN_U; ++u) {
+                c[u] = cost[y[u]];
+                op[u] = in_row[u];
+            }
+        } else {
+            unsigned int sv[SCAN_U];
 #pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) c[u] = cost[op[u] ? y[u] : x];
+            for (int u = 0; u < SCAN_U; ++u) {
+                sv[u] = st[y[u]];
+                if (EAGER) c[u] = cost[y[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) op[u] = in_row[u] & ((sv[u] & 3u) == 1u);
+            if (!EAGER) {
+#pragma unroll
+                for (int u = 0; u < SCAN_U; ++u) c[u] = cost[op[u] ? y[u] : x];
+            }
         }
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
@@ -444,7 +453,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     const int n = R.n, N = n + 1, root = n;
     unsigned char *st = LDS ? lst : w.st;
     Ctl *ctl = LDS ? lctl : w.ctl;
-    double *cost = (LDS >= 2) ? lcost : w.cost;
+    // OC: the LDS array holds the costs of open nodes only (+inf elsewhere),
+    // for the parent search; every cost-to-come is kept in w.cost
+    constexpr bool OC = LDS >= 2;
+    double *cost = OC ? lcost : w.cost;
     unsigned long long w_out = 0, w_in = 0, w_cand = 0, w_commit = 0, w_open = 0, w_iters = 0;
     unsigned long long tk_setup = 0, tk_select = 0, tk_frontier = 0, tk_connect = 0, tk_check = 0;
     unsigned long long tk = (t.rank == 0) ? clock_ticks() : 0;
@@ -474,7 +486,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         bool cand = false;
         if (v == root) {
             st[v] = (unsigned char)(S_CLOSED | (in_goal_q(P.x_q, P) ? S_GOAL : 0));
-            cost[v] = 0.0;
+            cost[v] = OC ? __longlong_as_double(COST_INF_BITS) : 0.0;
+            if (OC) w.cost[v] = 0.0;
             w.parent[v] = -1;
             w.gi[v] = 0;
             w.ai[v] = -1;
@@ -493,6 +506,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             }
             st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
             cost[v] = __longlong_as_double(COST_INF_BITS);
+            if (OC) w.cost[v] = __longlong_as_double(COST_INF_BITS);
             w.parent[v] = -1;
             w.gi[v] = -1;
             w.ai[v] = -2;
@@ -566,6 +580,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             if (active && lg == 0) {
                 if (free_edge) {
                     st[v] = (unsigned char)(S_OPEN | (st[v] & S_GOAL));
+                    if (OC) w.cost[v] = cost[v];
                     w.parent[v] = root;
                     w.ai[v] = 0;
                     // the open set of iteration 1 is the root's children
@@ -647,8 +662,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             double c = 0.0;
             if (set == S_GROUP) {
                 st[v] = (unsigned char)(S_CLOSED | goal);
+                if (OC) cost[v] = __longlong_as_double(COST_INF_BITS);
             } else if (set == S_OPEN || set == S_NEW) {
-                c = cost[v];
+                if (OC && set == S_NEW) {
+                    c = w.cost[v];
+                    cost[v] = c;  // open from this iteration on
+                } else {
+                    c = cost[v];
+                }
                 in_g = c <= thr;
                 rem = !in_g;
                 st[v] = (unsigned char)((in_g ? S_GROUP : S_OPEN) | goal);
@@ -752,10 +773,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    scan_row<CL, LDS == 0, LDS == 2>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
+                    scan_row<CL, LDS == 0, OC>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
-                const bool ok = active && by != 0x7fffffff;
+                const bool ok = active && best < __longlong_as_double(COST_INF_BITS);
                 const unsigned long long c0 = (t.wave == 0) ? clock_ticks() : 0;
                 int yq[3] = {0, 0, 0};
                 double ys[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, tau = 0.0;
@@ -776,7 +797,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     st[x] = (unsigned char)((commit ? S_NEW : S_UNEXPLORED) | goal);
                 }
                 if (commit) {
-                    cost[x] = best;
+                    // not in the LDS array yet: x is open from the next iteration
+                    (OC ? w.cost : cost)[x] = best;
                     w.parent[x] = by;
                     w.ai[x] = ii;
                     ++w_commit;
@@ -814,14 +836,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 const int hc = ld_cnt(&ctl->hit_cnt[hit_parity]);
                 for (int k = 0; k < hc; ++k) {
                     int v = w.hits[k];
-                    double c = cost[v];
+                    double c = (OC ? w.cost : cost)[v];
                     if (z < 0 || c < pc || (c == pc && v < z)) {
                         z = v;
                         pc = c;
                     }
                 }
             }
-            pc = cost[z];
+            pc = (OC ? w.cost : cost)[z];
             for (int v = z; v >= 0 && plen <= N; v = w.parent[v]) ++plen;
             int pos = plen - 1;
             for (int v = z; v >= 0 && pos >= 0; v = w.parent[v], --pos)
@@ -848,10 +870,6 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
             if (t.lane == 0 && v) atomicAdd(&res->work[k], v);
         }
-    }
-    if (LDS >= 2) {
-        team_sync(t);  // the path walk above has read the costs
-        for (int v = t.rank; v < N; v += t.size) w.cost[v] = cost[v];
     }
     team_sync(t);
 }

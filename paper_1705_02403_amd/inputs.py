@@ -322,6 +322,14 @@ def di_radius_of(n: int) -> float:
     return DI_RADIUS * (16384.0 / float(n)) ** (1.0 / 6.0)
 
 
+def clustered_samples(seed: int, dim: int, n: int, extent: float) -> np.ndarray:
+    """n grid samples uniform in [0, extent]^dim (SoA FP32): a dense cluster
+    whose cells hold far more samples than uniform sets do."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(0, int(extent * QSCALE) + 1, size=(dim, n), dtype=np.int64)
+    return from_grid(k)
+
+
 def tiny_problem(seed: int, dim: int, n: int, m: int, lam: float, step: float = 0.01,
                  smin: float = 0.1, smax: float = 0.3) -> Problem:
     """Small Euclidean instance for brute-force cross-checks."""

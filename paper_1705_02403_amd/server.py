@@ -23,9 +23,9 @@ from . import gmt
 
 
 def roadmap_bytes(n: int, dim: int, kind: int, nnz: int) -> int:
-    """Device bytes of a roadmap: samples, row pointers, the in-table (columns
-    and costs, plus their packed records) and the out-table."""
-    b = 4 * dim * n + 4 * (n + 1) + 12 * nnz + 12 * nnz
+    """Device bytes of a roadmap: samples, row pointers, the in-table (columns,
+    plus (cost, column) records with 256 padding records) and the out-table."""
+    b = 4 * dim * n + 4 * (n + 1) + 4 * nnz + 12 * (nnz + 256)
     if kind == gmt.GMT_COST_DOUBLE_INTEGRATOR:
         b += 8 * nnz + 4 * (n + 1) + 4 * nnz  # arrival times + transposed table
     return b

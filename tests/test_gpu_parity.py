@@ -71,7 +71,9 @@ def compare_tree(res, ref, exact_cost=True):
 
 # --- neighbour tables -------------------------------------------------------
 
-EU_TABLES = [("2d", 0, 2000), ("2d", 1, 2000), ("2d", 2, 5003), ("3d", 0, 16384), ("3d", 3, 3001)]
+# the 3D n = 65536 table spans 16 tiles of the row-pointer scan
+EU_TABLES = [("2d", 0, 2000), ("2d", 1, 2000), ("2d", 2, 5003), ("3d", 0, 16384), ("3d", 3, 3001),
+             ("3d", 5, 65536)]
 
 
 @pytest.mark.parametrize("kind,seed,n", EU_TABLES)
@@ -96,6 +98,21 @@ def test_euclid_table_tiny(n):
     rm = build(prob, r)
     rp, col, cost, _ = rm.export()
     ref = O.neighbors(prob.samples, O.EUCLID, r)
+    np.testing.assert_array_equal(rp, ref.row_ptr)
+    np.testing.assert_array_equal(col, ref.col)
+    np.testing.assert_array_equal(cost, ref.cost)
+    rm.free()
+
+
+@pytest.mark.parametrize("dim,n,extent,r", [(2, 3000, 0.05, 0.1), (3, 2500, 0.04, 0.05)])
+def test_euclid_table_clustered(dim, n, extent, r):
+    """Every sample in one or a few cells: rows past one block of rows per
+    workgroup and staged neighbourhoods past one chunk."""
+    say("euclid clustered table %dD n %d" % (dim, n))
+    s = I.clustered_samples(11, dim, n, extent)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_EUCLIDEAN, r)
+    rp, col, cost, _ = rm.export()
+    ref = O.neighbors(s, O.EUCLID, r)
     np.testing.assert_array_equal(rp, ref.row_ptr)
     np.testing.assert_array_equal(col, ref.col)
     np.testing.assert_array_equal(cost, ref.cost)
