@@ -29,6 +29,11 @@ TRAFFIC = {"sources_sha256": "cc5d775df7bf6df9bd3c961aa12f93836bbc6387ae46a15f34
            "bytes_per_launch": int((2.0 * 70667371 + 5053419) * 1024)}
 
 
+def say(msg):
+    """Progress line on stderr (the JSON line alone goes to stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def kernel_digest():
     import hashlib
     h = hashlib.sha256()
@@ -65,6 +70,8 @@ def parse():
                     help="time the batches only (for counter runs): no latency, server, build or oracle sections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--euclid-sizes", default="16384,65536,262144,1048576",
+                    help="sample counts of the 3D Euclidean table builds reported (empty: none)")
     ap.add_argument("--mixed-requests", type=int, default=512,
                     help="mixed 2D/3D/6D replanning stream (0: skip)")
     ap.add_argument("--mixed-rate", type=float, default=2000.0)
@@ -376,26 +383,33 @@ def main():
                     "peak_inflight_requests": rep.engine.get("peak_inflight_requests"),
                     "identical_to_batch": "%d/%d" % (same, len(rep.served))}
 
-    # ---- Euclidean neighbour table build, 3D n=16384 (config 2 workload) ----
+    # ---- Euclidean neighbour table builds, 3D (config 2 workload and larger n) ----
+    # bytes the build must move: samples read, row pointers, 12-byte records
+    # and 4-byte columns written per edge
     build_line = None
-    if not args.only_throughput:
-        p3 = I.problem_3d(0)
+    if not args.only_throughput and args.euclid_sizes:
         from paper_1705_02403_amd import radius as RAD
-        r3 = RAD.problem_radius(p3)
-        d3 = torch.from_numpy(p3.samples).cuda()
-        bt = []
-        for k in range(6):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
-            torch.cuda.synchronize()
-            bt.append((time.perf_counter() - t) * 1e3)
-            e3 = rm3.nnz
-            rm3.free()
-        bt = float(np.median(bt[1:]))
-        build_line = {"workload": "3D Euclidean n=16384, r=%.4f" % r3, "edges": int(e3),
-                      "ms": round(bt, 3),
-                      "GB_per_s_out": round(12.0 * e3 / (bt * 1e-3) / 1e9, 1)}
+        build_line = []
+        for n3 in [int(x) for x in args.euclid_sizes.split(",")]:
+            p3 = I.problem_3d(0, n=n3)
+            r3 = RAD.problem_radius(p3)
+            d3 = torch.from_numpy(p3.samples).cuda()
+            bt = []
+            for k in range(5):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
+                torch.cuda.synchronize()
+                bt.append((time.perf_counter() - t) * 1e3)
+                e3 = rm3.nnz
+                rm3.free()
+            bt = float(np.median(bt[1:]))
+            nbytes = 12 * n3 + 4 * (n3 + 1) + 16 * e3
+            build_line.append({"workload": "3D Euclidean n=%d, r=%.4f" % (n3, r3), "edges": int(e3),
+                               "wall_ms": round(bt, 3), "bytes": int(nbytes),
+                               "GB_per_s_wall": round(nbytes / (bt * 1e-3) / 1e9, 1)})
+            say("euclid build n=%d: %.3f ms" % (n3, bt))
+            del d3
 
     learned = learned_report(args, torch, gmt, I) if args.learned else None
     mixed = (mixed_report(args, torch, gmt, I)

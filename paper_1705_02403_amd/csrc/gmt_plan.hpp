@@ -176,11 +176,44 @@ __device__ __forceinline__ bool in_staged_box(const int *q, const int *lbox, int
 
 __device__ __forceinline__ bool in_goal_q(const int *q, const ProbDev &P) {
     long long s = 0;
-    for (int a = 0; a < P.goal_dims; ++a) {
-        long long d = (long long)q[a] - P.goal_q[a];
-        s += d * d;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        if (a < P.goal_dims) {
+            long long d = (long long)q[a] - P.goal_q[a];
+            s += d * d;
+        }
     }
     return (double)s <= P.goal_r2q;
+}
+
+// Does a sample lie in any of the m staged boxes (closed)?  KIND 0: grid
+// coordinates q against integer boxes of pd dimensions; KIND 1: the exact
+// FP32 position pf against FP32 boxes (lower corner, then upper).  Every box
+// is tested, its bounds read together and the verdicts combined without
+// branches, so the LDS reads of several boxes are in flight at once.
+template <int KIND>
+__device__ __forceinline__ bool node_in_boxes(const int *q, const float *pf, const int *lbox, int m, int pd) {
+    bool dead = false;
+    if (KIND == 0) {
+#pragma unroll 4
+        for (int b = 0; b < m; ++b) {
+            const int *bx = lbox + b * 2 * pd;
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a < pd) in = in & (q[a] >= bx[a]) & (q[a] <= bx[pd + a]);
+            dead = dead | in;
+        }
+    } else {
+        const float2 *fb = (const float2 *)lbox;  // (lo0, lo1), (lo2, hi0), (hi1, hi2)
+#pragma unroll 4
+        for (int b = 0; b < m; ++b) {
+            const float2 u = fb[3 * b], v = fb[3 * b + 1], w = fb[3 * b + 2];
+            dead = dead | ((pf[0] >= u.x) & (pf[0] <= v.y) & (pf[1] >= u.y) & (pf[1] <= w.x) & (pf[2] >= v.x) &
+                           (pf[2] <= w.y));
+        }
+    }
+    return dead;
 }
 
 // does a trajectory point lie in box b (b = -1: outside [0,1]^3)?  Boxes as
@@ -493,17 +526,17 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             w.ai[v] = -1;
         } else if (v < n) {
             int q[6] = {0, 0, 0, 0, 0, 0};
-            for (int a = 0; a < R.dim; ++a) q[a] = (int)((double)R.s[(size_t)a * n + v] * GMT_QS);
-            bool dead = false;
-            if (KIND == 0) {
-                for (int b = 0; b < P.m && !dead; ++b) dead = point_in_box_q(q, lbox + b * 2 * P.pd, P.pd);
-            } else {
-                // grid coordinates are exact in FP32, as are the staged boxes
-                const float p0 = R.s[v], p1 = R.s[(size_t)n + v], p2 = R.s[2 * (size_t)n + v];
-                const float *fb = (const float *)lbox;
-                for (int b = 0; b < P.m && !dead; ++b, fb += 6)
-                    dead = p0 >= fb[0] && p0 <= fb[3] && p1 >= fb[1] && p1 <= fb[4] && p2 >= fb[2] && p2 <= fb[5];
+            float pf[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int a = 0; a < (KIND == 0 ? 3 : 6); ++a) {
+                if (KIND == 1 || a < R.dim) {
+                    const float x = R.s[(size_t)a * n + v];
+                    q[a] = (int)((double)x * GMT_QS);
+                    if (a < 3) pf[a] = x;
+                }
             }
+            // grid coordinates are exact in FP32, as are the staged boxes
+            const bool dead = node_in_boxes<KIND>(q, pf, lbox, P.m, P.pd);
             st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
             cost[v] = __longlong_as_double(COST_INF_BITS);
             if (OC) w.cost[v] = __longlong_as_double(COST_INF_BITS);
