@@ -84,7 +84,7 @@ static_assert(offsetof(Ctl, min_bits) % 8 == 0, "Ctl layout");
 struct QWs {
     unsigned char *st;  // (n+1) bytes, padded to a multiple of 4
     int *glist;
-    int4 *clist;        // candidate x with its in-row [begin, end)
+    int *clist;         // candidates x of the running iteration
     int *hits;
     Ctl *ctl;
     double *cost;
@@ -559,7 +559,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             }
         }
         const int slot = wave_append(&ctl->c_cnt, cand);
-        if (cand) w.clist[slot] = make_int4(v, 0, 0, 0);
+        if (cand) w.clist[slot] = v;
     }
     team_sync(t);
     // (b) edge cost from the root, one candidate per lane; those below r are
@@ -571,7 +571,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             bool ok = false;
             int v = 0;
             if (k < cc0) {
-                v = w.clist[k].x;
+                v = w.clist[k];
                 if (KIND == 0) {
                     long long d2 = 0;
                     for (int a = 0; a < R.dim; ++a) {
@@ -737,7 +737,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     if (lg == 0) w_out += (unsigned long long)(oe - ob);
                 }
                 // FRONT_U out-edges per lane per step: their loads are issued
-                // together; row extents are read for claimed nodes only
+                // together
                 for (int e0 = ob + lg; e0 < oe; e0 += FRONT_U * CL) {
                     int xs[FRONT_U];
 #pragma unroll
@@ -754,16 +754,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                             if ((sx & S_SET) == S_UNEXPLORED && !(sx & S_CLAIM)) cand[u] = claim(st, xs[u]);
                         }
                     }
-                    int ib[FRONT_U], ie[FRONT_U];
-#pragma unroll
-                    for (int u = 0; u < FRONT_U; ++u) {
-                        ib[u] = cand[u] ? R.in_ptr[xs[u]] : 0;
-                        ie[u] = cand[u] ? R.in_ptr[xs[u] + 1] : 0;
-                    }
 #pragma unroll
                     for (int u = 0; u < FRONT_U; ++u) {
                         const int slot = wave_append(&ctl->c_cnt, cand[u]);
-                        if (cand[u]) w.clist[slot] = make_int4(xs[u], ib[u], ie[u], 0);
+                        if (cand[u]) w.clist[slot] = xs[u];
                     }
                 }
             }
@@ -788,19 +782,25 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             constexpr int per_wave = GMT_WAVE / CL;
             const unsigned int *__restrict__ in_rec = R.in_rec;
             const int stride = t.nwaves * per_wave;
-            // the next round's candidate entry is loaded one round ahead
-            int4 ent_next = (t.wave * per_wave + sub < cc) ? w.clist[t.wave * per_wave + sub] : make_int4(0, 0, 0, 0);
+            // a round's candidate is read from the list two rounds ahead and
+            // its in-row extent one round ahead, so neither load is waited on
+            const int first = t.wave * per_wave + sub;
+            int x_next = first < cc ? w.clist[first] : 0;
+            int x_next2 = first + stride < cc ? w.clist[first + stride] : 0;
+            int ib_next = first < cc ? R.in_ptr[x_next] : 0;
+            int ie_next = first < cc ? R.in_ptr[x_next + 1] : 0;
             for (int base = t.wave * per_wave; base < cc; base += stride) {
                 const int k = base + sub;
                 const bool active = k < cc;
-                const int4 ent = ent_next;
-                ent_next = (k + stride < cc) ? w.clist[k + stride] : make_int4(0, 0, 0, 0);
-                const int x = ent.x;
+                const int x = x_next, ib = ib_next, ie = ie_next;
+                x_next = x_next2;
+                ib_next = k + stride < cc ? R.in_ptr[x_next] : 0;
+                ie_next = k + stride < cc ? R.in_ptr[x_next + 1] : 0;
+                x_next2 = k + 2 * stride < cc ? w.clist[k + 2 * stride] : 0;
                 double best = __longlong_as_double(COST_INF_BITS);
                 int by = 0x7fffffff, be = -1;
                 CandEnd ce;
                 if (active) {
-                    const int ib = ent.y, ie = ent.z;
                     load_end<KIND>(R, x, ce);
                     if (lg == 0) {
                         w_in += (unsigned long long)(ie - ib);
