@@ -16,7 +16,9 @@
 #define GMT_INV_QS (1.0 / 1048576.0)
 // records after the last one of an in-table, (cost 0, column 0), so that
 // the parent search may read a few slots past the end of the last row
+#ifndef GMT_REC_PAD
 #define GMT_REC_PAD 256
+#endif
 #define GMT_Q2 1099511627776.0  // 2^40
 
 // node bookkeeping values

@@ -403,8 +403,12 @@ __device__ __forceinline__ bool claim(unsigned char *st, int x) {
 // are not open are read and ignored -- a node committed by this iteration may
 // be written meanwhile, and it is not open either way.  Otherwise only open
 // slots read their own cost, the others cost[x].
+#ifndef SCAN_U
 #define SCAN_U 8
-#define FRONT_U 4
+#endif
+#ifndef FRONT_U
+#define FRONT_U 8
+#endif
 typedef __attribute__((address_space(1))) const unsigned int global_u32;
 static_assert(SCAN_U * 32 <= GMT_REC_PAD, "record padding must cover one stage of the widest lane group");
 
