@@ -154,6 +154,15 @@ __global__ void k_pack_rec(long long E, long long total, const int *__restrict__
     rec[3 * e + 2] = real ? (unsigned int)col[e] : 0u;
 }
 
+// double-integrator states as 8 floats per node (6 used), so that one node's
+// state is two aligned 16-byte loads from one line
+__global__ void k_aos8(const float *__restrict__ s, int n, float4 *__restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    out[2 * v] = make_float4(s[v], s[(size_t)n + v], s[2 * (size_t)n + v], s[3 * (size_t)n + v]);
+    out[2 * v + 1] = make_float4(s[4 * (size_t)n + v], s[5 * (size_t)n + v], 0.0f, 0.0f);
+}
+
 // the padding records (column 0, cost 0) after the E records of a table
 __global__ void k_rec_pad(unsigned int *__restrict__ rec, long long E) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;

@@ -175,6 +175,7 @@ struct gmt_roadmap {
     DevBuf s, in_ptr, in_col, in_tau, out_ptr, out_col;
     DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
     DevBuf in_rec;   // (edge cost, column) records of the in-table, 12 bytes per edge
+    DevBuf s8;       // double integrator: states as 8 floats per node
     bool out_shared = false;
 };
 
@@ -205,6 +206,7 @@ static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
     dev_free(rm->in_cost, s);
     dev_free(rm->in_tau, s);
     dev_free(rm->in_rec, s);
+    dev_free(rm->s8, s);
     if (!rm->out_shared) {
         dev_free(rm->out_ptr, s);
         dev_free(rm->out_col, s);
@@ -264,6 +266,11 @@ static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
                                                                 (unsigned int *)rm->in_rec.p);
     HIPCHK(hipGetLastError());
     dev_free(rm->in_cost, s);
+    if (rm->kind == GMT_COST_DOUBLE_INTEGRATOR) {
+        TRY(dev_alloc(rm->s8, 32 * (size_t)rm->n, s));
+        k_aos8<<<blocks_for(rm->n, 256), 256, 0, s>>>((const float *)rm->s.p, rm->n, (float4 *)rm->s8.p);
+        HIPCHK(hipGetLastError());
+    }
     return GMT_OK;
 }
 
@@ -691,6 +698,7 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
     P.rm.s = (const float *)rm->s.p;
     P.rm.in_ptr = (const int *)rm->in_ptr.p;
     P.rm.in_rec = (const unsigned int *)rm->in_rec.p;
+    P.rm.s8 = (const float4 *)rm->s8.p;
     P.rm.in_tau = (const double *)rm->in_tau.p;
     P.rm.out_ptr = (const int *)rm->out_ptr.p;
     P.rm.out_col = (const int *)rm->out_col.p;

@@ -59,6 +59,7 @@ struct RoadmapDev {
     int n, dim, kind;
     double r, R2;
     const float *s;  // SoA [dim][n]
+    const float4 *s8;  // double integrator: node v's state in s8[2v], s8[2v + 1]
     const int *in_ptr;
     const unsigned int *in_rec;  // per in-edge: edge cost (low, high words), column
     const double *in_tau;  // double integrator only
@@ -150,8 +151,13 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
 
 template <int DIM>
 __device__ __forceinline__ void sample_d(const RoadmapDev &R, int v, double *x) {
+    if (DIM == 6) {
+        const float4 a = R.s8[2 * v], b = R.s8[2 * v + 1];
+        x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w, x[4] = b.x, x[5] = b.y;
+    } else {
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) x[a] = (double)R.s[(size_t)a * R.n + v];
+        for (int a = 0; a < DIM; ++a) x[a] = (double)R.s[(size_t)a * R.n + v];
+    }
 }
 
 __device__ __forceinline__ bool point_in_box_q(const int *q, const int *box, int pd) {

@@ -27,7 +27,7 @@ def roadmap_bytes(n: int, dim: int, kind: int, nnz: int) -> int:
     plus (cost, column) records with 256 padding records) and the out-table."""
     b = 4 * dim * n + 4 * (n + 1) + 4 * nnz + 12 * (nnz + 256)
     if kind == gmt.GMT_COST_DOUBLE_INTEGRATOR:
-        b += 8 * nnz + 4 * (n + 1) + 4 * nnz  # arrival times + transposed table
+        b += 8 * nnz + 4 * (n + 1) + 4 * nnz + 32 * n  # arrival times, transposed table, 8-float states
     return b
 
 

@@ -51,4 +51,4 @@ def test_roadmap_bytes_formula():
     e = server.roadmap_bytes(100, 2, gmt.GMT_COST_EUCLIDEAN, 1000)
     d = server.roadmap_bytes(100, 6, gmt.GMT_COST_DOUBLE_INTEGRATOR, 1000)
     assert e == 4 * 200 + 404 + 4000 + 12 * (1000 + 256)
-    assert d == 4 * 600 + 404 + 4000 + 12 * (1000 + 256) + 8000 + 404 + 4000
+    assert d == 4 * 600 + 404 + 4000 + 12 * (1000 + 256) + 8000 + 404 + 4000 + 3200
