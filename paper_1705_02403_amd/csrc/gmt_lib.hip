@@ -576,8 +576,10 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // bytes of one query's workspace over N nodes (tree arrays included when the
 // caller does not supply them)
 static size_t qws_bytes(int N, bool own_tree) {
-    // control block, states, group / candidate / goal-hit lists, root-edge arrival times
-    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 3 * al256(4 * (size_t)N) + al256(8 * (size_t)N);
+    // control block, states, group and open lists (two each), candidate and
+    // goal-hit lists, root-edge arrival times
+    size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 2 * al256(8 * (size_t)N) + 2 * al256(4 * (size_t)N) +
+               al256(8 * (size_t)N);
     if (own_tree) b += al256(8 * (size_t)N) + 3 * al256(4 * (size_t)N);
     return b;
 }
@@ -590,7 +592,8 @@ static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi
     };
     w.ctl = (Ctl *)take(sizeof(Ctl));
     w.st = (unsigned char *)take((size_t)N);
-    w.glist = (int *)take(4 * (size_t)N);
+    w.glist = (int *)take(8 * (size_t)N);
+    w.olist = (int *)take(8 * (size_t)N);
     w.clist = (int *)take(4 * (size_t)N);
     w.hits = (int *)take(4 * (size_t)N);
     w.aux = (double *)take(8 * (size_t)N);

@@ -70,12 +70,11 @@ struct RoadmapDev {
 // per-query counters (double-buffered by iteration parity where a fast
 // thread of the next iteration could otherwise race a slow reader)
 struct Ctl {
-    int g_cnt;       // group size
+    int g_cnt[2];    // group size (lists glist[parity])
     int c_cnt;       // candidates
     int hit_cnt[2];  // goal nodes in the group
-    int rem_cnt[2];  // open nodes carried to the next iteration
-    int com_cnt[2];  // nodes added by the iteration
-    int pad[2];
+    int o_cnt[2];    // open list of the iterations of that parity (olist[parity])
+    int pad;
     unsigned long long min_bits[2];  // least cost over the next iteration's open set
 };
 // 64-bit LDS atomics need 8-byte alignment of these fields
@@ -84,7 +83,8 @@ static_assert(offsetof(Ctl, min_bits) % 8 == 0, "Ctl layout");
 // per-query device workspace; cost/parent/gi/ai are the tree outputs
 struct QWs {
     unsigned char *st;  // (n+1) bytes, padded to a multiple of 4
-    int *glist;
+    int *glist;         // 2 (n+1): the group of the iterations of each parity
+    int *olist;         // 2 (n+1): the open set of the iterations of each parity
     int *clist;         // candidates x of the running iteration
     int *hits;
     Ctl *ctl;
@@ -508,12 +508,11 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         // work counters are summed by atomics at the end: start them at zero
         // (the result block is reused across launches)
         for (int k = 0; k < W_COUNT; ++k) res->work[k] = 0ull;
-        ctl->g_cnt = 0;
         ctl->c_cnt = 0;
         for (int k = 0; k < 2; ++k) {
+            ctl->g_cnt[k] = 0;
             ctl->hit_cnt[k] = 0;
-            ctl->rem_cnt[k] = 0;
-            ctl->com_cnt[k] = 0;
+            ctl->o_cnt[k] = 0;
             ctl->min_bits[k] = COST_INF_BITS;
         }
     }
@@ -600,7 +599,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     }
                 }
             }
-            const int slot = wave_append(&ctl->g_cnt, ok);
+            const int slot = wave_append(&ctl->g_cnt[0], ok);
             if (ok) w.glist[slot] = v;
         }
     }
@@ -608,7 +607,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     // (c) lazy check of each root edge by CL lanes; a free edge adds the node
     //     (parent root, added at iteration 0), otherwise it stays unexplored
     {
-        const int gc0 = ld_cnt(&ctl->g_cnt);
+        const int gc0 = ld_cnt(&ctl->g_cnt[0]);
         const int sub = t.lane / CL, lg = t.lane & (CL - 1);
         constexpr int per_wave = GMT_WAVE / CL;
         for (int base = t.wave * per_wave; base < gc0; base += t.nwaves * per_wave) {
@@ -632,12 +631,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     cost[v] = __longlong_as_double(COST_INF_BITS);
                 }
             }
-            wave_count(&ctl->rem_cnt[1], joined);
+            // the open set of iteration 1
+            const int so = wave_append(&ctl->o_cnt[1], joined);
+            if (joined) w.olist[N + so] = v;
         }
     }
     team_sync(t);
     if (t.rank == 0) {
-        ctl->g_cnt = 0;  // compaction counters of iteration 0, reused by the select phase
+        ctl->g_cnt[0] = 0;  // compaction counters of iteration 0: no group precedes iteration 1
         ctl->c_cnt = 0;
     }
     team_sync(t);
@@ -646,7 +647,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     if (st[root] & S_GOAL) {
         status = ST_OK;
         z = root;
-    } else if (ld_cnt(&ctl->rem_cnt[1]) == 0) {
+    } else if (ld_cnt(&ctl->o_cnt[1]) == 0) {
         status = ST_NO_PATH;
     }
     if (t.rank == 0) {
@@ -662,7 +663,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             break;
         }
         const int p = it & 1;
-        const int open_n = ld_cnt(&ctl->rem_cnt[p]) + ld_cnt(&ctl->com_cnt[p]);
+        const int open_n = ld_cnt(&ctl->o_cnt[p]);
         const double mn = __longlong_as_double(
             (long long)__hip_atomic_load(&ctl->min_bits[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         // threshold index of this iteration (Algorithm 1 line 3)
@@ -697,34 +698,51 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             ctl->c_cnt = 0;  // read by the previous connect phase, before its barrier
         }
         // ---- select (line 3; line 10 of the previous iteration) ----
-        for (int v = t.rank; v < n; v += t.size) {
-            const unsigned char s = st[v];
-            const int set = s & S_SET;
-            const unsigned char goal = s & S_GOAL;
-            bool in_g = false, rem = false;
-            double c = 0.0;
-            if (set == S_GROUP) {
-                st[v] = (unsigned char)(S_CLOSED | goal);
+        // the previous iteration's group is closed (line 10 of that iteration)
+        {
+            const int gprev = ld_cnt(&ctl->g_cnt[p ^ 1]);
+            const int *gl = w.glist + (p ^ 1) * N;
+            for (int k = t.rank; k < gprev; k += t.size) {
+                const int v = gl[k];
+                st[v] = (unsigned char)(S_CLOSED | (st[v] & S_GOAL));
                 if (OC) cost[v] = __longlong_as_double(COST_INF_BITS);
-            } else if (set == S_OPEN || set == S_NEW) {
-                if (OC && set == S_NEW) {
-                    c = w.cost[v];
-                    cost[v] = c;  // open from this iteration on
-                } else {
-                    c = cost[v];
-                }
-                in_g = c <= thr;
-                rem = !in_g;
-                st[v] = (unsigned char)((in_g ? S_GROUP : S_OPEN) | goal);
-                if (in_g) w.gi[v] = ii;
             }
-            const int sg = wave_append(&ctl->g_cnt, in_g);
-            if (in_g) w.glist[sg] = v;
-            const bool hit = in_g && goal;
-            const int sh = wave_append(&ctl->hit_cnt[p], hit);
-            if (hit) w.hits[sh] = v;
-            wave_count(&ctl->rem_cnt[p ^ 1], rem);
-            if (rem) atomic_min_cost(&ctl->min_bits[p ^ 1], c);
+        }
+        // the open set: the group of this iteration, the rest carried over
+        {
+            const int *ol = w.olist + p * N;
+            int *ol_next = w.olist + (p ^ 1) * N, *gl = w.glist + p * N;
+            for (int k0 = wbase; k0 < open_n; k0 += t.size) {
+                const int k = k0 + t.lane;
+                const bool valid = k < open_n;
+                const int v = valid ? ol[k] : 0;
+                bool in_g = false, rem = false, hit = false;
+                double c = 0.0;
+                if (valid) {
+                    const unsigned char s = st[v];
+                    const unsigned char goal = s & S_GOAL;
+                    if (OC && (s & S_SET) == S_NEW) {
+                        c = w.cost[v];
+                        cost[v] = c;  // open from this iteration on
+                    } else {
+                        c = cost[v];
+                    }
+                    in_g = c <= thr;
+                    rem = !in_g;
+                    hit = in_g && goal;
+                    st[v] = (unsigned char)((in_g ? S_GROUP : S_OPEN) | goal);
+                    if (in_g) w.gi[v] = ii;
+                }
+                const int sg = wave_append(&ctl->g_cnt[p], in_g);
+                if (in_g) gl[sg] = v;
+                const int sh = wave_append(&ctl->hit_cnt[p], hit);
+                if (hit) w.hits[sh] = v;
+                const int sr = wave_append(&ctl->o_cnt[p ^ 1], rem);
+                if (rem) {
+                    ol_next[sr] = v;
+                    atomic_min_cost(&ctl->min_bits[p ^ 1], c);
+                }
+            }
         }
         team_sync(t);
         if (t.rank == 0) {
@@ -734,14 +752,15 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         }
         // ---- frontier (line 4): CL lanes per group member ----
         {
-            const int gc = ld_cnt(&ctl->g_cnt);
+            const int gc = ld_cnt(&ctl->g_cnt[p]);
+            const int *gl = w.glist + p * N;
             const int sub = t.lane / CL, lg = t.lane & (CL - 1);
             constexpr int per_wave = GMT_WAVE / CL;
             for (int gb = t.wave * per_wave; gb < gc; gb += t.nwaves * per_wave) {
                 const int gk = gb + sub;
                 int ob = 0, oe = 0;
                 if (gk < gc) {
-                    const int g = w.glist[gk];
+                    const int g = gl[gk];
                     ob = R.out_ptr[g];
                     oe = R.out_ptr[g + 1];
                     if (lg == 0) w_out += (unsigned long long)(oe - ob);
@@ -779,9 +798,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             tk = now;
             // next iteration's counters: their last readers finished before
             // the select barrier
-            ctl->g_cnt = 0;
-            ctl->rem_cnt[p] = 0;
-            ctl->com_cnt[p] = 0;
+            ctl->g_cnt[p ^ 1] = 0;  // the previous group, closed by this select
+            ctl->o_cnt[p] = 0;      // this iteration's open list, read by its select
             ctl->min_bits[p] = COST_INF_BITS;
             ctl->hit_cnt[p ^ 1] = 0;
         }
@@ -847,7 +865,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     ++w_commit;
                     atomic_min_cost(&ctl->min_bits[p ^ 1], best);
                 }
-                wave_count(&ctl->com_cnt[p ^ 1], commit);
+                const int so = wave_append(&ctl->o_cnt[p ^ 1], commit);
+                if (commit) w.olist[(p ^ 1) * N + so] = x;
             }
         }
         team_sync(t);
@@ -864,7 +883,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             hit_parity = p;
             break;
         }
-        if (ld_cnt(&ctl->rem_cnt[p ^ 1]) + ld_cnt(&ctl->com_cnt[p ^ 1]) == 0) {
+        if (ld_cnt(&ctl->o_cnt[p ^ 1]) == 0) {
             status = ST_NO_PATH;
             break;
         }
