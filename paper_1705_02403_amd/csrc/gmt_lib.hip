@@ -716,9 +716,11 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
         P.step_q = (long long)std::llround(o.edge_step * GMT_QS);
         if (P.step_q < 1) return fail(GMT_EINVAL, "edge_step below the grid quantum");
         P.traj_points = 0;
+        P.inv_k1 = 0.0;
     } else {
         if (o.traj_points < 2 || o.traj_points > 4096) return fail(GMT_EINVAL, "traj_points must lie in [2, 4096]");
         P.traj_points = o.traj_points;
+        P.inv_k1 = 1.0 / (double)(o.traj_points - 1);
         P.step_q = 1;
     }
     for (int a = 0; a < dim; ++a) {

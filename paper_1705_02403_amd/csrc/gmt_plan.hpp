@@ -100,6 +100,7 @@ struct ProbDev {
     QWs w;
     int pd, m, box_off, goal_dims;
     int max_iters, traj_points;
+    double inv_k1;  // 1 / (traj_points - 1), the step of normalised time
     long long step_q;
     double lambda, delta, goal_r2q;
     int x_q[6];     // x_init on the grid (Euclidean test) ...
@@ -310,7 +311,7 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, c
             const float *fbox = (const float *)lbox;
             DiPair d = make_pair(ys, c.xs);
             const int K = P.traj_points;
-            const double inv = 1.0 / (double)(K - 1);
+            const double inv = P.inv_k1;
             if (K <= 2 * CL) {
                 // this lane's trajectory points (k = lg, lg + CL), kept in registers
                 double p0[3], p1[3] = {0.0, 0.0, 0.0};
