@@ -271,9 +271,10 @@ gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count, const gmt_
 
 /* ---- prepared batches ---------------------------------------------------
  * Stage `count` queries once (inputs are copied; roadmaps must stay alive and
- * unchanged) and capture their launch sequence -- upload of the staged
- * queries, initialisation, the persistent planning kernel, download of the
- * results -- as a HIP graph; gmt_batch_run replays it and fills `results`
+ * unchanged), upload them to device memory once, and capture their launch
+ * sequence -- reset of the job-queue counters (a kernel, no memset), the
+ * persistent planning kernel, download of the results -- as a HIP graph;
+ * gmt_batch_run replays it (no host-to-device copy) and fills `results`
  * (statuses, paths, costs; device tree arrays are copied out when all four or
  * some of d_parent / d_cost / d_group_iter / d_added_iter are given).  Each
  * replay gives the results gmt_plan_batch gives for the same queries.  Launch

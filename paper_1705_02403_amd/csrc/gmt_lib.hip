@@ -972,10 +972,13 @@ static int max_coop_wgs(size_t lds, int kind, int level = 0, int cl = 16, int th
 
 // Copy the staged queries up, launch per kind, copy the results down and
 // record the completion event -- all asynchronous on `s`.
-// `events` false (graph capture): no event records.
-static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true) {
+// `events` false (graph capture): no event records.  `upload` false: the
+// staged queries are already in device memory (a prepared batch); only the
+// two queue counters of the staging header are reset, by a kernel.
+static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, bool upload = true) {
     WsBlock *w = r.w;
-    HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, r.used, hipMemcpyHostToDevice, s));
+    if (upload) HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, r.used, hipMemcpyHostToDevice, s));
+    else k_fill_int<<<1, 64, 0, s>>>((int *)w->stage_d.p, 2, 0);
     for (int k = 0; k < 5 && events; ++k)
         if (!r.ev[k] && (k == 4 || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
     if (r.n_euclid > 0)
@@ -1294,13 +1297,16 @@ extern "C" gmt_status gmt_batch_prepare(const gmt_problem *problems, int32_t cou
     b->run.prof = false;
     b->probs.assign(problems, problems + count);
     // cooperative launches (team_wgs > 1) cannot be captured: those batches
-    // are replayed as direct launches
+    // are replayed as direct launches.  Captured batches keep their staged
+    // queries in device memory: uploaded once here, not by each replay.
     if (b->run.team_wgs == 1) {
         hipStream_t cs = nullptr;
-        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        hipError_t e = hipMemcpyAsync(b->run.w->stage_d.p, b->run.w->stage_h, b->run.used, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            gmt_status ls = batch_launch(b->run, cs, false);
+            gmt_status ls = batch_launch(b->run, cs, false, false);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(cs, &g);
             b->graph = g;
