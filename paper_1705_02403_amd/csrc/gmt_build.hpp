@@ -29,12 +29,13 @@ namespace gmt {
 // 1024-thread workgroup scans a tile of SCAN_TILE elements (4 per thread) and
 // writes its total; one workgroup scans the totals (64-bit, so a sum beyond
 // the int32 range is seen by the caller); the tile offsets are added last,
-// and out[count] = total.  Partial sums are exact whenever the total fits in
+// and out[count] = total.  A single tile is finished by its own launch
+// (`total` given: out[count] and *total written there).  Partial sums are exact whenever the total fits in
 // int32, the only case in which the caller uses them.
 #define SCAN_TILE 4096
 
 __global__ void __launch_bounds__(1024) k_scan_tile(const int *__restrict__ in, int count, int *__restrict__ out,
-                                                    long long *__restrict__ tsum) {
+                                                    long long *__restrict__ tsum, long long *__restrict__ total) {
     __shared__ long long wsum[16];
     const int t = threadIdx.x, lane = lane_id(), w = t / GMT_WAVE;
     const long long base = (long long)blockIdx.x * SCAN_TILE + 4 * t;
@@ -71,7 +72,13 @@ __global__ void __launch_bounds__(1024) k_scan_tile(const int *__restrict__ in, 
         if (base + u < count) out[base + u] = (int)e;
         e += v[u];
     }
-    if (t == 0) tsum[blockIdx.x] = wsum[15];
+    if (t == 0) {
+        tsum[blockIdx.x] = wsum[15];
+        if (total) {  // the only tile
+            out[count] = (int)wsum[15];
+            *total = wsum[15];
+        }
+    }
 }
 
 __global__ void __launch_bounds__(1024) k_scan_top(const long long *__restrict__ tsum, int nt,

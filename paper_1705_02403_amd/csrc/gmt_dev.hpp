@@ -46,6 +46,31 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return (uint64_t)__ballot(p); }
 
+// Value of x in this lane's partner for stage OFF of a reduction over groups
+// of 2*OFF lanes, stages taken in order OFF = 1, 2, 4, ...: the partner is
+// lane ^ 1 and lane ^ 2 within a quad, then the mirror lane within 8 and
+// within 16 (which lies in the other half once each half is reduced), all
+// by DPP moves within a row; lane ^ 16 and up by a cross-lane permute.  Every
+// lane of the wave must be active.
+template <int OFF>
+__device__ __forceinline__ int lane_swap(int x) {
+    if (OFF == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    if (OFF == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    if (OFF == 4) return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    if (OFF == 8) return __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);  // row_mirror
+    return __shfl_xor(x, OFF);
+}
+
+template <int OFF>
+__device__ __forceinline__ float lane_swap_f(float x) {
+    return __int_as_float(lane_swap<OFF>(__float_as_int(x)));
+}
+
+template <int OFF>
+__device__ __forceinline__ double lane_swap_d(double x) {
+    return __hiloint2double(lane_swap<OFF>(__double2hiint(x)), lane_swap<OFF>(__double2loint(x)));
+}
+
 // number of set bits of `mask` below this lane
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned int)(mask >> 32),

@@ -225,9 +225,13 @@ static gmt_status scan_ints(const int *in, int count, int *out, long long *total
     TRY(dev_alloc(tb, sizeof(long long) * (2 * (size_t)nt + 1), s));
     long long *tsum = (long long *)tb.p, *toff = tsum + nt;
     long long *tot = total ? total : toff + nt;
-    k_scan_tile<<<nt, 1024, 0, s>>>(in, count, out, tsum);
-    k_scan_top<<<1, 1024, 0, s>>>(tsum, nt, toff, tot);
-    k_scan_add<<<blocks_for((long long)count + 1, 256), 256, 0, s>>>(out, count, toff, tot);
+    if (nt == 1) {
+        k_scan_tile<<<1, 1024, 0, s>>>(in, count, out, tsum, tot);
+    } else {
+        k_scan_tile<<<nt, 1024, 0, s>>>(in, count, out, tsum, nullptr);
+        k_scan_top<<<1, 1024, 0, s>>>(tsum, nt, toff, tot);
+        k_scan_add<<<blocks_for((long long)count + 1, 256), 256, 0, s>>>(out, count, toff, tot);
+    }
     HIPCHK(hipGetLastError());
     return GMT_OK;
 }

@@ -146,7 +146,7 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
     int leader = __ffsll((unsigned long long)m) - 1;
     int base = 0;
     if (lane_id() == leader) base = atomicAdd(counter, (int)__popcll(m));
-    base = __shfl(base, leader);
+    base = __builtin_amdgcn_readlane(base, leader);
     return pred ? base + lanes_below(m) : -1;
 }
 
@@ -254,18 +254,35 @@ __device__ __noinline__ void root_edge_cost(const ProbDev &P, int v, double &J, 
 // ---------------------------------------------------------------------------
 // connect phase helpers: groups of CL lanes
 // ---------------------------------------------------------------------------
+// one stage of the group reductions below
+template <int OFF>
+__device__ __forceinline__ void argmin_stage(double &v, int &y, int &e) {
+    const double ov = lane_swap_d<OFF>(v);
+    const int oy = lane_swap<OFF>(y), oe = lane_swap<OFF>(e);
+    const bool take = ov < v || (ov == v && oy < y);
+    v = take ? ov : v;
+    y = take ? oy : y;
+    e = take ? oe : e;
+}
+
+// lexicographic (value, index) minimum over each group of CL lanes, carried
+// payload e; every lane of the wave takes part
 template <int CL>
 __device__ __forceinline__ void group_argmin(double &v, int &y, int &e) {
+    if (CL > 1) argmin_stage<1>(v, y, e);
+    if (CL > 2) argmin_stage<2>(v, y, e);
+    if (CL > 4) argmin_stage<4>(v, y, e);
+    if (CL > 8) argmin_stage<8>(v, y, e);
+    if (CL > 16) argmin_stage<16>(v, y, e);
+    if (CL > 32) argmin_stage<32>(v, y, e);
+}
+
+template <int OFF>
+__device__ __forceinline__ void bbox_stage(float *lo, float *hi) {
 #pragma unroll
-    for (int off = CL / 2; off > 0; off >>= 1) {
-        double ov = __shfl_xor(v, off);
-        int oy = __shfl_xor(y, off);
-        int oe = __shfl_xor(e, off);
-        if (ov < v || (ov == v && oy < y)) {
-            v = ov;
-            y = oy;
-            e = oe;
-        }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], lane_swap_f<OFF>(lo[a]));
+        hi[a] = fmaxf(hi[a], lane_swap_f<OFF>(hi[a]));
     }
 }
 
@@ -329,13 +346,12 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, c
                     lo[a] = fminf(h0 ? v0 : 1e30f, h1 ? v1 : 1e30f) - 1e-6f;
                     hi[a] = fmaxf(h0 ? v0 : -1e30f, h1 ? v1 : -1e30f) + 1e-6f;
                 }
-#pragma unroll
-                for (int off = CL / 2; off > 0; off >>= 1)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
-                        hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off));
-                    }
+                if (CL > 1) bbox_stage<1>(lo, hi);
+                if (CL > 2) bbox_stage<2>(lo, hi);
+                if (CL > 4) bbox_stage<4>(lo, hi);
+                if (CL > 8) bbox_stage<8>(lo, hi);
+                if (CL > 16) bbox_stage<16>(lo, hi);
+                if (CL > 32) bbox_stage<32>(lo, hi);
                 // boxes overlapping that box, one per lane; then every lane tests
                 // its points exactly against each of them
                 for (int b0 = 0; b0 < P.m; b0 += CL) {
