@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--mixed-rate", type=float, default=2000.0)
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned sampler and compare it with plain GMT* at n=32768")
-    ap.add_argument("--learned-train", type=int, default=20000)
+    ap.add_argument("--learned-train", type=int, default=100000)
     ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--learned-test", type=int, default=200)
     return ap.parse_args()
@@ -93,7 +93,7 @@ def plan_bytes(w):
 
 def learned_report(args, torch, gmt, I):
     """Learned sampler (configuration 5): train on waypoints of plain GMT*
-    paths at n=32768, then compare the 50/50 learned mix at n in {2k, 4k, 8k}
+    paths at n=32768, then compare the 50/50 learned mix at n in {1k, 2k, 4k, 8k}
     with plain GMT* at n=32768 on held-out queries."""
     from paper_1705_02403_amd import radius, sampler as S
     dev = torch.device("cuda", 0)
@@ -131,6 +131,11 @@ def learned_report(args, torch, gmt, I):
 
     tests = [I.di_problem(2_000_000 + k, samples[k % sets], r=r_big, sample_seed=k % sets)
              for k in range(args.learned_test)]
+    # plain GMT* at n = 32768 gets its own tuned single-plan shape too
+    p0 = tests[0]
+    tuned_plain = gmt.gmt_autotune([gmt.BatchQuery(rms[p0.sample_seed], p0.x_init,
+                                                   gmt.make_goal(p0.goal_center, p0.goal_radius, 3),
+                                                   p0.boxes, p0.lam)], opts, single=True, reps=3)
     ref_cost, ref_ms = [], []
     for p in tests:
         res, ms = timed(lambda: gmt.gmt_plan(rms[p.sample_seed], p.x_init,
@@ -141,7 +146,7 @@ def learned_report(args, torch, gmt, I):
     ref_cost = np.array(ref_cost)
     rows = {}
     tuned_single = {}
-    for n in (2048, 4096, 8192):
+    for n in (1024, 2048, 4096, 8192):
         r_n = radius.di_radius(n)
         n_l = n // 2
         # single-plan launch shape for this n, tuned on one uniform sample set
@@ -158,6 +163,7 @@ def learned_report(args, torch, gmt, I):
         uni_full = [torch.from_numpy(I.di_samples(7_000 + ss, n)).to(dev) for ss in range(sets)]
         for learned in (True, False):
             costs, lat, rej = [], [], 0
+            parts = []
             for k, p in enumerate(tests):
                 goal = gmt.make_goal(p.goal_center, p.goal_radius, 3)
                 ss = k % sets
@@ -167,9 +173,14 @@ def learned_report(args, torch, gmt, I):
                         x, rj = S.mixed_samples(smp, p, n, 0, True, uniform=uni[ss], fallback=fb[ss], eps=eps[ss])
                     else:
                         x, rj = uni_full[ss], 0
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
                     rm = gmt.gmt_build_neighbors(x, gmt.GMT_COST_DOUBLE_INTEGRATOR, r_n)
+                    t2 = time.perf_counter()
                     res = gmt.gmt_plan(rm, p.x_init, goal, p.boxes, p.lam, opts, outputs=False)
+                    t3 = time.perf_counter()
                     rm.free()
+                    parts.append((t2 - t1, t3 - t2))
                     return res, rj
                 (res, rj), ms = timed(run)
                 rej += rj
@@ -183,6 +194,8 @@ def learned_report(args, torch, gmt, I):
                 "median_cost_ratio_vs_plain_n32768": round(float(np.median(ratio)), 4) if both.any() else None,
                 "mean_cost_ratio_vs_plain_n32768": round(float(np.mean(ratio)), 4) if both.any() else None,
                 "p50_ms_end_to_end": round(float(np.percentile(lat, 50)), 3),
+                "p50_ms_build": round(float(np.median([a for a, _ in parts])) * 1e3, 3),
+                "p50_ms_plan": round(float(np.median([b for _, b in parts])) * 1e3, 3),
                 "rejected_per_query": round(rej / len(tests), 1)}
     for rm in rms.values():
         rm.free()
@@ -194,7 +207,9 @@ def learned_report(args, torch, gmt, I):
             "test_problems": len(tests),
             "plain_n32768": {"solved": int(np.isfinite(ref_cost).sum()),
                              "p50_ms_plan_resident": round(float(np.percentile(ref_ms, 50)), 3),
-                             "build_ms": round(float(np.median(build_ms)), 3)},
+                             "build_ms": round(float(np.median(build_ms)), 3),
+                             "single_plan_shape": {kk: tuned_plain[kk] for kk in
+                                                   ("lanes", "team_wgs", "threads", "ms", "default_ms")}},
             "mixes": rows,
             "single_plan_shape": {str(k): {kk: v[kk] for kk in ("lanes", "team_wgs", "threads", "ms", "default_ms")}
                                   for k, v in tuned_single.items()},

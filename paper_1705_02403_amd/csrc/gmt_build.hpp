@@ -409,7 +409,8 @@ __device__ __forceinline__ DiPair di_pair(const double *src, const double *dst) 
 // from rows[1]).  The sources y are scanned in increasing order, prefiltered
 // by a lower bound on J, queued in LDS, and solved one per lane, so each row
 // comes out ascending.  Modes:
-//   DI_FILL    write the row at row_ptr[x];
+//   DI_FILL    write the row at row_ptr[x] (columns, arrival times, and
+//              (cost, column) records when `rec` is given, else costs);
 //   DI_SCRATCH write the row into scratch slot x of `cap` entries (entries
 //              past cap are dropped and x is appended to `ovf`: count ovf[0],
 //              list from ovf[1]); deg[x] receives the full row length.
@@ -419,7 +420,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
                                                  const int *__restrict__ rows, const int *__restrict__ row_ptr,
                                                  int cap, int *__restrict__ deg, int *__restrict__ ovf,
                                                  int *__restrict__ col, double *__restrict__ cost,
-                                                 double *__restrict__ tau) {
+                                                 double *__restrict__ tau, unsigned int *__restrict__ rec) {
     __shared__ int queue[4][DI_QCAP];
     const int wl = threadIdx.x / GMT_WAVE;
     const int lane = lane_id();
@@ -455,8 +456,15 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         const int k = found + lanes_below(m);
         if (hit && (mode == DI_FILL || k < cap)) {
             col[base + k] = y;
-            cost[base + k] = J;
             tau[base + k] = t;
+            if (rec) {
+                const unsigned long long b = (unsigned long long)__double_as_longlong(J);
+                rec[3 * (base + k)] = (unsigned int)(b & 0xffffffffull);
+                rec[3 * (base + k) + 1] = (unsigned int)(b >> 32);
+                rec[3 * (base + k) + 2] = (unsigned int)y;
+            } else {
+                cost[base + k] = J;
+            }
         }
         found += (int)__popcll(m);
         __builtin_amdgcn_wave_barrier();
@@ -491,13 +499,14 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
     }
 }
 
-// scratch rows (cap entries each) -> CSR; rows longer than cap are left to
-// a DI_FILL pass over the overflow list.  One wave per row.
+// scratch rows (cap entries each) -> CSR columns, arrival times and (cost,
+// column) records; rows longer than cap are left to a DI_FILL pass over the
+// overflow list.  One wave per row.
 __global__ void __launch_bounds__(256) k_di_compact(int n, int cap, const int *__restrict__ deg,
                                                     const int *__restrict__ row_ptr, const int *__restrict__ scol,
                                                     const double *__restrict__ scost, const double *__restrict__ stau,
-                                                    int *__restrict__ col, double *__restrict__ cost,
-                                                    double *__restrict__ tau) {
+                                                    int *__restrict__ col, double *__restrict__ tau,
+                                                    unsigned int *__restrict__ rec) {
     const int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
     if (x >= n) return;
     const int d = deg[x];
@@ -505,9 +514,13 @@ __global__ void __launch_bounds__(256) k_di_compact(int n, int cap, const int *_
     const size_t src = (size_t)x * cap;
     const int dst = row_ptr[x];
     for (int k = lane_id(); k < d; k += GMT_WAVE) {
-        col[dst + k] = scol[src + k];
-        cost[dst + k] = scost[src + k];
+        const int y = scol[src + k];
+        const unsigned long long b = (unsigned long long)__double_as_longlong(scost[src + k]);
+        col[dst + k] = y;
         tau[dst + k] = stau[src + k];
+        rec[3 * ((size_t)dst + k)] = (unsigned int)(b & 0xffffffffull);
+        rec[3 * ((size_t)dst + k) + 1] = (unsigned int)(b >> 32);
+        rec[3 * ((size_t)dst + k) + 2] = (unsigned int)y;
     }
 }
 

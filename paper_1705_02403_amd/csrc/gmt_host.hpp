@@ -18,7 +18,17 @@ struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     gmt_allocator a{nullptr, nullptr, nullptr};
+    bool view = false;  // a part of another buffer: never freed on its own
 };
+
+// a view of `bytes` bytes at `off` inside `block`
+inline DevBuf dev_view(const DevBuf &block, size_t off, size_t bytes) {
+    DevBuf v;
+    v.p = (char *)block.p + off;
+    v.bytes = bytes;
+    v.view = true;
+    return v;
+}
 
 // allocate `bytes` (rounded up to 256) with the allocator installed now
 gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s);

@@ -70,6 +70,10 @@ gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
 
 void dev_free(DevBuf &b, hipStream_t s) {
     if (!b.p) return;
+    if (b.view) {
+        b.p = nullptr;
+        return;
+    }
     if (b.a.free)
         b.a.free(b.p, b.a.ctx, (void *)s);
     else if (!b.a.alloc)
@@ -176,6 +180,7 @@ struct gmt_roadmap {
     DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
     DevBuf in_rec;   // (edge cost, column) records of the in-table, 12 bytes per edge
     DevBuf s8;       // double integrator: states as 8 floats per node
+    DevBuf tab;      // one block holding the tables above that are views into it
     bool out_shared = false;
 };
 
@@ -207,6 +212,7 @@ static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
     dev_free(rm->in_tau, s);
     dev_free(rm->in_rec, s);
     dev_free(rm->s8, s);
+    dev_free(rm->tab, s);
     if (!rm->out_shared) {
         dev_free(rm->out_ptr, s);
         dev_free(rm->out_col, s);
@@ -215,15 +221,26 @@ static void roadmap_release(gmt_roadmap *rm, hipStream_t s) {
 
 
 static inline unsigned blocks_for(long long threads, int per) { return (unsigned)((threads + per - 1) / per); }
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // exclusive scan of in[0, count) into out[0, count], out[count] = total; the
 // 64-bit total also goes to *total when given (device memory)
-static gmt_status scan_ints(const int *in, int count, int *out, long long *total, hipStream_t s) {
+static size_t scan_scratch_bytes(int count) {
+    const size_t nt = std::max<size_t>(1, ((size_t)count + SCAN_TILE - 1) / SCAN_TILE);
+    return sizeof(long long) * (2 * nt + 1);
+}
+
+// `scratch`: scan_scratch_bytes(count) device bytes, or null to allocate them
+static gmt_status scan_ints(const int *in, int count, int *out, long long *total, hipStream_t s,
+                            void *scratch = nullptr) {
     const int nt = std::max(1, (int)(((long long)count + SCAN_TILE - 1) / SCAN_TILE));
     DevBuf tb;
     Temps keep(s, {&tb});
-    TRY(dev_alloc(tb, sizeof(long long) * (2 * (size_t)nt + 1), s));
-    long long *tsum = (long long *)tb.p, *toff = tsum + nt;
+    if (!scratch) {
+        TRY(dev_alloc(tb, scan_scratch_bytes(count), s));
+        scratch = tb.p;
+    }
+    long long *tsum = (long long *)scratch, *toff = tsum + nt;
     long long *tot = total ? total : toff + nt;
     if (nt == 1) {
         k_scan_tile<<<1, 1024, 0, s>>>(in, count, out, tsum, tot);
@@ -236,21 +253,32 @@ static gmt_status scan_ints(const int *in, int count, int *out, long long *total
     return GMT_OK;
 }
 
-// out-neighbour table by transposing the in-table
-static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s) {
+// device bytes build_out_table needs as scratch for n nodes
+static size_t out_scratch_bytes(int n) { return 2 * al256(sizeof(int) * (size_t)n) + al256(scan_scratch_bytes(n)); }
+
+// out-neighbour table by transposing the in-table; out_ptr / out_col are
+// allocated here unless already set; `scratch` (out_scratch_bytes(n)) or null
+static gmt_status build_out_table(gmt_roadmap *rm, hipStream_t s, void *scratch = nullptr) {
     const int n = rm->n;
-    DevBuf deg, cursor;
-    Temps keep(s, {&deg, &cursor});
-    TRY(dev_alloc(rm->out_ptr, sizeof(int) * (n + 1), s));
-    TRY(dev_alloc(rm->out_col, sizeof(int) * std::max<long long>(rm->nnz, 1), s));
+    DevBuf deg, cursor, sb;
+    Temps keep(s, {&deg, &cursor, &sb});
+    if (!rm->out_ptr.p) TRY(dev_alloc(rm->out_ptr, sizeof(int) * (n + 1), s));
+    if (!rm->out_col.p) TRY(dev_alloc(rm->out_col, sizeof(int) * std::max<long long>(rm->nnz, 1), s));
     rm->out_shared = false;
-    TRY(dev_alloc(deg, sizeof(int) * n, s));
-    TRY(dev_alloc(cursor, sizeof(int) * n, s));
+    if (!scratch) {
+        TRY(dev_alloc(sb, out_scratch_bytes(n), s));
+        scratch = sb.p;
+    }
+    deg.p = scratch;
+    deg.view = true;
+    cursor.p = (char *)scratch + al256(sizeof(int) * (size_t)n);
+    cursor.view = true;
+    void *scan_tmp = (char *)scratch + 2 * al256(sizeof(int) * (size_t)n);
     k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)deg.p, n, 0);
     k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>((int *)cursor.p, n, 0);
     const unsigned wave_blocks = blocks_for((long long)n * GMT_WAVE, 256);
     k_out_count<<<wave_blocks, 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n, (int *)deg.p);
-    TRY(scan_ints((const int *)deg.p, n, (int *)rm->out_ptr.p, nullptr, s));
+    TRY(scan_ints((const int *)deg.p, n, (int *)rm->out_ptr.p, nullptr, s, scan_tmp));
     k_out_place<<<wave_blocks, 256, 0, s>>>((const int *)rm->in_ptr.p, (const int *)rm->in_col.p, n,
                                             (const int *)rm->out_ptr.p, (int *)cursor.p, (int *)rm->out_col.p);
     // out-rows stay in placement order: the frontier's candidate order does not
@@ -294,16 +322,24 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     g.G = (int)std::max(1.0, std::min({per_axis, (double)Gmax, (double)Gn}));
     g.ncell = 1;
     for (int a = 0; a < dim; ++a) g.ncell *= g.G;
-    DevBuf cell_of, cell_cnt, cell_start, cursor, pts, deg, scal;
-    Temps keep(s, {&cell_of, &cell_cnt, &cell_start, &cursor, &pts, &deg, &scal});
-    TRY(dev_alloc(cell_of, sizeof(int) * n, s));
-    TRY(dev_alloc(cell_cnt, sizeof(int) * g.ncell, s));
-    TRY(dev_alloc(cell_start, sizeof(int) * (g.ncell + 1), s));
-    TRY(dev_alloc(cursor, sizeof(int) * g.ncell, s));
-    TRY(dev_alloc(pts, sizeof(int4) * (size_t)n, s));
-    TRY(dev_alloc(deg, sizeof(int) * n, s));
-    TRY(dev_alloc(scal, 64, s));  // [0] flags, [1] maxdeg, [2..3] total (long long)
+    // one block of temporaries: cell of each sample, cell counts and starts,
+    // placement cursors, the cell-sorted samples, row lengths, flags, scan scratch
+    const size_t nc = (size_t)g.ncell;
+    const size_t o_cnt = al256(sizeof(int) * (size_t)n);
+    const size_t o_start = o_cnt + al256(sizeof(int) * nc);
+    const size_t o_cur = o_start + al256(sizeof(int) * (nc + 1));
+    const size_t o_pts = o_cur + al256(sizeof(int) * nc);
+    const size_t o_deg = o_pts + al256(sizeof(int4) * (size_t)n);
+    const size_t o_scal = o_deg + al256(sizeof(int) * (size_t)n);  // [0] flags, [1] maxdeg, [2..3] total
+    const size_t o_scan = o_scal + 256;
+    DevBuf tmp;
+    Temps keep(s, {&tmp});
+    TRY(dev_alloc(tmp, o_scan + al256(std::max(scan_scratch_bytes(g.ncell), scan_scratch_bytes(n))), s));
     TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
+    const DevBuf cell_of = dev_view(tmp, 0, 0), cell_cnt = dev_view(tmp, o_cnt, 0),
+                 cell_start = dev_view(tmp, o_start, 0), cursor = dev_view(tmp, o_cur, 0),
+                 pts = dev_view(tmp, o_pts, 0), deg = dev_view(tmp, o_deg, 0), scal = dev_view(tmp, o_scal, 0);
+    void *scan_tmp = (char *)tmp.p + o_scan;
     int *flags = (int *)scal.p, *maxdeg = flags + 1;
     long long *total = (long long *)(flags + 2);
     k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
@@ -312,14 +348,14 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, dim, 0, flags);
     k_eu_bin<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (int *)cell_of.p,
                                                (int *)cell_cnt.p);
-    TRY(scan_ints((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr, s));
+    TRY(scan_ints((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr, s, scan_tmp));
     k_eu_scatter<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (const int *)cell_of.p,
                                                    (const int *)cell_start.p, (int *)cursor.p, (int4 *)pts.p);
     // one workgroup per EU_XB cells along x
     const unsigned wgs = (unsigned)((g.G + EU_XB - 1) / EU_XB) * (unsigned)g.G * (unsigned)(dim == 3 ? g.G : 1);
     k_eu_rows<true><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, (int *)deg.p,
                                         maxdeg, nullptr, nullptr, nullptr);
-    TRY(scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s));
+    TRY(scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s, scan_tmp));
     int hs[4];
     HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -328,8 +364,11 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     if (hs[0]) return fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
     if (E > 0x7fffffffLL) return fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
     rm->nnz = E;
-    TRY(dev_alloc(rm->in_col, sizeof(int) * std::max<long long>(E, 1), s));
-    TRY(dev_alloc(rm->in_rec, 12 * (size_t)(E + GMT_REC_PAD), s));
+    // one block for the columns and the (cost, column) records with their padding
+    const size_t o_rec = al256(sizeof(int) * (size_t)std::max<long long>(E, 1));
+    TRY(dev_alloc(rm->tab, o_rec + 12 * (size_t)(E + GMT_REC_PAD), s));
+    rm->in_col = dev_view(rm->tab, 0, sizeof(int) * (size_t)std::max<long long>(E, 1));
+    rm->in_rec = dev_view(rm->tab, o_rec, 12 * (size_t)(E + GMT_REC_PAD));
     k_eu_rows<false><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, nullptr, nullptr,
                                          (const int *)rm->in_ptr.p, (unsigned int *)rm->in_rec.p,
                                          (int *)rm->in_col.p);
@@ -351,62 +390,76 @@ static const int kDiScratchCap = 384;
 static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n;
     const int cap = kDiScratchCap;
-    DevBuf deg, scal, ovf, scol, scost, stau;
-    Temps keep(s, {&deg, &scal, &ovf, &scol, &scost, &stau});
-    TRY(dev_alloc(deg, sizeof(int) * n, s));
-    TRY(dev_alloc(scal, 64, s));
-    TRY(dev_alloc(ovf, sizeof(int) * ((size_t)n + 1), s));
+    // one block of temporaries: row lengths, flags, overflow list, scratch
+    // rows, scan and transpose scratch
+    const size_t o_scal = al256(sizeof(int) * (size_t)n);
+    const size_t o_ovf = o_scal + 256;
+    const size_t o_scol = o_ovf + al256(sizeof(int) * ((size_t)n + 1));
+    const size_t o_scost = o_scol + al256(sizeof(int) * (size_t)n * cap);
+    const size_t o_stau = o_scost + al256(sizeof(double) * (size_t)n * cap);
+    const size_t o_scan = o_stau + al256(sizeof(double) * (size_t)n * cap);
+    const size_t o_out = o_scan + al256(scan_scratch_bytes(n));
+    DevBuf tmp;
+    Temps keep(s, {&tmp});
+    TRY(dev_alloc(tmp, o_out + out_scratch_bytes(n), s));
     TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
-    gmt_status st = dev_alloc(scol, sizeof(int) * (size_t)n * cap, s);
-    if (st == GMT_OK) st = dev_alloc(scost, sizeof(double) * (size_t)n * cap, s);
-    if (st == GMT_OK) st = dev_alloc(stau, sizeof(double) * (size_t)n * cap, s);
-    int *flags = (int *)scal.p;
+    char *T = (char *)tmp.p;
+    int *deg = (int *)T, *flags = (int *)(T + o_scal), *ovf = (int *)(T + o_ovf), *scol = (int *)(T + o_scol);
+    double *scost = (double *)(T + o_scost), *stau = (double *)(T + o_stau);
     long long *total = (long long *)(flags + 2);
     int hs[4] = {0, 0, 0, 0}, novf = 0;
-    if (st == GMT_OK) {
-        k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
-        k_fill_int<<<1, 64, 0, s>>>((int *)ovf.p, 1, 0);
-        k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
-        k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
-            (const float *)rm->s.p, n, rm->r, DI_SCRATCH, nullptr, nullptr, cap, (int *)deg.p, (int *)ovf.p,
-            (int *)scol.p, (double *)scost.p, (double *)stau.p);
-        st = scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s);
-    }
-    if (st == GMT_OK) {
+    k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
+    k_fill_int<<<1, 64, 0, s>>>(ovf, 1, 0);
+    k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
+    k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->r, DI_SCRATCH,
+                                                                     nullptr, nullptr, cap, deg, ovf, scol, scost,
+                                                                     stau, nullptr);
+    TRY(scan_ints(deg, n, (int *)rm->in_ptr.p, total, s, T + o_scan));
+    {
         hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(&novf, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, flags, sizeof hs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&novf, ovf, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour pass failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour pass failed: %s", hipGetErrorString(e));
     }
     long long E = 0;
     std::memcpy(&E, hs + 2, sizeof E);
-    if (st == GMT_OK) {
-        if (hs[0]) st = fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, on the 2^-20 grid");
-        else if (E > 0x7fffffffLL) st = fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
-    }
-    if (st == GMT_OK) {
-        rm->nnz = E;
-        size_t e1 = (size_t)std::max<long long>(E, 1);
-        st = dev_alloc(rm->in_col, sizeof(int) * e1, s);
-        if (st == GMT_OK) st = dev_alloc(rm->in_cost, sizeof(double) * e1, s);
-        if (st == GMT_OK) st = dev_alloc(rm->in_tau, sizeof(double) * e1, s);
-    }
-    if (st == GMT_OK) {
-        k_di_compact<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
-            n, cap, (const int *)deg.p, (const int *)rm->in_ptr.p, (const int *)scol.p, (const double *)scost.p,
-            (const double *)stau.p, (int *)rm->in_col.p, (double *)rm->in_cost.p, (double *)rm->in_tau.p);
-        if (novf > 0)
-            k_di_rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
-                (const float *)rm->s.p, n, rm->r, DI_FILL, (const int *)ovf.p, (const int *)rm->in_ptr.p, cap,
-                nullptr, nullptr, (int *)rm->in_col.p, (double *)rm->in_cost.p, (double *)rm->in_tau.p);
+    if (hs[0])
+        return fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, "
+                                "on the 2^-20 grid");
+    if (E > 0x7fffffffLL) return fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    rm->nnz = E;
+    // one block for the roadmap's tables: columns, arrival times, out-table,
+    // (cost, column) records with their padding, 8-float states
+    const size_t e1 = (size_t)std::max<long long>(E, 1);
+    const size_t o_tau = al256(sizeof(int) * e1);
+    const size_t o_optr = o_tau + al256(sizeof(double) * e1);
+    const size_t o_ocol = o_optr + al256(sizeof(int) * ((size_t)n + 1));
+    const size_t o_rec = o_ocol + al256(sizeof(int) * e1);
+    const size_t o_s8 = o_rec + al256(12 * ((size_t)E + GMT_REC_PAD));
+    TRY(dev_alloc(rm->tab, o_s8 + al256(32 * (size_t)n), s));
+    rm->in_col = dev_view(rm->tab, 0, sizeof(int) * e1);
+    rm->in_tau = dev_view(rm->tab, o_tau, sizeof(double) * e1);
+    rm->out_ptr = dev_view(rm->tab, o_optr, sizeof(int) * ((size_t)n + 1));
+    rm->out_col = dev_view(rm->tab, o_ocol, sizeof(int) * e1);
+    rm->in_rec = dev_view(rm->tab, o_rec, 12 * ((size_t)E + GMT_REC_PAD));
+    rm->s8 = dev_view(rm->tab, o_s8, 32 * (size_t)n);
+    int *col = (int *)rm->in_col.p;
+    double *tau = (double *)rm->in_tau.p;
+    unsigned int *rec = (unsigned int *)rm->in_rec.p;
+    k_di_compact<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(n, cap, deg, (const int *)rm->in_ptr.p, scol,
+                                                                         scost, stau, col, tau, rec);
+    if (novf > 0)
+        k_di_rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
+            (const float *)rm->s.p, n, rm->r, DI_FILL, ovf, (const int *)rm->in_ptr.p, cap, nullptr, nullptr, col,
+            nullptr, tau, rec);
+    k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>(rec, E);
+    k_aos8<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, (float4 *)rm->s8.p);
+    {
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) st = fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
     }
-    for (DevBuf *b : {&deg, &ovf, &scol, &scost, &stau}) dev_free(*b, s);
-    if (st == GMT_OK) st = build_out_table(rm, s);
-    if (st == GMT_OK) st = pack_records(rm, s);
-    return st;
+    return build_out_table(rm, s, T + o_out);
 }
 
 extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim,
@@ -575,7 +628,6 @@ struct WsBlock {
 static std::mutex g_ws_mu;
 static std::vector<WsBlock *> g_ws;
 
-static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // bytes of one query's workspace over N nodes (tree arrays included when the
 // caller does not supply them)
@@ -1431,7 +1483,9 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
             const int per_cu = 1024 / threads;  // workgroups per CU at the kernel's register budget
             std::vector<int> teams = {num_cus() * per_cu};
             for (int t = 8 * per_cu; t < num_cus() * per_cu; t *= 2) teams.push_back(t);
-            if (threads == 1024) teams = {num_cus() / 8, num_cus() / 4, num_cus() / 2, num_cus()};
+            // 1024-thread teams from one workgroup (a whole query in one CU's
+            // LDS, workgroup barriers only: small n) up to the whole GPU
+            if (threads == 1024) teams = {1, 4, num_cus() / 8, num_cus() / 4, num_cus() / 2, num_cus()};
             for (int l : lanes) {
                 const int cap = max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, l, threads);
                 for (int t : teams)
