@@ -150,6 +150,28 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
     return pred ? base + lanes_below(m) : -1;
 }
 
+// wave-aggregated append of up to U items per lane with one atomic for the
+// wave: item u of a lane gets slot[u] (-1 when pred[u] is false)
+template <int U>
+__device__ __forceinline__ void wave_append_n(int *counter, const bool *pred, int *slot) {
+    uint64_t m[U];
+    int pre[U], tot = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        m[u] = wave_ballot(pred[u]);
+        pre[u] = tot;
+        tot += (int)__popcll(m[u]);
+    }
+    int base = 0;
+    if (tot > 0) {
+        const int leader = __ffsll((unsigned long long)wave_ballot(true)) - 1;
+        if (lane_id() == leader) base = atomicAdd(counter, tot);
+        base = __builtin_amdgcn_readlane(base, leader);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) slot[u] = pred[u] ? base + pre[u] + lanes_below(m[u]) : -1;
+}
+
 template <int DIM>
 __device__ __forceinline__ void sample_d(const RoadmapDev &R, int v, double *x) {
     if (DIM == 6) {
@@ -773,15 +795,20 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             const int *gl = w.glist + p * N;
             const int sub = t.lane / CL, lg = t.lane & (CL - 1);
             constexpr int per_wave = GMT_WAVE / CL;
-            for (int gb = t.wave * per_wave; gb < gc; gb += t.nwaves * per_wave) {
+            // a round's group member is read two rounds ahead and its out-row
+            // extent one round ahead, so neither load is waited on
+            const int stride = t.nwaves * per_wave, first = t.wave * per_wave + sub;
+            int g1 = first < gc ? gl[first] : 0;
+            int g2 = first + stride < gc ? gl[first + stride] : 0;
+            int ob1 = first < gc ? R.out_ptr[g1] : 0, oe1 = first < gc ? R.out_ptr[g1 + 1] : 0;
+            for (int gb = t.wave * per_wave; gb < gc; gb += stride) {
                 const int gk = gb + sub;
-                int ob = 0, oe = 0;
-                if (gk < gc) {
-                    const int g = gl[gk];
-                    ob = R.out_ptr[g];
-                    oe = R.out_ptr[g + 1];
-                    if (lg == 0) w_out += (unsigned long long)(oe - ob);
-                }
+                const int ob = ob1, oe = oe1;
+                g1 = g2;
+                ob1 = gk + stride < gc ? R.out_ptr[g1] : 0;
+                oe1 = gk + stride < gc ? R.out_ptr[g1 + 1] : 0;
+                g2 = gk + 2 * stride < gc ? gl[gk + 2 * stride] : 0;
+                if (gk < gc && lg == 0) w_out += (unsigned long long)(oe - ob);
                 // FRONT_U out-edges per lane per step: their loads are issued
                 // together
                 for (int e0 = ob + lg; e0 < oe; e0 += FRONT_U * CL) {
@@ -800,11 +827,11 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                             if ((sx & S_SET) == S_UNEXPLORED && !(sx & S_CLAIM)) cand[u] = claim(st, xs[u]);
                         }
                     }
+                    int slot[FRONT_U];
+                    wave_append_n<FRONT_U>(&ctl->c_cnt, cand, slot);
 #pragma unroll
-                    for (int u = 0; u < FRONT_U; ++u) {
-                        const int slot = wave_append(&ctl->c_cnt, cand[u]);
-                        if (cand[u]) w.clist[slot] = xs[u];
-                    }
+                    for (int u = 0; u < FRONT_U; ++u)
+                        if (cand[u]) w.clist[slot[u]] = xs[u];
                 }
             }
         }

@@ -43,6 +43,14 @@ def test_di_inputs_are_valid():
     assert not np.any(I._in_any_box(I.to_grid(p.x_init[:3])[None, :], b))
 
 
+def test_clustered_samples_are_valid():
+    for dim in (2, 3):
+        s = I.clustered_samples(11, dim, 500, 0.05)
+        assert s.shape == (dim, 500) and s.dtype == np.float32 and I.on_grid(s)
+        assert np.all(s >= 0) and np.all(s <= 0.05)
+    assert np.array_equal(I.clustered_samples(4, 3, 64, 0.1), I.clustered_samples(4, 3, 64, 0.1))
+
+
 def test_poisson_stream_rate():
     t = I.poisson_arrivals(20000, 2000.0, seed=7)
     assert np.all(np.diff(t) > 0)
