@@ -812,19 +812,31 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 // FRONT_U out-edges per lane per step: their loads are issued
                 // together
                 for (int e0 = ob + lg; e0 < oe; e0 += FRONT_U * CL) {
+                    // slots past the row end read its first edge and are masked
                     int xs[FRONT_U];
+                    bool val[FRONT_U];
 #pragma unroll
                     for (int u = 0; u < FRONT_U; ++u) {
                         const int e = e0 + u * CL;
-                        xs[u] = e < oe ? R.out_col[e] : -1;
+                        val[u] = e < oe;
+                        xs[u] = ((global_u32 *)R.out_col)[val[u] ? e : e0];
                     }
+                    unsigned int sx[FRONT_U];
+#pragma unroll
+                    for (int u = 0; u < FRONT_U; ++u) sx[u] = st[xs[u]];
                     bool cand[FRONT_U];
 #pragma unroll
                     for (int u = 0; u < FRONT_U; ++u) {
-                        cand[u] = false;
-                        if (xs[u] >= 0) {
-                            const unsigned char sx = st[xs[u]];
-                            if ((sx & S_SET) == S_UNEXPLORED && !(sx & S_CLAIM)) cand[u] = claim(st, xs[u]);
+                        const bool want = val[u] & ((sx[u] & S_SET) == S_UNEXPLORED) & !(sx[u] & S_CLAIM);
+                        if (LDS >= 1) {
+                            // state in LDS: every slot issues its atomic (OR of 0
+                            // when it claims nothing), so they are in flight together
+                            unsigned int *wd = (unsigned int *)(st) + (xs[u] >> 2);
+                            const unsigned int bit = (unsigned int)S_CLAIM << ((xs[u] & 3) * 8);
+                            const unsigned int prev = atomicOr(wd, want ? bit : 0u);
+                            cand[u] = want & !(prev & bit);
+                        } else {
+                            cand[u] = want && claim(st, xs[u]);
                         }
                     }
                     int slot[FRONT_U];
