@@ -574,13 +574,12 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             w.ai[v] = -1;
         } else if (v < n) {
             int q[6] = {0, 0, 0, 0, 0, 0};
-            float pf[3] = {0.0f, 0.0f, 0.0f};
+            float pf[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int a = 0; a < (KIND == 0 ? 3 : 6); ++a) {
                 if (KIND == 1 || a < R.dim) {
-                    const float x = R.s[(size_t)a * n + v];
-                    q[a] = (int)((double)x * GMT_QS);
-                    if (a < 3) pf[a] = x;
+                    pf[a] = R.s[(size_t)a * n + v];
+                    q[a] = (int)((double)pf[a] * GMT_QS);
                 }
             }
             // grid coordinates are exact in FP32, as are the staged boxes
@@ -601,7 +600,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     cand = (double)d2 < R.R2;
                 } else {
                     double xs[6];
-                    sample_d<6>(R, v, xs);
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) xs[a] = (double)pf[a];
                     cand = di_may_connect(make_pair(P.x_d, xs), R.r);
                 }
             }
