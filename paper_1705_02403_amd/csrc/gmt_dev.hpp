@@ -50,8 +50,10 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return (uint64_t)__bal
 // of 2*OFF lanes, stages taken in order OFF = 1, 2, 4, ...: the partner is
 // lane ^ 1 and lane ^ 2 within a quad, then the mirror lane within 8 and
 // within 16 (which lies in the other half once each half is reduced), all
-// by DPP moves within a row; lane ^ 16 and up by a cross-lane permute.  Every
-// lane of the wave must be active.
+// by DPP moves within a row; lane ^ 16 and up by a cross-lane permute.  The
+// partner always lies in the same aligned group of 2*OFF lanes, so the lanes
+// of each such group must be active together (inactive groups may be
+// anywhere in the wave).
 template <int OFF>
 __device__ __forceinline__ int lane_swap(int x) {
     if (OFF == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
