@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
 # with this digest and the launch shape named; reported only while both match
-TRAFFIC = {"sources_sha256": "d8e45fe8379cd7e82b7dcd29606d5fbae617f126058fb576e2af9015ca1cc129",
+TRAFFIC = {"sources_sha256": "2945b5a09290d4ab8dfc763d7ea482d1359ff0c2aced8b0dfa2ee2a899464918",
            "batch": 4096, "lanes": 8, "threads": 1024,
            "bytes_per_launch": int((2.0 * 71622343 + 5660388) * 1024)}
 
