@@ -143,3 +143,56 @@ def test_forced_failures(world):
     # the library still works afterwards
     res = gmt.gmt_plan(rm, p.x_init, goal_of(p), p.boxes, p.lam, o, outputs=False)
     assert res.status in (gmt.GMT_OK, gmt.GMT_NO_PATH)
+
+
+@pytest.mark.parametrize("kind", ["euclid", "di"])
+def test_build_failure_frees_everything(kind):
+    """An allocator that fails after k successful allocations: every build
+    reports GMT_ENOMEM and returns each buffer it obtained (the live set is
+    empty afterwards), for every k until the build succeeds."""
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    say("build failure paths (%s)" % kind)
+    if kind == "euclid":
+        s = I.problem_3d(2, n=3000).samples
+        ck, r = gmt.GMT_COST_EUCLIDEAN, 0.2
+    else:
+        s = I.di_samples(5, 1024)
+        ck, r = gmt.GMT_COST_DOUBLE_INTEGRATOR, 2.5
+    d = torch.from_numpy(s).cuda()
+    live, budget = {}, [0]
+
+    @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+    def counted_alloc(nbytes, ctx, stream):
+        if budget[0] <= 0:
+            return None
+        budget[0] -= 1
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    @C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+    def counted_free(ptr, ctx, stream):
+        live.pop(int(ptr))
+
+    a = gmt.gmt_allocator(counted_alloc, counted_free, None)
+    assert gmt.lib().gmt_set_allocator(C.byref(a)) == gmt.GMT_OK
+    try:
+        for k in range(0, 40):
+            budget[0] = k
+            try:
+                rm = gmt.gmt_build_neighbors(d, ck, r)
+            except gmt.GmtError as e:
+                assert e.status == gmt.GMT_ENOMEM, (k, e.status)
+                torch.cuda.synchronize()
+                assert not live, (k, len(live))
+                continue
+            assert rm.nnz > 0
+            rm.free()
+            torch.cuda.synchronize()
+            assert not live
+            break
+        else:
+            raise AssertionError("the build never succeeded")
+    finally:
+        gmt.use_torch_allocator()
