@@ -239,7 +239,9 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
 #ifndef EU_XB
 #define EU_XB 2
 #endif
+#ifndef EU_CHUNK
 #define EU_CHUNK 1280
+#endif
 #define EU_ROWS 512
 #define EU_OBUF 256
 #define EU_FAR (1 << 29)
