@@ -371,9 +371,11 @@ static int euclid_edge_free(const orc_ctx *cx, int y, int x)
 }
 
 /* DI lazy check at traj_points times t_k = k tau/(K-1) of the optimal cubic.
- * *margin receives the distance (L-inf, position units) by which the decision
- * is robust: for a free edge the least clearance, for a colliding edge the
- * deepest penetration. */
+ * The cubic meets both boundary states exactly (p(0) = p_y, p(tau) = p_x), so
+ * the first and last points are the two states' own positions rather than the
+ * rounded polynomial values.  *margin receives the distance (L-inf, position
+ * units) by which the decision is robust: for a free edge the least
+ * clearance, for a colliding edge the deepest penetration. */
 static int di_edge_free(const orc_ctx *cx, int y, int x, double tau, double *margin)
 {
     double xy[6], xx[6];
@@ -385,7 +387,9 @@ static int di_edge_free(const orc_ctx *cx, int y, int x, double tau, double *mar
     for (int k = 0; k < K; ++k) {
         double t = (K > 1) ? tau * (double)k / (double)(K - 1) : 0.0;
         double p[3];
-        orc_di_point(xy, xx, tau, t, p);
+        if (k == 0) { p[0] = xy[0]; p[1] = xy[1]; p[2] = xy[2]; }
+        else if (k == K - 1) { p[0] = xx[0]; p[1] = xx[1]; p[2] = xx[2]; }
+        else orc_di_point(xy, xx, tau, t, p);
         /* workspace bound [0,1]^3: signed distance outside */
         double s = -INFINITY;
         for (int a = 0; a < 3; ++a) {
