@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
@@ -83,12 +84,27 @@ def parse():
     return ap.parse_args()
 
 
-def plan_bytes(w):
-    """Algorithmic bytes of planning work (FP64 edge costs):
-    4 B per out-edge walked (index), 28 B per in-edge scanned (index 4 + FP64
-    edge cost 8 + node state 16), 16 B per node added, 12 B per open-list
-    entry partitioned."""
-    return (4 * w["out_edges"] + 28 * w["in_edges"] + 16 * w["commits"] + 12 * w["open_entries"])
+def plan_bytes(w, in_edge=24):
+    """Algorithmic bytes of planning work: 4 B per out-edge walked (index),
+    `in_edge` B per in-edge scanned, 16 B per node added, 12 B per open-list
+    entry partitioned.  24 B per in-edge is the unit the method must move
+    (8 B index + FP32 edge cost, 16 B of node state gathered); the table as
+    built stores FP64 edge costs in 12-byte records, 28 B per in-edge."""
+    return (4 * w["out_edges"] + in_edge * w["in_edges"] + 16 * w["commits"] + 12 * w["open_entries"])
+
+
+def euclid_build_bytes(n, dim, edges, per_edge=8):
+    """Algorithmic bytes of a Euclidean table: samples read (4 B per
+    coordinate), row pointers, and per edge an index plus an FP32 cost (8 B);
+    the table as built writes a 12-byte (FP64 cost, column) record and a
+    4-byte column per edge (16 B)."""
+    return 4 * dim * n + 4 * (n + 1) + per_edge * edges
+
+
+def di_build_flops(tested, solved):
+    """Algorithmic flops of a double-integrator table: about 150 per pair whose
+    arrival-time quartic is solved, 10 per pair the lower bound rejects."""
+    return 150 * solved + 10 * (tested - solved)
 
 
 def learned_report(args, torch, gmt, I):
@@ -289,7 +305,8 @@ def main():
 
     # ---- resident roadmaps (untimed; the method precomputes them) ----
     samples = {ss: I.di_samples(ss, n) for ss in range(args.sample_sets)}
-    rms, build_ms = {}, []
+    rms, build_ms, di_builds = {}, [], []
+    gmt.gmt_profile_enable(True)
     for ss in range(args.sample_sets):
         d = torch.from_numpy(samples[ss]).cuda()
         torch.cuda.synchronize()
@@ -297,7 +314,23 @@ def main():
         rms[ss] = gmt.gmt_build_neighbors(d, gmt.GMT_COST_DOUBLE_INTEGRATOR, r)
         torch.cuda.synchronize()
         build_ms.append((time.perf_counter() - t0) * 1e3)
+        di_builds.append(gmt.gmt_last_build())
+    gmt.gmt_profile_enable(False)
+    gmt.gmt_profile_read()
     nnz = [rms[ss].nnz for ss in rms]
+    # the first build of the process also pays module loading: median of the rest
+    dib = di_builds[1:] if len(di_builds) > 1 else di_builds
+    di_kms = float(np.median([b["kernel_ms"] for b in dib]))
+    di_flops = float(np.median([di_build_flops(b["pairs_tested"], b["pairs_solved"]) for b in dib]))
+    di_build_line = {"workload": "6D double integrator n=%d, r=%.3f" % (n, r), "bound": "fp64-valu",
+                     "kernel_ms": round(di_kms, 4),
+                     "pairs_tested": int(np.median([b["pairs_tested"] for b in dib])),
+                     "pairs_solved": int(np.median([b["pairs_solved"] for b in dib])),
+                     "flops": int(di_flops), "achieved": round(di_flops / (di_kms * 1e-3) / 1e12, 2),
+                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(di_flops / (di_kms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
+                     "flop_model": "150 per solved pair + 10 per prefiltered pair",
+                     "wall_ms": round(float(np.median(build_ms[1:] or build_ms)), 3)}
 
     probs = [I.di_problem(k, samples[k % args.sample_sets], sample_seed=k % args.sample_sets)
              for k in range(args.batch)]
@@ -359,6 +392,7 @@ def main():
     avg_kernel_ms = kernel_ms / max(launches, 1)
     bytes_per_launch = plan_bytes(work)  # one launch plans the whole batch
     achieved = bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9
+    bytes_as_built = plan_bytes(work, in_edge=28)
     shape = (tuned["batch"] if tuned else {"lanes": args.lanes, "threads": args.threads})
     traffic = None
     if (kernel_digest() == TRAFFIC["sources_sha256"] and args.batch == TRAFFIC["batch"]
@@ -413,21 +447,30 @@ def main():
             p3 = I.problem_3d(0, n=n3)
             r3 = RAD.problem_radius(p3)
             d3 = torch.from_numpy(p3.samples).cuda()
-            bt = []
+            bt, kt = [], []
+            gmt.gmt_profile_enable(True)
             for k in range(5):
                 torch.cuda.synchronize()
                 t = time.perf_counter()
                 rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
                 torch.cuda.synchronize()
                 bt.append((time.perf_counter() - t) * 1e3)
+                kt.append(gmt.gmt_last_build()["kernel_ms"])
                 e3 = rm3.nnz
                 rm3.free()
+            gmt.gmt_profile_enable(False)
+            gmt.gmt_profile_read()
             bt = float(np.median(bt[1:]))
-            nbytes = 12 * n3 + 4 * (n3 + 1) + 16 * e3
+            kms = float(np.median(kt[1:]))
+            nbytes = euclid_build_bytes(n3, 3, e3)
+            built = euclid_build_bytes(n3, 3, e3, per_edge=16)
             build_line.append({"workload": "3D Euclidean n=%d, r=%.4f" % (n3, r3), "edges": int(e3),
-                               "wall_ms": round(bt, 3), "bytes": int(nbytes),
-                               "GB_per_s_wall": round(nbytes / (bt * 1e-3) / 1e9, 1)})
-            say("euclid build n=%d: %.3f ms" % (n3, bt))
+                               "kernel_ms": round(kms, 4), "wall_ms": round(bt, 3), "bytes": int(nbytes),
+                               "achieved": round(nbytes / (kms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "bytes_as_built": int(built),
+                               "frac_as_built": round(built / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+            say("euclid build n=%d: %.3f ms wall, %.3f ms kernels" % (n3, bt, kms))
             del d3
 
     learned = learned_report(args, torch, gmt, I) if args.learned else None
@@ -512,14 +555,21 @@ def main():
         "work_per_plan": {k: round(v / args.batch, 1) for k, v in work.items()},
         "oracle_check": check,
         "server": srv_line,
-        "euclid_build": build_line,
         "mixed_stream": mixed,
         "learned": learned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_plan<1> (one launch per batch)",
                      "avg_kernel_ms": round(avg_kernel_ms, 3),
-                     "bytes_per_launch": int(bytes_per_launch)},
+                     "bytes_per_launch": int(bytes_per_launch),
+                     "bytes_model": "4 B per out-edge + 24 B per scanned in-edge + 16 B per commit "
+                                    "+ 12 B per open entry",
+                     "as_built": {"bytes_per_launch": int(bytes_as_built),
+                                  "frac": round(bytes_as_built / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "note": "28 B per in-edge: 12-byte FP64-cost record + 16 B node state"},
+                     "traffic_frac": (round(traffic / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic else None)},
+        "build_rooflines": {"di": di_build_line, "euclid_3d": build_line},
         "cpu_baseline": cpu,
     }
     for rm in rms.values():

@@ -219,6 +219,29 @@ gmt_status gmt_last_work(gmt_work *out);
 gmt_status gmt_profile_enable(int32_t enable);
 gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches);
 
+/* Record of the last gmt_build_neighbors call on this thread.
+ *  edges         entries of the in-neighbour table;
+ *  pairs_tested  candidate pairs the build tested: Euclidean, the distance
+ *                tests of its counting pass over the staged cell
+ *                neighbourhoods; double integrator, every ordered pair;
+ *  pairs_solved  double integrator: pairs that passed the exact lower-bound
+ *                prefilter and whose arrival-time quartic was solved (0 for
+ *                the Euclidean cost);
+ *  kernel_ms     device time of the build's kernels, from HIP events on its
+ *                stream around its two device segments (the table is sized
+ *                on the host between them), while gmt_profile_enable is on;
+ *                0 otherwise;
+ *  segments      timed segments summed into kernel_ms. */
+typedef struct {
+    int64_t edges;
+    int64_t pairs_tested;
+    int64_t pairs_solved;
+    double kernel_ms;
+    int32_t segments;
+} gmt_build_info;
+
+gmt_status gmt_last_build(gmt_build_info *out);
+
 /* One query of a batch.  edge_step > 0 overrides the plan options' edge
  * step for this query (Euclidean roadmaps; 0: use the options'). */
 typedef struct {
@@ -391,6 +414,16 @@ gmt_status gmt_tune_clear(void);
  * the cache; a malformed line gives GMT_EINVAL and loads nothing. */
 gmt_status gmt_tune_save(const char *path);
 gmt_status gmt_tune_load(const char *path);
+
+/* Process teardown, for callers about to exit (the Python binding registers
+ * it with atexit): destroys every engine and prepared batch still alive
+ * (their workers are joined), synchronises the device, and frees the pool of
+ * per-query workspaces with its pinned host staging.  Afterwards every call
+ * that frees memory (gmt_roadmap_free, gmt_batch_free, ...) returns without
+ * touching the device -- what is still held is left to the process exit, so
+ * no allocator callback runs after its owner may have shut down -- and no
+ * planning or build call may follow.  Idempotent; always GMT_OK. */
+gmt_status gmt_shutdown(void);
 
 /* Thread-local message describing the last error on this thread. */
 const char *gmt_last_error(void);

@@ -184,15 +184,26 @@ struct EuGrid {
     int ncell;
 };
 
+// Cell of a sample; each axis index is clamped to [0, G-1], so a sample
+// outside the state space (which the build rejects once the flags of
+// k_check_samples reach the host) still lands in a real cell and every
+// count, scatter and row write stays in bounds until then.
 __device__ __forceinline__ int eu_cell_of(const int *q, const EuGrid &g) {
     int c = 0, mul = 1;
     for (int a = 0; a < g.dim; ++a) {
         int ca = (int)(((long long)q[a] * g.G) >> 20);
-        ca = ca >= g.G ? g.G - 1 : ca;
+        ca = ca >= g.G ? g.G - 1 : (ca < 0 ? 0 : ca);
         c += ca * mul;
         mul *= g.G;
     }
     return c;
+}
+
+// grid coordinate of a sample value; NaN and values beyond +-2 (never valid,
+// rejected by the build) map to 0 so the conversion is always defined
+__device__ __forceinline__ int eu_q(float x) {
+    const double v = (double)x;
+    return (v >= -2.0 && v <= 2.0) ? (int)(v * GMT_QS) : 0;
 }
 
 __global__ void k_eu_bin(const float *__restrict__ s, int n, EuGrid g, int *__restrict__ cell_of,
@@ -200,7 +211,7 @@ __global__ void k_eu_bin(const float *__restrict__ s, int n, EuGrid g, int *__re
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int q[3] = {0, 0, 0};
-    for (int a = 0; a < g.dim; ++a) q[a] = (int)((double)s[(size_t)a * n + i] * GMT_QS);
+    for (int a = 0; a < g.dim; ++a) q[a] = eu_q(s[(size_t)a * n + i]);
     int c = eu_cell_of(q, g);
     cell_of[i] = c;
     atomicAdd(&cell_cnt[c], 1);
@@ -215,7 +226,7 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
     int c = cell_of[i];
     int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
     int q[3] = {0, 0, 0};
-    for (int a = 0; a < g.dim; ++a) q[a] = (int)((double)s[(size_t)a * n + i] * GMT_QS);
+    for (int a = 0; a < g.dim; ++a) q[a] = eu_q(s[(size_t)a * n + i]);
     pts[pos] = make_int4(q[0], q[1], q[2], i);
 }
 
@@ -257,7 +268,7 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
                                                  const int *__restrict__ cell_start, double R2,
                                                  int *__restrict__ deg, int *__restrict__ maxdeg,
                                                  const int *__restrict__ row_ptr, unsigned int *__restrict__ rec,
-                                                 int *__restrict__ col) {
+                                                 int *__restrict__ col, unsigned long long *__restrict__ tested) {
     __shared__ int4 cand[EU_CHUNK];
     // per wave: EU_OBUF slots, then one that lanes without an edge write to
     __shared__ unsigned short oslot[COUNT ? 1 : 4 * (EU_OBUF + 2)];
@@ -293,6 +304,7 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
     __syncthreads();
     const int total = soff[nspan];
     unsigned short *wslot = oslot + (COUNT ? 0 : wave * (EU_OBUF + 2));
+    unsigned long long ntest = 0;  // distance tests of this wave (COUNT pass)
     for (int rb = p0; rb < p1; rb += EU_ROWS) {  // blocks of rows
         const int nr = min(EU_ROWS, p1 - rb);
         for (int i = tid; i < nr; i += 256) rcnt[i] = 0;
@@ -325,6 +337,7 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
             __syncthreads();
             for (int ri = wave; ri < nr; ri += 4) {
                 const int4 q = pts[rb + ri];
+                ntest += (unsigned long long)cntp;
                 int run = 0, fill = 0;
                 long long dst = COUNT ? 0 : (long long)row_ptr[q.w] + rcnt[ri];
                 // write the buffered entries of this row out
@@ -384,6 +397,7 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
                 atomicMax(maxdeg, rcnt[i]);
             }
     }
+    if (COUNT && tested && lane == 0 && ntest) atomicAdd(tested, ntest);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,7 +436,8 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
                                                  const int *__restrict__ rows, const int *__restrict__ row_ptr,
                                                  int cap, int *__restrict__ deg, int *__restrict__ ovf,
                                                  int *__restrict__ col, double *__restrict__ cost,
-                                                 double *__restrict__ tau, unsigned int *__restrict__ rec) {
+                                                 double *__restrict__ tau, unsigned int *__restrict__ rec,
+                                                 unsigned long long *__restrict__ solved) {
     __shared__ int queue[4][DI_QCAP];
     const int wl = threadIdx.x / GMT_WAVE;
     const int lane = lane_id();
@@ -440,6 +455,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
     di_load(s, n, x, xs);
     int qn = 0;      // queued survivors (wave-uniform)
     int found = 0;   // neighbours emitted so far (wave-uniform)
+    int nsolved = 0; // pairs past the prefilter (wave-uniform)
     const long long base = mode == DI_FILL ? (long long)row_ptr[x] : (long long)x * cap;
     auto drain = [&](int take) {
         // solve the first `take` queued sources, one per lane, in order
@@ -491,6 +507,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         uint64_t m = wave_ballot(pass);
         if (pass) qu[qn + lanes_below(m)] = y;
         qn += (int)__popcll(m);
+        nsolved += (int)__popcll(m);
         __builtin_amdgcn_wave_barrier();
         if (qn >= GMT_WAVE) drain(GMT_WAVE);
     }
@@ -498,6 +515,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
     if (lane == 0 && mode == DI_SCRATCH) {
         deg[x] = found;
         if (found > cap) ovf[1 + atomicAdd(&ovf[0], 1)] = x;
+        if (solved) atomicAdd(solved, (unsigned long long)nsolved);
     }
 }
 

@@ -32,8 +32,10 @@ inline DevBuf dev_view(const DevBuf &block, size_t off, size_t bytes) {
 
 // allocate `bytes` (rounded up to 256) with the allocator installed now
 gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s);
-// return a buffer to the allocator that produced it
+// return a buffer to the allocator that produced it (nothing after gmt_shutdown)
 void dev_free(DevBuf &b, hipStream_t s);
+// true once gmt_shutdown has run
+bool shut_down();
 
 }  // namespace gmt_host
 

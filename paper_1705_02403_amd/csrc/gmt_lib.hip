@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -15,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -35,6 +37,8 @@ using namespace gmt;
 static thread_local std::string g_last_error;
 static std::mutex g_alloc_mu;
 static gmt_allocator g_alloc = {nullptr, nullptr, nullptr};
+// set by gmt_shutdown: device memory still held is left to the process exit
+static std::atomic<bool> g_shut{false};
 
 namespace gmt_host {
 
@@ -70,7 +74,7 @@ gmt_status dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
 
 void dev_free(DevBuf &b, hipStream_t s) {
     if (!b.p) return;
-    if (b.view) {
+    if (b.view || g_shut.load()) {
         b.p = nullptr;
         return;
     }
@@ -80,6 +84,8 @@ void dev_free(DevBuf &b, hipStream_t s) {
         (void)hipFree(b.p);
     b.p = nullptr;
 }
+
+bool shut_down() { return g_shut.load(); }
 
 }  // namespace gmt_host
 
@@ -137,6 +143,47 @@ extern "C" gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches) {
     g_prof_launches = 0;
     return GMT_OK;
 }
+
+// build record of the last gmt_build_neighbors on this thread; its kernel
+// time is taken by HIP events around the build's device segments (the table
+// is sized on the host between them) while profiling is on
+static thread_local gmt_build_info g_last_build = {};
+
+extern "C" gmt_status gmt_last_build(gmt_build_info *out) {
+    if (!out) return fail(GMT_EINVAL, "null argument");
+    *out = g_last_build;
+    return GMT_OK;
+}
+
+struct BuildTimer {
+    hipStream_t s;
+    bool on = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double ms = 0.0;
+    int segments = 0;
+    explicit BuildTimer(hipStream_t s_) : s(s_) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+        if (on && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)) on = false;
+    }
+    ~BuildTimer() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void begin() {
+        if (on) (void)hipEventRecord(ev[0], s);
+    }
+    // close a segment: waits for it, so call only where the host waits anyway
+    void end() {
+        if (!on) return;
+        float t = 0.0f;
+        if (hipEventRecord(ev[1], s) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&t, ev[0], ev[1]) == hipSuccess) {
+            ms += t;
+            ++segments;
+        }
+    }
+};
 
 static double g_tick_ns = 0.0;  // wall-clock tick of the device, ns
 
@@ -342,7 +389,10 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     void *scan_tmp = (char *)tmp.p + o_scan;
     int *flags = (int *)scal.p, *maxdeg = flags + 1;
     long long *total = (long long *)(flags + 2);
-    k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
+    unsigned long long *tested = (unsigned long long *)(flags + 4);
+    BuildTimer bt(s);
+    bt.begin();
+    k_fill_int<<<1, 64, 0, s>>>(flags, 8, 0);
     k_fill_int<<<blocks_for(g.ncell, 256), 256, 0, s>>>((int *)cell_cnt.p, g.ncell, 0);
     k_fill_int<<<blocks_for(g.ncell, 256), 256, 0, s>>>((int *)cursor.p, g.ncell, 0);
     k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, dim, 0, flags);
@@ -354,13 +404,16 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     // one workgroup per EU_XB cells along x
     const unsigned wgs = (unsigned)((g.G + EU_XB - 1) / EU_XB) * (unsigned)g.G * (unsigned)(dim == 3 ? g.G : 1);
     k_eu_rows<true><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, (int *)deg.p,
-                                        maxdeg, nullptr, nullptr, nullptr);
+                                        maxdeg, nullptr, nullptr, nullptr, tested);
     TRY(scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s, scan_tmp));
-    int hs[4];
+    bt.end();
+    int hs[6];
     HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     long long E;
+    unsigned long long ntest;
     std::memcpy(&E, hs + 2, sizeof E);
+    std::memcpy(&ntest, hs + 4, sizeof ntest);
     if (hs[0]) return fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
     if (E > 0x7fffffffLL) return fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
     rm->nnz = E;
@@ -369,12 +422,15 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     TRY(dev_alloc(rm->tab, o_rec + 12 * (size_t)(E + GMT_REC_PAD), s));
     rm->in_col = dev_view(rm->tab, 0, sizeof(int) * (size_t)std::max<long long>(E, 1));
     rm->in_rec = dev_view(rm->tab, o_rec, 12 * (size_t)(E + GMT_REC_PAD));
+    bt.begin();
     k_eu_rows<false><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, nullptr, nullptr,
                                          (const int *)rm->in_ptr.p, (unsigned int *)rm->in_rec.p,
-                                         (int *)rm->in_col.p);
+                                         (int *)rm->in_col.p, nullptr);
     k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>((unsigned int *)rm->in_rec.p, E);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
+    bt.end();
+    g_last_build = gmt_build_info{E, (int64_t)ntest, 0, bt.ms, bt.segments};
     // the table is symmetric: the in-table serves as the out-table
     rm->out_ptr = rm->in_ptr;
     rm->out_col = rm->in_col;
@@ -407,14 +463,18 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     int *deg = (int *)T, *flags = (int *)(T + o_scal), *ovf = (int *)(T + o_ovf), *scol = (int *)(T + o_scol);
     double *scost = (double *)(T + o_scost), *stau = (double *)(T + o_stau);
     long long *total = (long long *)(flags + 2);
-    int hs[4] = {0, 0, 0, 0}, novf = 0;
-    k_fill_int<<<1, 64, 0, s>>>(flags, 4, 0);
+    unsigned long long *solved = (unsigned long long *)(flags + 4);
+    int hs[6] = {0, 0, 0, 0, 0, 0}, novf = 0;
+    BuildTimer bt(s);
+    bt.begin();
+    k_fill_int<<<1, 64, 0, s>>>(flags, 8, 0);
     k_fill_int<<<1, 64, 0, s>>>(ovf, 1, 0);
     k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
     k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->r, DI_SCRATCH,
                                                                      nullptr, nullptr, cap, deg, ovf, scol, scost,
-                                                                     stau, nullptr);
+                                                                     stau, nullptr, solved);
     TRY(scan_ints(deg, n, (int *)rm->in_ptr.p, total, s, T + o_scan));
+    bt.end();
     {
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(hs, flags, sizeof hs, hipMemcpyDeviceToHost, s);
@@ -423,7 +483,9 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
         if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour pass failed: %s", hipGetErrorString(e));
     }
     long long E = 0;
+    unsigned long long nsolved = 0;
     std::memcpy(&E, hs + 2, sizeof E);
+    std::memcpy(&nsolved, hs + 4, sizeof nsolved);
     if (hs[0])
         return fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, "
                                 "on the 2^-20 grid");
@@ -447,19 +509,23 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     int *col = (int *)rm->in_col.p;
     double *tau = (double *)rm->in_tau.p;
     unsigned int *rec = (unsigned int *)rm->in_rec.p;
+    bt.begin();
     k_di_compact<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(n, cap, deg, (const int *)rm->in_ptr.p, scol,
                                                                          scost, stau, col, tau, rec);
     if (novf > 0)
         k_di_rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
             (const float *)rm->s.p, n, rm->r, DI_FILL, ovf, (const int *)rm->in_ptr.p, cap, nullptr, nullptr, col,
-            nullptr, tau, rec);
+            nullptr, tau, rec, nullptr);
     k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>(rec, E);
     k_aos8<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, (float4 *)rm->s8.p);
     {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
     }
-    return build_out_table(rm, s, T + o_out);
+    TRY(build_out_table(rm, s, T + o_out));
+    bt.end();
+    g_last_build = gmt_build_info{E, (int64_t)n * (int64_t)(n - 1), (int64_t)nsolved, bt.ms, bt.segments};
+    return GMT_OK;
 }
 
 extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim,
@@ -601,7 +667,7 @@ extern "C" gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int
 
 extern "C" gmt_status gmt_roadmap_free(gmt_roadmap_t rm) {
     if (!rm) return GMT_OK;
-    (void)hipDeviceSynchronize();
+    if (!g_shut.load()) (void)hipDeviceSynchronize();
     roadmap_release(rm, nullptr);
     delete rm;
     return GMT_OK;
@@ -1325,6 +1391,12 @@ static int64_t steady_ns() {
 // ---------------------------------------------------------------------------
 // prepared batches: staged once, launch sequence captured as a HIP graph
 // ---------------------------------------------------------------------------
+// prepared batches and engines alive now (gmt_shutdown releases them)
+struct gmt_batch;
+static std::mutex g_live_mu;
+static std::set<gmt_batch *> g_live_batches;
+static std::set<gmt_engine *> g_live_engines;
+
 struct gmt_batch {
     BatchRun run;
     hipGraph_t graph = nullptr;
@@ -1344,9 +1416,13 @@ extern "C" gmt_status gmt_batch_prepare(const gmt_problem *problems, int32_t cou
         bo.plan.traj_points = 16;
     }
     gmt_batch *b = new gmt_batch();
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live_batches.insert(b);
+    }
     gmt_status st = batch_stage(problems, count, bo, false, nullptr, b->run, s);
     if (st != GMT_OK) {
-        delete b;
+        gmt_batch_free(b);
         return st;
     }
     b->run.own_all = true;
@@ -1395,6 +1471,11 @@ extern "C" gmt_status gmt_batch_run(gmt_batch_t b, gmt_result *results, void *st
 
 extern "C" gmt_status gmt_batch_free(gmt_batch_t b) {
     if (!b) return GMT_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!g_live_batches.erase(b)) return fail(GMT_EINVAL, "unknown or already freed batch");
+    }
+    if (g_shut.load()) return GMT_OK;
     (void)hipDeviceSynchronize();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1815,6 +1896,10 @@ extern "C" gmt_status gmt_engine_create(const gmt_engine_opts *opts, gmt_engine_
             return fail(GMT_EDEVICE, "stream creation failed");
         }
     E->worker = std::thread(engine_loop, E);
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live_engines.insert(E);
+    }
     *out = E;
     return GMT_OK;
 }
@@ -1944,6 +2029,10 @@ extern "C" gmt_status gmt_engine_get_stats(gmt_engine_t E, gmt_engine_stats *out
 extern "C" gmt_status gmt_engine_destroy(gmt_engine_t E) {
     if (!E) return GMT_OK;
     {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!g_live_engines.erase(E)) return fail(GMT_EINVAL, "unknown or already destroyed engine");
+    }
+    {
         std::lock_guard<std::mutex> lk(E->mu);
         E->stop = true;
     }
@@ -1958,5 +2047,37 @@ extern "C" gmt_status gmt_engine_destroy(gmt_engine_t E) {
     }
     for (auto &kv : E->reqs) delete kv.second;
     delete E;
+    return GMT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// process teardown
+// ---------------------------------------------------------------------------
+extern "C" gmt_status gmt_shutdown(void) {
+    if (g_shut.load()) return GMT_OK;
+    std::vector<gmt_engine *> engines;
+    std::vector<gmt_batch *> batches;
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        engines.assign(g_live_engines.begin(), g_live_engines.end());
+        batches.assign(g_live_batches.begin(), g_live_batches.end());
+    }
+    for (gmt_engine *E : engines) gmt_engine_destroy(E);  // joins the worker threads
+    for (gmt_batch *b : batches) gmt_batch_free(b);
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (WsBlock *w : g_ws) {
+            dev_free(w->mem, nullptr);
+            dev_free(w->tctl, nullptr);
+            dev_free(w->stage_d, nullptr);
+            dev_free(w->res_d, nullptr);
+            if (w->stage_h) (void)hipHostFree(w->stage_h);
+            if (w->res_h) (void)hipHostFree(w->res_h);
+            delete w;
+        }
+        g_ws.clear();
+    }
+    g_shut.store(true);
     return GMT_OK;
 }

@@ -357,6 +357,13 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, c
                 const bool h0 = lg < K, h1 = lg + CL < K;
                 di_point(ys, d, tau, (double)lg * inv, p0);
                 if (K > CL) di_point(ys, d, tau, (double)(lg + CL) * inv, p1);  // second point only when needed
+                // the trajectory ends exactly at x's state: the last point is x's
+                // own position (the first, at s = 0, is y's exactly already)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    p0[a] = (lg == K - 1) ? c.xs[a] : p0[a];
+                    p1[a] = (lg + CL == K - 1) ? c.xs[a] : p1[a];
+                }
                 // leaving [0,1]^3 is a collision
                 hit = (h0 && di_point_hits_d(p0, -1, nullptr)) || (h1 && di_point_hits_d(p1, -1, nullptr));
                 // conservative float box of the group's points (slack 1e-6 covers
@@ -402,6 +409,7 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, c
                 for (int k = lg; k < K && !hit; k += CL) {
                     double p[3];
                     di_point(ys, d, tau, (double)k * inv, p);
+                    if (k == K - 1) p[0] = c.xs[0], p[1] = c.xs[1], p[2] = c.xs[2];
                     if (di_point_hits_d(p, -1, nullptr)) hit = true;
                     for (int b = 0; b < P.m && !hit; ++b) {
                         const float *bx = fbox + b * 6;

@@ -483,6 +483,7 @@ extern "C" gmt_status gmt_sampler_generate(gmt_sampler_t s, const float *cond, c
 
 extern "C" gmt_status gmt_sampler_destroy(gmt_sampler_t s) {
     if (!s) return GMT_OK;
+    if (gmt_host::shut_down()) return GMT_OK;  // left to the process exit
     (void)hipDeviceSynchronize();
     free_train(s);
     free_infer(s);

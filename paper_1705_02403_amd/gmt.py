@@ -12,10 +12,13 @@ Loading never compiles: ``lib()`` raises when the library has not been built
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import subprocess
+import sys
 import threading
+import weakref
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -39,12 +42,12 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 # symbols the header declares (checked by the CPU tests)
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_batch",
-           "gmt_last_work", "gmt_profile_enable", "gmt_profile_read",
+           "gmt_last_work", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
            "gmt_engine_set_budget", "gmt_engine_get_stats", "gmt_engine_destroy",
            "gmt_batch_prepare", "gmt_batch_run", "gmt_batch_free",
            "gmt_autotune", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
-           "gmt_tune_load", "gmt_last_error", "gmt_version", "gmt_steady_ns"]
+           "gmt_tune_load", "gmt_shutdown", "gmt_last_error", "gmt_version", "gmt_steady_ns"]
 
 
 class GmtError(RuntimeError):
@@ -107,6 +110,14 @@ class gmt_work(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class gmt_build_info(C.Structure):
+    _fields_ = [("edges", C.c_int64), ("pairs_tested", C.c_int64), ("pairs_solved", C.c_int64),
+                ("kernel_ms", C.c_double), ("segments", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class gmt_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("path_len", C.c_int32),
                 ("path_cap", C.c_int32), ("path_cost", C.c_double),
@@ -136,6 +147,25 @@ class gmt_engine_stats(C.Structure):
 _lock = threading.Lock()
 _lib = None
 _alloc_keep = None
+# open handles (roadmaps, prepared batches, engines, samplers), closed at exit
+_live = weakref.WeakSet()
+
+
+def _track(obj) -> None:
+    _live.add(obj)
+
+
+def _at_exit() -> None:
+    """Close every handle still open while torch (whose allocator backs the
+    library's device memory) is alive, then release the library's pools
+    (gmt_shutdown).  Finalizers that run later do nothing."""
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        _lib.gmt_shutdown()
 
 
 class gmt_tune_shape(C.Structure):
@@ -175,6 +205,7 @@ def lib():
             L.gmt_plan_batch.argtypes = [C.POINTER(gmt_problem), i32, C.POINTER(gmt_batch_opts),
                                          C.POINTER(gmt_result), P]
             L.gmt_last_work.argtypes = [C.POINTER(gmt_work)]
+            L.gmt_last_build.argtypes = [C.POINTER(gmt_build_info)]
             L.gmt_profile_enable.argtypes = [i32]
             L.gmt_profile_read.argtypes = [C.POINTER(f64), C.POINTER(i64)]
             L.gmt_engine_create.argtypes = [C.POINTER(gmt_engine_opts), C.POINTER(P)]
@@ -196,6 +227,7 @@ def lib():
             L.gmt_tune_clear.argtypes = []
             L.gmt_tune_save.argtypes = [C.c_char_p]
             L.gmt_tune_load.argtypes = [C.c_char_p]
+            L.gmt_shutdown.argtypes = []
             L.gmt_last_error.restype = C.c_char_p
             L.gmt_version.restype = C.c_char_p
             L.gmt_steady_ns.restype = i64
@@ -203,6 +235,7 @@ def lib():
                 if name not in ("gmt_last_error", "gmt_version", "gmt_steady_ns"):
                     getattr(L, name).restype = i32
             _lib = L
+            atexit.register(_at_exit)
     return _lib
 
 
@@ -221,6 +254,14 @@ def gmt_last_work() -> dict:
     w = gmt_work()
     _check(lib().gmt_last_work(C.byref(w)), "gmt_last_work")
     return w.as_dict()
+
+
+def gmt_last_build() -> dict:
+    """Record of the last gmt_build_neighbors on this thread (kernel_ms is
+    measured only while profiling is enabled)."""
+    b = gmt_build_info()
+    _check(lib().gmt_last_build(C.byref(b)), "gmt_last_build")
+    return b.as_dict()
 
 
 def gmt_profile_enable(enable: bool = True) -> None:
@@ -292,6 +333,7 @@ class Roadmap:
     def __init__(self, handle: int, n: int, dim: int, kind: int, r: float):
         self.handle = C.c_void_p(handle)
         self.n, self.dim, self.kind, self.r = n, dim, kind, r
+        _track(self)
 
     @property
     def nnz(self) -> int:
@@ -318,7 +360,11 @@ class Roadmap:
             lib().gmt_roadmap_free(self.handle)
             self.handle = C.c_void_p(None)
 
+    close = free
+
     def __del__(self):  # pragma: no cover - interpreter shutdown order
+        if sys.is_finalizing():
+            return  # closed by the exit handler, or left to the process exit
         try:
             self.free()
         except Exception:
@@ -502,6 +548,7 @@ class GraphBatch(PreparedBatch):
         _check(lib().gmt_batch_prepare(self.probs, self.k, C.byref(self.bo), C.byref(h), _stream(stream)),
                "gmt_batch_prepare")
         self.handle = h
+        _track(self)
 
     def run(self, stream=None) -> None:
         _check(lib().gmt_batch_run(self.handle, self.res, _stream(stream)), "gmt_batch_run")
@@ -512,6 +559,8 @@ class GraphBatch(PreparedBatch):
             self.handle = C.c_void_p(None)
 
     def __del__(self):  # pragma: no cover
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -585,6 +634,7 @@ class Engine:
         h = C.c_void_p()
         _check(lib().gmt_engine_create(C.byref(eo), C.byref(h)), "gmt_engine_create")
         self.handle = h
+        _track(self)
 
     def submit(self, q: BatchQuery, path_cap: int = 512) -> int:
         xi = _host_f32(q.x_init)
@@ -652,6 +702,8 @@ class Engine:
             self.handle = C.c_void_p(None)
 
     def __del__(self):  # pragma: no cover
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

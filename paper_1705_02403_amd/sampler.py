@@ -7,6 +7,7 @@ library's kernels."""
 from __future__ import annotations
 
 import ctypes as C
+import sys
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -96,6 +97,7 @@ class Sampler:
         h = C.c_void_p()
         gmt._check(lib().gmt_sampler_create(p.ctypes.data, C.byref(h)), "gmt_sampler_create")
         self.handle = h
+        gmt._track(self)
         self.W = 0
 
     def params(self) -> np.ndarray:
@@ -148,6 +150,8 @@ class Sampler:
             self.handle = C.c_void_p(None)
 
     def __del__(self):  # pragma: no cover
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -151,3 +151,41 @@ def test_graph_batch_replays_equal_eager(world):
         for a, b in zip(gc.results(), eager[:3]):
             assert a.status == b.status and a.path_cost == b.path_cost
     gc.close()
+
+
+def test_engine_results_equal_oracle(world):
+    """Engine results against the FP64 oracle itself (not only against
+    gmt_plan): 2D queries bit-exact (status, path, cost); double-integrator
+    queries on the GPU-built table, which must equal the oracle's, with the
+    same path and the cost to 1e-12 where the oracle run is decisive."""
+    say("engine: results against the oracle")
+    rms, probs = world
+    s = probs[-1][1].samples
+    rdi = probs[-1][1].r
+    tab = O.neighbors(s, O.DI, rdi)
+    rp, col, cost, _ = rms[("di", 0)].export()
+    np.testing.assert_array_equal(rp, tab.row_ptr)
+    np.testing.assert_array_equal(col, tab.col)
+    eng = gmt.Engine(1 << 30, opts(), slots=3, max_batch=5)
+    tickets = [eng.submit(query(rms, k, p)) for k, p in probs]
+    compared = 0
+    for (key, p), tk in zip(probs, tickets):
+        res = eng.poll(tk, -1)
+        if key[0] == "2d":
+            ref = O.plan(p, O.euclid_radius(p))
+            assert res.status == ref.status
+            if ref.status == O.OK:
+                assert list(res.path) == list(ref.path) and res.path_cost == ref.path_cost
+            compared += 1
+        else:
+            ref = O.plan(p, rdi, tab)
+            assert res.status == ref.status
+            if ref.status == O.OK:
+                assert abs(res.path_cost - ref.path_cost) <= 1e-5 * ref.path_cost
+                if O.decisive(ref, O.DI, rel=1e-9, collide_abs=1e-9):
+                    assert list(res.path) == list(ref.path)
+                    assert abs(res.path_cost - ref.path_cost) <= 1e-12 * ref.path_cost
+                    compared += 1
+    say("engine vs oracle: %d of %d compared exactly" % (compared, len(probs)))
+    assert compared >= 12
+    eng.close()

@@ -40,7 +40,13 @@ def world():
     for ss in (0, 1):
         s = I.di_samples(ss, N)
         rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, R)
-        sets[ss] = (s, rm, O.neighbors(s, O.DI, R))
+        tab = O.neighbors(s, O.DI, R)
+        # the GPU-built table holds exactly the oracle's pairs (costs to 1e-12)
+        rp, col, cost, tau = rm.export()
+        np.testing.assert_array_equal(rp, tab.row_ptr)
+        np.testing.assert_array_equal(col, tab.col)
+        np.testing.assert_allclose(cost, tab.cost, rtol=1e-12, atol=0)
+        sets[ss] = (s, rm, tab)
     yield sets
     for _, rm, _ in sets.values():
         rm.free()
@@ -79,23 +85,29 @@ def test_batch_full_size_bench_shape(world):
         probs.append(p)
         qs.append(gmt.BatchQuery(rm, p.x_init, goal_of(p), p.boxes, p.lam))
     out = gmt.gmt_plan_batch(qs, gmt.make_opts(traj_points=16, lanes=8, threads=1024), outputs=True)
-    compared = 0
+    compared = tried = 0
     for p, res in zip(probs, out):
         tab = world[p.sample_seed][2]
-        if compared < 6:
+        if compared < 8:
             ref = O.plan(p, R, tab)
+            tried += 1
             assert res.status == ref.status
-            if O.decisive(ref, O.DI, rel=1e-9, collide_abs=1e-9) and tab.margin > 1e-9:
+            if O.decisive(ref, O.DI, rel=1e-9, collide_abs=1e-9):
+                fin = np.isfinite(ref.cost)
                 np.testing.assert_array_equal(res.parent.cpu().numpy(), ref.parent)
                 np.testing.assert_array_equal(res.group_iter.cpu().numpy(), ref.group_iter)
-                np.testing.assert_allclose(res.cost.cpu().numpy()[np.isfinite(ref.cost)],
-                                           ref.cost[np.isfinite(ref.cost)], rtol=1e-12, atol=0)
+                np.testing.assert_array_equal(res.added_iter.cpu().numpy(), ref.added_iter)
+                np.testing.assert_array_equal(np.isfinite(res.cost.cpu().numpy()), fin)
+                np.testing.assert_allclose(res.cost.cpu().numpy()[fin], ref.cost[fin], rtol=1e-12, atol=0)
+                if ref.status == O.OK:
+                    assert list(res.path) == list(ref.path)
                 compared += 1
             elif ref.status == O.OK:
                 assert abs(res.path_cost - ref.path_cost) <= 1e-5 * ref.path_cost
         if res.status == gmt.GMT_OK:
             check_tree_sampled(p, res, tab, rng)
-    assert compared >= 3
+    say("full-size batch: %d of %d oracle runs compared tree for tree" % (compared, tried))
+    assert compared >= 6
 
 
 @pytest.mark.parametrize("team_wgs,threads,lanes", [(0, 0, 0), (64, 256, 32), (32, 1024, 32)])
