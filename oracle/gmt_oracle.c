@@ -10,9 +10,10 @@
  *     an exact coordinate-compressed box union;
  *   - r-disk neighbour sets: nodes are neighbours when the connection cost is
  *     strictly below r (Section III-A, text before Algorithm 1);
- *   - Euclidean arc-length cost (Section II) and the double-integrator
+ *   - Euclidean arc-length cost (Section II), the double-integrator
  *     time-plus-effort cost (Section V-A; two-point BVP cost of the Section II
- *     footnote);
+ *     footnote) and the Dubins airplane's path length (Section V-A: a planar
+ *     Dubins car with an altitude single integrator, Euclidean length cost);
  *   - Algorithm 1 (GMT*), run literally: the threshold index i rises by one per
  *     pass, empty groups included; lambda = 0 selects FMT*'s single-cost group
  *     (Section III-A);
@@ -39,7 +40,7 @@
 #define ORC_Q2 1099511627776.0 /* 2^40 */
 
 enum { ORC_OK = 0, ORC_NO_PATH = 1, ORC_TIMEOUT = 2, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
-enum { ORC_EUCLID = 0, ORC_DI = 1 };
+enum { ORC_EUCLID = 0, ORC_DI = 1, ORC_DUBINS = 2 };
 
 /* ------------------------------------------------------------------------- */
 /* Theorem 1 radius                                                          */
@@ -302,6 +303,168 @@ void orc_di_point(const double *x0, const double *x1, double tau, double t, doub
 }
 
 /* ------------------------------------------------------------------------- */
+/* Dubins airplane (Section V-A): planar Dubins car of turning radius rho,     */
+/* altitude a single integrator with unbounded rate, cost = path length       */
+/* ------------------------------------------------------------------------- */
+/*
+ * State (x, y, z, h): position in [0,1]^3, heading theta = 2 pi h, h in [0,1).
+ * The horizontal projection of a trajectory is a curve of curvature at most
+ * 1/rho; the climb is free.  The length of a curve whose projection has length
+ * Lp and whose altitude changes by dz is at least sqrt(Lp^2 + dz^2) (Minkowski),
+ * with equality for a constant climb gradient, so the optimal cost is
+ * sqrt(Ld^2 + dz^2) with Ld the shortest Dubins path between the two planar
+ * poses, flown at constant gradient.
+ *
+ * Shortest Dubins path: the least of the candidate words of Dubins' theorem,
+ * constructed here from the turning circles.  A pose's left (right) circle
+ * has centre p + rho (-sin t, cos t) (p + rho (sin t, -cos t)).  Word
+ * "a S b" runs on the start's a-circle, leaves it along a common tangent and
+ * joins the goal's b-circle; word "a b a" runs on the start's and the goal's
+ * a-circles joined by a third circle of radius rho touching both.
+ */
+static double g_rho = 0.1; /* turning radius: orc_set_turn_radius */
+
+void orc_set_turn_radius(double rho) { g_rho = rho; }
+
+typedef struct {
+    int dir[3];    /* +1 left, -1 right, 0 straight */
+    double len[3]; /* planar length of each segment */
+    double total;  /* planar length */
+} orc_dpath;
+
+static double mod2pi(double a)
+{
+    const double tau = 2.0 * M_PI;
+    a = fmod(a, tau);
+    if (a < 0.0) a += tau;
+    return a;
+}
+
+static void turn_centre(double x, double y, double th, int dir, double rho, double *cx, double *cy)
+{
+    *cx = x - dir * rho * sin(th);
+    *cy = y + dir * rho * cos(th);
+}
+
+/* heading of a vehicle at point (px, py) on the circle of centre (cx, cy)
+ * travelled in direction dir */
+static double heading_on(double px, double py, double cx, double cy, int dir)
+{
+    return atan2(py - cy, px - cx) + dir * 0.5 * M_PI;
+}
+
+static void consider(orc_dpath *best, int d0, int d1, int d2, double a, double b, double c, double rho)
+{
+    double tot = a + b + c;
+    if (!(tot < best->total)) return;
+    best->dir[0] = d0; best->dir[1] = d1; best->dir[2] = d2;
+    best->len[0] = a; best->len[1] = b; best->len[2] = c;
+    best->total = tot;
+    (void)rho;
+}
+
+/* shortest planar Dubins path from (x0, y0, t0) to (x1, y1, t1) */
+static orc_dpath dubins_shortest(double x0, double y0, double t0, double x1, double y1, double t1, double rho)
+{
+    orc_dpath best = {{0, 0, 0}, {0.0, 0.0, 0.0}, INFINITY};
+    for (int a = -1; a <= 1; a += 2)
+        for (int b = -1; b <= 1; b += 2) {
+            /* a S b */
+            double c0x, c0y, c1x, c1y;
+            turn_centre(x0, y0, t0, a, rho, &c0x, &c0y);
+            turn_centre(x1, y1, t1, b, rho, &c1x, &c1y);
+            double vx = c1x - c0x, vy = c1y - c0y, D = hypot(vx, vy);
+            double psi, S;
+            if (a == b) {
+                psi = atan2(vy, vx);
+                S = D;
+            } else {
+                if (D < 2.0 * rho) continue;
+                S = sqrt(D * D - 4.0 * rho * rho);
+                psi = atan2(vy, vx) + a * atan2(2.0 * rho, S);
+            }
+            double arc0 = mod2pi(a * (psi - t0)), arc1 = mod2pi(b * (t1 - psi));
+            consider(&best, a, 0, b, rho * arc0, S, rho * arc1, rho);
+        }
+    for (int a = -1; a <= 1; a += 2) {
+        /* a (-a) a */
+        double c0x, c0y, c1x, c1y;
+        turn_centre(x0, y0, t0, a, rho, &c0x, &c0y);
+        turn_centre(x1, y1, t1, a, rho, &c1x, &c1y);
+        double vx = c1x - c0x, vy = c1y - c0y, D = hypot(vx, vy);
+        if (D > 4.0 * rho || D == 0.0) continue;
+        double h = sqrt(4.0 * rho * rho - 0.25 * D * D);
+        for (int side = -1; side <= 1; side += 2) {
+            double c2x = 0.5 * (c0x + c1x) - side * h * vy / D, c2y = 0.5 * (c0y + c1y) + side * h * vx / D;
+            double p0x = 0.5 * (c0x + c2x), p0y = 0.5 * (c0y + c2y); /* first switch */
+            double p1x = 0.5 * (c2x + c1x), p1y = 0.5 * (c2y + c1y); /* second switch */
+            double h0 = heading_on(p0x, p0y, c0x, c0y, a);
+            double h1 = heading_on(p1x, p1y, c2x, c2y, -a);
+            double arc0 = mod2pi(a * (h0 - t0)), arc1 = mod2pi(-a * (h1 - h0)), arc2 = mod2pi(a * (t1 - h1));
+            consider(&best, a, -a, a, rho * arc0, rho * arc1, rho * arc2, rho);
+        }
+    }
+    return best;
+}
+
+/* optimal cost of x0 -> x1 (4-vectors x, y, z, h) and its planar path */
+static double dubins_cost(const double *x0, const double *x1, orc_dpath *path_out)
+{
+    orc_dpath p = dubins_shortest(x0[0], x0[1], 2.0 * M_PI * x0[3], x1[0], x1[1], 2.0 * M_PI * x1[3], g_rho);
+    if (path_out) *path_out = p;
+    double dz = x1[2] - x0[2];
+    return sqrt(p.total * p.total + dz * dz);
+}
+
+void orc_dubins_cost(const double *x0, const double *x1, double *cost_out, double *planar_out, int *word_out,
+                     double *seg_out)
+{
+    orc_dpath p;
+    double c = dubins_cost(x0, x1, &p);
+    if (cost_out) *cost_out = c;
+    if (planar_out) *planar_out = p.total;
+    if (word_out) for (int k = 0; k < 3; ++k) word_out[k] = p.dir[k];
+    if (seg_out) for (int k = 0; k < 3; ++k) seg_out[k] = p.len[k];
+}
+
+/* position after planar arc length s along the path from pose (x0, y0, t0) */
+static void dubins_walk(const orc_dpath *p, double x0, double y0, double t0, double s, double rho, double *px,
+                        double *py, double *pt)
+{
+    double x = x0, y = y0, th = t0;
+    for (int k = 0; k < 3 && s > 0.0; ++k) {
+        double l = p->len[k] < s ? p->len[k] : s;
+        if (l <= 0.0) continue; /* an empty segment */
+        if (p->dir[k] == 0) {
+            x += l * cos(th);
+            y += l * sin(th);
+        } else {
+            double cx, cy;
+            turn_centre(x, y, th, p->dir[k], rho, &cx, &cy);
+            th += p->dir[k] * l / rho;
+            /* the vehicle sits at centre + rho * (dir * sin th, -dir * cos th) */
+            x = cx + p->dir[k] * rho * sin(th);
+            y = cy - p->dir[k] * rho * cos(th);
+        }
+        s -= l;
+    }
+    *px = x;
+    *py = y;
+    if (pt) *pt = th;
+}
+
+/* point k of K on the trajectory x0 -> x1: planar arc length u Ld and
+ * altitude z0 + u dz at u = k/(K-1) */
+void orc_dubins_point(const double *x0, const double *x1, int k, int K, double *p_out)
+{
+    orc_dpath p;
+    dubins_cost(x0, x1, &p);
+    double u = (K > 1) ? (double)k / (double)(K - 1) : 0.0;
+    dubins_walk(&p, x0[0], x0[1], 2.0 * M_PI * x0[3], u * p.total, g_rho, &p_out[0], &p_out[1], NULL);
+    p_out[2] = x0[2] + u * (x1[2] - x0[2]);
+}
+
+/* ------------------------------------------------------------------------- */
 /* edge costs and collision checks                                           */
 /* ------------------------------------------------------------------------- */
 
@@ -326,6 +489,17 @@ static double edge_cost(const orc_ctx *cx, int u, int v, double *tau_out)
         if (!(d2 < cx->R2)) return INFINITY;
         if (tau_out) *tau_out = 0.0;
         return sqrt(d2) / ORC_QS;
+    } else if (cx->kind == ORC_DUBINS) {
+        double xu[4], xv[4];
+        node_d(u, cx->n, 4, cx->samples, cx->x_init, xu);
+        node_d(v, cx->n, 4, cx->samples, cx->x_init, xv);
+        if (tau_out) *tau_out = 0.0;
+        /* the length is at least the straight-line distance: exact prefilter */
+        double e2 = 0.0;
+        for (int a = 0; a < 3; ++a) e2 += (xv[a] - xu[a]) * (xv[a] - xu[a]);
+        if (!(sqrt(e2) < cx->r)) return INFINITY;
+        double c = dubins_cost(xu, xv, NULL);
+        return (c < cx->r) ? c : INFINITY;
     } else {
         double xu[6], xv[6], J, tau;
         node_d(u, cx->n, 6, cx->samples, cx->x_init, xu);
@@ -412,9 +586,62 @@ static int di_edge_free(const orc_ctx *cx, int y, int x, double tau, double *mar
     return !hit;
 }
 
+/* signed clearance bookkeeping of one trajectory point p (position):
+ * leaving [0,1]^3 or entering a closed box is a hit */
+static void point_check(const orc_ctx *cx, const double *p, int *hit, double *clear, double *depth)
+{
+    double s = -INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        double e = fmax(-p[a], p[a] - 1.0);
+        if (e > s) s = e;
+    }
+    if (s > 0.0) { *hit = 1; if (s > *depth) *depth = s; } else if (-s < *clear) *clear = -s;
+    for (int b = 0; b < cx->m; ++b) {
+        double sb = -INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            double lo = cx->boxes[b * 6 + a], hi = cx->boxes[b * 6 + 3 + a];
+            double e = fmax(lo - p[a], p[a] - hi);
+            if (e > sb) sb = e;
+        }
+        if (sb <= 0.0) { *hit = 1; if (-sb > *depth) *depth = -sb; }
+        else if (sb < *clear) *clear = sb;
+    }
+}
+
+/* Dubins airplane lazy check: K points at equal steps of the path's length,
+ * K - 1 = max(1, ceil(L / step)) so consecutive points are at most `step`
+ * apart along the path; the first and last are the two states' own
+ * positions.  *margin: as for the double integrator, further capped by how
+ * far L / step lies from an integer (times step), since the point count
+ * itself is a rounded decision. */
+static int dubins_edge_free(const orc_ctx *cx, int y, int x, double *margin)
+{
+    double xy[4], xx[4];
+    node_d(y, cx->n, 4, cx->samples, cx->x_init, xy);
+    node_d(x, cx->n, 4, cx->samples, cx->x_init, xx);
+    double L = dubins_cost(xy, xx, NULL);
+    double parts = ceil(L / cx->step);
+    if (parts < 1.0) parts = 1.0;
+    int K = (int)parts + 1;
+    double frac = L / cx->step - floor(L / cx->step);
+    double count_margin = fmin(frac, 1.0 - frac) * cx->step;
+    double clear = INFINITY, depth = -INFINITY;
+    int hit = 0;
+    for (int k = 0; k < K; ++k) {
+        double p[3];
+        if (k == 0) { p[0] = xy[0]; p[1] = xy[1]; p[2] = xy[2]; }
+        else if (k == K - 1) { p[0] = xx[0]; p[1] = xx[1]; p[2] = xx[2]; }
+        else orc_dubins_point(xy, xx, k, K, p);
+        point_check(cx, p, &hit, &clear, &depth);
+    }
+    if (margin) *margin = fmin(hit ? depth : clear, count_margin);
+    return !hit;
+}
+
 static int edge_free(const orc_ctx *cx, int y, int x, double tau, double *margin)
 {
     if (cx->kind == ORC_EUCLID) { if (margin) *margin = INFINITY; return euclid_edge_free(cx, y, x); }
+    if (cx->kind == ORC_DUBINS) return dubins_edge_free(cx, y, x, margin);
     return di_edge_free(cx, y, x, tau, margin);
 }
 
@@ -422,7 +649,7 @@ int orc_edge_free(int n, int dim, int kind, const float *samples, const float *x
                   const float *boxes, int m, double step, int traj_points, int y, int x, double tau,
                   double *margin)
 {
-    orc_ctx cx = {n, dim, kind, kind == ORC_DI ? 3 : dim, samples, x_init, boxes, m, 0.0, step,
+    orc_ctx cx = {n, dim, kind, kind == ORC_EUCLID ? dim : 3, samples, x_init, boxes, m, 0.0, step,
                   traj_points, (int64_t)llround(step * ORC_QS), 0.0};
     return edge_free(&cx, y, x, tau, margin);
 }
@@ -471,6 +698,16 @@ int orc_neighbors(int n, int dim, int kind, const float *samples, double r, int 
                 if (mg < mm) mm = mg;
                 if (!(J < r)) continue;
                 cst = J;
+            } else if (kind == ORC_DUBINS) {
+                const double *xv = xd + (size_t)x * 4, *xu = xd + (size_t)y * 4;
+                double e2 = 0.0;
+                for (int a = 0; a < 3; ++a) e2 += (xv[a] - xu[a]) * (xv[a] - xu[a]);
+                if (!(sqrt(e2) < r)) continue; /* length >= distance */
+                double c = dubins_cost(xu, xv, NULL);
+                double mg = fabs(c - r) / r;
+                if (mg < mm) mm = mg;
+                if (!(c < r)) continue;
+                cst = c;
             } else {
                 double d2 = d2_q(q + (size_t)y * dim, q + (size_t)x * dim, dim);
                 if (!(d2 < R2)) continue;
@@ -565,7 +802,7 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
              double *margins)
 {
     if (n < 1 || !(r > 0.0) || !(lambda >= 0.0 && lambda <= 1.0)) return ORC_EINVAL;
-    orc_ctx cx = {n, dim, kind, kind == ORC_DI ? 3 : dim, samples, x_init, boxes, m, r, step,
+    orc_ctx cx = {n, dim, kind, kind == ORC_EUCLID ? dim : 3, samples, x_init, boxes, m, r, step,
                   traj_points, (int64_t)llround(step * ORC_QS), r * r * ORC_Q2};
     if (kind == ORC_EUCLID && cx.step_q < 1) return ORC_EINVAL;
     const int N = n + 1, root = n;
@@ -588,6 +825,12 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
             node_d(x, n, 6, samples, x_init, xv);
             orc_di_cost(xu, xv, &J, &tt);
             double mg = fabs(J - r) / r;
+            if (mg < margins[MG_ROOT]) margins[MG_ROOT] = mg;
+        } else if (kind == ORC_DUBINS) {
+            double xu[4], xv[4];
+            node_d(root, n, 4, samples, x_init, xu);
+            node_d(x, n, 4, samples, x_init, xv);
+            double mg = fabs(dubins_cost(xu, xv, NULL) - r) / r;
             if (mg < margins[MG_ROOT]) margins[MG_ROOT] = mg;
         }
     }
@@ -695,7 +938,7 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
                 stg_c[nS] = best;
                 ++nS;
             }
-            if (kind == ORC_DI && cm < margins[MG_COLLIDE]) margins[MG_COLLIDE] = cm;
+            if (kind != ORC_EUCLID && cm < margins[MG_COLLIDE]) margins[MG_COLLIDE] = cm;
         }
         for (int k = 0; k < nS; ++k) {
             int x = stg_x[k];
@@ -757,7 +1000,7 @@ int orc_dijkstra(int n, int dim, int kind, const float *samples, const float *x_
                  const int *out_ptr, const int *out_col, const double *out_cost,
                  const double *out_tau, int only_clear, double *dist)
 {
-    orc_ctx cx = {n, dim, kind, kind == ORC_DI ? 3 : dim, samples, x_init, boxes, m, r, step,
+    orc_ctx cx = {n, dim, kind, kind == ORC_EUCLID ? dim : 3, samples, x_init, boxes, m, r, step,
                   traj_points, (int64_t)llround(step * ORC_QS), r * r * ORC_Q2};
     const int N = n + 1, root = n;
     unsigned char *done = (unsigned char *)calloc((size_t)N, 1);

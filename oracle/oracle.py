@@ -25,7 +25,7 @@ SRC = os.path.join(HERE, "gmt_oracle.c")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "liborc.so")
 
-EUCLID, DI = 0, 1
+EUCLID, DI, DUBINS = 0, 1, 2
 OK, NO_PATH, TIMEOUT = 0, 1, 2
 MG_GROUP, MG_ARGMIN, MG_GOAL, MG_ROOT, MG_COLLIDE = 0, 1, 2, 3, 4
 
@@ -59,6 +59,12 @@ def lib():
             L.orc_di_cost.argtypes = [P, P, P, P]
             L.orc_di_point.restype = None
             L.orc_di_point.argtypes = [P, P, f64, f64, P]
+            L.orc_set_turn_radius.restype = None
+            L.orc_set_turn_radius.argtypes = [f64]
+            L.orc_dubins_cost.restype = None
+            L.orc_dubins_cost.argtypes = [P, P, P, P, P, P]
+            L.orc_dubins_point.restype = None
+            L.orc_dubins_point.argtypes = [P, P, i32, i32, P]
             L.orc_neighbors.restype = i32
             L.orc_neighbors.argtypes = [i32, i32, i32, P, f64, P, P, P, P, P]
             L.orc_transpose.restype = i32
@@ -98,7 +104,37 @@ def euclid_radius(prob) -> float:
 
 
 def problem_radius(prob) -> float:
-    return float(prob.r) if prob.kind == "di" else euclid_radius(prob)
+    return euclid_radius(prob) if prob.kind == "euclid" else float(prob.r)
+
+
+def set_turn_radius(rho: float) -> None:
+    """Turning radius of the Dubins airplane cost (process-wide in the oracle)."""
+    lib().orc_set_turn_radius(float(rho))
+
+
+def dubins_cost(x0, x1, rho: float):
+    """Dubins airplane cost x0 -> x1 (4-vectors x, y, z, heading in turns):
+    (cost, planar length, word (+1 left, -1 right, 0 straight) x3, planar
+    segment lengths x3)."""
+    set_turn_radius(rho)
+    a = np.ascontiguousarray(x0, np.float64)
+    b = np.ascontiguousarray(x1, np.float64)
+    c = np.zeros(1)
+    pl = np.zeros(1)
+    w = np.zeros(3, np.int32)
+    sg = np.zeros(3)
+    lib().orc_dubins_cost(_p(a), _p(b), _p(c), _p(pl), _p(w), _p(sg))
+    return float(c[0]), float(pl[0]), w, sg
+
+
+def dubins_point(x0, x1, k: int, K: int, rho: float) -> np.ndarray:
+    """Point k of K on the optimal trajectory x0 -> x1 (position)."""
+    set_turn_radius(rho)
+    a = np.ascontiguousarray(x0, np.float64)
+    b = np.ascontiguousarray(x1, np.float64)
+    p = np.zeros(3)
+    lib().orc_dubins_point(_p(a), _p(b), int(k), int(K), _p(p))
+    return p
 
 
 def di_cost(x0, x1):
@@ -132,7 +168,10 @@ class Csr:
         return int(self.row_ptr[-1])
 
 
-def neighbors(samples, kind: int, r: float) -> Csr:
+def neighbors(samples, kind: int, r: float, turn_radius: Optional[float] = None) -> Csr:
+    if kind == DUBINS:
+        assert turn_radius is not None, "the Dubins cost needs its turning radius"
+        set_turn_radius(turn_radius)
     s = _f32(samples)
     dim, n = s.shape
     rp = np.zeros(n + 1, np.int32)
@@ -181,17 +220,19 @@ class Plan:
 
 
 def kind_of(prob) -> int:
-    return DI if prob.kind == "di" else EUCLID
+    return {"di": DI, "dubins": DUBINS}.get(prob.kind, EUCLID)
 
 
 def plan(prob, r: float, table: Optional[Csr] = None, lam: Optional[float] = None,
          max_iters: int = 0) -> Plan:
     """Run Algorithm 1 on ``prob`` with radius ``r`` (table built when absent)."""
     kind = kind_of(prob)
+    if kind == DUBINS:
+        set_turn_radius(prob.turn_radius)
     s = _f32(prob.samples)
     dim, n = s.shape
     if table is None:
-        table = neighbors(s, kind, r)
+        table = neighbors(s, kind, r, prob.turn_radius)
     if kind == EUCLID:
         op, oc = table.row_ptr, table.col
     else:
@@ -230,10 +271,12 @@ def plan(prob, r: float, table: Optional[Csr] = None, lam: Optional[float] = Non
 def dijkstra(prob, r: float, table: Optional[Csr] = None, only_clear: bool = False) -> np.ndarray:
     """Least cost from the root over the collision-free disk graph ([n+1])."""
     kind = kind_of(prob)
+    if kind == DUBINS:
+        set_turn_radius(prob.turn_radius)
     s = _f32(prob.samples)
     dim, n = s.shape
     if table is None:
-        table = neighbors(s, kind, r)
+        table = neighbors(s, kind, r, prob.turn_radius)
     if kind == EUCLID:
         op, oc, ocost, otau = table.row_ptr, table.col, table.cost, table.tau
     else:
@@ -253,6 +296,8 @@ def dijkstra(prob, r: float, table: Optional[Csr] = None, only_clear: bool = Fal
 
 def edge_free(prob, y: int, x: int, tau: float = 0.0):
     """Lazy check of edge y -> x; returns (free, margin)."""
+    if kind_of(prob) == DUBINS:
+        set_turn_radius(prob.turn_radius)
     s = _f32(prob.samples)
     dim, n = s.shape
     xi = _f32(prob.x_init)
@@ -266,16 +311,17 @@ def edge_free(prob, y: int, x: int, tau: float = 0.0):
 
 def min_margin(p: Plan, kind: int) -> float:
     """Least relative decision margin of a plan (collision margin excluded)."""
-    keys = [MG_GROUP, MG_ARGMIN, MG_GOAL] + ([MG_ROOT] if kind == DI else [])
+    keys = [MG_GROUP, MG_ARGMIN, MG_GOAL] + ([MG_ROOT] if kind != EUCLID else [])
     return float(min(p.margins[k] for k in keys))
 
 
 def decisive(p: Plan, kind: int, rel: float = 1e-6, collide_abs: float = 1e-5) -> bool:
     """True when every decision of the run is separated by at least ``rel``
     (relative) and, for the double integrator, every lazy check by at least
-    ``collide_abs`` in position."""
+    ``collide_abs`` in position (and, for the Dubins airplane, every point
+    count by as much in path length)."""
     if min_margin(p, kind) < rel:
         return False
-    if kind == DI and p.margins[MG_COLLIDE] < collide_abs:
+    if kind != EUCLID and p.margins[MG_COLLIDE] < collide_abs:
         return False
     return True

@@ -73,6 +73,7 @@ class Problem:
     r_factor: float = 1.1
     seed: int = 0
     sample_seed: int = 0
+    turn_radius: float = 0.0  # Dubins airplane: least turning radius
 
     @property
     def n(self) -> int:
@@ -255,6 +256,77 @@ def problem_di(seed: int, n: int = 16384, sample_seed: Optional[int] = None, lam
     """Headline workload: 6D double integrator, n samples, 40 boxes, lambda 0.5."""
     ss = (seed % 8) if sample_seed is None else sample_seed
     return di_problem(seed, di_samples(ss, n), lam=lam, r=r, sample_seed=ss)
+
+
+# Dubins airplane workload (Section V-A's forest problem, synthetic): state
+# (x, y, z, h) with position in [0,1]^3 and heading 2 pi h, h in [0,1).
+DUBINS_START = (0.05, 0.05, 0.5, 0.125)  # heading 45 degrees, towards the goal
+DUBINS_GOAL = (0.95, 0.95, 0.5)
+DUBINS_TURN = 0.05     # least turning radius
+DUBINS_RADIUS = 0.27   # connection radius on the path length (mean in-degree near 7 ln n at n = 5000)
+DUBINS_STEP = 0.005    # spacing of the lazy check's points along a path
+
+
+def dubins_samples(sample_seed: int, n: int, goal_radius: float = 0.05) -> np.ndarray:
+    """SoA FP32 [4][n] states: position uniform in the unit cube, heading
+    uniform in [0, 1) turns, at least one position in the goal ball.  Free of
+    any box world, so one set serves many forests."""
+    rng = np.random.default_rng(30_000_001 + int(sample_seed))
+    pos = draw_positions(rng, n, 3)
+    head = rng.integers(0, QSCALE, size=(n, 1), dtype=np.int64)
+    gr = float(np.float32(goal_radius))
+    _ensure_goal_sample(rng, pos, to_grid(np.array(DUBINS_GOAL)), gr, None)
+    return np.ascontiguousarray(from_grid(np.concatenate([pos, head], axis=1).T))
+
+
+def draw_forest(rng: np.random.Generator, m: int, start_q: np.ndarray, goal_q: np.ndarray,
+                goal_radius: float, side=(0.02, 0.06), height=(0.3, 0.9), clear: float = 0.1) -> np.ndarray:
+    """m tree trunks: boxes standing on the ground (z from 0), footprints with
+    sides U[side] per axis and heights U[height]; a trunk whose footprint
+    comes within `clear` of the start's planar position, or that touches the
+    goal ball, is redrawn (the airplane cannot turn away from a trunk closer
+    than about two turning radii)."""
+    out = []
+    while len(out) < m:
+        sx, sy = rng.uniform(side[0], side[1], size=2)
+        hz = rng.uniform(height[0], height[1])
+        lo = np.array([rng.uniform(0.0, 1.0 - sx), rng.uniform(0.0, 1.0 - sy), 0.0])
+        hi = lo + np.array([sx, sy, hz])
+        lo_q, hi_q = to_grid(lo), to_grid(hi)
+        gap = np.maximum(np.maximum(lo_q[:2] - start_q[:2], 0), start_q[:2] - hi_q[:2]).astype(np.float64)
+        if float(np.sum(gap * gap)) <= (clear * QSCALE) ** 2:
+            continue
+        if _box_touches_ball(lo_q, hi_q, goal_q, goal_radius):
+            continue
+        out.append(np.concatenate([lo_q, hi_q]))
+    return np.array(out, dtype=np.int64).reshape(m, 6)
+
+
+def dubins_problem(seed: int, samples: np.ndarray, m: int = 150, lam: float = 0.5,
+                   r: float = DUBINS_RADIUS, turn_radius: float = DUBINS_TURN, step: float = DUBINS_STEP,
+                   jitter: float = 0.03, sample_seed: int = 0) -> Problem:
+    """Dubins airplane query in a synthetic forest of m trunks: start near
+    (0.05, 0.05, 0.5) (position jittered by U[-jitter, jitter] per axis) with
+    heading 45 degrees, goal ball of radius 0.05 about (0.95, 0.95, 0.5) over
+    position (any heading)."""
+    rng = np.random.default_rng(40_000_003 + int(seed))
+    start_p = np.array(DUBINS_START[:3]) + rng.uniform(-jitter, jitter, size=3)
+    start_q = np.concatenate([to_grid(start_p), to_grid([DUBINS_START[3]])])
+    goal_q = to_grid(np.array(DUBINS_GOAL))
+    gr = float(np.float32(0.05))
+    boxes_q = draw_forest(rng, m, start_q, goal_q, gr)
+    return Problem(kind="dubins", dim=4, pdim=3, samples=samples,
+                   x_init=from_grid(start_q), goal_center=from_grid(goal_q), goal_radius=gr,
+                   boxes=np.ascontiguousarray(from_grid(boxes_q)), lam=float(lam), step=float(step),
+                   traj_points=0, r=float(r), seed=int(seed), sample_seed=int(sample_seed),
+                   turn_radius=float(turn_radius))
+
+
+def problem_dubins(seed: int, n: int = 5000, sample_seed: Optional[int] = None, m: int = 150,
+                   lam: float = 0.5) -> Problem:
+    """Dubins airplane workload: n samples, m trunks, lambda 0.5."""
+    ss = (seed % 8) if sample_seed is None else sample_seed
+    return dubins_problem(seed, dubins_samples(ss, n), m=m, lam=lam, sample_seed=ss)
 
 
 def problem_ids(count: int, first: int = 0) -> List[int]:

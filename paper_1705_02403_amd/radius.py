@@ -61,3 +61,21 @@ def shared_roadmap_radius(dim: int, n: int, factor: float = 1.1) -> float:
     """Radius of a roadmap shared by many box worlds: Theorem 1 with the
     obstacle-free volume (Euclidean), or di_radius (double integrator)."""
     return di_radius(n) if dim == 6 else theorem1_radius(dim, 1.0, n, factor)
+
+
+# Dispersion constants of Halton sets: the largest D * n^(1/d) (D the radius
+# of the largest empty ball in [0,1]^d) measured for n in [1024, 65536],
+# rounded up: 1.44 in 2D, 1.66 in 3D.
+HALTON_KAPPA = {2: 1.5, 3: 1.7}
+
+
+def halton_radius(d: int, mu: float, n: int, factor: float = 1.1) -> float:
+    """Radius for a Halton sample set (Section III-A allows a smaller radius
+    than Theorem 1's for low-dispersion deterministic samples but gives no
+    value).  Every point of the free space lies within the dispersion D of a
+    sample, so two samples nearest to points eps apart are at most 2D + eps
+    apart: the radius is twice the dispersion bound kappa_d (mu/n)^(1/d), with
+    Theorem 1's margin factor.  It drops Theorem 1's (log n)^(1/d), which
+    covers the random gaps of uniform sampling.  Never above Theorem 1's
+    radius (at small n in 3D the dispersion term is the larger)."""
+    return min(factor * 2.0 * HALTON_KAPPA[d] * (mu / n) ** (1.0 / d), theorem1_radius(d, mu, n, factor))
