@@ -188,6 +188,32 @@ gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
                     int32_t *d_added_iter, int32_t *path, int32_t path_cap, int32_t *path_len,
                     double *path_cost, int32_t *iters, void *stream);
 
+/* ---- planning without device allocation ---------------------------------
+ * For callers that cannot allocate device memory: tight serving loops and
+ * harnesses that forbid hipMalloc while they run.  gmt_plan_noalloc solves one
+ * query exactly like gmt_plan (same arguments, same results, same errors) but
+ * never allocates: no allocator callback, hipMalloc, hipHostMalloc or event
+ * creation.  The query's workspace (staged query and boxes, result block,
+ * barrier block, node states and lists, about 33 bytes per node) lives in a
+ * static device array of GMT_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every device it runs on until the process ends; the tree is
+ * written straight into the caller's arrays.
+ *  d_parent, d_cost, d_group_iter, d_added_iter  required (n+1 entries each).
+ * Returns GMT_EINVAL (and runs nothing) when the query needs more than
+ * GMT_NOALLOC_SCRATCH_BYTES: with no boxes that is n above about 250 000.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; whatever must start at zero is cleared on each call.  Calls are
+ * serialised by a library lock held until the call's stream has been
+ * synchronised, so calls from several host threads wait for each other
+ * rather than overlap.  Synchronises `stream`. */
+#define GMT_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
+                            const float *boxes, int32_t m, double lambda, const gmt_plan_opts *opts,
+                            int32_t *d_parent, double *d_cost, int32_t *d_group_iter,
+                            int32_t *d_added_iter, int32_t *path, int32_t path_cap, int32_t *path_len,
+                            double *path_cost, int32_t *iters, void *stream);
+
 /* Exact work of one query (or the sum over a batch), counted by the plan
  * kernel: out-edges walked from group members (Alg. 1 line 4), in-edges
  * scanned for parents (lines 5-6), candidates processed, nodes added (lines

@@ -1052,18 +1052,19 @@ static void run_release(BatchRun &r) {
 }
 
 // Launch init + persistent planning over staged queries [first, first+count)
-// of one cost kind; queue counter `qslot` of the staging header.  Events e0 /
-// e1 (may be null) bracket the plan kernel.
-static gmt_status launch_plan_kind(WsBlock *w, int kind, int first, int count, int total, int nmax,
-                                   int teams, int team_wgs, int box_words_in, int qslot, int cl, int threads,
-                                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+// of one cost kind.  `stage_d` is the device copy of the staging block (queue
+// counters in its first 256 bytes, `total` ProbDev records, then the boxes);
+// queue counter `qslot`; `tctl` the teams' barrier blocks, `res_d` the
+// results.  Events e0 / e1 (may be null) bracket the plan kernel.
+static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, int kind, int first, int count,
+                                   int total, int nmax, int teams, int team_wgs, int box_words_in, int qslot, int cl,
+                                   int threads, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
     int box_words = plan_box_words(kind, box_words_in);
-    char *sd = (char *)w->stage_d.p;
+    char *sd = (char *)stage_d;
     int *queue = (int *)sd + qslot;
     const ProbDev *probs = (const ProbDev *)(sd + 256) + first;
     const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
-    TeamCtl *tctl = (TeamCtl *)w->tctl.p;
-    Result *res = (Result *)w->res_d.p + first;
+    Result *res = res_d + first;
     const int level = plan_level(team_wgs, threads, box_words, nmax);
     const size_t plds = plan_lds(box_words, nmax, level);
     if (plds > 64 * 1024)
@@ -1092,6 +1093,14 @@ static int max_coop_wgs(size_t lds, int kind, int level = 0, int cl = 16, int th
     return per * num_cus();
 }
 
+// workgroups of the cooperative team that runs a single plan: the requested
+// number (0: the default), capped at what can be co-resident
+static int single_team_wgs(int requested, int kind, int box_words, int nmax, int cl, int threads) {
+    const size_t lds = plan_lds(plan_box_words(kind, box_words), nmax, 0);
+    const int t = requested > 0 ? requested : default_team_wgs(threads);
+    return std::max(1, std::min(t, max_coop_wgs(lds, kind, 0, cl, threads)));
+}
+
 // Copy the staged queries up, launch per kind, copy the results down and
 // record the completion event -- all asynchronous on `s`.
 // `events` false (graph capture): no event records.  `upload` false: the
@@ -1104,13 +1113,14 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, b
     for (int k = 0; k < 5 && events; ++k)
         if (!r.ev[k] && (k == 4 || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
     if (r.n_euclid > 0)
-        TRY(launch_plan_kind(w, GMT_COST_EUCLIDEAN, 0, r.n_euclid, r.count, r.nmax_e, std::min(r.teams, r.n_euclid),
-                             r.team_wgs, r.box_words, 0, r.cl, r.threads, r.ev[0], r.ev[1], s));
+        TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, GMT_COST_EUCLIDEAN, 0,
+                             r.n_euclid, r.count, r.nmax_e, std::min(r.teams, r.n_euclid), r.team_wgs, r.box_words, 0,
+                             r.cl, r.threads, r.ev[0], r.ev[1], s));
     if (r.count - r.n_euclid > 0)
-        TRY(launch_plan_kind(w, GMT_COST_DOUBLE_INTEGRATOR, r.n_euclid, r.count - r.n_euclid, r.count, r.nmax_d,
+        TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, GMT_COST_DOUBLE_INTEGRATOR,
+                             r.n_euclid, r.count - r.n_euclid, r.count, r.nmax_d,
                              std::min(r.teams, r.count - r.n_euclid), r.team_wgs, r.box_words, 1, r.cl, r.threads,
-                             r.ev[2],
-                             r.ev[3], s));
+                             r.ev[2], r.ev[3], s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
     if (events) HIPCHK(hipEventRecord(r.ev[4], s));
     return GMT_OK;
@@ -1202,9 +1212,7 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     r.cl = lanes_of(bo.plan.lanes);
     r.threads = threads_of(bo.plan.threads);
     if (single) {
-        const size_t lds = plan_lds(plan_box_words(kind0, r.box_words), nmax, 0);
-        r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : default_team_wgs(r.threads);
-        r.team_wgs = std::max(1, std::min(r.team_wgs, max_coop_wgs(lds, kind0, 0, r.cl, r.threads)));
+        r.team_wgs = single_team_wgs(bo.plan.team_wgs, kind0, r.box_words, nmax, r.cl, r.threads);
         r.teams = 1;
     } else {
         r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
@@ -1380,6 +1388,131 @@ extern "C" gmt_status gmt_plan_batch(const gmt_problem *problems, int32_t count,
         bo.plan.traj_points = 16;
     }
     return run_sync(problems, count, bo, false, results, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// gmt_plan_noalloc: one query with its workspace in a static device array
+// ---------------------------------------------------------------------------
+// In host code `gmt_scratch` names a host-side stand-in, not device memory:
+// host code only ever uses the device address hipGetSymbolAddress returns,
+// fetched once per device with that device current.
+static __device__ __align__(256) unsigned char gmt_scratch[GMT_NOALLOC_SCRATCH_BYTES];
+
+static const int kMaxDevices = 64;
+static std::mutex g_na_mu;  // held for a whole call: the array and the staging below are shared
+static void *g_na_ptr[kMaxDevices] = {};
+// host staging of one query: queue counters, the query record, its boxes
+static unsigned char g_na_stage[256 + sizeof(ProbDev) + sizeof(int) * 2 * 3 * GMT_MAX_BOXES];
+static Result g_na_res;
+
+// one thread writes the path ending at z, root first, into out[0, len)
+__global__ void k_path_walk(const int *__restrict__ parent, int z, int len, int *__restrict__ out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int v = z;
+    for (int pos = len - 1; pos >= 0 && v >= 0; --pos) {
+        out[pos] = v;
+        v = parent[v];
+    }
+}
+
+// device address of the current device's array (g_na_mu held)
+static gmt_status noalloc_scratch(char **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GMT_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(gmt_scratch));
+        if (e != hipSuccess || !p)
+            return fail(GMT_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+        g_na_ptr[dev] = p;
+    }
+    *out = (char *)g_na_ptr[dev];
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, const gmt_goal *goal,
+                                       const float *boxes, int32_t m, double lambda,
+                                       const gmt_plan_opts *opts_in, int32_t *d_parent, double *d_cost,
+                                       int32_t *d_group_iter, int32_t *d_added_iter, int32_t *path,
+                                       int32_t path_cap, int32_t *path_len, double *path_cost,
+                                       int32_t *iters, void *stream) {
+    if (gmt_host::shut_down()) return fail(GMT_EINVAL, "library shut down");
+    if (!rm) return fail(GMT_EINVAL, "null roadmap");
+    if (!d_parent || !d_cost || !d_group_iter || !d_added_iter)
+        return fail(GMT_EINVAL, "gmt_plan_noalloc needs all four device tree arrays");
+    if (path_cap < 0 || (path_cap > 0 && !path)) return fail(GMT_EINVAL, "null path buffer");
+    if (!opts_in && rm->kind == GMT_COST_EUCLIDEAN) return fail(GMT_EINVAL, "Euclidean plans need opts.edge_step");
+    if (!goal) return fail(GMT_EINVAL, "null goal");
+    if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
+    hipStream_t s = (hipStream_t)stream;
+    const int N = rm->n + 1, pd = pdim_of(rm->kind, rm->dim), words = m * 2 * pd;
+    // scratch layout: staging block, result, team control, query workspace
+    const size_t stage_bytes = al256(256 + sizeof(ProbDev) + sizeof(int) * (size_t)words);
+    const size_t res_off = stage_bytes, tctl_off = res_off + al256(sizeof(Result));
+    const size_t ws_off = tctl_off + al256(sizeof(TeamCtl));
+    const size_t need = ws_off + qws_bytes(N, false);
+    if (need > (size_t)GMT_NOALLOC_SCRATCH_BYTES)
+        return fail(GMT_EINVAL, "query needs %zu scratch bytes (n = %d, m = %d); the static array holds %zu", need,
+                    rm->n, m, (size_t)GMT_NOALLOC_SCRATCH_BYTES);
+    gmt_batch_opts bo;
+    std::memset(&bo, 0, sizeof bo);
+    bo.plan = default_opts(opts_in);
+    if (!lanes_valid(bo.plan.lanes)) return fail(GMT_EINVAL, "lanes must be 0, 4, 8, 16 or 32");
+    if (!threads_valid(bo.plan.threads)) return fail(GMT_EINVAL, "threads must be 0, 256, 512 or 1024");
+    if (bo.plan.team_wgs < 0) return fail(GMT_EINVAL, "negative team_wgs");
+    gmt_problem pr;
+    pr.roadmap = rm;
+    pr.x_init = x_init;
+    pr.goal = *goal;
+    pr.boxes = boxes;
+    pr.m = m;
+    pr.lambda = lambda;
+    pr.edge_step = 0.0;
+    if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || bo.plan.threads == 0) tune_apply(&pr, 1, true, bo);
+    const int cl = lanes_of(bo.plan.lanes), threads = threads_of(bo.plan.threads);
+    const int team_wgs = single_team_wgs(bo.plan.team_wgs, rm->kind, std::max(words, 1), rm->n, cl, threads);
+
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    char *base = nullptr;
+    TRY(noalloc_scratch(&base));
+    ((int *)g_na_stage)[0] = 0;  // queue counters
+    ((int *)g_na_stage)[1] = 0;
+    ProbDev &P = *(ProbDev *)(g_na_stage + 256);
+    QueryIn q{rm, x_init, goal, boxes, m, lambda};
+    TRY(stage_query(q, bo.plan, P, (int *)(g_na_stage + 256 + sizeof(ProbDev)), 0));
+    qws_carve(base + ws_off, N, P.w, d_cost, d_parent, d_group_iter, d_added_iter);
+    TeamCtl *tctl = (TeamCtl *)(base + tctl_off);
+    Result *res_d = (Result *)(base + res_off);
+    HIPCHK(hipMemcpyAsync(base, g_na_stage, 256 + sizeof(ProbDev) + sizeof(int) * (size_t)words,
+                          hipMemcpyHostToDevice, s));
+    // barrier arrivals, generation and fault flag start at zero on every call
+    k_fill_int<<<1, 64, 0, s>>>((int *)tctl, (int)(sizeof(TeamCtl) / sizeof(int)), 0);
+    TRY(launch_plan_kind(base, tctl, res_d, rm->kind, 0, 1, 1, rm->n, 1, team_wgs, std::max(words, 1),
+                         rm->kind == GMT_COST_EUCLIDEAN ? 0 : 1, cl, threads, nullptr, nullptr, s));
+    HIPCHK(hipMemcpyAsync(&g_na_res, res_d, sizeof(Result), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Result &res = g_na_res;
+    g_last_work = gmt_work{};
+    work_add(g_last_work, res.work);
+    if (res.abort || res.status == ST_FAULT)
+        return fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
+    if (res.status == ST_OK && path_cap > 0) {
+        const int len = std::min(res.path_len, path_cap);
+        if (res.path_len <= GMT_PATH_INLINE) {
+            for (int i = 0; i < len; ++i) path[i] = res.path[i];
+        } else {
+            // the candidate list is free once the plan has finished
+            k_path_walk<<<1, 64, 0, s>>>(d_parent, res.z, res.path_len, P.w.clist);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(path, P.w.clist, sizeof(int) * (size_t)len, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    if (path_len) *path_len = res.path_len;
+    if (path_cost) *path_cost = res.path_cost;
+    if (iters) *iters = res.iters;
+    return status_of(res.status);
 }
 
 static int64_t steady_ns() {

@@ -41,7 +41,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 # symbols the header declares (checked by the CPU tests)
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
-           "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_batch",
+           "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_noalloc", "gmt_plan_batch",
            "gmt_last_work", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
            "gmt_engine_set_budget", "gmt_engine_get_stats", "gmt_engine_destroy",
@@ -202,6 +202,7 @@ def lib():
             L.gmt_plan.argtypes = [P, P, C.POINTER(gmt_goal), P, i32, f64, C.POINTER(gmt_plan_opts),
                                    P, P, P, P, P, i32, C.POINTER(i32), C.POINTER(f64),
                                    C.POINTER(i32), P]
+            L.gmt_plan_noalloc.argtypes = L.gmt_plan.argtypes
             L.gmt_plan_batch.argtypes = [C.POINTER(gmt_problem), i32, C.POINTER(gmt_batch_opts),
                                          C.POINTER(gmt_result), P]
             L.gmt_last_work.argtypes = [C.POINTER(gmt_work)]
@@ -460,6 +461,34 @@ def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_p
     L = int(plen.value) if st == GMT_OK else 0
     return PlanResult(int(st), path[:min(L, path_cap)].copy(), float(pcost.value), int(iters.value),
                       par, cst, gi, ai, gmt_last_work())
+
+
+def gmt_plan_noalloc(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_plan_opts,
+                     parent, cost, group_iter, added_iter, stream=None, path_cap: int = 4096) -> PlanResult:
+    """One query solved without device allocation: the caller supplies the four
+    device tree arrays (n+1 entries: int32, float64, int32, int32); the
+    library's static device array holds the workspace."""
+    N = rm.n + 1
+    for t, dt in ((parent, "torch.int32"), (cost, "torch.float64"), (group_iter, "torch.int32"),
+                  (added_iter, "torch.int32")):
+        if t is None or str(t.dtype) != dt or t.numel() < N or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("gmt_plan_noalloc needs contiguous device arrays of n+1 entries (%s)" % dt)
+    xi = _host_f32(x_init)
+    bx = _host_f32(boxes).reshape(-1)
+    pd = 3 if rm.kind == GMT_COST_DOUBLE_INTEGRATOR else rm.dim
+    m = int(bx.size // (2 * pd)) if bx.size else 0
+    path = np.zeros(path_cap, np.int32)
+    plen = C.c_int32()
+    pcost = C.c_double()
+    iters = C.c_int32()
+    st = lib().gmt_plan_noalloc(rm.handle, xi.ctypes.data, C.byref(goal), bx.ctypes.data if m else None, m,
+                                float(lam), C.byref(opts), _ptr(parent), _ptr(cost), _ptr(group_iter),
+                                _ptr(added_iter), path.ctypes.data, path_cap, C.byref(plen), C.byref(pcost),
+                                C.byref(iters), _stream(stream))
+    _check(st, "gmt_plan_noalloc", ok=(GMT_OK, GMT_NO_PATH, GMT_ETIMEOUT))
+    L = int(plen.value) if st == GMT_OK else 0
+    return PlanResult(int(st), path[:min(L, path_cap)].copy(), float(pcost.value), int(iters.value),
+                      parent, cost, group_iter, added_iter, gmt_last_work())
 
 
 @dataclass

@@ -42,6 +42,8 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.gmt_plan(None, None, None, None, 0, 0.5, None, None, None, None, None, None, 0,
                       None, None, None, None) == gmt.GMT_EINVAL
     assert "null" in gmt.last_error()
+    assert L.gmt_plan_noalloc(None, None, None, None, 0, 0.5, None, None, None, None, None, None, 0,
+                              None, None, None, None) == gmt.GMT_EINVAL
     S = sampler.lib()
     assert S.gmt_gemm_bf16(0, 1, 64, 64, 12, None, 16, None, 16, None, 0, None, None, 64, None) == gmt.GMT_EINVAL
     assert S.gmt_sampler_create(None, ctypes.byref(h)) == gmt.GMT_EINVAL
