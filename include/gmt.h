@@ -20,10 +20,14 @@
  *  - Neighbours: u -> v is an edge when c(u -> v) < r (strict), the connection
  *    rule stated before Algorithm 1.  For the Euclidean cost the test is
  *    d2 < fl(r*r) * 2^40 with d2 the exact squared distance in grid units.
- *  - Costs: Euclidean arc length (Section II), or for the 6D double
+ *  - Costs: Euclidean arc length (Section II); for the 6D double
  *    integrator x'' = u (Section V-A) the optimal J = tau + int |u|^2 dt over
- *    the arrival time tau (two-point BVP cost, Section II footnote).  Edge
- *    costs and costs-to-come are FP64.
+ *    the arrival time tau (two-point BVP cost, Section II footnote); for the
+ *    Dubins airplane (Section V-A: a planar Dubins car with an altitude single
+ *    integrator, bounded turning rate, Euclidean length cost) the length of
+ *    the shortest path, sqrt(Ld^2 + dz^2) with Ld the shortest planar Dubins
+ *    path of turning radius rho and dz the climb.  Edge costs and
+ *    costs-to-come are FP64.
  *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls that
  *    return host results synchronise that stream before returning.
  *  - Errors: every function returns a gmt_status; nothing throws or aborts
@@ -57,9 +61,16 @@ typedef enum {
 } gmt_status;
 
 typedef enum {
-    GMT_COST_EUCLIDEAN = 0,        /* state space [0,1]^d, d in {2, 3} */
-    GMT_COST_DOUBLE_INTEGRATOR = 1 /* state (p, v), p in [0,1]^3, v in [-1,1]^3, dim = 6 */
+    GMT_COST_EUCLIDEAN = 0,         /* state space [0,1]^d, d in {2, 3} */
+    GMT_COST_DOUBLE_INTEGRATOR = 1, /* state (p, v), p in [0,1]^3, v in [-1,1]^3, dim = 6 */
+    GMT_COST_DUBINS_AIRPLANE = 2    /* state (p, h), p in [0,1]^3, heading 2 pi h, h in [0,1), dim = 4 */
 } gmt_cost_kind;
+
+/* Parameters of a cost kind.  turn_radius: the Dubins airplane's least
+ * turning radius rho (> 0); unused by the other kinds. */
+typedef struct {
+    double turn_radius;
+} gmt_cost_params;
 
 /* Opaque device-resident roadmap: a sample set with its r-disk neighbour
  * table (Section V-A precomputes exactly this offline).  Read-only while
@@ -87,6 +98,9 @@ typedef struct {
  *  edge_step   Euclidean lazy check: points y + k (x-y)/K1, k = 0..K1, with
  *              K1 the least k >= 1 such that K1 * step >= |x - y| (the paper
  *              discretises edges; Section V-A).  Must be > 0 for Euclidean.
+ *              Dubins airplane: K = max(1, ceil(L / step)) + 1 points at equal
+ *              fractions of the path of length L (first and last at the two
+ *              states' positions).  Must be > 0 for both.
  *  traj_points double integrator: the optimal trajectory is checked at
  *              traj_points times t_k = k tau/(traj_points-1) (>= 2).
  *  max_iters   cap on the threshold index i of Algorithm 1 (<= 0: none).
@@ -134,6 +148,41 @@ gmt_status gmt_set_allocator(const gmt_allocator *allocator);
  * edges; GMT_ENOMEM; GMT_EDEVICE. */
 gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim, gmt_cost_kind kind,
                                double r_n, void *stream, gmt_roadmap_t *out);
+
+/* Halton sample set (Section V-A: the planner samples the deterministic,
+ * low-dispersion Halton sequence), generated on the device.
+ * Point k (k >= 1) has coordinate j equal to the radical inverse of k in the
+ * j-th prime base (2, 3, 5, 7, 11, 13) -- the base-b digits of k mirrored
+ * about the radix point -- rounded down to the 2^-20 grid (exact).  Positions
+ * take that value; double-integrator velocities (coordinates 3..5) take
+ * 2 * value - 1, in [-1, 1).  A point is skipped when its velocity lies
+ * outside the closed unit ball or its position inside one of the closed
+ * boxes (samples are drawn from free space, Algorithm 1's input).
+ *  n          samples wanted (0: nothing is written).
+ *  dim, kind  as for gmt_build_neighbors.
+ *  first      index of the first point examined (>= 1).
+ *  boxes      host FP32 [m][2*pdim] (lower corner, upper corner) on the grid;
+ *             may be NULL when m = 0.
+ *  d_samples  device FP32 SoA [dim][n] (the caller's): the first n points not
+ *             skipped, in index order -- ready for gmt_build_neighbors.
+ *  next       (may be NULL) receives the index after the last point
+ *             examined, so a later call can continue the sequence.
+ * Synchronises `stream`.  Errors: GMT_EINVAL for a bad dim/kind pair, n < 0,
+ * first outside [1, 2^31-1], off-grid boxes, or indices exhausted at 2^31-1
+ * before n points were kept; GMT_ENOMEM; GMT_EDEVICE. */
+gmt_status gmt_sample_halton(int32_t n, int32_t dim, gmt_cost_kind kind, int64_t first,
+                             const float *boxes, int32_t m, float *d_samples, int64_t *next,
+                             void *stream);
+
+/* gmt_build_neighbors with the cost kind's parameters: required for
+ * GMT_COST_DUBINS_AIRPLANE (dim 4: x, y, z, heading in turns), whose table
+ * lists every ordered pair with path length below r_n (the frontier walks
+ * the transposed out-table as for the double integrator).  params may be
+ * NULL for the other kinds.  Errors: as gmt_build_neighbors, plus GMT_EINVAL
+ * for a missing or non-positive turning radius. */
+gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, int32_t dim, gmt_cost_kind kind,
+                                  double r_n, const gmt_cost_params *params, void *stream,
+                                  gmt_roadmap_t *out);
 
 /* Wrap an externally computed in-neighbour table (host arrays, copied):
  * samples SoA [dim][n], row_ptr [n+1], col [nnz] (each row ascending, no

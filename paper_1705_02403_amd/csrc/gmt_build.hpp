@@ -18,6 +18,7 @@
 #pragma once
 
 #include "gmt_dev.hpp"
+#include "gmt_dubins.hpp"
 
 namespace gmt {
 
@@ -139,8 +140,11 @@ __global__ void k_check_samples(const float *__restrict__ s, int n, int dim, int
     for (int a = 0; a < dim; ++a) {
         float x = s[(size_t)a * n + i];
         double qd = (double)x * GMT_QS;
-        bool pos = (kind == 0) || a < 3;
-        double lo = pos ? 0.0 : -GMT_QS, hi = GMT_QS;
+        // positions in [0,1]; double-integrator velocities in [-1,1]; the
+        // Dubins heading (turns) in [0,1)
+        double lo = 0.0, hi = GMT_QS;
+        if (kind == 1 && a >= 3) lo = -GMT_QS;
+        if (kind == 2 && a == 3) hi = GMT_QS - 1.0;
         if (!(qd == floor(qd)) || !(qd >= lo && qd <= hi)) bad = true;
     }
     if (bad) atomicOr(&flags[0], 1);
@@ -161,13 +165,17 @@ __global__ void k_pack_rec(long long E, long long total, const int *__restrict__
     rec[3 * e + 2] = real ? (unsigned int)col[e] : 0u;
 }
 
-// double-integrator states as 8 floats per node (6 used), so that one node's
-// state is two aligned 16-byte loads from one line
-__global__ void k_aos8(const float *__restrict__ s, int n, float4 *__restrict__ out) {
+// states as 8 floats per node (the double integrator's 6 or the Dubins
+// airplane's 4 used, the rest zero), so that one node's state is one or two
+// aligned 16-byte loads from one line
+__global__ void k_aos8(const float *__restrict__ s, int n, int dim, float4 *__restrict__ out) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    out[2 * v] = make_float4(s[v], s[(size_t)n + v], s[2 * (size_t)n + v], s[3 * (size_t)n + v]);
-    out[2 * v + 1] = make_float4(s[4 * (size_t)n + v], s[5 * (size_t)n + v], 0.0f, 0.0f);
+    float x[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) x[a] = a < dim ? s[(size_t)a * n + v] : 0.0f;
+    out[2 * v] = make_float4(x[0], x[1], x[2], x[3]);
+    out[2 * v + 1] = make_float4(x[4], x[5], x[6], x[7]);
 }
 
 // the padding records (column 0, cost 0) after the E records of a table
@@ -421,10 +429,49 @@ __device__ __forceinline__ DiPair di_pair(const double *src, const double *dst) 
     return d;
 }
 
+// state of sample i of a pair-cost kind: CK 1 double integrator (6 values),
+// CK 2 Dubins airplane (4)
+template <int CK>
+__device__ __forceinline__ void pair_load(const float *__restrict__ s, int n, int i, double *x) {
+    if (CK == 1) {
+        di_load(s, n, i, x);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = (double)s[(size_t)a * n + i];
+    }
+}
+
+// exact necessary condition for c(y -> x) < r: the double integrator's
+// lower bounds on J; for the Dubins airplane the path is at least as long
+// as the straight segment (the slack keeps the test conservative under any
+// rounding of the squared distance)
+template <int CK>
+__device__ __forceinline__ bool pair_may_connect(const double *ys, const double *xs, double r) {
+    if (CK == 1) return di_may_connect(di_pair(ys, xs), r);
+    double e2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e2 += (xs[a] - ys[a]) * (xs[a] - ys[a]);
+    return e2 < r * r * (1.0 + 1e-9);
+}
+
+// cost c(y -> x), with the double integrator's arrival time in t
+template <int CK>
+__device__ __forceinline__ double pair_cost(const double *ys, const double *xs, double rho, double &t) {
+    if (CK == 1) {
+        double J;
+        di_cost(di_pair(ys, xs), J, t);
+        return J;
+    }
+    DubinsPath path;
+    t = 0.0;
+    return dubins_cost(ys, xs, rho, path);
+}
+
 // One wave per target row x (or per entry of `rows`: count rows[0], list
-// from rows[1]).  The sources y are scanned in increasing order, prefiltered
-// by a lower bound on J, queued in LDS, and solved one per lane, so each row
-// comes out ascending.  Modes:
+// from rows[1]), for the asymmetric costs (CK 1 double integrator, CK 2
+// Dubins airplane of turning radius rho).  The sources y are scanned in
+// increasing order, prefiltered by an exact lower bound on the cost, queued
+// in LDS, and solved one per lane, so each row comes out ascending.  Modes:
 //   DI_FILL    write the row at row_ptr[x] (columns, arrival times, and
 //              (cost, column) records when `rec` is given, else costs);
 //   DI_SCRATCH write the row into scratch slot x of `cap` entries (entries
@@ -432,7 +479,8 @@ __device__ __forceinline__ DiPair di_pair(const double *src, const double *dst) 
 //              list from ovf[1]); deg[x] receives the full row length.
 enum { DI_FILL = 0, DI_SCRATCH = 2 };
 
-__global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, int n, double r, int mode,
+template <int CK>
+__global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, int n, double r, double rho, int mode,
                                                  const int *__restrict__ rows, const int *__restrict__ row_ptr,
                                                  int cap, int *__restrict__ deg, int *__restrict__ ovf,
                                                  int *__restrict__ col, double *__restrict__ cost,
@@ -452,7 +500,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
     }
     int *qu = queue[wl];
     double xs[6];
-    di_load(s, n, x, xs);
+    pair_load<CK>(s, n, x, xs);
     int qn = 0;      // queued survivors (wave-uniform)
     int found = 0;   // neighbours emitted so far (wave-uniform)
     int nsolved = 0; // pairs past the prefilter (wave-uniform)
@@ -465,9 +513,8 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         if (lane < take) {
             y = qu[lane];
             double ys[6];
-            di_load(s, n, y, ys);
-            DiPair d = di_pair(ys, xs);
-            di_cost(d, J, t);
+            pair_load<CK>(s, n, y, ys);
+            J = pair_cost<CK>(ys, xs, rho, t);
             hit = J < r;
         }
         uint64_t m = wave_ballot(hit);
@@ -501,8 +548,8 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         bool pass = false;
         if (y < n && y != x) {
             double ys[6];
-            di_load(s, n, y, ys);
-            pass = di_may_connect(di_pair(ys, xs), r);
+            pair_load<CK>(s, n, y, ys);
+            pass = pair_may_connect<CK>(ys, xs, r);
         }
         uint64_t m = wave_ballot(pass);
         if (pass) qu[qn + lanes_below(m)] = y;

@@ -26,6 +26,7 @@
 #include "../../include/gmt.h"
 #include "gmt_host.hpp"
 #include "gmt_build.hpp"
+#include "gmt_sample.hpp"
 #include "gmt_dev.hpp"
 #include "gmt_plan.hpp"
 
@@ -222,6 +223,7 @@ extern "C" int64_t gmt_steady_ns(void);
 struct gmt_roadmap {
     int n = 0, dim = 0, kind = 0;
     double r = 0.0;
+    double rho = 0.0;  // Dubins airplane: turning radius
     long long nnz = 0;
     DevBuf s, in_ptr, in_col, in_tau, out_ptr, out_col;
     DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
@@ -236,7 +238,10 @@ static bool on_grid(double x) {
     return std::isfinite(q) && q == std::floor(q);
 }
 
-static int pdim_of(int kind, int dim) { return kind == GMT_COST_DOUBLE_INTEGRATOR ? 3 : dim; }
+// largest Halton index the generator evaluates (32-bit digit reversal)
+static const long long kHaltonLastIndex = (1ll << 31) - 1;
+
+static int pdim_of(int kind, int dim) { return kind == GMT_COST_EUCLIDEAN ? dim : 3; }
 
 static gmt_status check_shape(int32_t n, int32_t dim, gmt_cost_kind kind, double r) {
     if (n < 1) return fail(GMT_EINVAL, "n must be >= 1 (got %d)", n);
@@ -244,6 +249,8 @@ static gmt_status check_shape(int32_t n, int32_t dim, gmt_cost_kind kind, double
         if (dim != 2 && dim != 3) return fail(GMT_EINVAL, "Euclidean roadmaps need dim 2 or 3 (got %d)", dim);
     } else if (kind == GMT_COST_DOUBLE_INTEGRATOR) {
         if (dim != 6) return fail(GMT_EINVAL, "double-integrator roadmaps need dim 6 (got %d)", dim);
+    } else if (kind == GMT_COST_DUBINS_AIRPLANE) {
+        if (dim != 4) return fail(GMT_EINVAL, "Dubins airplane roadmaps need dim 4 (got %d)", dim);
     } else {
         return fail(GMT_EINVAL, "unknown cost kind %d", (int)kind);
     }
@@ -345,9 +352,9 @@ static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
                                                                 (unsigned int *)rm->in_rec.p);
     HIPCHK(hipGetLastError());
     dev_free(rm->in_cost, s);
-    if (rm->kind == GMT_COST_DOUBLE_INTEGRATOR) {
+    if (rm->kind != GMT_COST_EUCLIDEAN) {
         TRY(dev_alloc(rm->s8, 32 * (size_t)rm->n, s));
-        k_aos8<<<blocks_for(rm->n, 256), 256, 0, s>>>((const float *)rm->s.p, rm->n, (float4 *)rm->s8.p);
+        k_aos8<<<blocks_for(rm->n, 256), 256, 0, s>>>((const float *)rm->s.p, rm->n, rm->dim, (float4 *)rm->s8.p);
         HIPCHK(hipGetLastError());
     }
     return GMT_OK;
@@ -443,7 +450,10 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
 // the few longer rows are recomputed straight into it.
 static const int kDiScratchCap = 384;
 
-static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
+// Tables of the asymmetric costs: the double integrator and the Dubins
+// airplane (whose rows carry arrival times of zero).
+static gmt_status build_pairs(gmt_roadmap *rm, hipStream_t s) {
+    const bool dub = rm->kind == GMT_COST_DUBINS_AIRPLANE;
     const int n = rm->n;
     const int cap = kDiScratchCap;
     // one block of temporaries: row lengths, flags, overflow list, scratch
@@ -469,10 +479,13 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     bt.begin();
     k_fill_int<<<1, 64, 0, s>>>(flags, 8, 0);
     k_fill_int<<<1, 64, 0, s>>>(ovf, 1, 0);
-    k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, 6, 1, flags);
-    k_di_rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->r, DI_SCRATCH,
-                                                                     nullptr, nullptr, cap, deg, ovf, scol, scost,
-                                                                     stau, nullptr, solved);
+    k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->dim, rm->kind, flags);
+    {
+        auto rows = dub ? k_di_rows<2> : k_di_rows<1>;
+        rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->r, rm->rho,
+                                                                     DI_SCRATCH, nullptr, nullptr, cap, deg, ovf,
+                                                                     scol, scost, stau, nullptr, solved);
+    }
     TRY(scan_ints(deg, n, (int *)rm->in_ptr.p, total, s, T + o_scan));
     bt.end();
     {
@@ -486,6 +499,9 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     unsigned long long nsolved = 0;
     std::memcpy(&E, hs + 2, sizeof E);
     std::memcpy(&nsolved, hs + 4, sizeof nsolved);
+    if (hs[0] && dub)
+        return fail(GMT_EINVAL, "Dubins airplane samples must have position in [0,1]^3, heading in [0,1), "
+                                "on the 2^-20 grid");
     if (hs[0])
         return fail(GMT_EINVAL, "double-integrator samples must have position in [0,1]^3, velocity in [-1,1]^3, "
                                 "on the 2^-20 grid");
@@ -512,12 +528,14 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     bt.begin();
     k_di_compact<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(n, cap, deg, (const int *)rm->in_ptr.p, scol,
                                                                          scost, stau, col, tau, rec);
-    if (novf > 0)
-        k_di_rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
-            (const float *)rm->s.p, n, rm->r, DI_FILL, ovf, (const int *)rm->in_ptr.p, cap, nullptr, nullptr, col,
-            nullptr, tau, rec, nullptr);
+    if (novf > 0) {
+        auto rows = dub ? k_di_rows<2> : k_di_rows<1>;
+        rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
+            (const float *)rm->s.p, n, rm->r, rm->rho, DI_FILL, ovf, (const int *)rm->in_ptr.p, cap, nullptr,
+            nullptr, col, nullptr, tau, rec, nullptr);
+    }
     k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>(rec, E);
-    k_aos8<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, (float4 *)rm->s8.p);
+    k_aos8<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->dim, (float4 *)rm->s8.p);
     {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
@@ -528,25 +546,32 @@ static gmt_status build_di(gmt_roadmap *rm, hipStream_t s) {
     return GMT_OK;
 }
 
-extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim,
-                                          gmt_cost_kind kind, double r_n, void *stream,
-                                          gmt_roadmap_t *out) {
+extern "C" gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, int32_t dim,
+                                             gmt_cost_kind kind, double r_n, const gmt_cost_params *params,
+                                             void *stream, gmt_roadmap_t *out) {
     if (!out || !d_samples) return fail(GMT_EINVAL, "null argument");
     *out = nullptr;
     TRY(check_shape(n, dim, kind, r_n));
+    double rho = 0.0;
+    if (kind == GMT_COST_DUBINS_AIRPLANE) {
+        if (!params) return fail(GMT_EINVAL, "Dubins airplane roadmaps need the turning radius (params)");
+        rho = params->turn_radius;
+        if (!(rho > 0.0) || !std::isfinite(rho)) return fail(GMT_EINVAL, "turning radius must be finite and > 0");
+    }
     hipStream_t s = (hipStream_t)stream;
     gmt_roadmap *rm = new gmt_roadmap;
     rm->n = n;
     rm->dim = dim;
     rm->kind = kind;
     rm->r = r_n;
+    rm->rho = rho;
     gmt_status st = dev_alloc(rm->s, sizeof(float) * (size_t)dim * n, s);
     if (st == GMT_OK) {
         hipError_t e = hipMemcpyAsync(rm->s.p, d_samples, sizeof(float) * (size_t)dim * n,
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) st = fail(GMT_EDEVICE, "sample copy failed: %s", hipGetErrorString(e));
     }
-    if (st == GMT_OK) st = (kind == GMT_COST_EUCLIDEAN) ? build_euclid(rm, s) : build_di(rm, s);
+    if (st == GMT_OK) st = (kind == GMT_COST_EUCLIDEAN) ? build_euclid(rm, s) : build_pairs(rm, s);
     // the table is complete on return, so any stream may plan on it
     if (st == GMT_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(GMT_EDEVICE, "neighbour build failed");
     if (st != GMT_OK) {
@@ -559,6 +584,12 @@ extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int
     return GMT_OK;
 }
 
+extern "C" gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim,
+                                          gmt_cost_kind kind, double r_n, void *stream,
+                                          gmt_roadmap_t *out) {
+    return gmt_build_neighbors_ex(d_samples, n, dim, kind, r_n, nullptr, stream, out);
+}
+
 extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int32_t dim,
                                            gmt_cost_kind kind, double r_n, const int32_t *row_ptr,
                                            const int32_t *col, const double *cost, const double *tau,
@@ -567,6 +598,9 @@ extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int3
         return fail(GMT_EINVAL, "null argument");
     *out = nullptr;
     TRY(check_shape(n, dim, kind, r_n));
+    if (kind == GMT_COST_DUBINS_AIRPLANE)
+        return fail(GMT_EINVAL, "Dubins airplane roadmaps are built with gmt_build_neighbors_ex (the turning "
+                                "radius is part of the cost)");
     if (kind == GMT_COST_DOUBLE_INTEGRATOR && !tau && row_ptr[n] > 0)
         return fail(GMT_EINVAL, "double-integrator tables need arrival times");
     const int pd = pdim_of(kind, dim);
@@ -616,6 +650,67 @@ extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int3
         return st;
     }
     *out = rm;
+    return GMT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Halton sample sets
+// ---------------------------------------------------------------------------
+extern "C" gmt_status gmt_sample_halton(int32_t n, int32_t dim, gmt_cost_kind kind, int64_t first,
+                                        const float *boxes, int32_t m, float *d_samples, int64_t *next,
+                                        void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const bool di = kind == GMT_COST_DOUBLE_INTEGRATOR;
+    if (!((kind == GMT_COST_EUCLIDEAN && (dim == 2 || dim == 3)) || (di && dim == 6)))
+        return fail(GMT_EINVAL, "bad dim/kind pair (%d, %d)", dim, (int)kind);
+    if (n < 0) return fail(GMT_EINVAL, "n must be >= 0");
+    if (first < 1 || first > kHaltonLastIndex) return fail(GMT_EINVAL, "first index must lie in [1, 2^31-1]");
+    if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
+    if (m > 0 && !boxes) return fail(GMT_EINVAL, "null boxes");
+    if (n > 0 && !d_samples) return fail(GMT_EINVAL, "null output");
+    const int pd = di ? 3 : dim;
+    std::vector<int> bq((size_t)std::max(1, m * 2 * pd));
+    for (int k = 0; k < m * 2 * pd; ++k) {
+        if (!on_grid(boxes[k]) || std::fabs(boxes[k]) > 2.0f) return fail(GMT_EINVAL, "box %d off the grid", k / (2 * pd));
+        bq[k] = (int)std::llround((double)boxes[k] * GMT_QS);
+    }
+    if (n == 0) {
+        if (next) *next = first;
+        return GMT_OK;
+    }
+    // candidates per chunk: twice what is still missing (at least 64 K), so
+    // the double integrator's ball test (about half kept) rarely needs a second
+    const int chunk_cap = (int)std::min<long long>(std::max<long long>(2ll * n, 65536), 1ll << 26);
+    DevBuf flag, rank, sb, dbox, misc;
+    Temps keep(s, {&flag, &rank, &sb, &dbox, &misc});
+    TRY(dev_alloc(flag, sizeof(int) * (size_t)chunk_cap, s));
+    TRY(dev_alloc(rank, sizeof(int) * ((size_t)chunk_cap + 1), s));
+    TRY(dev_alloc(sb, scan_scratch_bytes(chunk_cap), s));
+    TRY(dev_alloc(dbox, sizeof(int) * bq.size(), s));
+    TRY(dev_alloc(misc, 2 * sizeof(long long), s));
+    long long *total = (long long *)misc.p, *last = total + 1;
+    HIPCHK(hipMemcpyAsync(dbox.p, bq.data(), sizeof(int) * bq.size(), hipMemcpyHostToDevice, s));
+    long long k0 = first, got = 0, last_h = -1;
+    while (got < n) {
+        const long long want = std::max<long long>(2 * (n - got), 65536);
+        const int count = (int)std::min<long long>(std::min<long long>(want, chunk_cap), kHaltonLastIndex - k0 + 1);
+        if (count <= 0) return fail(GMT_EINVAL, "Halton indices exhausted below 2^31 before %d samples were kept", n);
+        k_halton_flag<<<blocks_for(count, 256), 256, 0, s>>>((unsigned)k0, count, dim, di ? 1 : 0,
+                                                            (const int *)dbox.p, m, (int *)flag.p);
+        TRY(scan_ints((const int *)flag.p, count, (int *)rank.p, total, s, sb.p));
+        k_halton_place<<<blocks_for(count, 256), 256, 0, s>>>((unsigned)k0, count, dim, di ? 1 : 0,
+                                                             (const int *)flag.p, (const int *)rank.p, (int)got, n,
+                                                             d_samples, last);
+        long long kept = 0;
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&kept, total, sizeof kept, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&last_h, last, sizeof last_h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(GMT_EDEVICE, "Halton pass failed: %s", hipGetErrorString(e));
+        got = std::min<long long>(n, got + kept);
+        k0 += count;
+    }
+    if (next) *next = last_h + 1;
     return GMT_OK;
 }
 
@@ -820,6 +915,7 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
     P.rm.kind = rm->kind;
     P.rm.r = rm->r;
     P.rm.R2 = rm->r * rm->r * GMT_Q2;
+    P.rm.rho = rm->rho;
     P.rm.s = (const float *)rm->s.p;
     P.rm.in_ptr = (const int *)rm->in_ptr.p;
     P.rm.in_rec = (const unsigned int *)rm->in_rec.p;
@@ -839,6 +935,13 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
         if (P.step_q < 1) return fail(GMT_EINVAL, "edge_step below the grid quantum");
         P.traj_points = 0;
         P.inv_k1 = 0.0;
+    } else if (rm->kind == GMT_COST_DUBINS_AIRPLANE) {
+        // the check spaces points at most edge_step apart along a path no
+        // longer than r: cap their count
+        if (!(o.edge_step > 0.0) || !std::isfinite(o.edge_step)) return fail(GMT_EINVAL, "edge_step must be > 0");
+        if (rm->r / o.edge_step > 65536.0) return fail(GMT_EINVAL, "edge_step below r / 65536");
+        P.step_d = o.edge_step;
+        P.step_q = 1;
     } else {
         if (o.traj_points < 2 || o.traj_points > 4096) return fail(GMT_EINVAL, "traj_points must lie in [2, 4096]");
         P.traj_points = o.traj_points;
@@ -847,8 +950,10 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
     }
     for (int a = 0; a < dim; ++a) {
         double x = q.x_init[a];
-        double lo = a < pd ? 0.0 : -1.0;
-        if (!on_grid(x) || x < lo || x > 1.0) return fail(GMT_EINVAL, "x_init[%d] off the grid or out of range", a);
+        // positions in [0,1], velocities in [-1,1], the heading in [0,1)
+        double lo = a < pd ? 0.0 : (rm->kind == GMT_COST_DUBINS_AIRPLANE ? 0.0 : -1.0);
+        const bool high = rm->kind == GMT_COST_DUBINS_AIRPLANE && a == 3 ? x >= 1.0 : x > 1.0;
+        if (!on_grid(x) || x < lo || high) return fail(GMT_EINVAL, "x_init[%d] off the grid or out of range", a);
         P.x_q[a] = (int)(x * GMT_QS);
         P.x_d[a] = x;
     }
@@ -947,7 +1052,9 @@ static const void *plan_kernel_k(int level, int cl) {
 }
 
 static const void *plan_kernel(int kind, int level, int cl) {
-    return kind == GMT_COST_EUCLIDEAN ? plan_kernel_k<0>(level, cl) : plan_kernel_k<1>(level, cl);
+    return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_k<0>(level, cl)
+           : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_k<1>(level, cl)
+                                                 : plan_kernel_k<2>(level, cl);
 }
 
 static bool lanes_valid(int lanes) { return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32; }
@@ -990,12 +1097,13 @@ static TuneKey tune_key(const gmt_tune_shape &sh) {
                    sh.batch > 0 ? 1 : 0, sh.batch > 0 ? ceil_log2(sh.batch) : 0};
 }
 
-// shape of a call: the double integrator dominates a mixed batch
+// shape of a call: the double integrator dominates a mixed batch, then the
+// Dubins airplane
 static gmt_tune_shape tune_shape(const gmt_problem *problems, int count, bool single) {
     gmt_tune_shape sh{GMT_COST_EUCLIDEAN, 0, 0, 0, single ? 0 : count};
+    auto rank = [](int kind) { return kind == GMT_COST_DOUBLE_INTEGRATOR ? 2 : kind == GMT_COST_DUBINS_AIRPLANE ? 1 : 0; };
     for (int k = 0; k < count; ++k)
-        if (problems[k].roadmap && problems[k].roadmap->kind == GMT_COST_DOUBLE_INTEGRATOR)
-            sh.kind = GMT_COST_DOUBLE_INTEGRATOR;
+        if (problems[k].roadmap && rank(problems[k].roadmap->kind) > rank(sh.kind)) sh.kind = problems[k].roadmap->kind;
     for (int k = 0; k < count; ++k) {
         const gmt_roadmap *rm = problems[k].roadmap;
         if (!rm || rm->kind != sh.kind) continue;
@@ -1033,13 +1141,15 @@ static void tune_apply(const gmt_problem *problems, int count, bool single, gmt_
 struct BatchRun {
     WsBlock *w = nullptr;
     std::vector<int> order;  // kernel order -> caller index
-    int count = 0, n_euclid = 0, nmax_e = 0, nmax_d = 0;
+    int count = 0;
+    int kfirst[3] = {0, 0, 0}, kcount[3] = {0, 0, 0}, knmax[3] = {0, 0, 0};  // per cost kind, in kernel order
     int teams = 1, team_wgs = 1, box_words = 1, cl = 16, threads = 256;
     size_t used = 0;
     bool prof = false;
     bool own_all = false;  // tree arrays always in the workspace (prepared batches)
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // kernel brackets x2, done
+    hipEvent_t ev[7] = {};  // kernel brackets of each kind (2k, 2k+1), then done (kEvDone)
 };
+static const int kEvDone = 6;
 
 static void run_release(BatchRun &r) {
     for (hipEvent_t &e : r.ev)
@@ -1105,24 +1215,22 @@ static int single_team_wgs(int requested, int kind, int box_words, int nmax, int
 // record the completion event -- all asynchronous on `s`.
 // `events` false (graph capture): no event records.  `upload` false: the
 // staged queries are already in device memory (a prepared batch); only the
-// two queue counters of the staging header are reset, by a kernel.
+// three queue counters (one per cost kind) of the staging header are reset,
+// by a kernel.
 static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, bool upload = true) {
     WsBlock *w = r.w;
     if (upload) HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, r.used, hipMemcpyHostToDevice, s));
-    else k_fill_int<<<1, 64, 0, s>>>((int *)w->stage_d.p, 2, 0);
-    for (int k = 0; k < 5 && events; ++k)
-        if (!r.ev[k] && (k == 4 || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
-    if (r.n_euclid > 0)
-        TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, GMT_COST_EUCLIDEAN, 0,
-                             r.n_euclid, r.count, r.nmax_e, std::min(r.teams, r.n_euclid), r.team_wgs, r.box_words, 0,
-                             r.cl, r.threads, r.ev[0], r.ev[1], s));
-    if (r.count - r.n_euclid > 0)
-        TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, GMT_COST_DOUBLE_INTEGRATOR,
-                             r.n_euclid, r.count - r.n_euclid, r.count, r.nmax_d,
-                             std::min(r.teams, r.count - r.n_euclid), r.team_wgs, r.box_words, 1, r.cl, r.threads,
-                             r.ev[2], r.ev[3], s));
+    else k_fill_int<<<1, 64, 0, s>>>((int *)w->stage_d.p, 3, 0);
+    for (int k = 0; k <= kEvDone && events; ++k)
+        if (!r.ev[k] && (k == kEvDone || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
+    for (int kind = 0; kind < 3; ++kind)
+        if (r.kcount[kind] > 0)
+            TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, kind, r.kfirst[kind],
+                                 r.kcount[kind], r.count, r.knmax[kind], std::min(r.teams, r.kcount[kind]),
+                                 r.team_wgs, r.box_words, kind, r.cl, r.threads, r.ev[2 * kind], r.ev[2 * kind + 1],
+                                 s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
-    if (events) HIPCHK(hipEventRecord(r.ev[4], s));
+    if (events) HIPCHK(hipEventRecord(r.ev[kEvDone], s));
     return GMT_OK;
 }
 
@@ -1131,8 +1239,9 @@ static void batch_profile(BatchRun &r) {
     if (!r.prof) return;
     double ms = 0.0;
     long long n = 0;
-    for (int k = 0; k < 4; k += 2) {
-        if ((k == 0 && r.n_euclid == 0) || (k == 2 && r.count - r.n_euclid == 0)) continue;
+    for (int kind = 0; kind < 3; ++kind) {
+        if (r.kcount[kind] == 0) continue;
+        const int k = 2 * kind;
         float t = 0.0f;
         if (hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]) == hipSuccess) {
             ms += t;
@@ -1177,26 +1286,27 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     r.count = count;
     r.order.clear();
     r.order.reserve(count);
-    for (int pass = 0; pass < 2; ++pass)
+    // kernel order: Euclidean, then double integrator, then Dubins airplane
+    for (int kind = 0; kind < 3; ++kind) {
+        r.kfirst[kind] = (int)r.order.size();
+        r.kcount[kind] = r.knmax[kind] = 0;
         for (int k = 0; k < count; ++k) {
             const gmt_problem &pr = problems[k];
             if (!pr.roadmap) return fail(GMT_EINVAL, "problem %d: null roadmap", k);
-            if ((pr.roadmap->kind == GMT_COST_EUCLIDEAN) == (pass == 0)) r.order.push_back(k);
+            if (pr.roadmap->kind == kind) {
+                r.order.push_back(k);
+                ++r.kcount[kind];
+                r.knmax[kind] = std::max(r.knmax[kind], pr.roadmap->n);
+            }
         }
+    }
     size_t total_boxes = 0, ws_bytes = 0;
     std::vector<size_t> ws_off(count);
-    r.n_euclid = r.nmax_e = r.nmax_d = 0;
     r.box_words = 1;
     for (int j = 0; j < count; ++j) {
         const gmt_problem &pr = problems[r.order[j]];
         if (pr.m < 0 || pr.m > GMT_MAX_BOXES)
             return fail(GMT_EINVAL, "problem %d: box count %d outside [0, %d]", r.order[j], pr.m, GMT_MAX_BOXES);
-        if (pr.roadmap->kind == GMT_COST_EUCLIDEAN) {
-            ++r.n_euclid;
-            r.nmax_e = std::max(r.nmax_e, pr.roadmap->n);
-        } else {
-            r.nmax_d = std::max(r.nmax_d, pr.roadmap->n);
-        }
         const int words = pr.m * 2 * pdim_of(pr.roadmap->kind, pr.roadmap->dim);
         r.box_words = std::max(r.box_words, words);
         total_boxes += (size_t)words;
@@ -1205,8 +1315,9 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
         ws_off[j] = ws_bytes;
         ws_bytes += qws_bytes(pr.roadmap->n + 1, own);
     }
-    const int nmax = std::max(r.nmax_e, r.nmax_d);
-    const int kind0 = r.nmax_d > 0 ? GMT_COST_DOUBLE_INTEGRATOR : GMT_COST_EUCLIDEAN;
+    const int nmax = std::max(r.knmax[0], std::max(r.knmax[1], r.knmax[2]));
+    const int kind0 = r.kcount[1] > 0 ? GMT_COST_DOUBLE_INTEGRATOR
+                      : r.kcount[2] > 0 ? GMT_COST_DUBINS_AIRPLANE : GMT_COST_EUCLIDEAN;
     if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || bo.plan.threads == 0 || (!single && bo.workgroups == 0))
         tune_apply(problems, count, single, bo);
     r.cl = lanes_of(bo.plan.lanes);
@@ -1220,7 +1331,8 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
         const int level = plan_level(r.team_wgs, r.threads, pbw, nmax);
         const size_t lds = plan_lds(pbw, nmax, level);
         const int resident = std::min(max_coop_wgs(lds, 0, level, r.cl, r.threads),
-                                      max_coop_wgs(lds, 1, level, r.cl, r.threads));
+                                      std::min(max_coop_wgs(lds, 1, level, r.cl, r.threads),
+                                               max_coop_wgs(lds, 2, level, r.cl, r.threads)));
         int teams = bo.workgroups > 0 ? bo.workgroups / r.team_wgs : resident / r.team_wgs;
         teams = std::max(1, std::min(teams, count));
         if (r.team_wgs > 1) teams = std::max(1, std::min(teams, resident / r.team_wgs));
@@ -1233,6 +1345,7 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
         char *sh = (char *)r.w->stage_h;
         ((int *)sh)[0] = 0;  // queue counters, one per cost kind
         ((int *)sh)[1] = 0;
+        ((int *)sh)[2] = 0;
         ProbDev *P = (ProbDev *)(sh + 256);
         int *bx = (int *)(sh + 256 + sizeof(ProbDev) * count);
         int off = 0;
@@ -1331,7 +1444,7 @@ static gmt_status run_sync(const gmt_problem *problems, int count, const gmt_bat
     BatchRun r;
     TRY(batch_stage(problems, count, bo, single, results, r, s));
     gmt_status st = batch_launch(r, s);
-    if (st == GMT_OK && hipEventSynchronize(r.ev[4]) != hipSuccess) st = fail(GMT_EDEVICE, "planning launch failed");
+    if (st == GMT_OK && hipEventSynchronize(r.ev[kEvDone]) != hipSuccess) st = fail(GMT_EDEVICE, "planning launch failed");
     if (st != GMT_OK) {
         (void)hipStreamSynchronize(s);
         run_release(r);
@@ -1348,7 +1461,8 @@ extern "C" gmt_status gmt_plan(gmt_roadmap_t rm, const float *x_init, const gmt_
                                int32_t *iters, void *stream) {
     if (!rm) return fail(GMT_EINVAL, "null roadmap");
     if (path_cap > 0 && !path) return fail(GMT_EINVAL, "null path buffer");
-    if (!opts_in && rm->kind == GMT_COST_EUCLIDEAN) return fail(GMT_EINVAL, "Euclidean plans need opts.edge_step");
+    if (!opts_in && rm->kind != GMT_COST_DOUBLE_INTEGRATOR)
+        return fail(GMT_EINVAL, "Euclidean and Dubins airplane plans need opts.edge_step");
     if (!goal) return fail(GMT_EINVAL, "null goal");
     gmt_batch_opts bo;
     std::memset(&bo, 0, sizeof bo);
@@ -1442,7 +1556,8 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     if (!d_parent || !d_cost || !d_group_iter || !d_added_iter)
         return fail(GMT_EINVAL, "gmt_plan_noalloc needs all four device tree arrays");
     if (path_cap < 0 || (path_cap > 0 && !path)) return fail(GMT_EINVAL, "null path buffer");
-    if (!opts_in && rm->kind == GMT_COST_EUCLIDEAN) return fail(GMT_EINVAL, "Euclidean plans need opts.edge_step");
+    if (!opts_in && rm->kind != GMT_COST_DOUBLE_INTEGRATOR)
+        return fail(GMT_EINVAL, "Euclidean and Dubins airplane plans need opts.edge_step");
     if (!goal) return fail(GMT_EINVAL, "null goal");
     if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
     hipStream_t s = (hipStream_t)stream;
@@ -1478,6 +1593,7 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     TRY(noalloc_scratch(&base));
     ((int *)g_na_stage)[0] = 0;  // queue counters
     ((int *)g_na_stage)[1] = 0;
+    ((int *)g_na_stage)[2] = 0;
     ProbDev &P = *(ProbDev *)(g_na_stage + 256);
     QueryIn q{rm, x_init, goal, boxes, m, lambda};
     TRY(stage_query(q, bo.plan, P, (int *)(g_na_stage + 256 + sizeof(ProbDev)), 0));
@@ -1488,8 +1604,8 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
                           hipMemcpyHostToDevice, s));
     // barrier arrivals, generation and fault flag start at zero on every call
     k_fill_int<<<1, 64, 0, s>>>((int *)tctl, (int)(sizeof(TeamCtl) / sizeof(int)), 0);
-    TRY(launch_plan_kind(base, tctl, res_d, rm->kind, 0, 1, 1, rm->n, 1, team_wgs, std::max(words, 1),
-                         rm->kind == GMT_COST_EUCLIDEAN ? 0 : 1, cl, threads, nullptr, nullptr, s));
+    TRY(launch_plan_kind(base, tctl, res_d, rm->kind, 0, 1, 1, rm->n, 1, team_wgs, std::max(words, 1), rm->kind,
+                         cl, threads, nullptr, nullptr, s));
     HIPCHK(hipMemcpyAsync(&g_na_res, res_d, sizeof(Result), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Result &res = g_na_res;
@@ -1597,7 +1713,7 @@ extern "C" gmt_status gmt_batch_run(gmt_batch_t b, gmt_result *results, void *st
         HIPCHK(hipStreamSynchronize(s));
     } else {
         TRY(batch_launch(b->run, s));
-        HIPCHK(hipEventSynchronize(b->run.ev[4]));
+        HIPCHK(hipEventSynchronize(b->run.ev[kEvDone]));
     }
     return collect_results(b->run, results, s);
 }
@@ -1764,7 +1880,7 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
 }
 
 static bool tune_shape_valid(const gmt_tune_shape &sh) {
-    return (sh.kind == GMT_COST_EUCLIDEAN || sh.kind == GMT_COST_DOUBLE_INTEGRATOR) && sh.dim >= 1 &&
+    return (sh.kind >= GMT_COST_EUCLIDEAN && sh.kind <= GMT_COST_DUBINS_AIRPLANE) && sh.dim >= 1 &&
            sh.dim <= GMT_MAX_DIM && sh.n >= 1 && sh.m >= 0 && sh.batch >= 0;
 }
 
@@ -1831,7 +1947,7 @@ extern "C" gmt_status gmt_tune_load(const char *path) {
         const int got_n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %lf %lf %c", &k.kind, &k.dim, &k.nlog,
                                       &k.mlog, &k.mode, &k.blog, &c.lanes, &c.team_wgs, &c.workgroups, &c.threads,
                                       &c.ms, &c.default_ms, &tail);
-        const bool key_ok = (k.kind == GMT_COST_EUCLIDEAN || k.kind == GMT_COST_DOUBLE_INTEGRATOR) && k.dim >= 1 &&
+        const bool key_ok = (k.kind >= GMT_COST_EUCLIDEAN && k.kind <= GMT_COST_DUBINS_AIRPLANE) && k.dim >= 1 &&
                             k.dim <= GMT_MAX_DIM && k.nlog >= 0 && k.nlog <= 31 && k.mlog >= 0 && k.mlog <= 31 &&
                             (k.mode == 0 || k.mode == 1) && k.blog >= 0 && k.blog <= 31;
         if (got_n != 12 || !key_ok || !tune_choice_valid(c)) {
@@ -1903,7 +2019,7 @@ static void engine_loop(gmt_engine *E) {
         // completions
         for (EngineSlot &sl : E->slots) {
             if (!sl.busy) continue;
-            hipError_t q = hipEventQuery(sl.run.ev[4]);
+            hipError_t q = hipEventQuery(sl.run.ev[kEvDone]);
             if (q == hipErrorNotReady) continue;
             lk.unlock();
             gmt_status cs = (q == hipSuccess) ? batch_collect(sl.run, sl.results.data(), sl.stream)

@@ -37,6 +37,7 @@
 
 #include "gmt_build.hpp"
 #include "gmt_dev.hpp"
+#include "gmt_dubins.hpp"
 
 #define GMT_PATH_INLINE 500
 
@@ -58,8 +59,9 @@ namespace gmt {
 struct RoadmapDev {
     int n, dim, kind;
     double r, R2;
+    double rho;      // Dubins airplane: turning radius
     const float *s;  // SoA [dim][n]
-    const float4 *s8;  // double integrator: node v's state in s8[2v], s8[2v + 1]
+    const float4 *s8;  // double integrator / Dubins: node v's state in s8[2v] (, s8[2v + 1])
     const int *in_ptr;
     const unsigned int *in_rec;  // per in-edge: edge cost (low, high words), column
     const double *in_tau;  // double integrator only
@@ -101,6 +103,7 @@ struct ProbDev {
     int pd, m, box_off, goal_dims;
     int max_iters, traj_points;
     double inv_k1;  // 1 / (traj_points - 1), the step of normalised time
+    double step_d;  // Dubins airplane: largest spacing of check points along a path
     long long step_q;
     double lambda, delta, goal_r2q;
     int x_q[6];     // x_init on the grid (Euclidean test) ...
@@ -177,6 +180,9 @@ __device__ __forceinline__ void sample_d(const RoadmapDev &R, int v, double *x) 
     if (DIM == 6) {
         const float4 a = R.s8[2 * v], b = R.s8[2 * v + 1];
         x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w, x[4] = b.x, x[5] = b.y;
+    } else if (DIM == 4) {
+        const float4 a = R.s8[2 * v];
+        x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w;
     } else {
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[a] = (double)R.s[(size_t)a * R.n + v];
@@ -273,6 +279,37 @@ __device__ __noinline__ void root_edge_cost(const ProbDev &P, int v, double &J, 
     di_cost(make_pair(P.x_d, xs), J, tau);
 }
 
+// Dubins airplane cost of the root edge x_init -> v (out of line likewise)
+__device__ __noinline__ double root_edge_cost_dubins(const ProbDev &P, int v) {
+    double xs[4];
+    sample_d<4>(P.rm, v, xs);
+    DubinsPath path;
+    return dubins_cost(P.x_d, xs, P.rm.rho, path);
+}
+
+// Dubins airplane lazy check of y -> x by the CL lanes of a group: lane lg
+// tests points lg, lg + CL, ... of the edge's K points against the unit
+// cube and every staged box (exact doubles of the FP32 boxes).  Out of line:
+// its trigonometry would crowd the expansion loop's registers.
+__device__ __noinline__ bool dubins_lane_hits(const ProbDev &P, const double *ys, const double *xs, int lg, int CL,
+                                              const float *fbox) {
+    DubinsPath path;
+    const double L = dubins_cost(ys, xs, P.rm.rho, path);
+    const int K = dubins_points(L, P.step_d);
+    for (int k = lg; k < K; k += CL) {
+        double p[3];
+        dubins_point(ys, xs, path, k, K, P.rm.rho, p);
+        if (p[0] < 0.0 || p[0] > 1.0 || p[1] < 0.0 || p[1] > 1.0 || p[2] < 0.0 || p[2] > 1.0) return true;
+        for (int b = 0; b < P.m; ++b) {
+            const float *bx = fbox + b * 6;
+            if (p[0] >= (double)bx[0] && p[0] <= (double)bx[3] && p[1] >= (double)bx[1] && p[1] <= (double)bx[4] &&
+                p[2] >= (double)bx[2] && p[2] <= (double)bx[5])
+                return true;
+        }
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 // connect phase helpers: groups of CL lanes
 // ---------------------------------------------------------------------------
@@ -319,6 +356,8 @@ template <int KIND>
 __device__ __forceinline__ void load_end(const RoadmapDev &R, int x, CandEnd &c) {
     if (KIND == 0) {
         for (int a = 0; a < 3; ++a) c.xq[a] = a < R.dim ? (int)((double)R.s[(size_t)a * R.n + x] * GMT_QS) : 0;
+    } else if (KIND == 2) {
+        sample_d<4>(R, x, c.xs);
     } else {
         sample_d<6>(R, x, c.xs);
     }
@@ -346,6 +385,8 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, c
                 if (!aabb_disjoint(yq, c.xq, P.pd, lo, hi) && segment_hits_box(yq, c.xq, P.pd, K1, lo, hi))
                     hit = true;
             }
+        } else if (KIND == 2) {
+            hit = dubins_lane_hits(P, ys, c.xs, lg, CL, (const float *)lbox);
         } else {
             const float *fbox = (const float *)lbox;
             DiPair d = make_pair(ys, c.xs);
@@ -606,6 +647,12 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         d2 += dd * dd;
                     }
                     cand = (double)d2 < R.R2;
+                } else if (KIND == 2) {
+                    // the path is at least as long as the straight segment
+                    double e2 = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) e2 += ((double)pf[a] - P.x_d[a]) * ((double)pf[a] - P.x_d[a]);
+                    cand = e2 < R.r * R.r * (1.0 + 1e-9);
                 } else {
                     double xs[6];
 #pragma unroll
@@ -636,6 +683,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     }
                     cost[v] = sqrt((double)d2) * GMT_INV_QS;
                     ok = true;
+                } else if (KIND == 2) {
+                    const double c = root_edge_cost_dubins(P, v);
+                    ok = c < R.r;
+                    if (ok) cost[v] = c;
                 } else {
                     double J = 0.0, tau = 0.0;
                     root_edge_cost(P, v, J, tau);
@@ -908,6 +959,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 if (ok) {
                     if (KIND == 0) {
                         for (int a = 0; a < R.dim; ++a) yq[a] = (int)((double)R.s[(size_t)a * n + by] * GMT_QS);
+                    } else if (KIND == 2) {
+                        sample_d<4>(R, by, ys);
                     } else {
                         sample_d<6>(R, by, ys);
                         tau = R.in_tau[be];

@@ -32,7 +32,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 GMT_OK, GMT_NO_PATH, GMT_ETIMEOUT = 0, 1, 2
 GMT_EINVAL, GMT_ENOMEM, GMT_EDEVICE, GMT_EBUSY = -1, -2, -3, -4
-GMT_COST_EUCLIDEAN, GMT_COST_DOUBLE_INTEGRATOR = 0, 1
+GMT_COST_EUCLIDEAN, GMT_COST_DOUBLE_INTEGRATOR, GMT_COST_DUBINS_AIRPLANE = 0, 1, 2
 STATUS_NAMES = {0: "GMT_OK", 1: "GMT_NO_PATH", 2: "GMT_ETIMEOUT", -1: "GMT_EINVAL",
                 -2: "GMT_ENOMEM", -3: "GMT_EDEVICE", -4: "GMT_EBUSY"}
 
@@ -40,7 +40,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 # symbols the header declares (checked by the CPU tests)
-EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "gmt_roadmap_info",
+EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_build_neighbors_ex", "gmt_sample_halton", "gmt_roadmap_from_csr", "gmt_roadmap_info",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_noalloc", "gmt_plan_batch",
            "gmt_last_work", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
@@ -48,6 +48,12 @@ EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_roadmap_from_csr", "
            "gmt_batch_prepare", "gmt_batch_run", "gmt_batch_free",
            "gmt_autotune", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
            "gmt_tune_load", "gmt_shutdown", "gmt_last_error", "gmt_version", "gmt_steady_ns"]
+
+
+def pdim_of(kind: int, dim: int) -> int:
+    """Position dimensions (those boxes and the goal constrain): all of a
+    Euclidean state, the first 3 of a double-integrator or Dubins state."""
+    return dim if kind == GMT_COST_EUCLIDEAN else 3
 
 
 class GmtError(RuntimeError):
@@ -83,6 +89,10 @@ class gmt_allocator(C.Structure):
     _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)),
                 ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)),
                 ("ctx", C.c_void_p)]
+
+
+class gmt_cost_params(C.Structure):
+    _fields_ = [("turn_radius", C.c_double)]
 
 
 class gmt_goal(C.Structure):
@@ -194,6 +204,8 @@ def lib():
             P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
             L.gmt_set_allocator.argtypes = [C.POINTER(gmt_allocator)]
             L.gmt_build_neighbors.argtypes = [P, i32, i32, i32, f64, P, C.POINTER(P)]
+            L.gmt_build_neighbors_ex.argtypes = [P, i32, i32, i32, f64, C.POINTER(gmt_cost_params), P, C.POINTER(P)]
+            L.gmt_sample_halton.argtypes = [i32, i32, i32, i64, P, i32, P, C.POINTER(i64), P]
             L.gmt_roadmap_from_csr.argtypes = [P, i32, i32, i32, f64, P, P, P, P, P, C.POINTER(P)]
             L.gmt_roadmap_info.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                            C.POINTER(i64)]
@@ -364,24 +376,47 @@ class Roadmap:
     close = free
 
     def __del__(self):  # pragma: no cover - interpreter shutdown order
-        if sys.is_finalizing():
-            return  # closed by the exit handler, or left to the process exit
         try:
+            if sys.is_finalizing():
+                return  # closed by the exit handler, or left to the process exit
             self.free()
         except Exception:
             pass
 
 
-def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None) -> Roadmap:
-    """samples: CUDA float32 tensor [dim][n] (SoA) on the 2^-20 grid."""
+def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None, turn_radius=None) -> Roadmap:
+    """samples: CUDA float32 tensor [dim][n] (SoA) on the 2^-20 grid;
+    turn_radius: the Dubins airplane's (through gmt_build_neighbors_ex)."""
     import torch
     assert samples.is_cuda and samples.dtype == torch.float32 and samples.dim() == 2
     s = samples.contiguous()
     dim, n = int(s.shape[0]), int(s.shape[1])
     h = C.c_void_p()
-    _check(lib().gmt_build_neighbors(s.data_ptr(), n, dim, int(kind), float(r_n), _stream(stream),
-                                     C.byref(h)), "gmt_build_neighbors")
+    if turn_radius is None:
+        _check(lib().gmt_build_neighbors(s.data_ptr(), n, dim, int(kind), float(r_n), _stream(stream),
+                                         C.byref(h)), "gmt_build_neighbors")
+    else:
+        prm = gmt_cost_params(float(turn_radius))
+        _check(lib().gmt_build_neighbors_ex(s.data_ptr(), n, dim, int(kind), float(r_n), C.byref(prm),
+                                            _stream(stream), C.byref(h)), "gmt_build_neighbors_ex")
     return Roadmap(h.value, n, dim, int(kind), float(r_n))
+
+
+def gmt_sample_halton(n: int, dim: int, kind: int, first: int = 1, boxes=None, out=None, stream=None):
+    """Halton sample set on the device: returns (CUDA float32 [dim][n], next
+    index).  `boxes` host [m][2*pdim]; `out` an optional [dim][n] tensor."""
+    import torch
+    pd = pdim_of(kind, dim)
+    bx = _host_f32(boxes if boxes is not None else np.zeros((0, 2 * pd), np.float32)).reshape(-1)
+    m = int(bx.size // (2 * pd)) if bx.size else 0
+    if out is None:
+        out = torch.empty((dim, max(n, 0)), dtype=torch.float32, device=torch.device("cuda", torch.cuda.current_device()))
+    assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= dim * max(n, 0)
+    nxt = C.c_int64()
+    _check(lib().gmt_sample_halton(int(n), int(dim), int(kind), int(first), bx.ctypes.data if m else None, m,
+                                   out.data_ptr() if n > 0 else None, C.byref(nxt), _stream(stream)),
+           "gmt_sample_halton")
+    return out, int(nxt.value)
 
 
 def gmt_roadmap_from_csr(samples, kind: int, r_n: float, row_ptr, col, cost, tau=None,
@@ -439,7 +474,7 @@ def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_p
     import torch
     xi = _host_f32(x_init)
     bx = _host_f32(boxes).reshape(-1)
-    pd = 3 if rm.kind == GMT_COST_DOUBLE_INTEGRATOR else rm.dim
+    pd = pdim_of(rm.kind, rm.dim)
     m = int(bx.size // (2 * pd)) if bx.size else 0
     N = rm.n + 1
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -475,7 +510,7 @@ def gmt_plan_noalloc(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opt
             raise ValueError("gmt_plan_noalloc needs contiguous device arrays of n+1 entries (%s)" % dt)
     xi = _host_f32(x_init)
     bx = _host_f32(boxes).reshape(-1)
-    pd = 3 if rm.kind == GMT_COST_DOUBLE_INTEGRATOR else rm.dim
+    pd = pdim_of(rm.kind, rm.dim)
     m = int(bx.size // (2 * pd)) if bx.size else 0
     path = np.zeros(path_cap, np.int32)
     plen = C.c_int32()
@@ -519,7 +554,7 @@ class PreparedBatch:
         for j, q in enumerate(queries):
             xi = _host_f32(q.x_init)
             bx = _host_f32(q.boxes).reshape(-1)
-            pd = 3 if q.roadmap.kind == GMT_COST_DOUBLE_INTEGRATOR else q.roadmap.dim
+            pd = pdim_of(q.roadmap.kind, q.roadmap.dim)
             m = int(bx.size // (2 * pd)) if bx.size else 0
             path = np.zeros(path_cap, np.int32)
             self.keep += [xi, bx]
@@ -588,9 +623,9 @@ class GraphBatch(PreparedBatch):
             self.handle = C.c_void_p(None)
 
     def __del__(self):  # pragma: no cover
-        if sys.is_finalizing():
-            return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass
@@ -668,7 +703,7 @@ class Engine:
     def submit(self, q: BatchQuery, path_cap: int = 512) -> int:
         xi = _host_f32(q.x_init)
         bx = _host_f32(q.boxes).reshape(-1)
-        pd = 3 if q.roadmap.kind == GMT_COST_DOUBLE_INTEGRATOR else q.roadmap.dim
+        pd = pdim_of(q.roadmap.kind, q.roadmap.dim)
         m = int(bx.size // (2 * pd)) if bx.size else 0
         p = gmt_problem()
         p.roadmap = q.roadmap.handle
@@ -731,9 +766,9 @@ class Engine:
             self.handle = C.c_void_p(None)
 
     def __del__(self):  # pragma: no cover
-        if sys.is_finalizing():
-            return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass

@@ -150,9 +150,9 @@ class Sampler:
             self.handle = C.c_void_p(None)
 
     def __del__(self):  # pragma: no cover
-        if sys.is_finalizing():
-            return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass
