@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define GMT_GRID (1.0 / 1048576.0) /* coordinate quantum, 2^-20 */
-#define GMT_MAX_BOXES 2048         /* boxes per problem, staged in LDS (<= 48 KB) */
+#define GMT_MAX_BOXES 8192         /* boxes per problem: up to 64 staged in LDS, more culled by a grid */
 #define GMT_MAX_DIM 6
 
 typedef enum {

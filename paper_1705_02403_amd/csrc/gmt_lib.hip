@@ -792,16 +792,58 @@ static std::vector<WsBlock *> g_ws;
 
 // bytes of one query's workspace over N nodes (tree arrays included when the
 // caller does not supply them)
-static size_t qws_bytes(int N, bool own_tree) {
+// Box grid of a query (queries with more than kGridMinBoxes boxes): kGridCells
+// cells per position axis, each listing the boxes that overlap it.
+static const int kGridMinBoxes = 64;
+static const int kGridCells = 16;
+
+struct GridShape {
+    int G = 0;              // cells per axis (0: no grid)
+    int ncell = 0;
+    long long entries = 0;  // listed (cell, box) pairs
+};
+
+// the device's cell of a grid coordinate, clamped to the grid
+static int grid_axis_host(long long q, int G) {
+    long long c = (q * G) >> 20;
+    return (int)(c < 0 ? 0 : (c >= G ? G - 1 : c));
+}
+
+static GridShape grid_shape(const float *boxes, int m, int pd) {
+    GridShape g;
+    if (m <= kGridMinBoxes) return g;
+    g.G = kGridCells;
+    g.ncell = pd == 2 ? g.G * g.G : g.G * g.G * g.G;
+    for (int b = 0; b < m; ++b) {
+        long long cells = 1;
+        for (int a = 0; a < pd; ++a) {
+            // (coordinates off the grid or out of range are rejected when the
+            // query is staged; here they only must not overflow)
+            const double flo = boxes[(size_t)b * 2 * pd + a], fhi = boxes[(size_t)b * 2 * pd + pd + a];
+            const long long lo = std::isfinite(flo) ? std::llround(std::fmax(-4.0, std::fmin(4.0, flo)) * GMT_QS) : 0;
+            const long long hi = std::isfinite(fhi) ? std::llround(std::fmax(-4.0, std::fmin(4.0, fhi)) * GMT_QS) : 0;
+            const int c0 = grid_axis_host(lo, g.G), c1 = grid_axis_host(hi, g.G);
+            cells *= c1 >= c0 ? c1 - c0 + 1 : 0;
+        }
+        g.entries += cells;
+    }
+    return g;
+}
+
+static size_t qws_bytes(int N, bool own_tree, const GridShape &g = GridShape()) {
     // control block, states, group and open lists (two each), candidate and
     // goal-hit lists, root-edge arrival times
     size_t b = al256(sizeof(Ctl)) + al256((size_t)N) + 2 * al256(8 * (size_t)N) + 2 * al256(4 * (size_t)N) +
                al256(8 * (size_t)N);
     if (own_tree) b += al256(8 * (size_t)N) + 3 * al256(4 * (size_t)N);
+    if (g.G > 0)
+        b += al256(4 * ((size_t)g.ncell + 1)) + al256(4 * (size_t)g.ncell) +
+             al256(4 * (size_t)std::max<long long>(g.entries, 1));
     return b;
 }
 
-static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi, int *ai) {
+static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi, int *ai,
+                      const GridShape &g = GridShape()) {
     auto take = [&](size_t bytes) {
         char *q = p;
         p += al256(bytes);
@@ -818,6 +860,12 @@ static void qws_carve(char *p, int N, QWs &w, double *cost, int *parent, int *gi
     w.parent = parent ? parent : (int *)take(4 * (size_t)N);
     w.gi = gi ? gi : (int *)take(4 * (size_t)N);
     w.ai = ai ? ai : (int *)take(4 * (size_t)N);
+    w.gstart = w.gcur = w.gids = nullptr;
+    if (g.G > 0) {
+        w.gstart = (int *)take(4 * ((size_t)g.ncell + 1));
+        w.gcur = (int *)take(4 * (size_t)g.ncell);
+        w.gids = (int *)take(4 * (size_t)std::max<long long>(g.entries, 1));
+    }
 }
 
 static gmt_status ws_acquire(size_t bytes, int teams, hipStream_t s, WsBlock **out) {
@@ -966,6 +1014,8 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
         P.goal_q[a] = (int)((double)g.center[a] * GMT_QS);
     }
     P.goal_r2q = (double)g.radius * (double)g.radius * GMT_Q2;
+    P.gG = q.m > kGridMinBoxes ? kGridCells : 0;
+    P.gbox = nullptr;
     for (int b = 0; b < q.m; ++b) {
         const float *bx = q.boxes + (size_t)b * 2 * pd;
         bool inside = true;
@@ -1302,18 +1352,23 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     }
     size_t total_boxes = 0, ws_bytes = 0;
     std::vector<size_t> ws_off(count);
+    std::vector<GridShape> grids(count);
     r.box_words = 1;
     for (int j = 0; j < count; ++j) {
         const gmt_problem &pr = problems[r.order[j]];
         if (pr.m < 0 || pr.m > GMT_MAX_BOXES)
             return fail(GMT_EINVAL, "problem %d: box count %d outside [0, %d]", r.order[j], pr.m, GMT_MAX_BOXES);
-        const int words = pr.m * 2 * pdim_of(pr.roadmap->kind, pr.roadmap->dim);
-        r.box_words = std::max(r.box_words, words);
+        const int pd = pdim_of(pr.roadmap->kind, pr.roadmap->dim);
+        const int words = pr.m * 2 * pd;
+        if (pr.m > 0 && !pr.boxes) return fail(GMT_EINVAL, "problem %d: null boxes", r.order[j]);
+        grids[j] = grid_shape(pr.boxes, pr.m, pd);
+        // only queries without a grid stage their boxes in LDS
+        if (grids[j].G == 0) r.box_words = std::max(r.box_words, words);
         total_boxes += (size_t)words;
         const gmt_result *rr = results ? &results[r.order[j]] : nullptr;
         const bool own = !(rr && rr->d_parent && rr->d_cost && rr->d_group_iter && rr->d_added_iter);
         ws_off[j] = ws_bytes;
-        ws_bytes += qws_bytes(pr.roadmap->n + 1, own);
+        ws_bytes += qws_bytes(pr.roadmap->n + 1, own, grids[j]);
     }
     const int nmax = std::max(r.knmax[0], std::max(r.knmax[1], r.knmax[2]));
     const int kind0 = r.kcount[1] > 0 ? GMT_COST_DOUBLE_INTEGRATOR
@@ -1365,9 +1420,13 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
             const bool own = !(rr && rr->d_parent && rr->d_cost && rr->d_group_iter && rr->d_added_iter);
             char *base = (char *)r.w->mem.p + ws_off[j];
             if (own)
-                qws_carve(base, pr.roadmap->n + 1, P[j].w, nullptr, nullptr, nullptr, nullptr);
+                qws_carve(base, pr.roadmap->n + 1, P[j].w, nullptr, nullptr, nullptr, nullptr, grids[j]);
             else
-                qws_carve(base, pr.roadmap->n + 1, P[j].w, rr->d_cost, rr->d_parent, rr->d_group_iter, rr->d_added_iter);
+                qws_carve(base, pr.roadmap->n + 1, P[j].w, rr->d_cost, rr->d_parent, rr->d_group_iter, rr->d_added_iter,
+                          grids[j]);
+            // the query's boxes in the device copy of the staging block
+            P[j].gbox = (const int *)((char *)r.w->stage_d.p + 256 + sizeof(ProbDev) * count) + off;
+            P[j].gcap = (int)std::min<long long>(grids[j].entries, 0x7fffffff);
             off += P[j].m * 2 * P[j].pd;
         }
     }
@@ -1566,7 +1625,8 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     const size_t stage_bytes = al256(256 + sizeof(ProbDev) + sizeof(int) * (size_t)words);
     const size_t res_off = stage_bytes, tctl_off = res_off + al256(sizeof(Result));
     const size_t ws_off = tctl_off + al256(sizeof(TeamCtl));
-    const size_t need = ws_off + qws_bytes(N, false);
+    const GridShape grid = (m > 0 && boxes) ? grid_shape(boxes, m, pd) : GridShape();
+    const size_t need = ws_off + qws_bytes(N, false, grid);
     if (need > (size_t)GMT_NOALLOC_SCRATCH_BYTES)
         return fail(GMT_EINVAL, "query needs %zu scratch bytes (n = %d, m = %d); the static array holds %zu", need,
                     rm->n, m, (size_t)GMT_NOALLOC_SCRATCH_BYTES);
@@ -1586,7 +1646,8 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     pr.edge_step = 0.0;
     if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || bo.plan.threads == 0) tune_apply(&pr, 1, true, bo);
     const int cl = lanes_of(bo.plan.lanes), threads = threads_of(bo.plan.threads);
-    const int team_wgs = single_team_wgs(bo.plan.team_wgs, rm->kind, std::max(words, 1), rm->n, cl, threads);
+    const int team_wgs = single_team_wgs(bo.plan.team_wgs, rm->kind, grid.G > 0 ? 1 : std::max(words, 1), rm->n, cl,
+                                         threads);
 
     std::lock_guard<std::mutex> lk(g_na_mu);
     char *base = nullptr;
@@ -1597,15 +1658,17 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     ProbDev &P = *(ProbDev *)(g_na_stage + 256);
     QueryIn q{rm, x_init, goal, boxes, m, lambda};
     TRY(stage_query(q, bo.plan, P, (int *)(g_na_stage + 256 + sizeof(ProbDev)), 0));
-    qws_carve(base + ws_off, N, P.w, d_cost, d_parent, d_group_iter, d_added_iter);
+    qws_carve(base + ws_off, N, P.w, d_cost, d_parent, d_group_iter, d_added_iter, grid);
+    P.gbox = (const int *)(base + 256 + sizeof(ProbDev));
+    P.gcap = (int)std::min<long long>(grid.entries, 0x7fffffff);
     TeamCtl *tctl = (TeamCtl *)(base + tctl_off);
     Result *res_d = (Result *)(base + res_off);
     HIPCHK(hipMemcpyAsync(base, g_na_stage, 256 + sizeof(ProbDev) + sizeof(int) * (size_t)words,
                           hipMemcpyHostToDevice, s));
     // barrier arrivals, generation and fault flag start at zero on every call
     k_fill_int<<<1, 64, 0, s>>>((int *)tctl, (int)(sizeof(TeamCtl) / sizeof(int)), 0);
-    TRY(launch_plan_kind(base, tctl, res_d, rm->kind, 0, 1, 1, rm->n, 1, team_wgs, std::max(words, 1), rm->kind,
-                         cl, threads, nullptr, nullptr, s));
+    TRY(launch_plan_kind(base, tctl, res_d, rm->kind, 0, 1, 1, rm->n, 1, team_wgs,
+                         grid.G > 0 ? 1 : std::max(words, 1), rm->kind, cl, threads, nullptr, nullptr, s));
     HIPCHK(hipMemcpyAsync(&g_na_res, res_d, sizeof(Result), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Result &res = g_na_res;
@@ -2008,7 +2071,8 @@ struct gmt_engine {
 
 static size_t engine_req_bytes(const gmt_problem &p) {
     const int pd = pdim_of(p.roadmap->kind, p.roadmap->dim);
-    return qws_bytes(p.roadmap->n + 1, true) + sizeof(ProbDev) + sizeof(Result) + 4 * (size_t)p.m * 2 * pd;
+    const GridShape g = (p.m > 0 && p.boxes) ? grid_shape(p.boxes, p.m, pd) : GridShape();
+    return qws_bytes(p.roadmap->n + 1, true, g) + sizeof(ProbDev) + sizeof(Result) + 4 * (size_t)p.m * 2 * pd;
 }
 
 static void engine_loop(gmt_engine *E) {

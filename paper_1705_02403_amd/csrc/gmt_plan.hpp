@@ -95,6 +95,9 @@ struct QWs {
     int *gi;
     int *ai;
     double *aux;        // per node: arrival time of the root edge (iteration 0)
+    // box grid (queries with many boxes): gstart[ncell + 1] list offsets,
+    // gcur[ncell] fill cursors, gids the box indices listed per cell
+    int *gstart, *gcur, *gids;
 };
 
 struct ProbDev {
@@ -109,6 +112,12 @@ struct ProbDev {
     int x_q[6];     // x_init on the grid (Euclidean test) ...
     double x_d[6];  // ... and as doubles (double-integrator test)
     int goal_q[6];
+    // box culling: gG cells per position axis (0: every check tests every
+    // box, read from LDS); with gG > 0 the boxes are read from gbox (the
+    // staged grid integers in device memory) through the per-cell lists
+    int gG;
+    int gcap;  // entries the gids array holds
+    const int *gbox;
 };
 
 // work counters of one query (exact): out-edges walked, in-edges scanned,
@@ -311,6 +320,178 @@ __device__ __noinline__ bool dubins_lane_hits(const ProbDev &P, const double *ys
 }
 
 // ---------------------------------------------------------------------------
+// box grid: a uniform grid of gG cells per position axis over [0,1]^pd; each
+// cell lists the boxes that overlap it (a box [lo, hi] is listed in cells
+// floor(lo gG) .. floor(hi gG) per axis, clamped to the grid).  A point of
+// [0,1]^pd lies in cell floor(p gG) per axis, and any closed box containing
+// it is listed there, so testing that cell's boxes decides exactly what
+// testing every box decides.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int grid_axis_q(long long q, int G) {
+    long long c = (q * G) >> 20;
+    return (int)(c < 0 ? 0 : (c >= G ? G - 1 : c));
+}
+
+// Build the query's lists; every thread of the team calls it.
+__device__ void build_box_grid(const Team &t, const ProbDev &P) {
+    const QWs &w = P.w;
+    const int G = P.gG, pd = P.pd;
+    const int ncell = pd == 2 ? G * G : G * G * G;
+    for (int c = t.rank; c <= ncell; c += t.size) w.gstart[c] = 0;
+    for (int c = t.rank; c < ncell; c += t.size) w.gcur[c] = 0;
+    team_sync(t);
+    for (int b = t.rank; b < P.m; b += t.size) {
+        const int *bx = P.gbox + b * 2 * pd;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int a = 0; a < pd; ++a) {
+            lo[a] = grid_axis_q(bx[a], G);
+            hi[a] = grid_axis_q(bx[pd + a], G);
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) atomicAdd(&w.gstart[1 + x + G * (y + G * z)], 1);
+    }
+    team_sync(t);
+    if (t.wave == 0) {
+        // inclusive scan of gstart[1 .. ncell], 64 entries per step
+        int carry = 0;
+        for (int c0 = 1; c0 <= ncell; c0 += GMT_WAVE) {
+            const int c = c0 + t.lane;
+            int v = c <= ncell ? w.gstart[c] : 0;
+#pragma unroll
+            for (int off = 1; off < GMT_WAVE; off <<= 1) {
+                const int u = __shfl_up(v, off);
+                if (t.lane >= off) v += u;
+            }
+            if (c <= ncell) w.gstart[c] = v + carry;
+            carry += __shfl(v, GMT_WAVE - 1);
+        }
+    }
+    team_sync(t);
+    for (int b = t.rank; b < P.m; b += t.size) {
+        const int *bx = P.gbox + b * 2 * pd;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int a = 0; a < pd; ++a) {
+            lo[a] = grid_axis_q(bx[a], G);
+            hi[a] = grid_axis_q(bx[pd + a], G);
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const int cell = x + G * (y + G * z);
+                    const int slot = w.gstart[cell] + atomicAdd(&w.gcur[cell], 1);
+                    if (slot < P.gcap) w.gids[slot] = b;  // the host sized the lists exactly
+                }
+    }
+    team_sync(t);
+}
+
+// Is the grid point q (grid integers, inside [0, 2^20]^pd) in a box of its cell?
+__device__ __forceinline__ bool grid_point_hits_q(const ProbDev &P, const int *q) {
+    const int G = P.gG, pd = P.pd;
+    int cell = 0, mul = 1;
+    for (int a = 0; a < pd; ++a) {
+        cell += grid_axis_q(q[a], G) * mul;
+        mul *= G;
+    }
+    for (int e = P.w.gstart[cell], e1 = min(P.w.gstart[cell + 1], P.gcap); e < e1; ++e) {
+        const int *bx = P.gbox + P.w.gids[e] * 2 * pd;
+        bool in = true;
+        for (int a = 0; a < pd; ++a) in = in && bx[a] <= q[a] && q[a] <= bx[pd + a];
+        if (in) return true;
+    }
+    return false;
+}
+
+// The same for a point given exactly as num[a] / den grid units (den > 0,
+// 0 <= num[a] <= den 2^20): the Euclidean check's scaled points.
+__device__ __forceinline__ bool grid_point_hits_scaled(const ProbDev &P, const long long *num, long long den) {
+    const int G = P.gG, pd = P.pd;
+    int cell = 0, mul = 1;
+    for (int a = 0; a < pd; ++a) {
+        long long c = (num[a] * G) / (den << 20);
+        cell += (int)(c >= G ? G - 1 : c) * mul;
+        mul *= G;
+    }
+    for (int e = P.w.gstart[cell], e1 = min(P.w.gstart[cell + 1], P.gcap); e < e1; ++e) {
+        const int *bx = P.gbox + P.w.gids[e] * 2 * pd;
+        bool in = true;
+        for (int a = 0; a < pd; ++a) in = in && den * bx[a] <= num[a] && num[a] <= den * bx[pd + a];
+        if (in) return true;
+    }
+    return false;
+}
+
+// ... and for a position of the double integrator or the Dubins airplane
+// (doubles in [0,1]^3; the boxes' grid integers times 2^-20 are exact)
+__device__ __forceinline__ bool grid_point_hits_d(const ProbDev &P, const double *p) {
+    const int G = P.gG;
+    int cell = 0, mul = 1;
+    for (int a = 0; a < 3; ++a) {
+        int c = (int)floor(p[a] * (double)G);
+        cell += (c < 0 ? 0 : (c >= G ? G - 1 : c)) * mul;
+        mul *= G;
+    }
+    for (int e = P.w.gstart[cell], e1 = min(P.w.gstart[cell + 1], P.gcap); e < e1; ++e) {
+        const int *bx = P.gbox + P.w.gids[e] * 6;
+        if (p[0] >= (double)bx[0] * GMT_INV_QS && p[0] <= (double)bx[3] * GMT_INV_QS &&
+            p[1] >= (double)bx[1] * GMT_INV_QS && p[1] <= (double)bx[4] * GMT_INV_QS &&
+            p[2] >= (double)bx[2] * GMT_INV_QS && p[2] <= (double)bx[5] * GMT_INV_QS)
+            return true;
+    }
+    return false;
+}
+
+// Lazy check through the grid, points spread over the CL lanes of a group:
+// Euclidean points K1 y + k (x - y) (scaled by K1), k = 0..K1; the double
+// integrator's traj_points times; the Dubins airplane's points along the path.
+// Out of line: used only for queries with many boxes.
+template <int KIND>
+__device__ __noinline__ bool grid_lane_hits(const ProbDev &P, const int *yq, const double *ys, double tau,
+                                            const int *xq, const double *xs, int lg, int CL) {
+    if (KIND == 0) {
+        const int pd = P.pd;
+        long long d2 = 0;
+        for (int a = 0; a < pd; ++a) {
+            const long long dd = (long long)xq[a] - yq[a];
+            d2 += dd * dd;
+        }
+        const long long K1 = segment_parts(d2, P.step_q);
+        for (long long k = lg; k <= K1; k += CL) {
+            long long num[3] = {0, 0, 0};
+            for (int a = 0; a < pd; ++a) {
+                num[a] = K1 * yq[a] + k * ((long long)xq[a] - yq[a]);
+                if (num[a] < 0 || num[a] > (K1 << 20)) return true;
+            }
+            if (grid_point_hits_scaled(P, num, K1)) return true;
+        }
+        return false;
+    }
+    DubinsPath path;
+    DiPair d;
+    int K;
+    if (KIND == 2) {
+        K = dubins_points(dubins_cost(ys, xs, P.rm.rho, path), P.step_d);
+    } else {
+        d = make_pair(ys, xs);
+        K = P.traj_points;
+    }
+    for (int k = lg; k < K; k += CL) {
+        double p[3];
+        if (KIND == 2) {
+            dubins_point(ys, xs, path, k, K, P.rm.rho, p);
+        } else if (k == K - 1) {
+            p[0] = xs[0], p[1] = xs[1], p[2] = xs[2];
+        } else {
+            di_point(ys, d, tau, (double)k * P.inv_k1, p);
+        }
+        if (p[0] < 0.0 || p[0] > 1.0 || p[1] < 0.0 || p[1] > 1.0 || p[2] < 0.0 || p[2] > 1.0) return true;
+        if (grid_point_hits_d(P, p)) return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
 // connect phase helpers: groups of CL lanes
 // ---------------------------------------------------------------------------
 // one stage of the group reductions below
@@ -372,7 +553,9 @@ __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, c
                                                 double tau, const CandEnd &c, const int *lbox) {
     const int lg = lane_id() & (CL - 1);
     bool hit = false;
-    if (active) {
+    if (active && P.gG > 0) {
+        hit = grid_lane_hits<KIND>(P, yq, ys, tau, c.xq, c.xs, lg, CL);
+    } else if (active) {
         if (KIND == 0) {
             long long d2 = 0;
             for (int a = 0; a < P.pd; ++a) {
@@ -605,6 +788,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         }
     }
     team_sync(t);  // counters are zero before the appends below
+    if (P.gG > 0) build_box_grid(t, P);
 
     // ---- iteration 0: the root x_init is the only open node (lines 1-9) ----
     // (a) every node: obstacle and goal bits, tree arrays reset; samples that
@@ -632,7 +816,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 }
             }
             // grid coordinates are exact in FP32, as are the staged boxes
-            const bool dead = node_in_boxes<KIND>(q, pf, lbox, P.m, P.pd);
+            const bool dead = P.gG > 0 ? grid_point_hits_q(P, q) : node_in_boxes<KIND>(q, pf, lbox, P.m, P.pd);
             st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
             cost[v] = __longlong_as_double(COST_INF_BITS);
             if (OC) w.cost[v] = __longlong_as_double(COST_INF_BITS);
@@ -1102,7 +1286,8 @@ __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ pr
         }
         if (job >= count) return;
         const ProbDev &P = probs[job];
-        const int words = P.m * 2 * P.pd;
+        // grid queries read their boxes from device memory
+        const int words = P.gG > 0 ? 0 : P.m * 2 * P.pd;
         if (KIND == 0) {
             for (int k = threadIdx.x; k < words && k < box_words; k += blockDim.x) lbox[k] = boxes[P.box_off + k];
         } else {

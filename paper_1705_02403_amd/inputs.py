@@ -329,6 +329,68 @@ def problem_dubins(seed: int, n: int = 5000, sample_seed: Optional[int] = None, 
     return dubins_problem(seed, dubins_samples(ss, n), m=m, lam=lam, sample_seed=ss)
 
 
+def draw_trees(rng: np.random.Generator, trees: int, m: int, start_q: np.ndarray, goal_q: np.ndarray,
+               goal_radius: float, clear: float = 0.1) -> np.ndarray:
+    """A forest of `trees` trees described by m boxes in all (Section V-B
+    varies the resolution of the obstacle representation, not the obstacles):
+    each tree is a trunk (footprint half-width U[0.008, 0.02], height
+    U[0.3, 0.6]) under a cone canopy (base radius U[0.04, 0.08], height
+    U[0.15, 0.3]).  A tree given one box is its bounding box; with k >= 2 boxes
+    it is its trunk plus k - 1 slabs that cover the cone (slab j spans the j-th
+    of k - 1 equal height bands, as wide as the cone at the band's bottom).
+    The m boxes are spread over the trees as evenly as possible.  Trees whose
+    bounding box comes within `clear` of the start's planar position, or that
+    touch the goal ball, are redrawn."""
+    out = []
+    per = [m // trees + (1 if t < m % trees else 0) for t in range(trees)]
+    for t in range(trees):
+        while True:
+            w = rng.uniform(0.008, 0.02)
+            ht = rng.uniform(0.3, 0.6)
+            R = rng.uniform(0.04, 0.08)
+            hc = rng.uniform(0.15, 0.3)
+            cx = rng.uniform(R, 1.0 - R)
+            cy = rng.uniform(R, 1.0 - R)
+            blo = to_grid(np.array([cx - R, cy - R, 0.0]))
+            bhi = to_grid(np.array([cx + R, cy + R, min(ht + hc, 1.0)]))
+            gap = np.maximum(np.maximum(blo[:2] - start_q[:2], 0), start_q[:2] - bhi[:2]).astype(np.float64)
+            if float(np.sum(gap * gap)) <= (clear * QSCALE) ** 2 or _box_touches_ball(blo, bhi, goal_q, goal_radius):
+                continue
+            break
+        k = per[t]
+        if k == 0:
+            continue
+        if k == 1:
+            out.append(np.concatenate([blo, bhi]))
+            continue
+        out.append(np.concatenate([to_grid(np.array([cx - w, cy - w, 0.0])), to_grid(np.array([cx + w, cy + w, ht]))]))
+        for j in range(k - 1):
+            z0 = ht + hc * j / (k - 1)
+            z1 = ht + hc * (j + 1) / (k - 1)
+            rj = R * (1.0 - j / (k - 1))
+            out.append(np.concatenate([to_grid(np.array([cx - rj, cy - rj, min(z0, 1.0)])),
+                                       to_grid(np.array([cx + rj, cy + rj, min(z1, 1.0)]))]))
+    return np.array(out, dtype=np.int64).reshape(m, 6)
+
+
+def dubins_forest_problem(seed: int, samples: np.ndarray, m: int, trees: int = 150, lam: float = 0.5,
+                          sample_seed: int = 0) -> Problem:
+    """Dubins airplane query in a forest of `trees` trees described by m
+    boxes (the obstacle-count rows of Table III: one forest, finer boxes)."""
+    rng = np.random.default_rng(50_000_017 + int(seed))
+    start_p = np.array(DUBINS_START[:3]) + rng.uniform(-0.03, 0.03, size=3)
+    start_q = np.concatenate([to_grid(start_p), to_grid([DUBINS_START[3]])])
+    goal_q = to_grid(np.array(DUBINS_GOAL))
+    gr = float(np.float32(0.05))
+    # the same forest at every resolution: its own generator, seeded by `seed` only
+    boxes_q = draw_trees(np.random.default_rng(60_000_011 + int(seed)), trees, m, start_q, goal_q, gr)
+    return Problem(kind="dubins", dim=4, pdim=3, samples=samples,
+                   x_init=from_grid(start_q), goal_center=from_grid(goal_q), goal_radius=gr,
+                   boxes=np.ascontiguousarray(from_grid(boxes_q)), lam=float(lam), step=DUBINS_STEP,
+                   traj_points=0, r=DUBINS_RADIUS, seed=int(seed), sample_seed=int(sample_seed),
+                   turn_radius=DUBINS_TURN)
+
+
 def problem_ids(count: int, first: int = 0) -> List[int]:
     return list(range(first, first + count))
 
