@@ -391,6 +391,25 @@ def dubins_forest_problem(seed: int, samples: np.ndarray, m: int, trees: int = 1
                    turn_radius=DUBINS_TURN)
 
 
+def collapse_schedule(seed: int, rate: float, t_max: float, pdim: int = 3, side=(0.05, 0.1)):
+    """Boxes added over time (Section V-C models a collapsing cave as randomly
+    placed boxes added at a rate): a Poisson stream of `rate` boxes per
+    second up to t_max, each with sides U[side] per axis placed uniformly in
+    the unit cube; returns [(time, box [2*pdim])]."""
+    rng = np.random.default_rng(70_000_001 + int(seed))
+    out = []
+    t = 0.0
+    if rate <= 0.0:
+        return out
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > t_max:
+            return out
+        sd = rng.uniform(side[0], side[1], size=pdim)
+        lo = rng.uniform(0.0, 1.0 - sd)
+        out.append((float(t), from_grid(np.concatenate([to_grid(lo), to_grid(lo + sd)]))))
+
+
 def problem_ids(count: int, first: int = 0) -> List[int]:
     return list(range(first, first + count))
 
