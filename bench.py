@@ -81,6 +81,16 @@ def parse():
     ap.add_argument("--learned-train", type=int, default=100000)
     ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--learned-test", type=int, default=200)
+    ap.add_argument("--dubins-queries", type=int, default=512)
+    ap.add_argument("--dubins-latency", type=int, default=100)
+    ap.add_argument("--forest-queries", type=int, default=12)
+    ap.add_argument("--halton-queries", type=int, default=8)
+    ap.add_argument("--replan-scenarios", type=int, default=64)
+    ap.add_argument("--cpu-2d", type=int, default=100, help="single-core oracle latency: 2D problems")
+    ap.add_argument("--cpu-3d", type=int, default=6, help="single-core oracle latency: 3D problems")
+    ap.add_argument("--cpu-di", type=int, default=40, help="single-core oracle latency: 6D problems")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the Dubins, Halton and replanning sections")
     return ap.parse_args()
 
 
@@ -232,6 +242,192 @@ def learned_report(args, torch, gmt, I):
             "note": "end-to-end = sampler inference + neighbour build + plan; uniform draws, "
                     "fallbacks and noise are query-independent and resident (8 pools per n); "
                     "r(n) = 1.75 (16384/n)^(1/6) for every n"}
+
+
+def lat_stats(ms):
+    ms = np.asarray(ms, np.float64)
+    return {"p50_ms": round(float(np.percentile(ms, 50)), 3), "p99_ms": round(float(np.percentile(ms, 99)), 3)}
+
+
+def single_latency(torch, gmt, rm, probs, opts, warm=5):
+    """Wall time of gmt_plan (entry to path on the host) per query."""
+    out, ms = [], []
+    for k, p in enumerate(list(probs[:warm]) + list(probs)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = gmt.gmt_plan(rm, p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, p.pdim), p.boxes, p.lam,
+                           opts, outputs=False)
+        dt = (time.perf_counter() - t) * 1e3
+        if k >= warm:
+            ms.append(dt)
+            out.append(res)
+    return out, ms
+
+
+def batch_rate(torch, gmt, queries, opts, reps=3):
+    """plans/s of one prepared batch (median of `reps` timed runs after one warm-up)."""
+    pb = gmt.PreparedBatch(queries, opts)
+    pb.run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        pb.run()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return len(queries) / float(np.median(ts)), pb.results()
+
+
+def dubins_report(args, torch, gmt, I):
+    """Dubins airplane (Section V-A's third workload): n = 5000 samples, forests
+    of 150 trunks: single-plan latency and batch plans/s; then one forest described by 150 .. 5000 boxes (Table III's obstacle rows)."""
+    dev = torch.device("cuda", 0)
+    n, sets = 5000, 4
+    samples, rms, bms = {}, {}, []
+    gmt.gmt_profile_enable(True)
+    for ss in range(sets):
+        samples[ss] = I.dubins_samples(ss, n)
+        rms[ss] = gmt.gmt_build_neighbors(torch.from_numpy(samples[ss]).to(dev), gmt.GMT_COST_DUBINS_AIRPLANE,
+                                          I.DUBINS_RADIUS, turn_radius=I.DUBINS_TURN)
+        bms.append(gmt.gmt_last_build())
+    gmt.gmt_profile_enable(False)
+    gmt.gmt_profile_read()
+    opts = gmt.make_opts(edge_step=I.DUBINS_STEP)
+    probs = [I.dubins_problem(k, samples[k % sets], sample_seed=k % sets) for k in range(args.dubins_queries)]
+    lat, lres = [], []
+    for ss in range(sets):
+        sub = [p for p in probs if p.sample_seed == ss][:max(args.dubins_latency // sets, 1)]
+        o, m = single_latency(torch, gmt, rms[ss], sub, opts)
+        lat += m
+        lres += o
+    qs = [gmt.BatchQuery(rms[p.sample_seed], p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, 3), p.boxes, p.lam,
+                         p.step) for p in probs]
+    rate, bres = batch_rate(torch, gmt, qs, opts)
+    sweep = []
+    for m in (150, 500, 1500, 5000):
+        fp = [I.dubins_forest_problem(k, samples[0], m) for k in range(args.forest_queries)]
+        o, ms = single_latency(torch, gmt, rms[0], fp, opts, warm=2)
+        fq = [gmt.BatchQuery(rms[0], p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, 3), p.boxes, p.lam, p.step)
+              for p in fp]
+        frate, _ = batch_rate(torch, gmt, fq * max(1, 256 // len(fq)), opts, reps=2)
+        costs = [x.path_cost for x in o if x.status == gmt.GMT_OK]
+        sweep.append(dict(boxes=m, solved="%d/%d" % (len(costs), len(o)), **lat_stats(ms),
+                          batch_plans_per_s=round(frate, 1),
+                          median_cost=round(float(np.median(costs)), 4) if costs else None))
+    for rm in rms.values():
+        rm.free()
+    bk = [b["kernel_ms"] for b in bms[1:]] or [bms[0]["kernel_ms"]]
+    return {"workload": "Dubins airplane n=%d, 150 trunks, turning radius %.2f, r=%.2f, step %.3f, lambda 0.5"
+                        % (n, I.DUBINS_TURN, I.DUBINS_RADIUS, I.DUBINS_STEP),
+            "roadmap_edges": int(bms[0]["edges"]), "build_kernel_ms": round(float(np.median(bk)), 3),
+            "single": dict(queries=len(lat), solved=sum(r.status == gmt.GMT_OK for r in lres), **lat_stats(lat)),
+            "batch": {"queries": len(qs), "plans_per_s": round(rate, 1),
+                      "solved": sum(r.status == gmt.GMT_OK for r in bres)},
+            "obstacle_sweep": sweep,
+            "paper_context": "Table III forest rows on a GTX 980 at n = 5k: 150 / 500 / 1500 / 5000 boxes in "
+                             "7 / 14 / 18 / 26 ms (different forest and hardware)"}
+
+
+def halton_report(args, torch, gmt, I):
+    """Halton sample sets (Section V-A) against uniform ones: 3D workload at
+    n = 16384 (Halton radius vs Theorem 1's), and the double integrator."""
+    from paper_1705_02403_amd import radius as RAD
+    dev = torch.device("cuda", 0)
+    rows = {}
+    probs = [I.problem_3d(k) for k in range(args.halton_queries)]
+    for mode in ("uniform", "halton"):
+        lat, costs, ok, edges, gen_ms = [], [], 0, [], []
+        for p in probs:
+            mu = RAD.free_volume(3, p.boxes)
+            if mode == "halton":
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                x, _ = gmt.gmt_sample_halton(p.n, 3, gmt.GMT_COST_EUCLIDEAN, 1, p.boxes)
+                torch.cuda.synchronize()
+                gen_ms.append((time.perf_counter() - t) * 1e3)
+                r = RAD.halton_radius(3, mu, p.n)
+            else:
+                x = torch.from_numpy(p.samples).to(dev)
+                r = RAD.theorem1_radius(3, mu, p.n)
+            rm = gmt.gmt_build_neighbors(x, gmt.GMT_COST_EUCLIDEAN, r)
+            edges.append(rm.nnz)
+            o, ms = single_latency(torch, gmt, rm, [p], gmt.make_opts(edge_step=p.step), warm=1)
+            lat += ms
+            if o[0].status == gmt.GMT_OK:
+                ok += 1
+                costs.append(o[0].path_cost)
+            rm.free()
+        rows[mode] = dict(solved="%d/%d" % (ok, len(probs)), mean_edges=int(np.mean(edges)),
+                          median_cost=round(float(np.median(costs)), 4) if costs else None, **lat_stats(lat))
+        if gen_ms:
+            rows[mode]["sample_ms"] = round(float(np.median(gen_ms)), 3)
+    return {"workload": "3D, n=16384, 60 boxes: uniform samples at Theorem 1's radius vs Halton samples at "
+                        "the Halton radius (twice a dispersion bound)", "rows": rows}
+
+
+def replan_report(args, torch, gmt, I):
+    """Replanning in a collapsing world (Section V-C): scenarios on one resident
+    double-integrator roadmap, all replanned every 10 ms of world time."""
+    from paper_1705_02403_amd import replan as RP
+    dev = torch.device("cuda", 0)
+    s = I.di_samples(0, 16384)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).to(dev), gmt.GMT_COST_DOUBLE_INTEGRATOR, I.DI_RADIUS)
+    ec = RP.EdgeCosts(rm)
+    plan = RP.library_planner(rm, gmt.make_opts(traj_points=16), 3)
+    out = []
+    for rate in (0.0, 20.0, 50.0):
+        scen = []
+        for k in range(args.replan_scenarios):
+            p = I.di_problem(500 + k, s)
+            scen.append(RP.Scenario(p.x_init, p.goal_center, p.goal_radius, p.boxes,
+                                    I.collapse_schedule(k, rate, 4.0), p.lam))
+        st = RP.Replanner(s, ec, plan, scen, pdim=3, dt=0.01, speed=2.0, t_max=4.0).run()
+        st["boxes_per_s"] = rate
+        out.append(st)
+    rm.free()
+    return {"workload": "6D double integrator n=16384, 40 boxes plus a Poisson collapse, %d scenarios, "
+                        "10 ms ticks, robots fly 2 cost units per second" % args.replan_scenarios, "runs": out}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_latency_report(args):
+    """Single-core oracle latency (the serial FP64 C oracle, one thread) per
+    workload: bounded samples of the 2D, 3D and 6D configurations."""
+    from oracle import oracle as O
+    from paper_1705_02403_amd import inputs as I
+    out = {}
+    for name, make, count in (("2d_n2000", lambda k: I.problem_2d(k), args.cpu_2d),
+                              ("3d_n16384", lambda k: I.problem_3d(k), args.cpu_3d),
+                              ("di_n16384", None, args.cpu_di)):
+        ms = []
+        if make is None:
+            s = I.di_samples(0, 16384)
+            tab = O.neighbors(s, O.DI, I.DI_RADIUS)
+            probs = [I.di_problem(k, s) for k in range(count)]
+            for p in probs:
+                t = time.perf_counter()
+                O.plan(p, p.r, tab)
+                ms.append((time.perf_counter() - t) * 1e3)
+        else:
+            for k in range(count):
+                p = make(k)
+                r = O.euclid_radius(p)
+                tab = O.neighbors(p.samples, O.EUCLID, r)  # precomputed, as the roadmap is
+                t = time.perf_counter()
+                O.plan(p, r, tab)
+                ms.append((time.perf_counter() - t) * 1e3)
+        out[name] = dict(problems=count, **lat_stats(ms))
+    return out
 
 
 def mixed_report(args, torch, gmt, I):
@@ -474,6 +670,14 @@ def main():
             del d3
 
     learned = learned_report(args, torch, gmt, I) if args.learned else None
+    extra = {}
+    if not args.no_extra and not args.only_throughput:
+        say("dubins airplane")
+        extra["dubins"] = dubins_report(args, torch, gmt, I)
+        say("halton")
+        extra["halton"] = halton_report(args, torch, gmt, I)
+        say("replanning")
+        extra["replanning"] = replan_report(args, torch, gmt, I)
     mixed = (mixed_report(args, torch, gmt, I)
              if args.mixed_requests > 0 and not args.only_throughput else None)
 
@@ -520,12 +724,17 @@ def main():
             for th in ths:
                 th.join()
             dt = time.perf_counter() - t
+            say("cpu latency")
             cpu = {"value": round(done[0] / dt, 2), "unit": "plans/s", "cores": cores,
                    "kind": "oracle",
                    "sample": "%d FP64 oracle plans (Algorithm 1, serial C) of the same 6D DI n=%d "
-                             "queries on sample set 0, %d threads for %.1f s; its neighbour table "
-                             "(%.1f s, OpenMP) built beforehand like the GPU roadmaps"
-                             % (done[0], n, cores, dt, oracle_build_s)}
+                             "queries on sample set 0, one thread per core (%d) for %.1f s; its "
+                             "neighbour table (%.1f s, OpenMP) built beforehand like the GPU roadmaps"
+                             % (done[0], n, cores, dt, oracle_build_s),
+                   "cpu_model": cpu_model(), "nproc": cores,
+                   "single_core_latency": cpu_latency_report(args),
+                   "latency_note": "one thread, serial C oracle, tables precomputed (excluded, as the "
+                                   "roadmap is); bounded samples, problem counts stated"}
 
     line = {
         "metric": "plans/s + p50/p99 plan latency, 6D double-integrator n=16k; cost vs FP64 oracle",
@@ -557,6 +766,9 @@ def main():
         "server": srv_line,
         "mixed_stream": mixed,
         "learned": learned,
+        "dubins": extra.get("dubins"),
+        "halton": extra.get("halton"),
+        "replanning": extra.get("replanning"),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_plan<1> (one launch per batch)",

@@ -1086,25 +1086,33 @@ static int plan_level(int team_wgs, int threads, int box_words, int nmax) {
     return plan_lds(box_words, nmax, 1) <= kLdsStateLimit ? 1 : 0;
 }
 
-template <int K, int L>
+template <int K, int L, bool G>
 static const void *plan_kernel_cl(int cl) {
     switch (cl) {
-    case 4: return (const void *)k_plan<K, L, 4>;
-    case 8: return (const void *)k_plan<K, L, 8>;
-    case 32: return (const void *)k_plan<K, L, 32>;
-    default: return (const void *)k_plan<K, L, 16>;
+    case 4: return (const void *)k_plan<K, L, 4, G>;
+    case 8: return (const void *)k_plan<K, L, 8, G>;
+    case 32: return (const void *)k_plan<K, L, 32, G>;
+    default: return (const void *)k_plan<K, L, 16, G>;
     }
 }
 
-template <int K>
+template <int K, bool G>
 static const void *plan_kernel_k(int level, int cl) {
-    return level == 2 ? plan_kernel_cl<K, 2>(cl) : level == 1 ? plan_kernel_cl<K, 1>(cl) : plan_kernel_cl<K, 0>(cl);
+    return level == 2   ? plan_kernel_cl<K, 2, G>(cl)
+           : level == 1 ? plan_kernel_cl<K, 1, G>(cl)
+                        : plan_kernel_cl<K, 0, G>(cl);
 }
 
-static const void *plan_kernel(int kind, int level, int cl) {
-    return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_k<0>(level, cl)
-           : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_k<1>(level, cl)
-                                                 : plan_kernel_k<2>(level, cl);
+// the plan kernel of a cost kind, state placement and lane width; `grid`:
+// the variant with box-grid culling (for launches with such queries)
+static const void *plan_kernel(int kind, int level, int cl, bool grid = false) {
+    if (grid)
+        return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_k<0, true>(level, cl)
+               : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_k<1, true>(level, cl)
+                                                     : plan_kernel_k<2, true>(level, cl);
+    return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_k<0, false>(level, cl)
+           : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_k<1, false>(level, cl)
+                                                 : plan_kernel_k<2, false>(level, cl);
 }
 
 static bool lanes_valid(int lanes) { return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32; }
@@ -1193,6 +1201,7 @@ struct BatchRun {
     std::vector<int> order;  // kernel order -> caller index
     int count = 0;
     int kfirst[3] = {0, 0, 0}, kcount[3] = {0, 0, 0}, knmax[3] = {0, 0, 0};  // per cost kind, in kernel order
+    bool kgrid[3] = {false, false, false};  // a query of that kind culls its boxes by a grid
     int teams = 1, team_wgs = 1, box_words = 1, cl = 16, threads = 256;
     size_t used = 0;
     bool prof = false;
@@ -1218,7 +1227,7 @@ static void run_release(BatchRun &r) {
 // results.  Events e0 / e1 (may be null) bracket the plan kernel.
 static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, int kind, int first, int count,
                                    int total, int nmax, int teams, int team_wgs, int box_words_in, int qslot, int cl,
-                                   int threads, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+                                   int threads, bool with_grid, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
     int box_words = plan_box_words(kind, box_words_in);
     char *sd = (char *)stage_d;
     int *queue = (int *)sd + qslot;
@@ -1228,15 +1237,16 @@ static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, 
     const int level = plan_level(team_wgs, threads, box_words, nmax);
     const size_t plds = plan_lds(box_words, nmax, level);
     if (plds > 64 * 1024)
-        (void)hipFuncSetAttribute(plan_kernel(kind, level, cl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
+        (void)hipFuncSetAttribute(plan_kernel(kind, level, cl, with_grid), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)plds);
     if (e0) HIPCHK(hipEventRecord(e0, s));
     dim3 grid(teams * team_wgs), block(threads);
     int st_bytes = nmax + 1;
     void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
     if (team_wgs > 1)
-        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, 0, cl), grid, block, args, (unsigned)plds, s));
+        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, 0, cl, with_grid), grid, block, args, (unsigned)plds, s));
     else
-        HIPCHK(hipLaunchKernel(plan_kernel(kind, level, cl), grid, block, args, plds, s));
+        HIPCHK(hipLaunchKernel(plan_kernel(kind, level, cl, with_grid), grid, block, args, plds, s));
     if (e1) HIPCHK(hipEventRecord(e1, s));
     return GMT_OK;
 }
@@ -1245,9 +1255,10 @@ static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, 
 // workgroups (measured fastest at n = 16384), or one per CU for smaller ones
 static int default_team_wgs(int threads) { return threads >= 1024 ? std::max(1, num_cus() / 8) : num_cus(); }
 
-static int max_coop_wgs(size_t lds, int kind, int level = 0, int cl = 16, int threads = 256) {
+static int max_coop_wgs(size_t lds, int kind, int level = 0, int cl = 16, int threads = 256, bool grid = false) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, level, cl), threads, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, plan_kernel(kind, level, cl, grid), threads, lds) !=
+            hipSuccess ||
         per < 1)
         per = 1;
     return per * num_cus();
@@ -1255,10 +1266,10 @@ static int max_coop_wgs(size_t lds, int kind, int level = 0, int cl = 16, int th
 
 // workgroups of the cooperative team that runs a single plan: the requested
 // number (0: the default), capped at what can be co-resident
-static int single_team_wgs(int requested, int kind, int box_words, int nmax, int cl, int threads) {
+static int single_team_wgs(int requested, int kind, int box_words, int nmax, int cl, int threads, bool grid) {
     const size_t lds = plan_lds(plan_box_words(kind, box_words), nmax, 0);
     const int t = requested > 0 ? requested : default_team_wgs(threads);
-    return std::max(1, std::min(t, max_coop_wgs(lds, kind, 0, cl, threads)));
+    return std::max(1, std::min(t, max_coop_wgs(lds, kind, 0, cl, threads, grid)));
 }
 
 // Copy the staged queries up, launch per kind, copy the results down and
@@ -1277,8 +1288,8 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, b
         if (r.kcount[kind] > 0)
             TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, kind, r.kfirst[kind],
                                  r.kcount[kind], r.count, r.knmax[kind], std::min(r.teams, r.kcount[kind]),
-                                 r.team_wgs, r.box_words, kind, r.cl, r.threads, r.ev[2 * kind], r.ev[2 * kind + 1],
-                                 s));
+                                 r.team_wgs, r.box_words, kind, r.cl, r.threads, r.kgrid[kind], r.ev[2 * kind],
+                                 r.ev[2 * kind + 1], s));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
     if (events) HIPCHK(hipEventRecord(r.ev[kEvDone], s));
     return GMT_OK;
@@ -1354,6 +1365,7 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     std::vector<size_t> ws_off(count);
     std::vector<GridShape> grids(count);
     r.box_words = 1;
+    r.kgrid[0] = r.kgrid[1] = r.kgrid[2] = false;
     for (int j = 0; j < count; ++j) {
         const gmt_problem &pr = problems[r.order[j]];
         if (pr.m < 0 || pr.m > GMT_MAX_BOXES)
@@ -1362,6 +1374,7 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
         const int words = pr.m * 2 * pd;
         if (pr.m > 0 && !pr.boxes) return fail(GMT_EINVAL, "problem %d: null boxes", r.order[j]);
         grids[j] = grid_shape(pr.boxes, pr.m, pd);
+        if (grids[j].G > 0) r.kgrid[pr.roadmap->kind] = true;
         // only queries without a grid stage their boxes in LDS
         if (grids[j].G == 0) r.box_words = std::max(r.box_words, words);
         total_boxes += (size_t)words;
@@ -1378,16 +1391,17 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     r.cl = lanes_of(bo.plan.lanes);
     r.threads = threads_of(bo.plan.threads);
     if (single) {
-        r.team_wgs = single_team_wgs(bo.plan.team_wgs, kind0, r.box_words, nmax, r.cl, r.threads);
+        r.team_wgs = single_team_wgs(bo.plan.team_wgs, kind0, r.box_words, nmax, r.cl, r.threads, r.kgrid[kind0]);
         r.teams = 1;
     } else {
         r.team_wgs = bo.plan.team_wgs > 0 ? bo.plan.team_wgs : 1;
         const int pbw = plan_box_words(kind0, r.box_words);
         const int level = plan_level(r.team_wgs, r.threads, pbw, nmax);
         const size_t lds = plan_lds(pbw, nmax, level);
-        const int resident = std::min(max_coop_wgs(lds, 0, level, r.cl, r.threads),
-                                      std::min(max_coop_wgs(lds, 1, level, r.cl, r.threads),
-                                               max_coop_wgs(lds, 2, level, r.cl, r.threads)));
+        int resident = 1 << 30;
+        for (int kind = 0; kind < 3; ++kind)
+            if (r.kcount[kind] > 0)
+                resident = std::min(resident, max_coop_wgs(lds, kind, level, r.cl, r.threads, r.kgrid[kind]));
         int teams = bo.workgroups > 0 ? bo.workgroups / r.team_wgs : resident / r.team_wgs;
         teams = std::max(1, std::min(teams, count));
         if (r.team_wgs > 1) teams = std::max(1, std::min(teams, resident / r.team_wgs));
@@ -1647,7 +1661,7 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || bo.plan.threads == 0) tune_apply(&pr, 1, true, bo);
     const int cl = lanes_of(bo.plan.lanes), threads = threads_of(bo.plan.threads);
     const int team_wgs = single_team_wgs(bo.plan.team_wgs, rm->kind, grid.G > 0 ? 1 : std::max(words, 1), rm->n, cl,
-                                         threads);
+                                         threads, grid.G > 0);
 
     std::lock_guard<std::mutex> lk(g_na_mu);
     char *base = nullptr;
@@ -1668,7 +1682,7 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
     // barrier arrivals, generation and fault flag start at zero on every call
     k_fill_int<<<1, 64, 0, s>>>((int *)tctl, (int)(sizeof(TeamCtl) / sizeof(int)), 0);
     TRY(launch_plan_kind(base, tctl, res_d, rm->kind, 0, 1, 1, rm->n, 1, team_wgs,
-                         grid.G > 0 ? 1 : std::max(words, 1), rm->kind, cl, threads, nullptr, nullptr, s));
+                         grid.G > 0 ? 1 : std::max(words, 1), rm->kind, cl, threads, grid.G > 0, nullptr, nullptr, s));
     HIPCHK(hipMemcpyAsync(&g_na_res, res_d, sizeof(Result), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Result &res = g_na_res;
@@ -1880,14 +1894,17 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
             // LDS, workgroup barriers only: small n) up to the whole GPU
             if (threads == 1024) teams = {1, 4, num_cus() / 8, num_cus() / 4, num_cus() / 2, num_cus()};
             for (int l : lanes) {
-                const int cap = max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, l, threads);
+                // (either kernel variant may run: the tighter cap)
+                const int cap = std::min(max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, l, threads, false),
+                                         max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, l, threads, true));
                 for (int t : teams)
                     if (t >= 1) add(l, std::min(t, cap), 0, threads);
             }
         }
         // the library default first
         const int dteam = std::min(default_team_wgs(kDefaultThreads),
-                                   max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, 16, kDefaultThreads));
+                                   std::min(max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, 16, kDefaultThreads, false),
+                                            max_coop_wgs(plan_lds(bw, sh.n, 0), sh.kind, 0, 16, kDefaultThreads, true)));
         add(16, dteam, 0, kDefaultThreads);
         for (size_t k = 0; k < cands.size(); ++k)
             if (cands[k].plan.lanes == 16 && cands[k].plan.team_wgs == dteam && cands[k].plan.threads == kDefaultThreads)

@@ -548,12 +548,15 @@ __device__ __forceinline__ void load_end(const RoadmapDev &R, int x, CandEnd &c)
 // wave calls it; returns the verdict for this lane's group.  y is given by
 // its grid coordinates yq (KIND 0) or its state ys and the edge's arrival
 // time tau (KIND 1).
-template <int KIND, int CL>
+// GRID: the kernel variant for batches with box-grid queries (it still takes
+// the plain path for queries without a grid); without it no grid code is
+// compiled in.
+template <int KIND, int CL, bool GRID>
 __device__ __forceinline__ bool group_edge_free(const ProbDev &P, bool active, const int *yq, const double *ys,
                                                 double tau, const CandEnd &c, const int *lbox) {
     const int lg = lane_id() & (CL - 1);
     bool hit = false;
-    if (active && P.gG > 0) {
+    if (GRID && active && P.gG > 0) {
         hit = grid_lane_hits<KIND>(P, yq, ys, tau, c.xq, c.xs, lg, CL);
     } else if (active) {
         if (KIND == 0) {
@@ -759,7 +762,7 @@ __device__ __forceinline__ unsigned long long clock_ticks() { return wall_clock6
 //   2: also the costs-to-come, copied out to the tree output at the end --
 //      every cost gather of the parent search is then an LDS read.
 // CL: lanes per candidate in the connect phase.
-template <int KIND, int LDS, int CL>
+template <int KIND, int LDS, int CL, bool GRID>
 __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsigned char *lst, Ctl *lctl,
                           double *lcost, Result *res) {
     const RoadmapDev &R = P.rm;
@@ -788,7 +791,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         }
     }
     team_sync(t);  // counters are zero before the appends below
-    if (P.gG > 0) build_box_grid(t, P);
+    if (GRID && P.gG > 0) build_box_grid(t, P);
 
     // ---- iteration 0: the root x_init is the only open node (lines 1-9) ----
     // (a) every node: obstacle and goal bits, tree arrays reset; samples that
@@ -816,7 +819,8 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                 }
             }
             // grid coordinates are exact in FP32, as are the staged boxes
-            const bool dead = P.gG > 0 ? grid_point_hits_q(P, q) : node_in_boxes<KIND>(q, pf, lbox, P.m, P.pd);
+            const bool dead =
+                (GRID && P.gG > 0) ? grid_point_hits_q(P, q) : node_in_boxes<KIND>(q, pf, lbox, P.m, P.pd);
             st[v] = (unsigned char)((dead ? S_DEAD : S_UNEXPLORED) | (in_goal_q(q, P) ? S_GOAL : 0));
             cost[v] = __longlong_as_double(COST_INF_BITS);
             if (OC) w.cost[v] = __longlong_as_double(COST_INF_BITS);
@@ -899,7 +903,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             CandEnd ce;
             if (active) load_end<KIND>(R, v, ce);
             const double tau = (KIND == 1 && active) ? w.aux[v] : 0.0;
-            const bool free_edge = group_edge_free<KIND, CL>(P, active, P.x_q, P.x_d, tau, ce, lbox);
+            const bool free_edge = group_edge_free<KIND, CL, GRID>(P, active, P.x_q, P.x_d, tau, ce, lbox);
             const bool joined = active && lg == 0 && free_edge;
             if (active && lg == 0) {
                 if (free_edge) {
@@ -1150,7 +1154,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         tau = R.in_tau[be];
                     }
                 }
-                const bool free_edge = group_edge_free<KIND, CL>(P, ok, yq, ys, tau, ce, lbox);
+                const bool free_edge = group_edge_free<KIND, CL, GRID>(P, ok, yq, ys, tau, ce, lbox);
                 if (t.wave == 0) tk_check += clock_ticks() - c0;
                 const bool commit = ok && free_edge && lg == 0;
                 if (active && lg == 0) {
@@ -1248,7 +1252,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // ---------------------------------------------------------------------------
 // Workgroups of 256, 512 or 1024 threads; registers are sized for 16 waves
 // per CU (four 256-thread workgroups or one of 1024 threads).
-template <int KIND, int LDS, int CL>
+template <int KIND, int LDS, int CL, bool GRID>
 __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
@@ -1297,7 +1301,7 @@ __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ pr
                 fbox[k] = (float)((double)boxes[P.box_off + k] * GMT_INV_QS);
         }
         __syncthreads();
-        run_query<KIND, LDS, CL>(t, P, lbox, lst, lctl, lcost, res + job);
+        run_query<KIND, LDS, CL, GRID>(t, P, lbox, lst, lctl, lcost, res + job);
         if (t.nwg > 1 && ld_acquire(t.abort)) return;
     }
 }
