@@ -105,9 +105,9 @@ def plan_bytes(w, in_edge=24):
 
 def euclid_build_bytes(n, dim, edges, per_edge=8):
     """Algorithmic bytes of a Euclidean table: samples read (4 B per
-    coordinate), row pointers, and per edge an index plus an FP32 cost (8 B);
-    the table as built writes a 12-byte (FP64 cost, column) record and a
-    4-byte column per edge (16 B)."""
+    coordinate), row pointers, and per edge an index plus an FP32 cost (8 B).
+    The table as built writes one 8-byte (squared distance, column) record
+    per edge, the row pointers and the row lengths (4 B per sample more)."""
     return 4 * dim * n + 4 * (n + 1) + per_edge * edges
 
 
@@ -632,9 +632,9 @@ def main():
                     "peak_inflight_requests": rep.engine.get("peak_inflight_requests"),
                     "identical_to_batch": "%d/%d" % (same, len(rep.served))}
 
-    # ---- Euclidean neighbour table builds, 3D (config 2 workload and larger n) ----
-    # bytes the build must move: samples read, row pointers, 12-byte records
-    # and 4-byte columns written per edge
+    # ---- Euclidean neighbour table builds, 3D (the 3D workload and larger n) ----
+    # bytes the build must move: samples read, row pointers, an index and a
+    # cost per edge; as built: one 8-byte record per edge and the row lengths
     build_line = None
     if not args.only_throughput and args.euclid_sizes:
         from paper_1705_02403_amd import radius as RAD
@@ -653,14 +653,16 @@ def main():
                 bt.append((time.perf_counter() - t) * 1e3)
                 kt.append(gmt.gmt_last_build()["kernel_ms"])
                 e3 = rm3.nnz
+                held = rm3.device_bytes
                 rm3.free()
             gmt.gmt_profile_enable(False)
             gmt.gmt_profile_read()
             bt = float(np.median(bt[1:]))
             kms = float(np.median(kt[1:]))
             nbytes = euclid_build_bytes(n3, 3, e3)
-            built = euclid_build_bytes(n3, 3, e3, per_edge=16)
+            built = euclid_build_bytes(n3, 3, e3) + 4 * n3
             build_line.append({"workload": "3D Euclidean n=%d, r=%.4f" % (n3, r3), "edges": int(e3),
+                               "device_bytes": int(held),
                                "kernel_ms": round(kms, 4), "wall_ms": round(bt, 3), "bytes": int(nbytes),
                                "achieved": round(nbytes / (kms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -139,13 +139,18 @@ gmt_status gmt_set_allocator(const gmt_allocator *allocator);
  *  out        receives the roadmap; free with gmt_roadmap_free.
  * The table holds, for every sample x, its in-neighbours y (c(y -> x) < r)
  * with FP64 costs (and FP64 arrival times for the double integrator), plus
- * the out-neighbour table; for the symmetric Euclidean cost one table serves
- * both.  Row order on the device is unspecified (gmt_roadmap_export returns
- * ascending rows).  Synchronises `stream` (to size the table, and on return:
- * the table is complete).
+ * the out-neighbour table.  The symmetric Euclidean cost keeps one table in
+ * fixed-capacity rows: an 8-byte record per edge (the exact squared grid
+ * distance above the column, the cost being its square root times 2^-20),
+ * row x in slots [x * cap, x * cap + deg x), cap sized from the expected
+ * degree and, should a row be longer, raised to the longest and the single
+ * pass run again.  Row order on the device is unspecified
+ * (gmt_roadmap_export returns ascending rows).  Synchronises `stream` (to
+ * size the table, and on return: the table is complete).
  * Errors: GMT_EINVAL for n < 1, a bad dim/kind pair, r_n <= 0 or non-finite,
- * samples off the grid or outside the state space, or more than 2^31-1
- * edges; GMT_ENOMEM; GMT_EDEVICE. */
+ * samples off the grid or outside the state space, more than 2^31-1 edges,
+ * and for the Euclidean cost more than 2^22 samples or n * cap above the
+ * int32 index range; GMT_ENOMEM; GMT_EDEVICE. */
 gmt_status gmt_build_neighbors(const float *d_samples, int32_t n, int32_t dim, gmt_cost_kind kind,
                                double r_n, void *stream, gmt_roadmap_t *out);
 
@@ -187,8 +192,12 @@ gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, int32_t dim
 /* Wrap an externally computed in-neighbour table (host arrays, copied):
  * samples SoA [dim][n], row_ptr [n+1], col [nnz] (each row ascending, no
  * self edges), cost [nnz] FP64, tau [nnz] FP64 (double integrator only, else
- * NULL).  The out-neighbour table is derived.  Same errors as
- * gmt_build_neighbors, plus GMT_EINVAL for a malformed table. */
+ * NULL).  The out-neighbour table is derived.  A Euclidean table's costs
+ * must be the distances of the samples as the library computes them,
+ * sqrt(d2) * 2^-20 with d2 the exact squared distance on the 2^-20 grid
+ * (what gmt_roadmap_export returns); its rows may list any pairs.  Same
+ * errors as gmt_build_neighbors, plus GMT_EINVAL for a malformed table or
+ * a Euclidean cost that is not that distance. */
 gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int32_t dim, gmt_cost_kind kind,
                                 double r_n, const int32_t *row_ptr, const int32_t *col,
                                 const double *cost, const double *tau, void *stream,
@@ -197,6 +206,10 @@ gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int32_t dim, gm
 /* Sizes of a roadmap: samples, state dimension, cost kind, number of edges. */
 gmt_status gmt_roadmap_info(gmt_roadmap_t rm, int32_t *n, int32_t *dim, int32_t *kind,
                             int64_t *nnz);
+
+/* Device bytes a roadmap holds (samples, tables, records, padding), for
+ * callers that keep roadmaps resident under a memory budget. */
+gmt_status gmt_roadmap_bytes(gmt_roadmap_t rm, int64_t *bytes);
 
 /* Copy the in-neighbour table to host arrays: row_ptr [n+1], col [nnz],
  * cost [nnz], tau [nnz] (any of row_ptr/col/cost/tau may be NULL), each row
@@ -297,15 +310,16 @@ gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches);
 /* Record of the last gmt_build_neighbors call on this thread.
  *  edges         entries of the in-neighbour table;
  *  pairs_tested  candidate pairs the build tested: Euclidean, the distance
- *                tests of its counting pass over the staged cell
+ *                tests of its (last) pass over the staged cell
  *                neighbourhoods; double integrator, every ordered pair;
  *  pairs_solved  double integrator: pairs that passed the exact lower-bound
  *                prefilter and whose arrival-time quartic was solved (0 for
  *                the Euclidean cost);
  *  kernel_ms     device time of the build's kernels, from HIP events on its
- *                stream around its two device segments (the table is sized
- *                on the host between them), while gmt_profile_enable is on;
- *                0 otherwise;
+ *                stream around its device segments (double integrator: two,
+ *                the table sized on the host between them; Euclidean: one
+ *                pass, and one more when a row outgrew the slots), while
+ *                gmt_profile_enable is on; 0 otherwise;
  *  segments      timed segments summed into kernel_ms. */
 typedef struct {
     int64_t edges;

@@ -238,23 +238,26 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
     pts[pos] = make_int4(q[0], q[1], q[2], i);
 }
 
-// Rows of the Euclidean table.  Cells have edge >= r/2 (G per axis), so the
-// r-ball of a sample lies in the 5^d cells around its own; the samples are
-// sorted by cell (pts).  One 256-thread workgroup takes EU_XB cells that
-// follow each other along x: it stages the samples of the cells within two
-// cells of them in LDS (at most 25 runs of the sorted order, cells along x
-// being contiguous) in chunks of EU_CHUNK, padded to a multiple of 128 with
-// samples far outside every r-ball, and each wave takes rows in turn and
-// tests the staged samples 128 at a time (two per lane, their LDS reads
-// issued together).  Grid coordinates differ by less than 2^30, so d2 =
+// Rows of the Euclidean table, one pass.  Cells have edge >= r/2 (G per
+// axis), so the r-ball of a sample lies in the 5^d cells around its own; the
+// samples are sorted by cell (pts).  One 256-thread workgroup takes EU_XB
+// cells that follow each other along x: it stages the samples of the cells
+// within two cells of them in LDS (at most 25 runs of the sorted order,
+// cells along x being contiguous) in chunks of EU_CHUNK, padded to a multiple
+// of 128 with samples far outside every r-ball, and each wave takes rows in
+// turn and tests the staged samples 128 at a time (two per lane, their LDS
+// reads issued together).  Grid coordinates differ by less than 2^30, so d2 =
 // |q_i - q_j|^2 is exact in FP64 for real pairs (each square below 2^42, the
 // sum below 2^53) and far above r^2 for the padding.
-// COUNT: row lengths.  Otherwise the rows are written, in staging order
-// (the parent search does not depend on it), as (cost, column) records plus
-// the column array: each wave gathers the staging slots of its row's edges
-// in an LDS buffer of EU_OBUF entries and writes them out in contiguous
-// runs, taking the cost sqrt(d2) * 2^-20 (rounded once) per written edge,
-// not per test.
+//
+// Row x has `cap` slots at x * cap: each edge is one 8-byte record, the exact
+// squared grid distance d2 (< 3 * 2^40, 42 bits) above the column (22 bits).
+// The parent search takes the edge cost sqrt(d2) * 2^-20 from it; the frontier
+// reads the columns.  Edges past `cap` are counted but not written: deg[x] is
+// the full row length and *maxdeg its maximum, so the host can rerun the pass
+// with a larger cap.  Rows come out in staging order (the parent search does
+// not depend on it): each wave gathers the staging slots of its row's edges in
+// an LDS buffer of EU_OBUF entries and writes them out in contiguous runs.
 #ifndef EU_XB
 #define EU_XB 2
 #endif
@@ -271,15 +274,14 @@ __device__ __forceinline__ double eu_d2(const int4 &c, const int4 &q) {
     return d0 * d0 + d1 * d1 + d2 * d2;
 }
 
-template <bool COUNT>
 __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restrict__ pts,
-                                                 const int *__restrict__ cell_start, double R2,
+                                                 const int *__restrict__ cell_start, double R2, int cap,
                                                  int *__restrict__ deg, int *__restrict__ maxdeg,
-                                                 const int *__restrict__ row_ptr, unsigned int *__restrict__ rec,
-                                                 int *__restrict__ col, unsigned long long *__restrict__ tested) {
+                                                 unsigned long long *__restrict__ rec,
+                                                 unsigned long long *__restrict__ tested) {
     __shared__ int4 cand[EU_CHUNK];
     // per wave: EU_OBUF slots, then one that lanes without an edge write to
-    __shared__ unsigned short oslot[COUNT ? 1 : 4 * (EU_OBUF + 2)];
+    __shared__ unsigned short oslot[4 * (EU_OBUF + 2)];
     __shared__ int rcnt[EU_ROWS];
     __shared__ int sb[25], soff[26];
     const int G = g.G;
@@ -311,8 +313,7 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
     }
     __syncthreads();
     const int total = soff[nspan];
-    unsigned short *wslot = oslot + (COUNT ? 0 : wave * (EU_OBUF + 2));
-    unsigned long long ntest = 0;  // distance tests of this wave (COUNT pass)
+    unsigned short *wslot = oslot + wave * (EU_OBUF + 2);
     for (int rb = p0; rb < p1; rb += EU_ROWS) {  // blocks of rows
         const int nr = min(EU_ROWS, p1 - rb);
         for (int i = tid; i < nr; i += 256) rcnt[i] = 0;
@@ -345,10 +346,9 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
             __syncthreads();
             for (int ri = wave; ri < nr; ri += 4) {
                 const int4 q = pts[rb + ri];
-                ntest += (unsigned long long)cntp;
                 int run = 0, fill = 0;
-                long long dst = COUNT ? 0 : (long long)row_ptr[q.w] + rcnt[ri];
-                // write the buffered entries of this row out
+                int slot0 = rcnt[ri];  // slots of this row already taken
+                // write the buffered entries of this row out, those that fit
                 // (up to EU_OBUF / 64 entries per lane, their LDS reads issued together)
                 auto flush = [&]() {
                     constexpr int FU = EU_OBUF / GMT_WAVE;
@@ -362,21 +362,17 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
                     int4 c[FU];
 #pragma unroll
                     for (int u = 0; u < FU; ++u) c[u] = cand[sl[u]];
-                    unsigned int *r = rec + 3 * (dst + lane);
-                    int *cp = col + dst + lane;
+                    unsigned long long *r = rec + (long long)q.w * cap;
 #pragma unroll
                     for (int u = 0; u < FU; ++u) {
-                        if (lane + u * GMT_WAVE < fill) {
-                            const unsigned long long bits =
-                                (unsigned long long)__double_as_longlong(sqrt(eu_d2(c[u], q)) * GMT_INV_QS);
-                            r[3 * u * GMT_WAVE] = (unsigned int)(bits & 0xffffffffull);
-                            r[3 * u * GMT_WAVE + 1] = (unsigned int)(bits >> 32);
-                            r[3 * u * GMT_WAVE + 2] = (unsigned int)c[u].w;
-                            cp[u * GMT_WAVE] = c[u].w;
+                        const int k = slot0 + lane + u * GMT_WAVE;
+                        if (lane + u * GMT_WAVE < fill && k < cap) {
+                            const unsigned long long d2 = (unsigned long long)eu_d2(c[u], q);
+                            r[k] = (d2 << EU_COL_BITS) | (unsigned long long)(unsigned int)c[u].w;
                         }
                     }
                     __builtin_amdgcn_wave_barrier();
-                    dst += fill;
+                    slot0 += fill;
                     fill = 0;
                 };
                 for (int k0 = 0; k0 < cntp; k0 += 2 * GMT_WAVE) {
@@ -386,26 +382,65 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
                     const uint64_t mb = wave_ballot(db < R2 && cb.w != q.w);
                     const bool oka = (ma >> lane) & 1ull, okb = (mb >> lane) & 1ull;
                     const int pa = (int)__popcll(ma), pb = (int)__popcll(mb);
-                    if (!COUNT) {
-                        if (fill + pa + pb > EU_OBUF) flush();
-                        wslot[oka ? fill + lanes_below(ma) : EU_OBUF] = (unsigned short)(k0 + lane);
-                        wslot[okb ? fill + pa + lanes_below(mb) : EU_OBUF] = (unsigned short)(k0 + GMT_WAVE + lane);
-                        fill += pa + pb;
-                    }
+                    if (fill + pa + pb > EU_OBUF) flush();
+                    wslot[oka ? fill + lanes_below(ma) : EU_OBUF] = (unsigned short)(k0 + lane);
+                    wslot[okb ? fill + pa + lanes_below(mb) : EU_OBUF] = (unsigned short)(k0 + GMT_WAVE + lane);
+                    fill += pa + pb;
                     run += pa + pb;
                 }
-                if (!COUNT) flush();
+                flush();
                 if (lane == 0) rcnt[ri] += run;
             }
         }
         __syncthreads();
-        if (COUNT)
-            for (int i = tid; i < nr; i += 256) {
-                deg[pts[rb + i].w] = rcnt[i];
-                atomicMax(maxdeg, rcnt[i]);
-            }
+        for (int i = tid; i < nr; i += 256) {
+            deg[pts[rb + i].w] = rcnt[i];
+            atomicMax(maxdeg, rcnt[i]);
+        }
     }
-    if (COUNT && tested && lane == 0 && ntest) atomicAdd(tested, ntest);
+    if (tested && tid == 0) {
+        // distance tests: every row of the workgroup against every staged slot
+        unsigned long long slots = 0;
+        for (int c0 = 0; c0 < total; c0 += EU_CHUNK) slots += (unsigned long long)((min(EU_CHUNK, total - c0) + 127) & ~127);
+        atomicAdd(tested, slots * (unsigned long long)(p1 - p0));
+    }
+}
+
+// padding records after the last row's slots: column 0, distance 0
+__global__ void k_rec8_pad(unsigned long long *__restrict__ rec, long long at) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < GMT_REC_PAD) rec[at + k] = 0ull;
+}
+
+// compact (column, FP64 cost) copies of the rows (row_ptr: exclusive scan of
+// deg), for exporting a table: one wave per row
+__global__ void k_eu_unpack(int n, int cap, const int *__restrict__ deg, const int *__restrict__ row_ptr,
+                            const unsigned long long *__restrict__ rec, int *__restrict__ col,
+                            double *__restrict__ cost) {
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
+    if (x >= n) return;
+    const int d = deg[x], dst = row_ptr[x];
+    for (int k = lane_id(); k < d; k += GMT_WAVE) {
+        const unsigned long long r = rec[(long long)x * cap + k];
+        col[dst + k] = (int)(r & EU_COL_MASK);
+        cost[dst + k] = sqrt((double)(r >> EU_COL_BITS)) * GMT_INV_QS;
+    }
+}
+
+// row lengths of a CSR table
+__global__ void k_row_lengths(const int *__restrict__ row_ptr, int n, int *__restrict__ deg) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) deg[x] = row_ptr[x + 1] - row_ptr[x];
+}
+
+// records of an imported table: row x of the CSR (col, exact d2) to slots x * cap
+__global__ void k_eu_pack(int n, int cap, const int *__restrict__ row_ptr, const int *__restrict__ col,
+                          const unsigned long long *__restrict__ d2, unsigned long long *__restrict__ rec) {
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) / GMT_WAVE;
+    if (x >= n) return;
+    const int b = row_ptr[x], e = row_ptr[x + 1];
+    for (int k = b + lane_id(); k < e; k += GMT_WAVE)
+        rec[(long long)x * cap + (k - b)] = (d2[k] << EU_COL_BITS) | (unsigned long long)(unsigned int)col[k];
 }
 
 // ---------------------------------------------------------------------------

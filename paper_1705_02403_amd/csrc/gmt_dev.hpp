@@ -20,6 +20,10 @@
 #define GMT_REC_PAD 256
 #endif
 #define GMT_Q2 1099511627776.0  // 2^40
+// Euclidean edge records, 8 bytes: the exact squared grid distance d2 (below
+// 3 * 2^40 inside the unit cube, 42 bits) above the column (22 bits)
+#define EU_COL_BITS 22
+#define EU_COL_MASK ((1u << EU_COL_BITS) - 1u)
 
 // node bookkeeping values
 #define ADDED_UNEXPLORED 0x7fffffff  // not in the tree, may still connect

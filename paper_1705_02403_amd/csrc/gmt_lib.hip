@@ -225,9 +225,12 @@ struct gmt_roadmap {
     double r = 0.0;
     double rho = 0.0;  // Dubins airplane: turning radius
     long long nnz = 0;
+    int cap = 0;       // Euclidean: slots per row (row x at x * cap), deg[x] used
+    DevBuf deg;        // Euclidean: row lengths
     DevBuf s, in_ptr, in_col, in_tau, out_ptr, out_col;
     DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
-    DevBuf in_rec;   // (edge cost, column) records of the in-table, 12 bytes per edge
+    DevBuf in_rec;   // in-table records: (edge cost, column), 12 bytes per edge; Euclidean:
+                     // (d2, column), 8 bytes per slot, cap slots per row
     DevBuf s8;       // double integrator: states as 8 floats per node
     DevBuf tab;      // one block holding the tables above that are views into it
     bool out_shared = false;
@@ -360,8 +363,20 @@ static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
     return GMT_OK;
 }
 
+// slots per row of a Euclidean table: room for the mean degree of an interior
+// sample, (n - 1) times the volume of the r-ball, and its spread (a longer
+// row makes the build run its pass again with the measured maximum)
+static int eu_capacity(int n, int dim, double r) {
+    const double zeta = dim == 2 ? M_PI : 4.0 / 3.0 * M_PI;
+    double m = std::min((double)(n - 1), (n - 1) * zeta * std::pow(std::min(r, 2.0), dim));
+    double cap = std::min((double)std::max(n - 1, 1), 1.25 * m + 4.0 * std::sqrt(m) + 16.0);
+    return ((int)std::ceil(cap) + 7) & ~7;
+}
+
 static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     const int n = rm->n, dim = rm->dim;
+    if (n > (1 << EU_COL_BITS))
+        return fail(GMT_EINVAL, "Euclidean roadmaps hold at most %d samples (got %d)", 1 << EU_COL_BITS, n);
     // squared radius in grid units; every pair of the unit cube lies below
     // 4 * 2^40, so a larger radius selects the same pairs (and the kernel's
     // padding samples stay outside)
@@ -377,14 +392,13 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     g.ncell = 1;
     for (int a = 0; a < dim; ++a) g.ncell *= g.G;
     // one block of temporaries: cell of each sample, cell counts and starts,
-    // placement cursors, the cell-sorted samples, row lengths, flags, scan scratch
+    // placement cursors, the cell-sorted samples, flags, scan scratch
     const size_t nc = (size_t)g.ncell;
     const size_t o_cnt = al256(sizeof(int) * (size_t)n);
     const size_t o_start = o_cnt + al256(sizeof(int) * nc);
     const size_t o_cur = o_start + al256(sizeof(int) * (nc + 1));
     const size_t o_pts = o_cur + al256(sizeof(int) * nc);
-    const size_t o_deg = o_pts + al256(sizeof(int4) * (size_t)n);
-    const size_t o_scal = o_deg + al256(sizeof(int) * (size_t)n);  // [0] flags, [1] maxdeg, [2..3] total
+    const size_t o_scal = o_pts + al256(sizeof(int4) * (size_t)n);  // [0] flags, [1] maxdeg, [2..3] total, [4..5] tests
     const size_t o_scan = o_scal + 256;
     DevBuf tmp;
     Temps keep(s, {&tmp});
@@ -392,7 +406,7 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     TRY(dev_alloc(rm->in_ptr, sizeof(int) * (n + 1), s));
     const DevBuf cell_of = dev_view(tmp, 0, 0), cell_cnt = dev_view(tmp, o_cnt, 0),
                  cell_start = dev_view(tmp, o_start, 0), cursor = dev_view(tmp, o_cur, 0),
-                 pts = dev_view(tmp, o_pts, 0), deg = dev_view(tmp, o_deg, 0), scal = dev_view(tmp, o_scal, 0);
+                 pts = dev_view(tmp, o_pts, 0), scal = dev_view(tmp, o_scal, 0);
     void *scan_tmp = (char *)tmp.p + o_scan;
     int *flags = (int *)scal.p, *maxdeg = flags + 1;
     long long *total = (long long *)(flags + 2);
@@ -410,38 +424,43 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
                                                    (const int *)cell_start.p, (int *)cursor.p, (int4 *)pts.p);
     // one workgroup per EU_XB cells along x
     const unsigned wgs = (unsigned)((g.G + EU_XB - 1) / EU_XB) * (unsigned)g.G * (unsigned)(dim == 3 ? g.G : 1);
-    k_eu_rows<true><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, (int *)deg.p,
-                                        maxdeg, nullptr, nullptr, nullptr, tested);
-    TRY(scan_ints((const int *)deg.p, n, (int *)rm->in_ptr.p, total, s, scan_tmp));
-    bt.end();
+    int cap = eu_capacity(n, dim, rm->r);
     int hs[6];
-    HIPCHK(hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    for (int attempt = 0;; ++attempt) {
+        // one block: the row lengths, then the slots with the padding records
+        const size_t slots = (size_t)n * (size_t)cap + GMT_REC_PAD;
+        const size_t o_rec = al256(sizeof(int) * (size_t)n);
+        TRY(dev_alloc(rm->tab, o_rec + 8 * slots, s));
+        rm->deg = dev_view(rm->tab, 0, sizeof(int) * (size_t)n);
+        rm->in_rec = dev_view(rm->tab, o_rec, 8 * slots);
+        if (attempt > 0) bt.begin();
+        k_fill_int<<<1, 64, 0, s>>>(maxdeg, 5, 0);  // maxdeg, total, tests
+        k_eu_rows<<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, cap, (int *)rm->deg.p,
+                                      maxdeg, (unsigned long long *)rm->in_rec.p, tested);
+        TRY(scan_ints((const int *)rm->deg.p, n, (int *)rm->in_ptr.p, total, s, scan_tmp));
+        k_rec8_pad<<<blocks_for(GMT_REC_PAD, 256), 256, 0, s>>>((unsigned long long *)rm->in_rec.p,
+                                                               (long long)n * cap);
+        bt.end();
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, scal.p, sizeof hs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour pass failed: %s", hipGetErrorString(e));
+        if (hs[0]) return fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
+        if (hs[1] <= cap) break;
+        // a row longer than the slots: again with room for the longest
+        dev_free(rm->tab, s);
+        rm->deg = rm->in_rec = DevBuf();
+        cap = (hs[1] + 7) & ~7;
+    }
     long long E;
     unsigned long long ntest;
     std::memcpy(&E, hs + 2, sizeof E);
     std::memcpy(&ntest, hs + 4, sizeof ntest);
-    if (hs[0]) return fail(GMT_EINVAL, "samples must lie in [0,1]^d on the 2^-20 grid");
-    if (E > 0x7fffffffLL) return fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
+    if ((long long)n * cap + GMT_REC_PAD > 0x7fffffffLL)
+        return fail(GMT_EINVAL, "table of %d rows x %d slots exceeds the int32 index range", n, cap);
     rm->nnz = E;
-    // one block for the columns and the (cost, column) records with their padding
-    const size_t o_rec = al256(sizeof(int) * (size_t)std::max<long long>(E, 1));
-    TRY(dev_alloc(rm->tab, o_rec + 12 * (size_t)(E + GMT_REC_PAD), s));
-    rm->in_col = dev_view(rm->tab, 0, sizeof(int) * (size_t)std::max<long long>(E, 1));
-    rm->in_rec = dev_view(rm->tab, o_rec, 12 * (size_t)(E + GMT_REC_PAD));
-    bt.begin();
-    k_eu_rows<false><<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, nullptr, nullptr,
-                                         (const int *)rm->in_ptr.p, (unsigned int *)rm->in_rec.p,
-                                         (int *)rm->in_col.p, nullptr);
-    k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>((unsigned int *)rm->in_rec.p, E);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
-    bt.end();
+    rm->cap = cap;
     g_last_build = gmt_build_info{E, (int64_t)ntest, 0, bt.ms, bt.segments};
-    // the table is symmetric: the in-table serves as the out-table
-    rm->out_ptr = rm->in_ptr;
-    rm->out_col = rm->in_col;
-    rm->out_shared = true;
     return GMT_OK;
 }
 
@@ -619,6 +638,33 @@ extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int3
             if (!(cost[e] >= 0.0) || !std::isfinite(cost[e])) return fail(GMT_EINVAL, "bad cost in row %d", i);
         }
     }
+    // Euclidean tables hold (d2, column) records: every cost must be the
+    // distance of its two samples as the library computes it, sqrt(d2) * 2^-20
+    // with d2 the exact squared grid distance
+    std::vector<unsigned long long> d2;
+    int cap = 0;
+    if (kind == GMT_COST_EUCLIDEAN) {
+        if (n > (1 << EU_COL_BITS))
+            return fail(GMT_EINVAL, "Euclidean roadmaps hold at most %d samples (got %d)", 1 << EU_COL_BITS, n);
+        d2.resize((size_t)row_ptr[n]);
+        for (int i = 0; i < n; ++i) {
+            cap = std::max(cap, row_ptr[i + 1] - row_ptr[i]);
+            for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                long long acc = 0;
+                for (int a = 0; a < dim; ++a) {
+                    const long long dq = std::llround((double)samples[(size_t)a * n + i] * GMT_QS) -
+                                         std::llround((double)samples[(size_t)a * n + col[e]] * GMT_QS);
+                    acc += dq * dq;
+                }
+                d2[e] = (unsigned long long)acc;
+                if (cost[e] != std::sqrt((double)acc) * GMT_INV_QS)
+                    return fail(GMT_EINVAL, "edge %d of row %d: a Euclidean cost must be the samples' distance", e, i);
+            }
+        }
+        cap = (cap + 7) & ~7;
+        if ((long long)n * cap + GMT_REC_PAD > 0x7fffffffLL)
+            return fail(GMT_EINVAL, "table of %d rows x %d slots exceeds the int32 index range", n, cap);
+    }
     hipStream_t s = (hipStream_t)stream;
     gmt_roadmap *rm = new gmt_roadmap;
     rm->n = n;
@@ -626,7 +672,6 @@ extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int3
     rm->kind = kind;
     rm->r = r_n;
     rm->nnz = row_ptr[n];
-    size_t e1 = (size_t)std::max<long long>(rm->nnz, 1);
     gmt_status st = GMT_OK;
     auto up = [&](DevBuf &b, const void *h, size_t bytes) {
         if (st != GMT_OK) return;
@@ -638,11 +683,34 @@ extern "C" gmt_status gmt_roadmap_from_csr(const float *samples, int32_t n, int3
     up(rm->s, samples, sizeof(float) * (size_t)dim * n);
     up(rm->in_ptr, row_ptr, sizeof(int) * (n + 1));
     up(rm->in_col, col, sizeof(int) * rm->nnz);
-    up(rm->in_cost, cost, sizeof(double) * rm->nnz);
-    (void)e1;
-    if (kind == GMT_COST_DOUBLE_INTEGRATOR) up(rm->in_tau, tau, sizeof(double) * rm->nnz);
-    if (st == GMT_OK) st = build_out_table(rm, s);
-    if (st == GMT_OK) st = pack_records(rm, s);
+    if (kind == GMT_COST_EUCLIDEAN) {
+        // rows into slots x * cap; the CSR columns and distances are temporaries
+        DevBuf dd;
+        Temps keep(s, {&dd});
+        up(dd, d2.data(), sizeof(unsigned long long) * d2.size());
+        const size_t o_rec = al256(sizeof(int) * (size_t)n);
+        if (st == GMT_OK) st = dev_alloc(rm->tab, o_rec + 8 * ((size_t)n * cap + GMT_REC_PAD), s);
+        if (st == GMT_OK) {
+            rm->cap = cap;
+            rm->deg = dev_view(rm->tab, 0, sizeof(int) * (size_t)n);
+            rm->in_rec = dev_view(rm->tab, o_rec, 8 * ((size_t)n * cap + GMT_REC_PAD));
+            k_row_lengths<<<blocks_for(n, 256), 256, 0, s>>>((const int *)rm->in_ptr.p, n, (int *)rm->deg.p);
+            k_eu_pack<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>(
+                n, cap, (const int *)rm->in_ptr.p, (const int *)rm->in_col.p, (const unsigned long long *)dd.p,
+                (unsigned long long *)rm->in_rec.p);
+            k_rec8_pad<<<blocks_for(GMT_REC_PAD, 256), 256, 0, s>>>((unsigned long long *)rm->in_rec.p,
+                                                                   (long long)n * cap);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = fail(GMT_EDEVICE, "table packing failed: %s", hipGetErrorString(e));
+        }
+        dev_free(rm->in_col, s);
+    } else {
+        up(rm->in_cost, cost, sizeof(double) * rm->nnz);
+        if (kind == GMT_COST_DOUBLE_INTEGRATOR) up(rm->in_tau, tau, sizeof(double) * rm->nnz);
+        if (st == GMT_OK) st = build_out_table(rm, s);
+        if (st == GMT_OK) st = pack_records(rm, s);
+    }
     if (st != GMT_OK) {
         (void)hipStreamSynchronize(s);
         roadmap_release(rm, s);
@@ -724,23 +792,48 @@ extern "C" gmt_status gmt_roadmap_info(gmt_roadmap_t rm, int32_t *n, int32_t *di
     return GMT_OK;
 }
 
+// Euclidean rows as (column, cost) arrays at row_ptr (device temporaries)
+static gmt_status eu_unpack(gmt_roadmap *rm, std::vector<int> &cl, std::vector<double> &cs, hipStream_t s) {
+    const size_t E = (size_t)rm->nnz;
+    if (!E) return GMT_OK;
+    DevBuf t;
+    Temps keep(s, {&t});
+    const size_t o_cost = al256(sizeof(int) * E);
+    TRY(dev_alloc(t, o_cost + sizeof(double) * E, s));
+    k_eu_unpack<<<blocks_for((long long)rm->n * GMT_WAVE, 256), 256, 0, s>>>(
+        rm->n, rm->cap, (const int *)rm->deg.p, (const int *)rm->in_ptr.p,
+        (const unsigned long long *)rm->in_rec.p, (int *)t.p, (double *)((char *)t.p + o_cost));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cl.data(), t.p, sizeof(int) * E, hipMemcpyDeviceToHost, s));
+    if (!cs.empty())
+        HIPCHK(hipMemcpyAsync(cs.data(), (char *)t.p + o_cost, sizeof(double) * E, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return GMT_OK;
+}
+
 extern "C" gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int32_t *col,
                                          double *cost, double *tau, void *stream) {
     if (!rm) return fail(GMT_EINVAL, "null roadmap");
     hipStream_t s = (hipStream_t)stream;
     const size_t E = (size_t)rm->nnz;
     std::vector<int> rp(rm->n + 1), cl(E);
-    std::vector<unsigned int> rc(cost ? 3 * E : 0);
     std::vector<double> cs(cost ? E : 0), ta(tau && rm->in_tau.p ? E : 0);
     HIPCHK(hipMemcpyAsync(rp.data(), rm->in_ptr.p, sizeof(int) * (rm->n + 1), hipMemcpyDeviceToHost, s));
-    if (E) HIPCHK(hipMemcpyAsync(cl.data(), rm->in_col.p, sizeof(int) * E, hipMemcpyDeviceToHost, s));
-    if (E && !rc.empty()) HIPCHK(hipMemcpyAsync(rc.data(), rm->in_rec.p, 12 * E, hipMemcpyDeviceToHost, s));
-    if (E && !ta.empty()) HIPCHK(hipMemcpyAsync(ta.data(), rm->in_tau.p, sizeof(double) * E, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (size_t k = 0; k < cs.size(); ++k) {  // (cost low word, high word, column) records
-        const unsigned long long b = (unsigned long long)rc[3 * k] | ((unsigned long long)rc[3 * k + 1] << 32);
-        std::memcpy(&cs[k], &b, sizeof b);
+    if (rm->kind == GMT_COST_EUCLIDEAN) {
+        TRY(eu_unpack(rm, cl, cs, s));
+    } else {
+        std::vector<unsigned int> rc(cost ? 3 * E : 0);
+        if (E) HIPCHK(hipMemcpyAsync(cl.data(), rm->in_col.p, sizeof(int) * E, hipMemcpyDeviceToHost, s));
+        if (E && !rc.empty()) HIPCHK(hipMemcpyAsync(rc.data(), rm->in_rec.p, 12 * E, hipMemcpyDeviceToHost, s));
+        if (E && !ta.empty())
+            HIPCHK(hipMemcpyAsync(ta.data(), rm->in_tau.p, sizeof(double) * E, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t k = 0; k < cs.size(); ++k) {  // (cost low word, high word, column) records
+            const unsigned long long b = (unsigned long long)rc[3 * k] | ((unsigned long long)rc[3 * k + 1] << 32);
+            std::memcpy(&cs[k], &b, sizeof b);
+        }
     }
+    HIPCHK(hipStreamSynchronize(s));
     // device rows may be in any order (the parent search does not depend on
     // it); exported rows are ascending
     std::vector<int> idx;
@@ -757,6 +850,19 @@ extern "C" gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int
         }
     }
     if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int) * (rm->n + 1));
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_roadmap_bytes(gmt_roadmap_t rm, int64_t *bytes) {
+    if (!rm || !bytes) return fail(GMT_EINVAL, "null argument");
+    int64_t b = 0;
+    for (const DevBuf *d : {&rm->s, &rm->in_ptr, &rm->in_col, &rm->in_cost, &rm->in_tau, &rm->in_rec, &rm->s8,
+                            &rm->tab, &rm->deg})
+        if (d->p && !d->view) b += (int64_t)d->bytes;
+    if (!rm->out_shared)
+        for (const DevBuf *d : {&rm->out_ptr, &rm->out_col})
+            if (d->p && !d->view) b += (int64_t)d->bytes;
+    *bytes = b;
     return GMT_OK;
 }
 
@@ -967,6 +1073,8 @@ static gmt_status stage_query(const QueryIn &q, const gmt_plan_opts &o, ProbDev 
     P.rm.s = (const float *)rm->s.p;
     P.rm.in_ptr = (const int *)rm->in_ptr.p;
     P.rm.in_rec = (const unsigned int *)rm->in_rec.p;
+    P.rm.deg = (const int *)rm->deg.p;
+    P.rm.cap = rm->cap;
     P.rm.s8 = (const float4 *)rm->s8.p;
     P.rm.in_tau = (const double *)rm->in_tau.p;
     P.rm.out_ptr = (const int *)rm->out_ptr.p;

@@ -63,7 +63,13 @@ struct RoadmapDev {
     const float *s;  // SoA [dim][n]
     const float4 *s8;  // double integrator / Dubins: node v's state in s8[2v] (, s8[2v + 1])
     const int *in_ptr;
-    const unsigned int *in_rec;  // per in-edge: edge cost (low, high words), column
+    // double integrator / Dubins: per in-edge, edge cost (low, high words) and
+    // column, rows at in_ptr; Euclidean: 8-byte (d2, column) records, row x in
+    // slots [x * cap, x * cap + deg[x]) -- the table is symmetric, so the
+    // same rows are the out-rows
+    const unsigned int *in_rec;
+    const int *deg;
+    int cap;
     const double *in_tau;  // double integrator only
     const int *out_ptr;
     const int *out_col;
@@ -742,6 +748,83 @@ __device__ __forceinline__ void scan_row(const unsigned char *st, const double *
     }
 }
 
+// in-row of x: the record range the parent search scans
+template <int KIND>
+__device__ __forceinline__ void in_extent(const RoadmapDev &R, int x, int &b, int &e) {
+    if (KIND == 0) {
+        b = x * R.cap;
+        e = b + R.deg[x];
+    } else {
+        b = R.in_ptr[x];
+        e = R.in_ptr[x + 1];
+    }
+}
+
+// out-row of g: the Euclidean records (a symmetric table), else the
+// transposed table's columns
+template <int KIND>
+__device__ __forceinline__ void out_extent(const RoadmapDev &R, int g, int &b, int &e) {
+    if (KIND == 0) {
+        in_extent<0>(R, g, b, e);
+    } else {
+        b = R.out_ptr[g];
+        e = R.out_ptr[g + 1];
+    }
+}
+
+// scan_row over Euclidean records: the edge cost is sqrt(d2) * 2^-20, taken
+// after the state and cost gathers are issued.  Slots past the row end read
+// the next row's slots or the padding (any bits): their column is replaced by
+// x and they are masked off.
+template <int CL, bool EAGER, bool OPEN_COST>
+__device__ __forceinline__ void scan_row8(const unsigned char *st, const double *__restrict__ cost,
+                                          const unsigned int *rec_in, int x, int ib, int ie, int lg,
+                                          double &best, int &by) {
+    typedef __attribute__((address_space(1))) const unsigned long long global_u64;
+    global_u64 *rp = (global_u64 *)rec_in + (ib + lg);
+    for (int f0 = ib + lg; f0 < ie; f0 += SCAN_U * CL, rp += SCAN_U * CL) {
+        unsigned long long r[SCAN_U];
+        int y[SCAN_U];
+        bool in_row[SCAN_U];
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) r[u] = rp[u * CL];
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            in_row[u] = f0 + u * CL < ie;
+            y[u] = in_row[u] ? (int)((unsigned int)r[u] & EU_COL_MASK) : x;
+        }
+        double c[SCAN_U];
+        bool op[SCAN_U];
+        if (OPEN_COST) {
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                c[u] = cost[y[u]];
+                op[u] = in_row[u];
+            }
+        } else {
+            unsigned int sv[SCAN_U];
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                sv[u] = st[y[u]];
+                if (EAGER) c[u] = cost[y[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) op[u] = in_row[u] & ((sv[u] & 3u) == 1u);
+            if (!EAGER) {
+#pragma unroll
+                for (int u = 0; u < SCAN_U; ++u) c[u] = cost[op[u] ? y[u] : x];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const double v = c[u] + sqrt((double)(r[u] >> EU_COL_BITS)) * GMT_INV_QS;
+            const bool better = op[u] & ((v < best) | ((v == best) & (y[u] < by)));
+            best = better ? v : best;
+            by = better ? y[u] : by;
+        }
+    }
+}
+
 __device__ __forceinline__ int ld_cnt(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1047,13 +1130,14 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             const int stride = t.nwaves * per_wave, first = t.wave * per_wave + sub;
             int g1 = first < gc ? gl[first] : 0;
             int g2 = first + stride < gc ? gl[first + stride] : 0;
-            int ob1 = first < gc ? R.out_ptr[g1] : 0, oe1 = first < gc ? R.out_ptr[g1 + 1] : 0;
+            int ob1 = 0, oe1 = 0;
+            if (first < gc) out_extent<KIND>(R, g1, ob1, oe1);
             for (int gb = t.wave * per_wave; gb < gc; gb += stride) {
                 const int gk = gb + sub;
                 const int ob = ob1, oe = oe1;
                 g1 = g2;
-                ob1 = gk + stride < gc ? R.out_ptr[g1] : 0;
-                oe1 = gk + stride < gc ? R.out_ptr[g1 + 1] : 0;
+                ob1 = oe1 = 0;
+                if (gk + stride < gc) out_extent<KIND>(R, g1, ob1, oe1);
                 g2 = gk + 2 * stride < gc ? gl[gk + 2 * stride] : 0;
                 if (gk < gc && lg == 0) w_out += (unsigned long long)(oe - ob);
                 // FRONT_U out-edges per lane per step: their loads are issued
@@ -1066,7 +1150,9 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                     for (int u = 0; u < FRONT_U; ++u) {
                         const int e = e0 + u * CL;
                         val[u] = e < oe;
-                        xs[u] = ((global_u32 *)R.out_col)[val[u] ? e : e0];
+                        xs[u] = KIND == 0
+                                    ? (int)(((global_u32 *)R.in_rec)[2 * (long long)(val[u] ? e : e0)] & EU_COL_MASK)
+                                    : ((global_u32 *)R.out_col)[val[u] ? e : e0];
                     }
                     unsigned int sx[FRONT_U];
 #pragma unroll
@@ -1118,15 +1204,15 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             const int first = t.wave * per_wave + sub;
             int x_next = first < cc ? w.clist[first] : 0;
             int x_next2 = first + stride < cc ? w.clist[first + stride] : 0;
-            int ib_next = first < cc ? R.in_ptr[x_next] : 0;
-            int ie_next = first < cc ? R.in_ptr[x_next + 1] : 0;
+            int ib_next = 0, ie_next = 0;
+            if (first < cc) in_extent<KIND>(R, x_next, ib_next, ie_next);
             for (int base = t.wave * per_wave; base < cc; base += stride) {
                 const int k = base + sub;
                 const bool active = k < cc;
                 const int x = x_next, ib = ib_next, ie = ie_next;
                 x_next = x_next2;
-                ib_next = k + stride < cc ? R.in_ptr[x_next] : 0;
-                ie_next = k + stride < cc ? R.in_ptr[x_next + 1] : 0;
+                ib_next = ie_next = 0;
+                if (k + stride < cc) in_extent<KIND>(R, x_next, ib_next, ie_next);
                 x_next2 = k + 2 * stride < cc ? w.clist[k + 2 * stride] : 0;
                 double best = __longlong_as_double(COST_INF_BITS);
                 int by = 0x7fffffff, be = -1;
@@ -1137,7 +1223,10 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
                         w_in += (unsigned long long)(ie - ib);
                         ++w_cand;
                     }
-                    scan_row<CL, LDS == 0, OC>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
+                    if (KIND == 0)
+                        scan_row8<CL, LDS == 0, OC>(st, cost, in_rec, x, ib, ie, lg, best, by);
+                    else
+                        scan_row<CL, LDS == 0, OC>(st, cost, in_rec, x, ib, ie, lg, best, by, be);
                 }
                 group_argmin<CL>(best, by, be);
                 const bool ok = active && best < __longlong_as_double(COST_INF_BITS);

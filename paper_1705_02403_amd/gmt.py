@@ -40,7 +40,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 # symbols the header declares (checked by the CPU tests)
-EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_build_neighbors_ex", "gmt_sample_halton", "gmt_roadmap_from_csr", "gmt_roadmap_info",
+EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_build_neighbors_ex", "gmt_sample_halton", "gmt_roadmap_from_csr", "gmt_roadmap_info", "gmt_roadmap_bytes",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_noalloc", "gmt_plan_batch",
            "gmt_last_work", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
@@ -209,6 +209,7 @@ def lib():
             L.gmt_roadmap_from_csr.argtypes = [P, i32, i32, i32, f64, P, P, P, P, P, C.POINTER(P)]
             L.gmt_roadmap_info.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                            C.POINTER(i64)]
+            L.gmt_roadmap_bytes.argtypes = [P, C.POINTER(C.c_int64)]
             L.gmt_roadmap_export.argtypes = [P, P, P, P, P, P]
             L.gmt_roadmap_free.argtypes = [P]
             L.gmt_plan.argtypes = [P, P, C.POINTER(gmt_goal), P, i32, f64, C.POINTER(gmt_plan_opts),
@@ -355,6 +356,13 @@ class Roadmap:
         _check(lib().gmt_roadmap_info(self.handle, C.byref(n), C.byref(d), C.byref(k), C.byref(e)),
                "gmt_roadmap_info")
         return int(e.value)
+
+    @property
+    def device_bytes(self) -> int:
+        """Device memory the roadmap holds."""
+        b = C.c_int64()
+        _check(lib().gmt_roadmap_bytes(self.handle, C.byref(b)), "gmt_roadmap_bytes")
+        return int(b.value)
 
     def export(self, stream=None):
         """(row_ptr, col, cost, tau) of the in-neighbour table as numpy arrays."""

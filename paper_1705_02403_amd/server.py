@@ -22,10 +22,19 @@ import numpy as np
 from . import gmt
 
 
-def roadmap_bytes(n: int, dim: int, kind: int, nnz: int) -> int:
-    """Device bytes of a roadmap: samples, row pointers, the in-table (columns,
-    plus (cost, column) records with 256 padding records) and the out-table."""
-    b = 4 * dim * n + 4 * (n + 1) + 4 * nnz + 12 * (nnz + 256)
+def roadmap_bytes(n: int, dim: int, kind: int, nnz: int, cap: int = 0) -> int:
+    """Device bytes of a roadmap, estimated before it is built: samples, row
+    pointers and records.  Euclidean: row lengths and `cap` 8-byte slots per
+    row (the expected degree, or nnz / n when cap is not given) plus 256
+    padding slots.  Otherwise: columns, 12-byte (cost, column) records plus
+    256 padding records, and for the double integrator arrival times, the
+    transposed table and 8-float states.  A built roadmap reports its own
+    figure (Roadmap.device_bytes)."""
+    b = 4 * dim * n + 4 * (n + 1)
+    if kind == gmt.GMT_COST_EUCLIDEAN:
+        slots = n * cap if cap else nnz
+        return b + 4 * n + 8 * (slots + 256)
+    b += 4 * nnz + 12 * (nnz + 256)
     if kind == gmt.GMT_COST_DOUBLE_INTEGRATOR:
         b += 8 * nnz + 4 * (n + 1) + 4 * nnz + 32 * n  # arrival times, transposed table, 8-float states
     return b
@@ -38,7 +47,7 @@ class RoadmapCache:
                  size_of: Callable[["gmt.Roadmap"], int] = None):
         self.budget = int(budget)
         self.build = build
-        self.size_of = size_of or (lambda rm: roadmap_bytes(rm.n, rm.dim, rm.kind, rm.nnz))
+        self.size_of = size_of or (lambda rm: rm.device_bytes)
         self.items: "collections.OrderedDict[Hashable, list]" = collections.OrderedDict()
         self.bytes = 0
         self.hits = 0

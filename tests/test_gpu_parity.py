@@ -8,6 +8,8 @@ code; trees must match wherever the oracle's decision margins exceed what
 FP64 rounding can move, and costs agree to 1e-12 relative.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -116,6 +118,59 @@ def test_euclid_table_clustered(dim, n, extent, r):
     np.testing.assert_array_equal(rp, ref.row_ptr)
     np.testing.assert_array_equal(col, ref.col)
     np.testing.assert_array_equal(cost, ref.cost)
+    rm.free()
+
+
+def test_euclid_table_import_and_bytes():
+    """The oracle's table imported through gmt_roadmap_from_csr plans the
+    same trees as the built one; a cost that is not the samples' distance is
+    refused; device bytes cover the records."""
+    prob = I.problem_2d(4, n=3000)
+    r = O.euclid_radius(prob)
+    say("euclid import 2D n %d" % prob.n)
+    ref_tab = O.neighbors(prob.samples, O.EUCLID, r)
+    built = build(prob, r)
+    imp = gmt.gmt_roadmap_from_csr(prob.samples, gmt.GMT_COST_EUCLIDEAN, r, ref_tab.row_ptr, ref_tab.col,
+                                   ref_tab.cost)
+    rp, col, cost, _ = imp.export()
+    np.testing.assert_array_equal(rp, ref_tab.row_ptr)
+    np.testing.assert_array_equal(col, ref_tab.col)
+    np.testing.assert_array_equal(cost, ref_tab.cost)
+    ref = O.plan(prob, r)
+    for rm in (built, imp):
+        res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, prob.lam, opts_of(prob))
+        compare_tree(res, ref)
+        assert rm.device_bytes >= 8 * rm.nnz + 4 * 2 * prob.n
+    bad = ref_tab.cost.copy()
+    bad[len(bad) // 2] = np.nextafter(bad[len(bad) // 2], 1.0)
+    with pytest.raises(gmt.GmtError) as e:
+        gmt.gmt_roadmap_from_csr(prob.samples, gmt.GMT_COST_EUCLIDEAN, r, ref_tab.row_ptr, ref_tab.col, bad)
+    assert e.value.status == gmt.GMT_EINVAL
+    built.free()
+    imp.free()
+
+
+def test_plan_on_clustered_table():
+    """A table whose rows outgrow the first capacity estimate (the pass runs
+    again with the longest row's length) plans the oracle's tree."""
+    s = I.clustered_samples(12, 2, 2500, 0.05)
+    base = I.geometric_problem(3, 2, 16, 0, 0.1, 0.2, step=0.001, goal_radius=0.004, start=0.0, goal=0.05)
+    box = I.from_grid(I.to_grid(np.array([[0.015, 0.02, 0.035, 0.03]])))
+    prob = dataclasses.replace(base, samples=s, boxes=np.ascontiguousarray(box.astype(np.float32)))
+    r = 0.012
+    say("euclid clustered plan")
+    gmt.gmt_profile_enable(True)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_EUCLIDEAN, r)
+    info = gmt.gmt_last_build()
+    gmt.gmt_profile_enable(False)
+    gmt.gmt_profile_read()
+    assert info["segments"] == 2  # rows of up to 497 past the estimate of 24 slots
+    rp, col, cost, _ = rm.export()
+    ref_tab = O.neighbors(s, O.EUCLID, r)
+    np.testing.assert_array_equal(col, ref_tab.col)
+    np.testing.assert_array_equal(cost, ref_tab.cost)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, prob.lam, opts_of(prob))
+    compare_tree(res, O.plan(prob, r))
     rm.free()
 
 

@@ -49,6 +49,8 @@ def test_pinned_roadmaps_are_not_evicted():
 
 def test_roadmap_bytes_formula():
     e = server.roadmap_bytes(100, 2, gmt.GMT_COST_EUCLIDEAN, 1000)
+    ec = server.roadmap_bytes(100, 2, gmt.GMT_COST_EUCLIDEAN, 1000, cap=16)
     d = server.roadmap_bytes(100, 6, gmt.GMT_COST_DOUBLE_INTEGRATOR, 1000)
-    assert e == 4 * 200 + 404 + 4000 + 12 * (1000 + 256)
+    assert e == 4 * 200 + 404 + 400 + 8 * (1000 + 256)
+    assert ec == 4 * 200 + 404 + 400 + 8 * (1600 + 256)
     assert d == 4 * 600 + 404 + 4000 + 12 * (1000 + 256) + 8000 + 404 + 4000 + 3200
