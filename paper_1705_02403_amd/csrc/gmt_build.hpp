@@ -3,22 +3,23 @@
 // before Algorithm 1).
 //
 // Euclidean (dim 2/3): samples are binned into a uniform grid of cells with
-// edge >= r, so every neighbour of a sample lies in the 3^d cells around it.
-// One wave owns one row: lanes stride over the members of those cells
-// (coalesced reads of the cell-sorted coordinate copy), test d2 < fl(r*r) 2^40
-// exactly in integers, compact hits into LDS by ballot, sort the row by
-// neighbour index in LDS and write it out.  Rows are visited in cell order
-// so neighbouring waves read the same cells.
+// edge >= r/2 and copied in cell order; a workgroup stages the samples around
+// a tile of cells in LDS and each wave scans, for one row at a time, the
+// slabs of cells within r of the row, first in FP32 with a margin above the
+// rounding error, then exactly in FP64 for the pairs that pass (k_eu_rows).
+// Rows are fixed-capacity slots of 8-byte (exact d2, column) records.
 //
-// Double integrator (dim 6): the cost is asymmetric and velocity-dependent,
+// Double integrator and Dubins airplane (dim 6 / 4): the cost is asymmetric,
 // so no spatial pruning holds at the workloads' radius; one wave owns one
 // target row x and streams all sources y in index order.  A cheap exact
-// lower bound rejects ~94% of pairs; survivors are queued in LDS and solved
+// lower bound rejects most pairs; survivors are queued in LDS and solved
 // 64 at a time (full lanes); hits keep index order, so rows come out sorted.
 #pragma once
 
 #include "gmt_dev.hpp"
 #include "gmt_dubins.hpp"
+
+#include <type_traits>
 
 namespace gmt {
 
@@ -225,30 +226,52 @@ __global__ void k_eu_bin(const float *__restrict__ s, int n, EuGrid g, int *__re
     atomicAdd(&cell_cnt[c], 1);
 }
 
-// cell-sorted copy of the samples: pts[pos] = (grid coordinates, sample index)
+// cell-sorted copy of the samples: pts[pos] = (grid coordinates as floats,
+// sample index as the bits of w); grid coordinates are integers below 2^21,
+// exact in FP32, and so is the difference of two of them
 __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
                              const int *__restrict__ cell_of, const int *__restrict__ cell_start,
-                             int *__restrict__ cursor, int4 *__restrict__ pts) {
+                             int *__restrict__ cursor, float4 *__restrict__ pts) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = cell_of[i];
     int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
     int q[3] = {0, 0, 0};
     for (int a = 0; a < g.dim; ++a) q[a] = eu_q(s[(size_t)a * n + i]);
-    pts[pos] = make_int4(q[0], q[1], q[2], i);
+    pts[pos] = make_float4((float)q[0], (float)q[1], (float)q[2], __int_as_float(i));
 }
 
-// Rows of the Euclidean table, one pass.  Cells have edge >= r/2 (G per
-// axis), so the r-ball of a sample lies in the 5^d cells around its own; the
-// samples are sorted by cell (pts).  One 256-thread workgroup takes EU_XB
-// cells that follow each other along x: it stages the samples of the cells
-// within two cells of them in LDS (at most 25 runs of the sorted order,
-// cells along x being contiguous) in chunks of EU_CHUNK, padded to a multiple
-// of 128 with samples far outside every r-ball, and each wave takes rows in
-// turn and tests the staged samples 128 at a time (two per lane, their LDS
-// reads issued together).  Grid coordinates differ by less than 2^30, so d2 =
-// |q_i - q_j|^2 is exact in FP64 for real pairs (each square below 2^42, the
-// sum below 2^53) and far above r^2 for the padding.
+// Rows of the Euclidean table, one pass.  Cells have edge h >= r / EU_W
+// (G per axis; cell id (z G + y) G + x in 3D, y G + x in 2D), so the r-ball
+// of a sample lies in the (2 EU_W + 1)^d cells around its own, and a sample
+// more than EU_W cells away along any axis is at least EU_W h >= r away.
+//
+// Tiles.  A workgroup of EU_WAVES waves takes EU_XB cells that follow each
+// other along the slowest axis (z in 3D, y in 2D: the "slab" axis) at one
+// (x, y) resp. x; their samples are its rows.  It stages in LDS the samples of
+// the slabs within EU_W cells of them, slab after slab: inside a slab each
+// line of cells along x within EU_W of the tile's x is one contiguous run of
+// the cell-sorted samples, and every thread loads its share of the staging at
+// once (the run of each element found by binary search).  A row then scans
+// one contiguous window of the staging, its own 2 EU_W + 1 slabs, in steps of
+// up to four blocks of 64 samples (one per lane per block, the LDS reads of a
+// step issued together); the last step reads at most 127 samples past the
+// window, which only adds pairs farther than r apart.  Staging goes in chunks
+// of EU_CHUNK followed by EU_PAD samples far outside every r-ball.  Tiles are
+// ordered so that each of the eight XCDs (which take workgroups in turn)
+// works through one contiguous range of neighbouring tiles, which stage mostly
+// the same samples, through its own L2.
+//
+// Each pair is first tested in FP32 against fl(R2 (1 + 2^-20)) rounded up:
+// the coordinate differences are exact and the three rounded operations of
+// d2 = dx dx + dy dy + dz dz err by less than 3 2^-24 relative, so every pair
+// with d2 < R2 passes.  The staging slots of passing pairs are appended per
+// wave to an LDS buffer of EU_OBUF entries (ballot and lane count); writing
+// them out decides each exactly: d2 is summed in FP64 onto 2^52, where every
+// partial sum is an integer below 2^53 and so exact, the pair is an edge iff
+// that sum is below 2^52 + ceil(R2) (R2 is the squared radius in grid units)
+// and the row's own sample is not the candidate, and the low 52 bits of the
+// sum are d2 itself.
 //
 // Row x has `cap` slots at x * cap: each edge is one 8-byte record, the exact
 // squared grid distance d2 (< 3 * 2^40, 42 bits) above the column (22 bits).
@@ -256,100 +279,187 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
 // reads the columns.  Edges past `cap` are counted but not written: deg[x] is
 // the full row length and *maxdeg its maximum, so the host can rerun the pass
 // with a larger cap.  Rows come out in staging order (the parent search does
-// not depend on it): each wave gathers the staging slots of its row's edges in
-// an LDS buffer of EU_OBUF entries and writes them out in contiguous runs.
+// not depend on it).
+#ifndef EU_W
+#define EU_W 2
+#endif
 #ifndef EU_XB
-#define EU_XB 2
+#define EU_XB 4
 #endif
 #ifndef EU_CHUNK
-#define EU_CHUNK 1280
+#define EU_CHUNK 2304
 #endif
-#define EU_ROWS 512
+#ifndef EU_WAVES
+#define EU_WAVES 8
+#endif
+#define EU_SPAN (2 * EU_W + 1)
+#define EU_THREADS (EU_WAVES * GMT_WAVE)
+#define EU_ROWS 256
 #define EU_OBUF 256
-#define EU_FAR (1 << 29)
-static_assert(EU_CHUNK % 256 == 0 && EU_CHUNK <= 65536 && EU_OBUF >= 128, "staging and output buffer shapes");
+#define EU_FAR 536870912.0f  // 2^29 grid units: beyond every r-ball
+#define EU_RUNS ((EU_XB + 2 * EU_W) * EU_SPAN)
+#define EU_PAD 128
+#define EU_STAGE (EU_CHUNK + EU_PAD)
+static_assert(EU_CHUNK % 128 == 0 && EU_CHUNK <= 65536 && EU_OBUF >= 4 * GMT_WAVE && EU_RUNS <= 256 && EU_WAVES >= 2,
+              "staging and output buffer shapes");
 
-__device__ __forceinline__ double eu_d2(const int4 &c, const int4 &q) {
-    const double d0 = (double)(c.x - q.x), d1 = (double)(c.y - q.y), d2 = (double)(c.z - q.z);
-    return d0 * d0 + d1 * d1 + d2 * d2;
+// cells along x, y (3D) and tiles along the slab axis, in launch order
+__host__ __device__ inline int eu_tiles(int G, int dim) {
+    return G * (dim == 3 ? G : 1) * ((G + EU_XB - 1) / EU_XB);
 }
 
-__global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restrict__ pts,
-                                                 const int *__restrict__ cell_start, double R2, int cap,
-                                                 int *__restrict__ deg, int *__restrict__ maxdeg,
-                                                 unsigned long long *__restrict__ rec,
-                                                 unsigned long long *__restrict__ tested) {
-    __shared__ int4 cand[EU_CHUNK];
-    // per wave: EU_OBUF slots, then one that lanes without an edge write to
-    __shared__ unsigned short oslot[4 * (EU_OBUF + 2)];
+__global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *__restrict__ pts,
+                                                        const int *__restrict__ cell_start, float R2f,
+                                                        double R2b, int cap, int *__restrict__ deg,
+                                                        int *__restrict__ maxdeg,
+                                                        unsigned long long *__restrict__ rec,
+                                                        unsigned long long *__restrict__ tested) {
+    __shared__ float4 cand[EU_STAGE];
+    // per wave: staging slots of the row's passing pairs, then one slot per lane
+    __shared__ int oslot[EU_WAVES * EU_OBUF];
     __shared__ int rcnt[EU_ROWS];
-    __shared__ int sb[25], soff[26];
-    const int G = g.G;
-    const int GX = (G + EU_XB - 1) / EU_XB;
-    const int bx = blockIdx.x % GX, yz = blockIdx.x / GX;
-    const int cy = yz % G, cz = g.dim == 3 ? yz / G : 0;
-    const int cx0 = bx * EU_XB, cx1 = min(cx0 + EU_XB, G) - 1;
-    const int rowc = (cz * G + cy) * G;
-    const int p0 = cell_start[rowc + cx0], p1 = cell_start[rowc + cx1 + 1];
-    if (p0 == p1) return;  // no rows: the whole workgroup leaves
-    const int tid = threadIdx.x, wave = tid / GMT_WAVE, lane = lane_id();
-    const int zr = g.dim == 3 ? 2 : 0;
-    const int nspan = (2 * zr + 1) * 5;
-    if (tid < nspan) {
-        const int z = cz + tid / 5 - zr, y = cy + tid % 5 - 2;
-        int b = 0, e = 0;
-        if (z >= 0 && z < (g.dim == 3 ? G : 1) && y >= 0 && y < G) {
-            const int rc = (z * G + y) * G;
-            b = cell_start[rc + max(cx0 - 2, 0)];
-            e = cell_start[rc + min(cx1 + 2, G - 1) + 1];
+    __shared__ int sb[EU_RUNS], soff[EU_RUNS + 1];
+    __shared__ int rbeg[EU_XB], rpre[EU_XB + 1];
+    __shared__ unsigned long long wtest;
+    const int G = g.G, dim = g.dim;
+    const int nm = dim == 3 ? G : 1;
+    const int ntile = eu_tiles(G, dim);
+    int b = blockIdx.x;
+    {
+        const int per = ntile / 8, rem = ntile % 8, x = b % 8;
+        b = x * per + min(x, rem) + b / 8;
+    }
+    const int cx = b % G, cm = (b / G) % nm, s0 = (b / G / nm) * EU_XB;
+    const int s1 = min(s0 + EU_XB, G) - 1;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / GMT_WAVE), lane = lane_id();
+    const int nmid = dim == 3 ? EU_SPAN : 1;
+    const int xs0 = max(s0 - EU_W, 0), xs1 = min(s1 + EU_W, G - 1);
+    const int nrun = (xs1 - xs0 + 1) * nmid;
+    const int xlo = max(cx - EU_W, 0), xhi = min(cx + EU_W, G - 1);
+    // run k: slab xs0 + k / nmid, line y = cm - EU_W + k % nmid, cells xlo..xhi
+    for (int k = tid; k < nrun; k += EU_THREADS) {
+        const int sl = xs0 + k / nmid, m = dim == 3 ? cm - EU_W + k % nmid : 0;
+        int bb = 0, e = 0;
+        if (m >= 0 && m < nm) {
+            const int line = (sl * nm + m) * G;
+            bb = cell_start[line + xlo];
+            e = cell_start[line + xhi + 1];
         }
-        sb[tid] = b;
-        soff[tid + 1] = e - b;
+        sb[k] = bb;
+        soff[k + 1] = e - bb;
     }
-    __syncthreads();
+    if (tid < EU_XB) {
+        const int sl = s0 + tid;
+        int bb = 0, e = 0;
+        if (sl <= s1) {
+            const int c = (sl * nm + cm) * G + cx;
+            bb = cell_start[c];
+            e = cell_start[c + 1];
+        }
+        rbeg[tid] = bb;
+        rpre[tid + 1] = e - bb;
+    }
     if (tid == 0) {
-        soff[0] = 0;
-        for (int k = 1; k <= nspan; ++k) soff[k] += soff[k - 1];
+        wtest = 0;
+        rpre[0] = 0;
     }
     __syncthreads();
-    const int total = soff[nspan];
-    unsigned short *wslot = oslot + wave * (EU_OBUF + 2);
-    for (int rb = p0; rb < p1; rb += EU_ROWS) {  // blocks of rows
-        const int nr = min(EU_ROWS, p1 - rb);
-        for (int i = tid; i < nr; i += 256) rcnt[i] = 0;
+    if (wave == 0) {  // exclusive scan of the run lengths, four per lane
+        int v[4], acc = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = 4 * lane + u;
+            v[u] = k < nrun ? soff[k + 1] : 0;
+            acc += v[u];
+        }
+        int x = acc;
+#pragma unroll
+        for (int off = 1; off < GMT_WAVE; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        int run = x - acc;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = 4 * lane + u;
+            if (k < nrun) soff[k] = run;
+            run += v[u];
+        }
+        if (lane == GMT_WAVE - 1) soff[nrun] = x;
+    } else if (tid == GMT_WAVE) {
+        for (int j = 1; j <= EU_XB; ++j) rpre[j] += rpre[j - 1];
+    }
+    __syncthreads();
+    const int nrows = rpre[EU_XB];
+    if (nrows == 0) return;  // the same for the whole workgroup
+    const int total = soff[nrun];
+    int *wslot = oslot + wave * EU_OBUF;
+    unsigned long long ntest = 0;
+    // sample index (position in pts) and slab of row ri of the tile
+    auto row_at = [&](int ri, int &slab) {
+        int j = 0;
+#pragma unroll
+        for (int t = 1; t < EU_XB; ++t)
+            if (ri >= rpre[t]) j = t;
+        slab = s0 + j;
+        return rbeg[j] + (ri - rpre[j]);
+    };
+    for (int r0 = 0; r0 < nrows; r0 += EU_ROWS) {  // blocks of rows
+        const int nr = min(EU_ROWS, nrows - r0);
+        for (int i = tid; i < nr; i += EU_THREADS) rcnt[i] = 0;
         for (int c0 = 0; c0 < total; c0 += EU_CHUNK) {
             const int cnt = min(EU_CHUNK, total - c0);
-            const int cntp = (cnt + 127) & ~127;
             __syncthreads();  // the previous chunk is no longer read
-            // stage [c0, c0 + cnt) and the padding up to cntp: up to
-            // EU_CHUNK / 256 samples per thread, loads issued together
-            constexpr int SU = EU_CHUNK / 256;
-            int4 v[SU];
+            // stage [c0, c0 + cnt): run by run, a wave per run, the first 64
+            // samples of each of a wave's runs loaded together
+            {
+                // stage [c0, c0 + cnt): every thread's loads issued together,
+                // the run of each element found by binary search
+                constexpr int SU = (EU_CHUNK + EU_THREADS - 1) / EU_THREADS;
+                float4 v[SU];
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                const int k = tid + u * 256;
-                v[u] = make_int4(EU_FAR, EU_FAR, EU_FAR, -1);
-                if (k < cnt) {
-                    const int f = c0 + k;
-                    int lo = 0, hi = nspan;  // soff[lo] <= f < soff[hi]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (soff[mid] <= f) lo = mid;
-                        else hi = mid;
+                for (int u = 0; u < SU; ++u) {
+                    const int e = tid + u * EU_THREADS;
+                    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (e < cnt) {
+                        const int f = c0 + e;
+                        int lo = 0, hi = nrun;  // soff[lo] <= f < soff[hi]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (soff[mid] <= f) lo = mid;
+                            else hi = mid;
+                        }
+                        v[u] = pts[sb[lo] + (f - soff[lo])];
                     }
-                    v[u] = pts[sb[lo] + (f - soff[lo])];
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < SU; ++u)
-                if (tid + u * 256 < cntp) cand[tid + u * 256] = v[u];
+                for (int u = 0; u < SU; ++u)
+                    if (tid + u * EU_THREADS < cnt) cand[tid + u * EU_THREADS] = v[u];
+            }
+            for (int k = tid; k < EU_PAD; k += EU_THREADS)
+                cand[cnt + k] = make_float4(EU_FAR, EU_FAR, EU_FAR, __int_as_float(-1));
             __syncthreads();
-            for (int ri = wave; ri < nr; ri += 4) {
-                const int4 q = pts[rb + ri];
-                int run = 0, fill = 0;
-                int slot0 = rcnt[ri];  // slots of this row already taken
-                // write the buffered entries of this row out, those that fit
-                // (up to EU_OBUF / 64 entries per lane, their LDS reads issued together)
+            int sn;
+            int pn = wave < nr ? row_at(r0 + wave, sn) : 0;
+            float4 qn = wave < nr ? pts[pn] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int ri = wave; ri < nr; ri += EU_WAVES) {
+                const float4 q = qn;
+                const int slab = sn;
+                if (ri + EU_WAVES < nr) {  // the wave's next row, loaded early
+                    pn = row_at(r0 + ri + EU_WAVES, sn);
+                    qn = pts[pn];
+                }
+                const int qi = __float_as_int(q.w);
+                const int wlo = soff[(max(slab - EU_W, 0) - xs0) * nmid];
+                const int whi = soff[(min(slab + EU_W, G - 1) - xs0 + 1) * nmid];
+                // uniform across the wave: scalar loop control
+                const int lo = __builtin_amdgcn_readfirstlane(max(wlo, c0) - c0);
+                const int hi = __builtin_amdgcn_readfirstlane(min(whi, c0 + cnt) - c0);
+                if (lo >= hi) continue;
+                const double qx = (double)q.x, qy = (double)q.y, qz = (double)q.z;
+                int fill = 0;
+                int slot0 = __builtin_amdgcn_readfirstlane(rcnt[ri]);  // edges of this row already counted
+                // decide the buffered pairs exactly, write the edges that fit
                 auto flush = [&]() {
                     constexpr int FU = EU_OBUF / GMT_WAVE;
                     __builtin_amdgcn_wave_barrier();
@@ -359,50 +469,80 @@ __global__ void __launch_bounds__(256) k_eu_rows(EuGrid g, const int4 *__restric
                         const int raw = wslot[lane + u * GMT_WAVE];
                         sl[u] = lane + u * GMT_WAVE < fill ? raw : 0;
                     }
-                    int4 c[FU];
+                    float4 c[FU];
 #pragma unroll
                     for (int u = 0; u < FU; ++u) c[u] = cand[sl[u]];
-                    unsigned long long *r = rec + (long long)q.w * cap;
+                    unsigned long long *r = rec + (long long)qi * cap;
 #pragma unroll
                     for (int u = 0; u < FU; ++u) {
-                        const int k = slot0 + lane + u * GMT_WAVE;
-                        if (lane + u * GMT_WAVE < fill && k < cap) {
-                            const unsigned long long d2 = (unsigned long long)eu_d2(c[u], q);
-                            r[k] = (d2 << EU_COL_BITS) | (unsigned long long)(unsigned int)c[u].w;
+                        if (u * GMT_WAVE >= fill) break;
+                        const double dx = (double)c[u].x - qx, dy = (double)c[u].y - qy,
+                                     dz = (double)c[u].z - qz;
+                        const double d2b = fma(dz, dz, fma(dy, dy, fma(dx, dx, 4503599627370496.0)));
+                        const bool ok = lane + u * GMT_WAVE < fill && d2b < R2b && __float_as_int(c[u].w) != qi;
+                        const uint64_t m = wave_ballot(ok);
+                        const int k = slot0 + lanes_below(m);
+                        if (ok && k < cap) {
+                            const unsigned long long d2 =
+                                (unsigned long long)__double_as_longlong(d2b) & 0xFFFFFFFFFFFFFull;
+                            r[k] = (d2 << EU_COL_BITS) | (unsigned long long)(unsigned int)__float_as_int(c[u].w);
                         }
+                        slot0 += (int)__popcll(m);
                     }
                     __builtin_amdgcn_wave_barrier();
-                    slot0 += fill;
                     fill = 0;
                 };
-                for (int k0 = 0; k0 < cntp; k0 += 2 * GMT_WAVE) {
-                    const int4 ca = cand[k0 + lane], cb = cand[k0 + GMT_WAVE + lane];
-                    const double da = eu_d2(ca, q), db = eu_d2(cb, q);
-                    const uint64_t ma = wave_ballot(da < R2 && ca.w != q.w);
-                    const uint64_t mb = wave_ballot(db < R2 && cb.w != q.w);
-                    const bool oka = (ma >> lane) & 1ull, okb = (mb >> lane) & 1ull;
-                    const int pa = (int)__popcll(ma), pb = (int)__popcll(mb);
-                    if (fill + pa + pb > EU_OBUF) flush();
-                    wslot[oka ? fill + lanes_below(ma) : EU_OBUF] = (unsigned short)(k0 + lane);
-                    wslot[okb ? fill + pa + lanes_below(mb) : EU_OBUF] = (unsigned short)(k0 + GMT_WAVE + lane);
-                    fill += pa + pb;
-                    run += pa + pb;
-                }
-                flush();
-                if (lane == 0) rcnt[ri] += run;
+                // one step: 64 (G = 1) to 256 (G = 4) samples, one per lane per
+                // block, the LDS reads of the step issued together
+                auto step = [&](int k0, auto GB) {
+                    constexpr int NB = decltype(GB)::value;
+                    float4 c[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) c[u] = cand[k0 + u * GMT_WAVE + lane];
+                    bool h[NB];
+                    uint64_t m[NB];
+                    int tot = 0;
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const float dx = c[u].x - q.x, dy = c[u].y - q.y, dz = c[u].z - q.z;
+                        h[u] = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < R2f;
+                        m[u] = (uint64_t)__builtin_amdgcn_ballot_w64(h[u]);
+                        tot += (int)__popcll(m[u]);
+                    }
+                    if (fill + tot > EU_OBUF) flush();
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        if (h[u]) wslot[fill + lanes_below(m[u])] = k0 + u * GMT_WAVE + lane;
+                        fill += (int)__popcll(m[u]);
+                    }
+                };
+                // whole steps of four blocks, then one step of four, two or one
+                // blocks for the rest (at most 127 samples past the window)
+                int k0 = lo;
+                for (; k0 + 4 * GMT_WAVE <= hi; k0 += 4 * GMT_WAVE) step(k0, std::integral_constant<int, 4>());
+                const int rest = hi - k0;
+                if (rest > 2 * GMT_WAVE) step(k0, std::integral_constant<int, 4>());
+                else if (rest > GMT_WAVE) step(k0, std::integral_constant<int, 2>());
+                else if (rest > 0) step(k0, std::integral_constant<int, 1>());
+                ntest += (unsigned long long)(k0 - lo) +
+                         (rest > 2 * GMT_WAVE ? 4 : rest > GMT_WAVE ? 2 : rest > 0 ? 1 : 0) * GMT_WAVE;
+                if (fill) flush();
+                if (lane == 0) rcnt[ri] = slot0;
             }
         }
         __syncthreads();
-        for (int i = tid; i < nr; i += 256) {
-            deg[pts[rb + i].w] = rcnt[i];
+        for (int i = tid; i < nr; i += EU_THREADS) {
+            int sl;
+            const int pi = row_at(r0 + i, sl);
+            deg[__float_as_int(pts[pi].w)] = rcnt[i];
             atomicMax(maxdeg, rcnt[i]);
         }
     }
-    if (tested && tid == 0) {
-        // distance tests: every row of the workgroup against every staged slot
-        unsigned long long slots = 0;
-        for (int c0 = 0; c0 < total; c0 += EU_CHUNK) slots += (unsigned long long)((min(EU_CHUNK, total - c0) + 127) & ~127);
-        atomicAdd(tested, slots * (unsigned long long)(p1 - p0));
+    if (tested) {
+        // pairs tested in FP32, the windows rounded up to whole steps
+        if (lane == 0) atomicAdd(&wtest, ntest);
+        __syncthreads();
+        if (tid == 0) atomicAdd(tested, wtest);
     }
 }
 

@@ -381,11 +381,17 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     // 4 * 2^40, so a larger radius selects the same pairs (and the kernel's
     // padding samples stay outside)
     const double R2 = std::min(rm->r * rm->r * GMT_Q2, 4.0 * GMT_Q2);
+    // the exact test of an integer d2 < R2 as a sum biased by 2^52, and the
+    // FP32 pre-test's bound, above R2 by more than its rounding error
+    const double R2b = 4503599627370496.0 + std::ceil(R2);
+    const double R2hi = R2 * (1.0 + std::ldexp(1.0, -20));
+    float R2f = (float)R2hi;
+    if ((double)R2f < R2hi) R2f = std::nextafter(R2f, INFINITY);
     EuGrid g;
     g.dim = dim;
-    // cells of edge >= r/2 (the 5^d cells around a sample cover its r-ball),
-    // at most about one cell per sample
-    const double per_axis = std::floor(2.0 / rm->r);
+    // cells of edge >= r / EU_W (the (2 EU_W + 1)^d cells around a sample
+    // cover its r-ball), at most about one cell per sample
+    const double per_axis = std::floor((double)EU_W / rm->r);
     const int Gmax = dim == 2 ? 2048 : 160;
     const int Gn = (int)std::floor(std::pow((double)n, 1.0 / dim)) + 1;
     g.G = (int)std::max(1.0, std::min({per_axis, (double)Gmax, (double)Gn}));
@@ -398,7 +404,7 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     const size_t o_start = o_cnt + al256(sizeof(int) * nc);
     const size_t o_cur = o_start + al256(sizeof(int) * (nc + 1));
     const size_t o_pts = o_cur + al256(sizeof(int) * nc);
-    const size_t o_scal = o_pts + al256(sizeof(int4) * (size_t)n);  // [0] flags, [1] maxdeg, [2..3] total, [4..5] tests
+    const size_t o_scal = o_pts + al256(sizeof(float4) * (size_t)n);  // [0] flags, [1] maxdeg, [2..3] total, [4..5] tests
     const size_t o_scan = o_scal + 256;
     DevBuf tmp;
     Temps keep(s, {&tmp});
@@ -421,9 +427,9 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
                                                (int *)cell_cnt.p);
     TRY(scan_ints((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr, s, scan_tmp));
     k_eu_scatter<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (const int *)cell_of.p,
-                                                   (const int *)cell_start.p, (int *)cursor.p, (int4 *)pts.p);
-    // one workgroup per EU_XB cells along x
-    const unsigned wgs = (unsigned)((g.G + EU_XB - 1) / EU_XB) * (unsigned)g.G * (unsigned)(dim == 3 ? g.G : 1);
+                                                   (const int *)cell_start.p, (int *)cursor.p, (float4 *)pts.p);
+    // one workgroup per EU_XB cells along the slowest axis
+    const unsigned wgs = (unsigned)eu_tiles(g.G, dim);
     int cap = eu_capacity(n, dim, rm->r);
     int hs[6];
     for (int attempt = 0;; ++attempt) {
@@ -435,7 +441,8 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
         rm->in_rec = dev_view(rm->tab, o_rec, 8 * slots);
         if (attempt > 0) bt.begin();
         k_fill_int<<<1, 64, 0, s>>>(maxdeg, 5, 0);  // maxdeg, total, tests
-        k_eu_rows<<<wgs, 256, 0, s>>>(g, (const int4 *)pts.p, (const int *)cell_start.p, R2, cap, (int *)rm->deg.p,
+        k_eu_rows<<<wgs, EU_THREADS, 0, s>>>(g, (const float4 *)pts.p, (const int *)cell_start.p, R2f, R2b, cap,
+                                      (int *)rm->deg.p,
                                       maxdeg, (unsigned long long *)rm->in_rec.p, tested);
         TRY(scan_ints((const int *)rm->deg.p, n, (int *)rm->in_ptr.p, total, s, scan_tmp));
         k_rec8_pad<<<blocks_for(GMT_REC_PAD, 256), 256, 0, s>>>((unsigned long long *)rm->in_rec.p,
