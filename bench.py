@@ -25,9 +25,13 @@ FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
 # with this digest and the launch shape named; reported only while both match
-TRAFFIC = {"sources_sha256": "2945b5a09290d4ab8dfc763d7ea482d1359ff0c2aced8b0dfa2ee2a899464918",
+TRAFFIC = {"sources_sha256": "482b27186df2d37188ae501c1913d0824addd32347eb8d820f67cbe32c6e28d7",
            "batch": 4096, "lanes": 8, "threads": 1024,
-           "bytes_per_launch": int((2.0 * 71622343 + 5660388) * 1024)}
+           "bytes_per_launch": int((2.0 * 71646376 + 5661304) * 1024)}
+# the same for the Euclidean row kernel k_eu_rows building the 3D table at
+# n = 1048576 (medians of five builds)
+EU_TRAFFIC = {"sources_sha256": "8706551abd768542af306f0e97e937887a6272b44a79e3d39fc693fdf7a69059", "n": 1048576,
+              "bytes_per_launch": int((2.0 * 55938.5 + 2967653.4) * 1024)}
 
 
 def say(msg):
@@ -35,10 +39,10 @@ def say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_digest():
+def kernel_digest(files=("gmt_plan.hpp", "gmt_dev.hpp")):
     import hashlib
     h = hashlib.sha256()
-    for f in ("gmt_plan.hpp", "gmt_dev.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1705_02403_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -661,13 +665,18 @@ def main():
             kms = float(np.median(kt[1:]))
             nbytes = euclid_build_bytes(n3, 3, e3)
             built = euclid_build_bytes(n3, 3, e3) + 4 * n3
+            eu_traffic = None
+            if (n3 == EU_TRAFFIC["n"] and
+                    kernel_digest(("gmt_build.hpp", "gmt_dev.hpp")) == EU_TRAFFIC["sources_sha256"]):
+                eu_traffic = EU_TRAFFIC["bytes_per_launch"]
             build_line.append({"workload": "3D Euclidean n=%d, r=%.4f" % (n3, r3), "edges": int(e3),
                                "device_bytes": int(held),
                                "kernel_ms": round(kms, 4), "wall_ms": round(bt, 3), "bytes": int(nbytes),
                                "achieved": round(nbytes / (kms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "bytes_as_built": int(built),
-                               "frac_as_built": round(built / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+                               "frac_as_built": round(built / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "traffic_k_eu_rows": eu_traffic})
             say("euclid build n=%d: %.3f ms wall, %.3f ms kernels" % (n3, bt, kms))
             del d3
 
