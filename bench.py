@@ -9,6 +9,7 @@ timing, as the method precomputes its roadmap offline).  Prints one JSON line.
 
 import argparse
 import json
+import math
 import os
 import sys
 import threading
@@ -80,8 +81,8 @@ def parse():
     ap.add_argument("--mixed-requests", type=int, default=512,
                     help="mixed 2D/3D/6D replanning stream (0: skip)")
     ap.add_argument("--mixed-rate", type=float, default=2000.0)
-    ap.add_argument("--learned", action="store_true",
-                    help="also train the learned sampler and compare it with plain GMT* at n=32768")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the learned sampler and its comparison with plain GMT* at n=32768")
     ap.add_argument("--learned-train", type=int, default=100000)
     ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--learned-test", type=int, default=200)
@@ -174,59 +175,76 @@ def learned_report(args, torch, gmt, I):
         ref_cost.append(res.path_cost if res.status == gmt.GMT_OK else np.inf)
         ref_ms.append(ms)
     ref_cost = np.array(ref_cost)
-    rows = {}
-    tuned_single = {}
+    plain_p50 = float(np.percentile(ref_ms, 50))
+    # Sample sets of n < 32768 at three edge rules: the radius rule r(n) with
+    # 16 trajectory points (edges grow as n shrinks), the same radius with the
+    # trajectory points scaled by r(n) / r(32768) (the checked points stay as
+    # dense along an edge as at n = 32768), and plain's own radius r(32768)
+    # with 16 points (the same edges as plain; only the samples differ).
+    rows, tuned_single = {}, {}
     for n in (1024, 2048, 4096, 8192):
         r_n = radius.di_radius(n)
+        k_scaled = int(math.ceil(16.0 * r_n / r_big))
         n_l = n // 2
-        # single-plan launch shape for this n, tuned on one uniform sample set
-        rm_t = gmt.gmt_build_neighbors(torch.from_numpy(I.di_samples(7_000, n)).to(dev),
-                                       gmt.GMT_COST_DOUBLE_INTEGRATOR, r_n)
-        p0 = tests[0]
-        tuned_single[n] = gmt.gmt_autotune([gmt.BatchQuery(rm_t, p0.x_init, gmt.make_goal(p0.goal_center,
-                                            p0.goal_radius, 3), p0.boxes, p0.lam)], opts, single=True, reps=3)
-        rm_t.free()
         # query-independent draws stay resident: `sets` pools, query k uses pool k % sets
         uni = [torch.from_numpy(I.di_samples(7_000 + ss, n - n_l)).to(dev) for ss in range(sets)]
         fb = [torch.from_numpy(I.di_samples(8_000 + ss, n_l)).to(dev) for ss in range(sets)]
         eps = [torch.from_numpy(I.normal_draws(9_000 + ss, n_l)).to(dev) for ss in range(sets)]
         uni_full = [torch.from_numpy(I.di_samples(7_000 + ss, n)).to(dev) for ss in range(sets)]
-        for learned in (True, False):
-            costs, lat, rej = [], [], 0
-            parts = []
-            for k, p in enumerate(tests):
-                goal = gmt.make_goal(p.goal_center, p.goal_radius, 3)
-                ss = k % sets
+        rules = (("", r_n, 16), ("_points_scaled", r_n, k_scaled), ("_equal_r", r_big, 16))
+        for tag, rr, kp in rules:
+            opts_k = gmt.make_opts(traj_points=kp)
+            # single-plan launch shape for this set size and edge rule, tuned on a uniform set
+            rm_t = gmt.gmt_build_neighbors(torch.from_numpy(I.di_samples(7_000, n)).to(dev),
+                                           gmt.GMT_COST_DOUBLE_INTEGRATOR, rr)
+            p0 = tests[0]
+            tuned_single["n%d%s" % (n, tag)] = gmt.gmt_autotune(
+                [gmt.BatchQuery(rm_t, p0.x_init, gmt.make_goal(p0.goal_center, p0.goal_radius, 3), p0.boxes,
+                                p0.lam)], opts_k, single=True, reps=3)
+            rm_t.free()
+            for learned in ((True, False) if tag != "_points_scaled" else (True,)):
+                costs, lat, rej, parts = [], [], 0, []
+                for k, p in enumerate(tests):
+                    goal = gmt.make_goal(p.goal_center, p.goal_radius, 3)
+                    ss = k % sets
 
-                def run():
-                    if learned:
-                        x, rj = S.mixed_samples(smp, p, n, 0, True, uniform=uni[ss], fallback=fb[ss], eps=eps[ss])
-                    else:
-                        x, rj = uni_full[ss], 0
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    rm = gmt.gmt_build_neighbors(x, gmt.GMT_COST_DOUBLE_INTEGRATOR, r_n)
-                    t2 = time.perf_counter()
-                    res = gmt.gmt_plan(rm, p.x_init, goal, p.boxes, p.lam, opts, outputs=False)
-                    t3 = time.perf_counter()
-                    rm.free()
-                    parts.append((t2 - t1, t3 - t2))
-                    return res, rj
-                (res, rj), ms = timed(run)
-                rej += rj
-                costs.append(res.path_cost if res.status == gmt.GMT_OK else np.inf)
-                lat.append(ms)
-            costs = np.array(costs)
-            both = np.isfinite(costs) & np.isfinite(ref_cost)
-            ratio = costs[both] / ref_cost[both]
-            rows["%s_n%d" % ("learned" if learned else "uniform", n)] = {
-                "solved": int(np.isfinite(costs).sum()),
-                "median_cost_ratio_vs_plain_n32768": round(float(np.median(ratio)), 4) if both.any() else None,
-                "mean_cost_ratio_vs_plain_n32768": round(float(np.mean(ratio)), 4) if both.any() else None,
-                "p50_ms_end_to_end": round(float(np.percentile(lat, 50)), 3),
-                "p50_ms_build": round(float(np.median([a for a, _ in parts])) * 1e3, 3),
-                "p50_ms_plan": round(float(np.median([b for _, b in parts])) * 1e3, 3),
-                "rejected_per_query": round(rej / len(tests), 1)}
+                    def run():
+                        t0 = time.perf_counter()
+                        if learned:
+                            x, rj = S.mixed_samples(smp, p, n, 0, True, uniform=uni[ss], fallback=fb[ss],
+                                                    eps=eps[ss])
+                        else:
+                            x, rj = uni_full[ss], 0
+                        torch.cuda.synchronize()
+                        t1 = time.perf_counter()
+                        rm = gmt.gmt_build_neighbors(x, gmt.GMT_COST_DOUBLE_INTEGRATOR, rr)
+                        t2 = time.perf_counter()
+                        res = gmt.gmt_plan(rm, p.x_init, goal, p.boxes, p.lam, opts_k, outputs=False)
+                        t3 = time.perf_counter()
+                        rm.free()
+                        parts.append((t1 - t0, t2 - t1, t3 - t2))
+                        return res, rj
+                    (res, rj), ms = timed(run)
+                    rej += rj
+                    costs.append(res.path_cost if res.status == gmt.GMT_OK else np.inf)
+                    lat.append(ms)
+                costs = np.array(costs)
+                both = np.isfinite(costs) & np.isfinite(ref_cost)
+                ratio = costs[both] / ref_cost[both]
+                e2e = float(np.percentile(lat, 50))
+                rows["%s%s_n%d" % ("learned" if learned else "uniform", tag, n)] = {
+                    "n": n, "r": round(rr, 4), "traj_points": kp,
+                    "solved": int(np.isfinite(costs).sum()),
+                    "median_cost_ratio_vs_plain_n32768": round(float(np.median(ratio)), 4) if both.any() else None,
+                    "mean_cost_ratio_vs_plain_n32768": round(float(np.mean(ratio)), 4) if both.any() else None,
+                    "p50_ms_end_to_end": round(e2e, 3),
+                    "p99_ms_end_to_end": round(float(np.percentile(lat, 99)), 3),
+                    "faster_than_plain_resident": bool(e2e < plain_p50),
+                    "p50_ms_sampler": round(float(np.median([a for a, _, _ in parts])) * 1e3, 3),
+                    "p50_ms_build": round(float(np.median([b for _, b, _ in parts])) * 1e3, 3),
+                    "p50_ms_plan": round(float(np.median([c for _, _, c in parts])) * 1e3, 3),
+                    "rejected_per_query": round(rej / len(tests), 1)}
+        say("learned n=%d done" % n)
     for rm in rms.values():
         rm.free()
     smp.close()
@@ -235,17 +253,18 @@ def learned_report(args, torch, gmt, I):
             "train_steps": args.learned_steps, "train_s": round(train_s, 2),
             "loss_first_last": [[round(v, 4) for v in hist[0][1:]], [round(v, 4) for v in hist[-1][1:]]],
             "test_problems": len(tests),
-            "plain_n32768": {"solved": int(np.isfinite(ref_cost).sum()),
-                             "p50_ms_plan_resident": round(float(np.percentile(ref_ms, 50)), 3),
+            "plain_n32768": {"solved": int(np.isfinite(ref_cost).sum()), "r": round(r_big, 4),
+                             "p50_ms_plan_resident": round(plain_p50, 3),
                              "build_ms": round(float(np.median(build_ms)), 3),
                              "single_plan_shape": {kk: tuned_plain[kk] for kk in
                                                    ("lanes", "team_wgs", "threads", "ms", "default_ms")}},
             "mixes": rows,
-            "single_plan_shape": {str(k): {kk: v[kk] for kk in ("lanes", "team_wgs", "threads", "ms", "default_ms")}
+            "single_plan_shape": {k: {kk: v[kk] for kk in ("lanes", "team_wgs", "threads", "ms", "default_ms")}
                                   for k, v in tuned_single.items()},
-            "note": "end-to-end = sampler inference + neighbour build + plan; uniform draws, "
-                    "fallbacks and noise are query-independent and resident (8 pools per n); "
-                    "r(n) = 1.75 (16384/n)^(1/6) for every n"}
+            "note": "end-to-end = sampler inference + neighbour build + plan, synchronised, per query; uniform "
+                    "draws, fallbacks and noise are query-independent and resident (8 pools per n); edge rules: "
+                    "r(n) = 1.75 (16384/n)^(1/6) with 16 trajectory points; r(n) with ceil(16 r(n)/r(32768)) "
+                    "points (_points_scaled); plain's r(32768) with 16 points (_equal_r)"}
 
 
 def lat_stats(ms):
@@ -680,7 +699,10 @@ def main():
             say("euclid build n=%d: %.3f ms wall, %.3f ms kernels" % (n3, bt, kms))
             del d3
 
-    learned = learned_report(args, torch, gmt, I) if args.learned else None
+    learned = None
+    if not args.no_learned and not args.only_throughput:
+        say("learned sampler")
+        learned = learned_report(args, torch, gmt, I)
     extra = {}
     if not args.no_extra and not args.only_throughput:
         say("dubins airplane")

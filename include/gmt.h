@@ -66,10 +66,17 @@ typedef enum {
     GMT_COST_DUBINS_AIRPLANE = 2    /* state (p, h), p in [0,1]^3, heading 2 pi h, h in [0,1), dim = 4 */
 } gmt_cost_kind;
 
-/* Parameters of a cost kind.  turn_radius: the Dubins airplane's least
- * turning radius rho (> 0); unused by the other kinds. */
+/* Parameters of a table build.  turn_radius: the Dubins airplane's least
+ * turning radius rho (> 0); unused by the other kinds.  row_slots: for the
+ * asymmetric kinds (double integrator, Dubins airplane), the scratch entries
+ * each row gets in the single pass over all ordered pairs; a longer row is
+ * computed again, straight into the table, by a pass of its own.  0 picks
+ * max(384, 2^25 / n) (at most n): sizes device memory (20 bytes per entry,
+ * freed when the build returns) and speed only, never the table.  Must be
+ * >= 0; unused by the Euclidean kind. */
 typedef struct {
     double turn_radius;
+    int32_t row_slots;
 } gmt_cost_params;
 
 /* Opaque device-resident roadmap: a sample set with its r-disk neighbour
@@ -179,12 +186,12 @@ gmt_status gmt_sample_halton(int32_t n, int32_t dim, gmt_cost_kind kind, int64_t
                              const float *boxes, int32_t m, float *d_samples, int64_t *next,
                              void *stream);
 
-/* gmt_build_neighbors with the cost kind's parameters: required for
+/* gmt_build_neighbors with the build's parameters: required for
  * GMT_COST_DUBINS_AIRPLANE (dim 4: x, y, z, heading in turns), whose table
  * lists every ordered pair with path length below r_n (the frontier walks
  * the transposed out-table as for the double integrator).  params may be
  * NULL for the other kinds.  Errors: as gmt_build_neighbors, plus GMT_EINVAL
- * for a missing or non-positive turning radius. */
+ * for a missing or non-positive turning radius or a negative row_slots. */
 gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, int32_t dim, gmt_cost_kind kind,
                                   double r_n, const gmt_cost_params *params, void *stream,
                                   gmt_roadmap_t *out);

@@ -226,6 +226,7 @@ struct gmt_roadmap {
     double rho = 0.0;  // Dubins airplane: turning radius
     long long nnz = 0;
     int cap = 0;       // Euclidean: slots per row (row x at x * cap), deg[x] used
+    int row_slots = 0; // asymmetric kinds: scratch entries per row asked for by the caller (0: default)
     DevBuf deg;        // Euclidean: row lengths
     DevBuf s, in_ptr, in_col, in_tau, out_ptr, out_col;
     DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
@@ -471,17 +472,26 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     return GMT_OK;
 }
 
-// One pass over all ordered pairs writes each row into a scratch slot of
-// kDiScratchCap entries; the rows are then compacted into the CSR table, and
-// the few longer rows are recomputed straight into it.
-static const int kDiScratchCap = 384;
+// One pass over all ordered pairs writes each row into a scratch slot; the
+// rows are then compacted into the CSR table, and the few longer rows are
+// recomputed straight into it (one wave scanning all sources, so each costs
+// a whole serial row).  A slot holds at least kDiScratchMin entries, and more
+// while the n slots stay within kDiScratchBudget entries (20 bytes each): sets
+// whose samples gather (learned proposals) have rows far above the mean.
+static const long long kDiScratchMin = 384;
+static const long long kDiScratchBudget = 1ll << 25;
+
+static int di_scratch_cap(int n) {
+    const long long cap = std::max(kDiScratchMin, kDiScratchBudget / std::max(n, 1));
+    return (int)std::min<long long>(cap, ((long long)n + 7) & ~7ll);
+}
 
 // Tables of the asymmetric costs: the double integrator and the Dubins
 // airplane (whose rows carry arrival times of zero).
 static gmt_status build_pairs(gmt_roadmap *rm, hipStream_t s) {
     const bool dub = rm->kind == GMT_COST_DUBINS_AIRPLANE;
     const int n = rm->n;
-    const int cap = kDiScratchCap;
+    const int cap = rm->row_slots > 0 ? (rm->row_slots + 7) & ~7 : di_scratch_cap(n);
     // one block of temporaries: row lengths, flags, overflow list, scratch
     // rows, scan and transpose scratch
     const size_t o_scal = al256(sizeof(int) * (size_t)n);
@@ -584,6 +594,8 @@ extern "C" gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, 
         rho = params->turn_radius;
         if (!(rho > 0.0) || !std::isfinite(rho)) return fail(GMT_EINVAL, "turning radius must be finite and > 0");
     }
+    const int row_slots = params ? params->row_slots : 0;
+    if (row_slots < 0) return fail(GMT_EINVAL, "row_slots must be >= 0 (got %d)", row_slots);
     hipStream_t s = (hipStream_t)stream;
     gmt_roadmap *rm = new gmt_roadmap;
     rm->n = n;
@@ -591,6 +603,7 @@ extern "C" gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, 
     rm->kind = kind;
     rm->r = r_n;
     rm->rho = rho;
+    rm->row_slots = row_slots;
     gmt_status st = dev_alloc(rm->s, sizeof(float) * (size_t)dim * n, s);
     if (st == GMT_OK) {
         hipError_t e = hipMemcpyAsync(rm->s.p, d_samples, sizeof(float) * (size_t)dim * n,

@@ -92,7 +92,7 @@ class gmt_allocator(C.Structure):
 
 
 class gmt_cost_params(C.Structure):
-    _fields_ = [("turn_radius", C.c_double)]
+    _fields_ = [("turn_radius", C.c_double), ("row_slots", C.c_int32)]
 
 
 class gmt_goal(C.Structure):
@@ -392,19 +392,21 @@ class Roadmap:
             pass
 
 
-def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None, turn_radius=None) -> Roadmap:
+def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None, turn_radius=None,
+                        row_slots=None) -> Roadmap:
     """samples: CUDA float32 tensor [dim][n] (SoA) on the 2^-20 grid;
-    turn_radius: the Dubins airplane's (through gmt_build_neighbors_ex)."""
+    turn_radius: the Dubins airplane's; row_slots: scratch entries per row of
+    the asymmetric kinds' build (both through gmt_build_neighbors_ex)."""
     import torch
     assert samples.is_cuda and samples.dtype == torch.float32 and samples.dim() == 2
     s = samples.contiguous()
     dim, n = int(s.shape[0]), int(s.shape[1])
     h = C.c_void_p()
-    if turn_radius is None:
+    if turn_radius is None and row_slots is None:
         _check(lib().gmt_build_neighbors(s.data_ptr(), n, dim, int(kind), float(r_n), _stream(stream),
                                          C.byref(h)), "gmt_build_neighbors")
     else:
-        prm = gmt_cost_params(float(turn_radius))
+        prm = gmt_cost_params(float(turn_radius or 0.0), int(row_slots or 0))
         _check(lib().gmt_build_neighbors_ex(s.data_ptr(), n, dim, int(kind), float(r_n), C.byref(prm),
                                             _stream(stream), C.byref(h)), "gmt_build_neighbors_ex")
     return Roadmap(h.value, n, dim, int(kind), float(r_n))

@@ -118,21 +118,36 @@ def _box_touches_ball(lo: np.ndarray, hi: np.ndarray, c_q: np.ndarray, radius: f
 
 def draw_boxes(rng: np.random.Generator, m: int, pdim: int, smin: float, smax: float,
                start_q: np.ndarray, goal_q: np.ndarray, goal_radius: float) -> np.ndarray:
-    """m boxes (int64 grid units [m, 2*pdim]) avoiding the start and the goal ball."""
+    """m boxes (int64 grid units [m, 2*pdim]) avoiding the start and the goal ball.
+
+    Each attempt draws the sides U[smin, smax] per axis, then the lower
+    corner U[0, 1 - side] per axis (2*pdim uniform doubles from `rng`, in that
+    order) and is rejected when the box contains the start or touches the goal
+    ball.  Attempts are evaluated a block at a time; the generator is then
+    left exactly where drawing the accepted attempts one by one leaves it."""
+    if m <= 0:
+        return np.zeros((0, 2 * pdim), dtype=np.int64)
     out = []
-    while len(out) < m:
-        side = rng.uniform(smin, smax, size=pdim)
-        lo = rng.uniform(0.0, 1.0 - side)
+    have = 0
+    lim = float(goal_radius) * float(goal_radius) * float(QSCALE) * float(QSCALE)
+    while have < m:
+        k = 2 * (m - have) + 8
+        state = rng.bit_generator.state
+        d = rng.random(2 * pdim * k).reshape(k, 2 * pdim)
+        side = smin + (smax - smin) * d[:, :pdim]
+        lo = (1.0 - side) * d[:, pdim:]
         lo_q = to_grid(lo)
         hi_q = np.minimum(to_grid(lo + side), QSCALE)
-        if np.all((start_q[:pdim] >= lo_q) & (start_q[:pdim] <= hi_q)):
-            continue
-        if _box_touches_ball(lo_q, hi_q, goal_q, goal_radius):
-            continue
-        out.append(np.concatenate([lo_q, hi_q]))
-    if not out:
-        return np.zeros((0, 2 * pdim), dtype=np.int64)
-    return np.stack(out).astype(np.int64)
+        holds_start = np.all((start_q[:pdim] >= lo_q) & (start_q[:pdim] <= hi_q), axis=1)
+        gap = np.maximum(np.maximum(lo_q - goal_q, 0), goal_q - hi_q)
+        touches = np.sum(gap * gap, axis=1).astype(np.float64) <= lim
+        ok = np.flatnonzero(~holds_start & ~touches)[: m - have]
+        used = int(ok[-1]) + 1 if len(ok) == m - have else k
+        rng.bit_generator.state = state
+        rng.random(2 * pdim * used)  # consume exactly the attempts made
+        out.append(np.concatenate([lo_q[ok], hi_q[ok]], axis=1))
+        have += len(ok)
+    return np.concatenate(out).astype(np.int64)
 
 
 def draw_positions(rng: np.random.Generator, k: int, pdim: int) -> np.ndarray:

@@ -174,13 +174,15 @@ def test_plan_on_clustered_table():
     rm.free()
 
 
-@pytest.mark.parametrize("seed,n,r", [(0, 1024, None), (1, 2048, None), (2, 777, None),
-                                      (3, 2048, 3.0)])  # rows of up to 699: past the scratch capacity
-def test_di_table(seed, n, r):
-    say("di table seed %d n %d" % (seed, n))
+@pytest.mark.parametrize("seed,n,r,slots", [(0, 1024, None, None), (1, 2048, None, None), (2, 777, None, None),
+                                            (3, 2048, 3.0, None),   # rows of up to 699
+                                            (3, 2048, 3.0, 384),    # those rows past their scratch slots
+                                            (4, 1500, None, 40)])   # a third of the rows recomputed
+def test_di_table(seed, n, r, slots):
+    say("di table seed %d n %d slots %s" % (seed, n, slots))
     s = I.di_samples(seed, n)
     r = r or 1.75 * (16384.0 / n) ** (1.0 / 6.0)
-    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, r)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, r, row_slots=slots)
     rp, col, cost, tau = rm.export()
     ref = O.neighbors(s, O.DI, r)
     if ref.margin > 1e-9:
