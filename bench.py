@@ -91,9 +91,11 @@ def parse():
     ap.add_argument("--forest-queries", type=int, default=12)
     ap.add_argument("--halton-queries", type=int, default=8)
     ap.add_argument("--replan-scenarios", type=int, default=64)
-    ap.add_argument("--cpu-2d", type=int, default=100, help="single-core oracle latency: 2D problems")
-    ap.add_argument("--cpu-3d", type=int, default=6, help="single-core oracle latency: 3D problems")
-    ap.add_argument("--cpu-di", type=int, default=40, help="single-core oracle latency: 6D problems")
+    ap.add_argument("--cpu-2d", type=int, default=200, help="single-core oracle latency: 2D problems")
+    ap.add_argument("--cpu-3d", type=int, default=200, help="single-core oracle latency: 3D problems")
+    ap.add_argument("--cpu-di", type=int, default=200, help="single-core oracle latency: 6D problems")
+    ap.add_argument("--cpu-mixed", type=int, default=64,
+                    help="oracle throughput over the first requests of the mixed 2D/3D/6D set (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the Dubins, Halton and replanning sections")
     return ap.parse_args()
@@ -423,34 +425,97 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_latency_report(args):
-    """Single-core oracle latency (the serial FP64 C oracle, one thread) per
-    workload: bounded samples of the 2D, 3D and 6D configurations."""
+def _run_pool(jobs, cores):
+    """Run the callables in `jobs` on `cores` threads (the oracle's C calls
+    release the GIL, so each thread keeps one core busy); returns each job's
+    wall time in ms, in job order, and the makespan in s."""
+    ms = [0.0] * len(jobs)
+    nxt = [0]
+    lock = threading.Lock()
+
+    def worker():
+        while True:
+            with lock:
+                k = nxt[0]
+                nxt[0] += 1
+            if k >= len(jobs):
+                return
+            t = time.perf_counter()
+            jobs[k]()
+            ms[k] = (time.perf_counter() - t) * 1e3
+    ths = [threading.Thread(target=worker) for _ in range(max(1, cores))]
+    t = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    return ms, time.perf_counter() - t
+
+
+def cpu_latency_report(args, cores):
+    """Single-core oracle latency (the serial FP64 C oracle, one thread per
+    plan) per workload: the 2D, 3D and 6D configurations, their neighbour
+    tables built beforehand (excluded, as the GPU's roadmaps are resident).
+    Problems run `cores` at a time, one per thread."""
     from oracle import oracle as O
     from paper_1705_02403_amd import inputs as I
     out = {}
     for name, make, count in (("2d_n2000", lambda k: I.problem_2d(k), args.cpu_2d),
                               ("3d_n16384", lambda k: I.problem_3d(k), args.cpu_3d),
                               ("di_n16384", None, args.cpu_di)):
-        ms = []
+        if count <= 0:
+            continue
+        jobs = []
+        t = time.perf_counter()
         if make is None:
             s = I.di_samples(0, 16384)
             tab = O.neighbors(s, O.DI, I.DI_RADIUS)
-            probs = [I.di_problem(k, s) for k in range(count)]
-            for p in probs:
-                t = time.perf_counter()
-                O.plan(p, p.r, tab)
-                ms.append((time.perf_counter() - t) * 1e3)
+            for k in range(count):
+                p = I.di_problem(k, s)
+                jobs.append(lambda p=p: O.plan(p, p.r, tab))
         else:
             for k in range(count):
                 p = make(k)
                 r = O.euclid_radius(p)
-                tab = O.neighbors(p.samples, O.EUCLID, r)  # precomputed, as the roadmap is
-                t = time.perf_counter()
-                O.plan(p, r, tab)
-                ms.append((time.perf_counter() - t) * 1e3)
-        out[name] = dict(problems=count, **lat_stats(ms))
+                tab = O.neighbors(p.samples, O.EUCLID, r)
+                jobs.append(lambda p=p, r=r, tab=tab: O.plan(p, r, tab))
+        tables_s = time.perf_counter() - t
+        ms, _ = _run_pool(jobs, cores)
+        out[name] = dict(problems=count, tables_s=round(tables_s, 1), **lat_stats(ms))
     return out
+
+
+def cpu_mixed_report(args, cores):
+    """Oracle throughput on the mixed 2D/3D/6D set (configuration 4): the
+    first --cpu-mixed requests in arrival order, one worker thread per core,
+    all at t = 0; tables of their shared sample sets built beforehand."""
+    from oracle import oracle as O
+    from paper_1705_02403_amd import inputs as I, radius
+    specs = I.batch_specs(512)[:args.cpu_mixed]
+    tabs, samples = {}, {}
+    t = time.perf_counter()
+    for sp in specs:
+        key = (sp["dim"], sp["n"], sp["sample_seed"])
+        if key in tabs:
+            continue
+        x = (I.di_samples(sp["sample_seed"], sp["n"]) if sp["dim"] == 6
+             else I.uniform_samples(sp["dim"], sp["n"], sp["sample_seed"]))
+        samples[key] = x
+        rr = radius.shared_roadmap_radius(sp["dim"], sp["n"])
+        tabs[key] = (rr, O.neighbors(x, O.DI if sp["dim"] == 6 else O.EUCLID, rr))
+    tables_s = time.perf_counter() - t
+    jobs = []
+    for sp in specs:
+        key = (sp["dim"], sp["n"], sp["sample_seed"])
+        p = I.mixed_problem(sp, samples[key])
+        rr, tab = tabs[key]
+        jobs.append(lambda p=p, rr=rr, tab=tab: O.plan(p, rr, tab))
+    ms, wall = _run_pool(jobs, cores)
+    return {"value": round(len(jobs) / wall, 2), "unit": "plans/s", "cores": cores, "problems": len(jobs),
+            "roadmaps": len(tabs), "tables_s": round(tables_s, 1), "makespan_s": round(wall, 2),
+            "dims": {str(d): sum(sp["dim"] == d for sp in specs) for d in (2, 3, 6)},
+            "sample": "the first %d of the 512 mixed requests (arrival order), all at t = 0, one oracle "
+                      "thread per core" % len(jobs)}
 
 
 def mixed_report(args, torch, gmt, I):
@@ -765,9 +830,10 @@ def main():
                              "neighbour table (%.1f s, OpenMP) built beforehand like the GPU roadmaps"
                              % (done[0], n, cores, dt, oracle_build_s),
                    "cpu_model": cpu_model(), "nproc": cores,
-                   "single_core_latency": cpu_latency_report(args),
-                   "latency_note": "one thread, serial C oracle, tables precomputed (excluded, as the "
-                                   "roadmap is); bounded samples, problem counts stated"}
+                   "single_core_latency": cpu_latency_report(args, cores),
+                   "latency_note": "serial C oracle, one thread per plan, %d plans at a time; tables "
+                                   "precomputed (excluded, as the roadmap is)" % cores,
+                   "mixed_set": cpu_mixed_report(args, cores) if args.cpu_mixed > 0 else None}
 
     line = {
         "metric": "plans/s + p50/p99 plan latency, 6D double-integrator n=16k; cost vs FP64 oracle",
