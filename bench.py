@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--server-requests", type=int, default=4096)
     ap.add_argument("--server-rate", type=float, default=20000.0)
     ap.add_argument("--server-slots", type=int, default=4)
+    ap.add_argument("--server-low-requests", type=int, default=512,
+                    help="requests of the low-load server run (0: skip)")
+    ap.add_argument("--server-low-rate", type=float, default=500.0)
     ap.add_argument("--server-max-batch", type=int, default=256)
     ap.add_argument("--server-threads", type=int, default=0,
                     help="threads per workgroup for the server's batches (0: library choice)")
@@ -717,8 +720,29 @@ def main():
                     "threads": args.server_threads,
                     "plans_per_s": round(rep.plans_per_s, 1), "p50_ms": round(rep.p50_ms, 3),
                     "p99_ms": round(rep.p99_ms, 3), "batches": rep.engine.get("batches"),
+                    "lone_launches": rep.engine.get("lone_launches"),
                     "peak_inflight_requests": rep.engine.get("peak_inflight_requests"),
                     "identical_to_batch": "%d/%d" % (same, len(rep.served))}
+        # low load: requests often find the device idle and run in the
+        # single-plan launch shape
+        if args.server_low_requests > 0:
+            arr = I.poisson_arrivals(args.server_low_requests, args.server_low_rate, seed=12)
+            lreqs = [server.Request(float(t), probs[k % len(probs)].sample_seed,
+                                    (lambda q: lambda rm: q)(queries[k % len(queries)]), tag=k)
+                     for k, t in enumerate(arr)]
+            srv = server.ReplanServer(lambda key: rms[key], sopts, engine_budget=8 << 30,
+                                      roadmap_budget=1 << 40, slots=args.server_slots,
+                                      max_batch=args.server_max_batch)
+            srv.serve(lreqs[:32])
+            low = srv.serve(lreqs)
+            srv.engine.close()
+            by_tag = {s.tag: s for s in low.served}
+            same = sum(by_tag[k].path_cost == out[k % len(out)].path_cost for k in by_tag)
+            srv_line["low_load"] = {"arrival_rate_hz": args.server_low_rate, "requests": len(low.served),
+                                    "plans_per_s": round(low.plans_per_s, 1), "p50_ms": round(low.p50_ms, 3),
+                                    "p99_ms": round(low.p99_ms, 3), "batches": low.engine.get("batches"),
+                                    "lone_launches": low.engine.get("lone_launches"),
+                                    "identical_to_batch": "%d/%d" % (same, len(low.served))}
 
     # ---- Euclidean neighbour table builds, 3D (the 3D workload and larger n) ----
     # bytes the build must move: samples read, row pointers, an index and a

@@ -424,6 +424,9 @@ typedef struct {
     int32_t queue_cap;    /* queued requests before GMT_EBUSY (0: unbounded) */
     int32_t workgroups;   /* persistent workgroups per batch (0: fill the GPU) */
     gmt_plan_opts plan;   /* shared plan options */
+    int32_t batch_only;   /* 0: a request launched alone while no other batch runs
+                             takes gmt_plan's launch shape (a team of workgroups,
+                             lower latency); 1: one workgroup per request always */
 } gmt_engine_opts;
 
 typedef struct {
@@ -432,6 +435,7 @@ typedef struct {
     int64_t inflight_bytes;          /* admitted now */
     int64_t peak_inflight_bytes;
     int64_t peak_inflight_requests;
+    int64_t lone_launches;           /* batches launched alone in gmt_plan's shape */
 } gmt_engine_stats;
 
 gmt_status gmt_engine_create(const gmt_engine_opts *opts, gmt_engine_t *out);

@@ -2285,6 +2285,11 @@ static void engine_loop(gmt_engine *E) {
                 sl.reqs.push_back(r);
             }
             if (sl.reqs.empty()) break;
+            // a request launched alone while no other batch is on the device
+            // takes the single-plan launch shape (a team of workgroups, the
+            // latency mode) instead of one workgroup
+            bool lone = sl.reqs.size() == 1 && !E->o.batch_only;
+            for (const EngineSlot &x : E->slots) lone = lone && !x.busy;
             sl.probs.resize(sl.reqs.size());
             sl.results.assign(sl.reqs.size(), gmt_result{});
             for (size_t k = 0; k < sl.reqs.size(); ++k) {
@@ -2301,7 +2306,8 @@ static void engine_loop(gmt_engine *E) {
             std::memset(&bo, 0, sizeof bo);
             bo.plan = E->o.plan;
             bo.workgroups = E->o.workgroups;
-            gmt_status ss = batch_stage(sl.probs.data(), (int)sl.probs.size(), bo, false, nullptr, sl.run, sl.stream);
+            gmt_status ss = batch_stage(sl.probs.data(), (int)sl.probs.size(), bo, lone, nullptr, sl.run, sl.stream);
+            if (lone) E->st.lone_launches += 1;
             if (ss == GMT_OK) ss = batch_launch(sl.run, sl.stream);
             lk.lock();
             if (ss != GMT_OK) {

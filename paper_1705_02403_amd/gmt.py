@@ -142,13 +142,14 @@ class gmt_batch_opts(C.Structure):
 
 class gmt_engine_opts(C.Structure):
     _fields_ = [("budget_bytes", C.c_size_t), ("slots", C.c_int32), ("max_batch", C.c_int32),
-                ("queue_cap", C.c_int32), ("workgroups", C.c_int32), ("plan", gmt_plan_opts)]
+                ("queue_cap", C.c_int32), ("workgroups", C.c_int32), ("plan", gmt_plan_opts),
+                ("batch_only", C.c_int32)]
 
 
 class gmt_engine_stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "cancelled", "rejected", "batches",
                                          "queued", "inflight_bytes", "peak_inflight_bytes",
-                                         "peak_inflight_requests")]
+                                         "peak_inflight_requests", "lone_launches")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -702,9 +703,9 @@ class Engine:
     """Continuous-batching engine (``gmt_engine_*``)."""
 
     def __init__(self, budget_bytes: int, opts: gmt_plan_opts, slots: int = 4, max_batch: int = 256,
-                 queue_cap: int = 0, workgroups: int = 0):
+                 queue_cap: int = 0, workgroups: int = 0, batch_only: bool = False):
         eo = gmt_engine_opts(int(budget_bytes), int(slots), int(max_batch), int(queue_cap),
-                             int(workgroups), opts)
+                             int(workgroups), opts, int(bool(batch_only)))
         h = C.c_void_p()
         _check(lib().gmt_engine_create(C.byref(eo), C.byref(h)), "gmt_engine_create")
         self.handle = h

@@ -72,6 +72,25 @@ def test_engine_results_equal_alone(world):
     eng.close()
 
 
+@pytest.mark.parametrize("batch_only", [False, True])
+def test_engine_lone_requests(world, batch_only):
+    """A request submitted while the device is idle runs alone in gmt_plan's
+    launch shape (unless batch_only); either way its result is gmt_plan's."""
+    say("engine: lone requests, batch_only=%s" % batch_only)
+    rms, probs = world
+    eng = gmt.Engine(1 << 30, opts(), slots=2, max_batch=8, batch_only=batch_only)
+    for k, p in probs:
+        ref = alone(rms, k, p)
+        res = eng.poll(eng.submit(query(rms, k, p)), -1)  # one at a time: the device is idle
+        assert res.status == ref.status
+        assert list(res.path) == list(ref.path)
+        assert res.path_cost == ref.path_cost
+    st = eng.stats()
+    assert st["completed"] == len(probs)
+    assert st["lone_launches"] == (0 if batch_only else len(probs))
+    eng.close()
+
+
 def test_engine_budget_admission(world):
     say("engine: small budget")
     rms, probs = world
