@@ -588,11 +588,6 @@ __global__ void k_eu_pack(int n, int cap, const int *__restrict__ row_ptr, const
 // ---------------------------------------------------------------------------
 #define DI_QCAP 128
 
-__device__ __forceinline__ void di_load(const float *__restrict__ s, int n, int i, double *x) {
-#pragma unroll
-    for (int a = 0; a < 6; ++a) x[a] = (double)s[(size_t)a * n + i];
-}
-
 __device__ __forceinline__ DiPair di_pair(const double *src, const double *dst) {
     DiPair d;
 #pragma unroll
@@ -604,15 +599,15 @@ __device__ __forceinline__ DiPair di_pair(const double *src, const double *dst) 
     return d;
 }
 
-// state of sample i of a pair-cost kind: CK 1 double integrator (6 values),
-// CK 2 Dubins airplane (4)
+// state of sample i of a pair-cost kind from the 8-float copy s8 (two
+// 16-byte loads): CK 1 double integrator (6 values), CK 2 Dubins airplane (4)
 template <int CK>
-__device__ __forceinline__ void pair_load(const float *__restrict__ s, int n, int i, double *x) {
+__device__ __forceinline__ void pair_load(const float4 *__restrict__ s8, int i, double *x) {
+    const float4 a = s8[2 * i];
+    x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w;
     if (CK == 1) {
-        di_load(s, n, i, x);
-    } else {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) x[a] = (double)s[(size_t)a * n + i];
+        const float4 b = s8[2 * i + 1];
+        x[4] = b.x, x[5] = b.y;
     }
 }
 
@@ -655,7 +650,7 @@ __device__ __forceinline__ double pair_cost(const double *ys, const double *xs, 
 enum { DI_FILL = 0, DI_SCRATCH = 2 };
 
 template <int CK>
-__global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, int n, double r, double rho, int mode,
+__global__ void __launch_bounds__(256) k_di_rows(const float4 *__restrict__ s8, int n, double r, double rho, int mode,
                                                  const int *__restrict__ rows, const int *__restrict__ row_ptr,
                                                  int cap, int *__restrict__ deg, int *__restrict__ ovf,
                                                  int *__restrict__ col, double *__restrict__ cost,
@@ -675,7 +670,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
     }
     int *qu = queue[wl];
     double xs[6];
-    pair_load<CK>(s, n, x, xs);
+    pair_load<CK>(s8, x, xs);
     int qn = 0;      // queued survivors (wave-uniform)
     int found = 0;   // neighbours emitted so far (wave-uniform)
     int nsolved = 0; // pairs past the prefilter (wave-uniform)
@@ -688,7 +683,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         if (lane < take) {
             y = qu[lane];
             double ys[6];
-            pair_load<CK>(s, n, y, ys);
+            pair_load<CK>(s8, y, ys);
             J = pair_cost<CK>(ys, xs, rho, t);
             hit = J < r;
         }
@@ -723,7 +718,7 @@ __global__ void __launch_bounds__(256) k_di_rows(const float *__restrict__ s, in
         bool pass = false;
         if (y < n && y != x) {
             double ys[6];
-            pair_load<CK>(s, n, y, ys);
+            pair_load<CK>(s8, y, ys);
             pass = pair_may_connect<CK>(ys, xs, r);
         }
         uint64_t m = wave_ballot(pass);

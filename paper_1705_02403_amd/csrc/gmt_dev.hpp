@@ -308,8 +308,11 @@ __device__ inline void di_cost(const DiPair &d, double &J, double &tau) {
 // Exact necessary condition for J(src -> dst) < r, from two lower bounds of
 // J: J >= 2|dv| (effort >= |dv|^2/tau, then AM-GM) and, writing
 // J = tau + N(tau)/tau^3 with N(tau) = 4S tau^2 - 12B tau + 12C >= Nmin =
-// 12C - 9B^2/S, J >= (4/3)(3 Nmin)^(1/4).  A relative slack of 1e-9 keeps
-// rounding from rejecting a true neighbour.
+// 12C - 9B^2/S, J >= (4/3)(3 Nmin)^(1/4).  The second bound is tested
+// multiplied through by S > 0 (no division): 12 C S - 9 B^2 >= L S with
+// L = (27/256) r^4.  A relative slack of 1e-9 on each limit, and on the second
+// an absolute slack of 1e-12 (12 C S + 9 B^2) for the cancellation of its two
+// terms, keep rounding from rejecting a true neighbour.
 __device__ __forceinline__ bool di_may_connect(const DiPair &d, double r) {
     double dv2 = 0.0, S = 0.0, B = 0.0, C = 0.0;
 #pragma unroll
@@ -320,11 +323,12 @@ __device__ __forceinline__ bool di_may_connect(const DiPair &d, double r) {
         B += d.a[k] * (d.v0[k] + d.v1[k]);
         C += d.a[k] * d.a[k];
     }
-    double r2 = r * r;
-    if (4.0 * dv2 >= r2 * (1.0 + 1e-9)) return false;
-    double Nmin = (S > 0.0) ? 12.0 * C - 9.0 * B * B / S : 12.0 * C;
-    if (Nmin >= (27.0 / 256.0) * r2 * r2 * (1.0 + 1e-9)) return false;
-    return true;
+    const double r2 = r * r;
+    const double L = (27.0 / 256.0) * r2 * r2 * (1.0 + 1e-9);
+    const double cs = 12.0 * C * S, b2 = 9.0 * B * B;
+    const bool far_v = 4.0 * dv2 >= r2 * (1.0 + 1e-9);
+    const bool far_n = S > 0.0 ? cs - b2 >= L * S + 1e-12 * (cs + b2) : 12.0 * C >= L;
+    return !(far_v | far_n);
 }
 
 // position along the optimal trajectory at normalised time s in [0,1]:

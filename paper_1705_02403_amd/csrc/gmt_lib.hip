@@ -511,14 +511,18 @@ static gmt_status build_pairs(gmt_roadmap *rm, hipStream_t s) {
     long long *total = (long long *)(flags + 2);
     unsigned long long *solved = (unsigned long long *)(flags + 4);
     int hs[6] = {0, 0, 0, 0, 0, 0}, novf = 0;
+    // the states as 8 floats per node: the pair passes read them, and so
+    // does the planner's lazy check
+    TRY(dev_alloc(rm->s8, 32 * (size_t)n, s));
     BuildTimer bt(s);
     bt.begin();
     k_fill_int<<<1, 64, 0, s>>>(flags, 8, 0);
     k_fill_int<<<1, 64, 0, s>>>(ovf, 1, 0);
     k_check_samples<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->dim, rm->kind, flags);
+    k_aos8<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->dim, (float4 *)rm->s8.p);
     {
         auto rows = dub ? k_di_rows<2> : k_di_rows<1>;
-        rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->r, rm->rho,
+        rows<<<blocks_for((long long)n * GMT_WAVE, 256), 256, 0, s>>>((const float4 *)rm->s8.p, n, rm->r, rm->rho,
                                                                      DI_SCRATCH, nullptr, nullptr, cap, deg, ovf,
                                                                      scol, scost, stau, nullptr, solved);
     }
@@ -544,20 +548,18 @@ static gmt_status build_pairs(gmt_roadmap *rm, hipStream_t s) {
     if (E > 0x7fffffffLL) return fail(GMT_EINVAL, "table of %lld edges exceeds the int32 index range", E);
     rm->nnz = E;
     // one block for the roadmap's tables: columns, arrival times, out-table,
-    // (cost, column) records with their padding, 8-float states
+    // (cost, column) records with their padding
     const size_t e1 = (size_t)std::max<long long>(E, 1);
     const size_t o_tau = al256(sizeof(int) * e1);
     const size_t o_optr = o_tau + al256(sizeof(double) * e1);
     const size_t o_ocol = o_optr + al256(sizeof(int) * ((size_t)n + 1));
     const size_t o_rec = o_ocol + al256(sizeof(int) * e1);
-    const size_t o_s8 = o_rec + al256(12 * ((size_t)E + GMT_REC_PAD));
-    TRY(dev_alloc(rm->tab, o_s8 + al256(32 * (size_t)n), s));
+    TRY(dev_alloc(rm->tab, o_rec + al256(12 * ((size_t)E + GMT_REC_PAD)), s));
     rm->in_col = dev_view(rm->tab, 0, sizeof(int) * e1);
     rm->in_tau = dev_view(rm->tab, o_tau, sizeof(double) * e1);
     rm->out_ptr = dev_view(rm->tab, o_optr, sizeof(int) * ((size_t)n + 1));
     rm->out_col = dev_view(rm->tab, o_ocol, sizeof(int) * e1);
     rm->in_rec = dev_view(rm->tab, o_rec, 12 * ((size_t)E + GMT_REC_PAD));
-    rm->s8 = dev_view(rm->tab, o_s8, 32 * (size_t)n);
     int *col = (int *)rm->in_col.p;
     double *tau = (double *)rm->in_tau.p;
     unsigned int *rec = (unsigned int *)rm->in_rec.p;
@@ -567,11 +569,10 @@ static gmt_status build_pairs(gmt_roadmap *rm, hipStream_t s) {
     if (novf > 0) {
         auto rows = dub ? k_di_rows<2> : k_di_rows<1>;
         rows<<<blocks_for((long long)novf * GMT_WAVE, 256), 256, 0, s>>>(
-            (const float *)rm->s.p, n, rm->r, rm->rho, DI_FILL, ovf, (const int *)rm->in_ptr.p, cap, nullptr,
+            (const float4 *)rm->s8.p, n, rm->r, rm->rho, DI_FILL, ovf, (const int *)rm->in_ptr.p, cap, nullptr,
             nullptr, col, nullptr, tau, rec, nullptr);
     }
     k_rec_pad<<<blocks_for(3 * GMT_REC_PAD, 256), 256, 0, s>>>(rec, E);
-    k_aos8<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, rm->dim, (float4 *)rm->s8.p);
     {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(GMT_EDEVICE, "neighbour fill failed: %s", hipGetErrorString(e));
