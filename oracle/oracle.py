@@ -24,6 +24,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gmt_oracle.c")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "liborc.so")
+# a build of the same source to load instead (the sanitizer run of the pins)
+LIB_OVERRIDE = os.environ.get("GMT_ORACLE_LIB")
 
 EUCLID, DI, DUBINS = 0, 1, 2
 OK, NO_PATH, TIMEOUT = 0, 1, 2
@@ -43,12 +45,24 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(path: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts), for running the pins under them."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fPIC", "-shared", "-fopenmp",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-o", path, SRC, "-lm"])
+    return path
+
+
 def lib():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            L = C.CDLL(LIB)
+            if LIB_OVERRIDE:
+                L = C.CDLL(LIB_OVERRIDE)
+            else:
+                build()
+                L = C.CDLL(LIB)
             P = C.c_void_p
             i32, f64 = C.c_int, C.c_double
             L.orc_free_volume.restype = f64
