@@ -227,6 +227,19 @@ gmt_status gmt_roadmap_export(gmt_roadmap_t rm, int32_t *row_ptr, int32_t *col, 
 /* Release a roadmap (NULL is accepted). */
 gmt_status gmt_roadmap_free(gmt_roadmap_t rm);
 
+/* Checkpoint a roadmap to a file and back, so that a resident table survives
+ * a restart without being rebuilt.  gmt_roadmap_save writes the roadmap's
+ * device arrays as they are (samples, tables, records) behind a header; it
+ * synchronises `stream`.  gmt_roadmap_load reads such a file, checks on the
+ * host that the samples lie in the state space on the 2^-20 grid and that
+ * every row pointer and column stays within the table, and uploads it; the
+ * result plans exactly as the saved roadmap did.  The caller owns the
+ * returned roadmap (gmt_roadmap_free).  Errors: GMT_EINVAL for a null
+ * argument, a file that cannot be opened, read or written, or one that is not
+ * a whole, consistent roadmap file; GMT_ENOMEM; GMT_EDEVICE. */
+gmt_status gmt_roadmap_save(gmt_roadmap_t rm, const char *path, void *stream);
+gmt_status gmt_roadmap_load(const char *path, void *stream, gmt_roadmap_t *out);
+
 /* Solve one query with Algorithm 1 on a resident roadmap.
  *  x_init     host [dim], in free space (Problem 1 requires x_init in X_free).
  *  goal       goal ball (see gmt_goal).

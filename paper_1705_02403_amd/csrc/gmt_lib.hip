@@ -887,6 +887,158 @@ extern "C" gmt_status gmt_roadmap_bytes(gmt_roadmap_t rm, int64_t *bytes) {
     return GMT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// roadmap checkpoints: the device arrays as they are, behind a header
+// ---------------------------------------------------------------------------
+static const char kRoadmapMagic[8] = {'G', 'M', 'T', 'R', 'M', 'A', 'P', '1'};
+
+// the arrays a roadmap may hold, in file order
+static DevBuf *roadmap_field(gmt_roadmap *rm, int k) {
+    DevBuf *f[] = {&rm->s, &rm->in_ptr, &rm->in_col, &rm->in_cost, &rm->in_tau,
+                   &rm->in_rec, &rm->s8, &rm->deg, &rm->out_ptr, &rm->out_col};
+    return f[k];
+}
+static const int kRoadmapFields = 10;
+
+struct RoadmapHeader {
+    char magic[8];
+    int32_t kind, n, dim, cap, out_shared, pad;
+    int64_t nnz;
+    double r, rho;
+    uint64_t bytes[kRoadmapFields];
+};
+
+extern "C" gmt_status gmt_roadmap_save(gmt_roadmap_t rm, const char *path, void *stream) {
+    if (!rm || !path) return fail(GMT_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    RoadmapHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kRoadmapMagic, 8);
+    h.kind = rm->kind, h.n = rm->n, h.dim = rm->dim, h.cap = rm->cap, h.out_shared = rm->out_shared;
+    h.nnz = rm->nnz, h.r = rm->r, h.rho = rm->rho;
+    for (int k = 0; k < kRoadmapFields; ++k) {
+        const DevBuf *b = roadmap_field(rm, k);
+        h.bytes[k] = b->p ? (uint64_t)b->bytes : 0;
+    }
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(GMT_EINVAL, "cannot open %s for writing", path);
+    bool ok = std::fwrite(&h, sizeof h, 1, f) == 1;
+    std::vector<char> host;
+    for (int k = 0; k < kRoadmapFields && ok; ++k) {
+        const DevBuf *b = roadmap_field(rm, k);
+        if (!h.bytes[k]) continue;
+        host.resize(h.bytes[k]);
+        hipError_t e = hipMemcpyAsync(host.data(), b->p, h.bytes[k], hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            std::fclose(f);
+            return fail(GMT_EDEVICE, "roadmap download failed: %s", hipGetErrorString(e));
+        }
+        ok = std::fwrite(host.data(), 1, host.size(), f) == host.size();
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? GMT_OK : fail(GMT_EINVAL, "writing %s failed", path);
+}
+
+// a loaded table must keep every read of the planner in bounds: sizes,
+// row pointers and columns are checked on the host before anything is uploaded
+static gmt_status check_loaded(const RoadmapHeader &h, const std::vector<std::vector<char>> &a) {
+    const long long n = h.n, E = h.nnz;
+    const bool eu = h.kind == GMT_COST_EUCLIDEAN;
+    if (E < 0 || E > 0x7fffffffLL) return fail(GMT_EINVAL, "bad edge count");
+    if (eu && (h.cap < 0 || n * h.cap + GMT_REC_PAD > 0x7fffffffLL)) return fail(GMT_EINVAL, "bad slot count");
+    if (!eu && h.out_shared) return fail(GMT_EINVAL, "bad out-table flag");
+    auto need = [&](int k, long long bytes) { return (long long)a[k].size() >= bytes; };
+    // fields: s, in_ptr, in_col, in_cost, in_tau, in_rec, s8, deg, out_ptr, out_col
+    if (!need(0, 4 * h.dim * n) || !need(1, 4 * (n + 1))) return fail(GMT_EINVAL, "samples or row pointers missing");
+    // samples in the state space and on the grid, as a build requires
+    const float *smp = (const float *)a[0].data();
+    const int pd = pdim_of(h.kind, h.dim);
+    for (int d = 0; d < h.dim; ++d)
+        for (long long i = 0; i < n; ++i) {
+            const double x = smp[d * n + i];
+            const double lo = d < pd ? 0.0 : (h.kind == GMT_COST_DOUBLE_INTEGRATOR ? -1.0 : 0.0);
+            const double hi = (h.kind == GMT_COST_DUBINS_AIRPLANE && d == 3) ? 1.0 - GMT_INV_QS : 1.0;
+            if (!on_grid(x) || x < lo || x > hi) return fail(GMT_EINVAL, "sample %lld off the grid or out of range", i);
+        }
+    const int *rp = (const int *)a[1].data();
+    if (rp[0] != 0 || rp[n] != E) return fail(GMT_EINVAL, "row pointers do not span the edges");
+    for (long long i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(GMT_EINVAL, "row pointers decrease");
+    if (eu) {
+        if (!need(7, 4 * n) || !need(5, 8 * (n * h.cap + GMT_REC_PAD))) return fail(GMT_EINVAL, "Euclidean rows missing");
+        const int *deg = (const int *)a[7].data();
+        const unsigned long long *rec = (const unsigned long long *)a[5].data();
+        for (long long i = 0; i < n; ++i) {
+            if (deg[i] < 0 || deg[i] > h.cap || deg[i] != rp[i + 1] - rp[i]) return fail(GMT_EINVAL, "bad row length");
+            for (int k = 0; k < deg[i]; ++k)
+                if ((long long)(rec[i * h.cap + k] & EU_COL_MASK) >= n) return fail(GMT_EINVAL, "bad column");
+        }
+        for (int k = 0; k < GMT_REC_PAD; ++k)
+            if ((long long)(rec[n * h.cap + k] & EU_COL_MASK) >= n) return fail(GMT_EINVAL, "bad padding");
+    } else {
+        if (!need(2, 4 * E) || !need(4, 8 * E) || !need(5, 12 * (E + GMT_REC_PAD)) || !need(6, 32 * n) ||
+            !need(8, 4 * (n + 1)) || !need(9, 4 * E))
+            return fail(GMT_EINVAL, "tables missing");
+        const int *col = (const int *)a[2].data(), *op = (const int *)a[8].data(), *oc = (const int *)a[9].data();
+        const unsigned int *rec = (const unsigned int *)a[5].data();
+        for (long long e = 0; e < E + GMT_REC_PAD; ++e)
+            if ((long long)rec[3 * e + 2] >= n) return fail(GMT_EINVAL, "bad record column");
+        for (long long e = 0; e < E; ++e)
+            if (col[e] < 0 || col[e] >= n || oc[e] < 0 || oc[e] >= n) return fail(GMT_EINVAL, "bad column");
+        if (op[0] != 0 || op[n] != E) return fail(GMT_EINVAL, "out-row pointers do not span the edges");
+        for (long long i = 0; i < n; ++i)
+            if (op[i + 1] < op[i]) return fail(GMT_EINVAL, "out-row pointers decrease");
+    }
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_roadmap_load(const char *path, void *stream, gmt_roadmap_t *out) {
+    if (!path || !out) return fail(GMT_EINVAL, "null argument");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(GMT_EINVAL, "cannot open %s", path);
+    RoadmapHeader h;
+    std::vector<std::vector<char>> a(kRoadmapFields);
+    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, kRoadmapMagic, 8) == 0;
+    for (int k = 0; k < kRoadmapFields && ok; ++k) {
+        if (h.bytes[k] > (1ull << 40)) ok = false;
+        if (!ok || !h.bytes[k]) continue;
+        a[k].resize(h.bytes[k]);
+        ok = std::fread(a[k].data(), 1, a[k].size(), f) == a[k].size();
+    }
+    std::fclose(f);
+    if (!ok) return fail(GMT_EINVAL, "%s is not a whole roadmap file", path);
+    TRY(check_shape(h.n, h.dim, (gmt_cost_kind)h.kind, h.r));
+    TRY(check_loaded(h, a));
+    gmt_roadmap *rm = new gmt_roadmap;
+    rm->n = h.n, rm->dim = h.dim, rm->kind = h.kind, rm->r = h.r, rm->rho = h.rho;
+    rm->nnz = h.nnz, rm->cap = h.cap, rm->out_shared = h.out_shared != 0;
+    gmt_status st = GMT_OK;
+    for (int k = 0; k < kRoadmapFields && st == GMT_OK; ++k) {
+        if (a[k].empty()) continue;
+        DevBuf *b = roadmap_field(rm, k);
+        st = dev_alloc(*b, a[k].size(), s);
+        if (st != GMT_OK) break;
+        hipError_t e = hipMemcpyAsync(b->p, a[k].data(), a[k].size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && k == kRoadmapFields - 1) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "roadmap upload failed: %s", hipGetErrorString(e));
+    }
+    if (st == GMT_OK) {
+        hipError_t e = hipStreamSynchronize(s);  // the host copies are freed on return
+        if (e != hipSuccess) st = fail(GMT_EDEVICE, "roadmap upload failed: %s", hipGetErrorString(e));
+    }
+    if (st != GMT_OK) {
+        (void)hipStreamSynchronize(s);
+        roadmap_release(rm, s);
+        delete rm;
+        return st;
+    }
+    *out = rm;
+    return GMT_OK;
+}
+
 extern "C" gmt_status gmt_roadmap_free(gmt_roadmap_t rm) {
     if (!rm) return GMT_OK;
     if (!g_shut.load()) (void)hipDeviceSynchronize();

@@ -15,6 +15,7 @@ from __future__ import annotations
 import atexit
 import ctypes as C
 import os
+import struct
 import subprocess
 import sys
 import threading
@@ -41,6 +42,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 # symbols the header declares (checked by the CPU tests)
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_build_neighbors_ex", "gmt_sample_halton", "gmt_roadmap_from_csr", "gmt_roadmap_info", "gmt_roadmap_bytes",
+           "gmt_roadmap_save", "gmt_roadmap_load",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_noalloc", "gmt_plan_batch",
            "gmt_last_work", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
@@ -206,6 +208,8 @@ def lib():
             L.gmt_set_allocator.argtypes = [C.POINTER(gmt_allocator)]
             L.gmt_build_neighbors.argtypes = [P, i32, i32, i32, f64, P, C.POINTER(P)]
             L.gmt_build_neighbors_ex.argtypes = [P, i32, i32, i32, f64, C.POINTER(gmt_cost_params), P, C.POINTER(P)]
+            L.gmt_roadmap_save.argtypes = [P, C.c_char_p, P]
+            L.gmt_roadmap_load.argtypes = [C.c_char_p, P, C.POINTER(P)]
             L.gmt_sample_halton.argtypes = [i32, i32, i32, i64, P, i32, P, C.POINTER(i64), P]
             L.gmt_roadmap_from_csr.argtypes = [P, i32, i32, i32, f64, P, P, P, P, P, C.POINTER(P)]
             L.gmt_roadmap_info.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
@@ -377,6 +381,10 @@ class Roadmap:
                                         _stream(stream)), "gmt_roadmap_export")
         return rp, col[:E], cost[:E], (None if tau is None else tau[:E])
 
+    def save(self, path: str, stream=None) -> None:
+        """Checkpoint the roadmap to `path` (gmt_roadmap_save)."""
+        _check(lib().gmt_roadmap_save(self.handle, os.fsencode(path), _stream(stream)), "gmt_roadmap_save")
+
     def free(self) -> None:
         if self.handle:
             lib().gmt_roadmap_free(self.handle)
@@ -411,6 +419,17 @@ def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None, turn_radius
         _check(lib().gmt_build_neighbors_ex(s.data_ptr(), n, dim, int(kind), float(r_n), C.byref(prm),
                                             _stream(stream), C.byref(h)), "gmt_build_neighbors_ex")
     return Roadmap(h.value, n, dim, int(kind), float(r_n))
+
+
+def gmt_roadmap_load(path: str, stream=None) -> Roadmap:
+    """A roadmap checkpointed with Roadmap.save (gmt_roadmap_load)."""
+    h = C.c_void_p()
+    _check(lib().gmt_roadmap_load(os.fsencode(path), _stream(stream), C.byref(h)), "gmt_roadmap_load")
+    n, dim, kind, nnz = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().gmt_roadmap_info(h, C.byref(n), C.byref(dim), C.byref(kind), C.byref(nnz)), "gmt_roadmap_info")
+    with open(path, "rb") as f:  # the radius from the file's header (magic, 6 int32, int64, r)
+        r = struct.unpack_from("<8s6iqd", f.read(48))[8]
+    return Roadmap(h.value, int(n.value), int(dim.value), int(kind.value), float(r))
 
 
 def gmt_sample_halton(n: int, dim: int, kind: int, first: int = 1, boxes=None, out=None, stream=None):

@@ -12,6 +12,7 @@ arrival to completion; throughput is completed queries over the makespan.
 from __future__ import annotations
 
 import collections
+import json
 import threading
 import time
 from dataclasses import dataclass, field
@@ -137,9 +138,13 @@ class ReplanServer:
                                  workgroups=workgroups)
         self.path_cap = path_cap
 
-    def serve(self, requests: List[Request], realtime: bool = True) -> ServeReport:
+    def serve(self, requests: List[Request], realtime: bool = True, record: Optional[str] = None) -> ServeReport:
         """Replay ``requests`` at their arrival times (``realtime``) or all at
-        once, and collect every result."""
+        once, and collect every result.  ``record``: a file to which one JSON
+        line per request is appended as it completes (tag, roadmap key,
+        arrival, submit and completion times on the engine's steady clock,
+        latency, status, iterations, path length and cost)."""
+        out = open(record, "a") if record else None
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         t0 = gmt.gmt_steady_ns() + 2_000_000  # start 2 ms from now
         tickets: Dict[int, tuple] = {}
@@ -190,7 +195,15 @@ class ReplanServer:
             last_done = max(last_done, done)
             served.append(Served(r.tag, res.status, res.path, res.path_cost, (done - at) / 1e6,
                                  (res.work["submit_ns"] - at) / 1e6))
+            if out:
+                out.write(json.dumps({"tag": str(r.tag), "key": str(r.key), "arrival_ns": at,
+                                      "submit_ns": res.work["submit_ns"], "done_ns": done,
+                                      "latency_ms": round((done - at) / 1e6, 4), "status": int(res.status),
+                                      "iterations": int(res.iters), "path_len": len(res.path),
+                                      "path_cost": float(res.path_cost)}) + "\n")
         th.join()
+        if out:
+            out.close()
         lat = np.array([s.latency_ms for s in served]) if served else np.zeros(1)
         first = t0
         span = max(last_done - first, 1) / 1e9

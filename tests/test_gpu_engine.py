@@ -1,6 +1,8 @@
 """Continuous-batching engine on the GPU: every result equals the same query
 solved alone; admission keeps in-flight workspaces under the budget."""
 
+import json
+
 import numpy as np
 import pytest
 
@@ -127,7 +129,7 @@ def test_engine_rejects_what_never_fits_and_cancels(world):
     eng.close()
 
 
-def test_server_poisson_stream(world):
+def test_server_poisson_stream(world, tmp_path):
     say("server: poisson stream")
     rms, probs = world
     arrivals = I.poisson_arrivals(40, 2000.0, seed=7)
@@ -138,13 +140,20 @@ def test_server_poisson_stream(world):
             rm, p.x_init, gmt.make_goal(p.goal_center, p.goal_radius, p.pdim), p.boxes, p.lam))(p), tag=k))
     srv = server.ReplanServer(lambda key: rms[key], opts(), engine_budget=1 << 30, roadmap_budget=1 << 40,
                               slots=4, max_batch=32)
-    rep = srv.serve(reqs)
+    log = tmp_path / "plans.jsonl"
+    rep = srv.serve(reqs, record=str(log))
     srv.engine.close()
     assert len(rep.served) == 40
     ref = {k: alone(rms, *probs[k % len(probs)]) for k in range(40)}
     for s in rep.served:
         assert s.status == ref[s.tag].status and s.path_cost == ref[s.tag].path_cost
     assert rep.p99_ms >= rep.p50_ms > 0
+    # one record per request, in completion order, matching what was served
+    recs = [json.loads(line) for line in log.read_text().splitlines()]
+    assert [r["tag"] for r in recs] == [str(s.tag) for s in rep.served]
+    for r, s in zip(recs, rep.served):
+        assert r["status"] == s.status and r["path_cost"] == s.path_cost and r["path_len"] == len(s.path)
+        assert r["done_ns"] >= r["submit_ns"] > 0 and r["iterations"] >= 0
 
 
 def test_graph_batch_replays_equal_eager(world):

@@ -9,6 +9,7 @@ FP64 rounding can move, and costs agree to 1e-12 relative.
 """
 
 import dataclasses
+import struct
 
 import numpy as np
 import pytest
@@ -458,3 +459,58 @@ def test_errors_and_degenerate_queries():
     compare_tree(res, O.plan(pg, r))
     assert list(res.path) == [prob.n] and res.path_cost == 0.0
     rm.free()
+
+
+# --- checkpoints ------------------------------------------------------------
+
+def test_roadmap_save_load_plans_identically(tmp_path):
+    """A roadmap saved and loaded again exports the same table and plans the
+    same trees (Euclidean 2D, double integrator, Dubins airplane); files that
+    are cut short or point outside the table are rejected."""
+    say("roadmap checkpoints")
+    cases = []
+    p2 = I.problem_2d(3)
+    r2 = O.euclid_radius(p2)
+    cases.append(("2d", p2, build(p2, r2), gmt.make_opts(edge_step=p2.step)))
+    s6 = I.di_samples(3, 2048)
+    pdi = I.di_problem(5, s6, r=1.75 * 8.0 ** (1.0 / 6.0))
+    cases.append(("di", pdi, gmt.gmt_build_neighbors(torch.from_numpy(s6).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR,
+                                                     pdi.r), gmt.make_opts(traj_points=16)))
+    s4 = I.dubins_samples(1, 1500)
+    pdu = I.dubins_problem(2, s4, m=40)
+    cases.append(("dubins", pdu, gmt.gmt_build_neighbors(torch.from_numpy(s4).cuda(), gmt.GMT_COST_DUBINS_AIRPLANE,
+                                                         pdu.r, turn_radius=I.DUBINS_TURN),
+                  gmt.make_opts(edge_step=pdu.step)))
+    for name, p, rm, opts in cases:
+        path = str(tmp_path / (name + ".gmtr"))
+        rm.save(path)
+        rl = gmt.gmt_roadmap_load(path)
+        assert (rl.n, rl.dim, rl.kind, rl.r, rl.nnz) == (rm.n, rm.dim, rm.kind, rm.r, rm.nnz)
+        for a, b in zip(rm.export(), rl.export()):
+            if a is not None:
+                assert np.array_equal(a, b), name
+        goal = gmt.make_goal(p.goal_center, p.goal_radius, p.pdim)
+        x = gmt.gmt_plan(rm, p.x_init, goal, p.boxes, p.lam, opts)
+        y = gmt.gmt_plan(rl, p.x_init, goal, p.boxes, p.lam, opts)
+        assert x.status == y.status and list(x.path) == list(y.path) and x.path_cost == y.path_cost, name
+        assert np.array_equal(x.parent.cpu().numpy(), y.parent.cpu().numpy()), name
+        assert np.array_equal(x.group_iter.cpu().numpy(), y.group_iter.cpu().numpy()), name
+        # a file cut short, and one whose first column points past the table
+        data = open(path, "rb").read()
+        bad = str(tmp_path / (name + "_short.gmtr"))
+        open(bad, "wb").write(data[:len(data) // 2])
+        with pytest.raises(gmt.GmtError):
+            gmt.gmt_roadmap_load(bad)
+        # header: magic, 6 int32, nnz, r, rho, 10 field sizes; then the fields
+        # (samples first, row pointers second)
+        sizes = struct.unpack_from("<8s6iqdd10Q", data)[10:20]
+        at = struct.calcsize("<8s6iqdd10Q") + sizes[0] + 4
+        worse = bytearray(data)
+        worse[at:at + 4] = struct.pack("<i", 0x7fffffff)  # row_ptr[1] far past the edges
+        open(bad, "wb").write(bytes(worse))
+        with pytest.raises(gmt.GmtError):
+            gmt.gmt_roadmap_load(bad)
+        rl.free()
+        rm.free()
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_roadmap_load(str(tmp_path / "missing.gmtr"))
