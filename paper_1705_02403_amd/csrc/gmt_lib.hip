@@ -18,6 +18,7 @@
 #include <map>
 #include <set>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <unordered_map>
 #include <string>
@@ -1002,11 +1003,28 @@ extern "C" gmt_status gmt_roadmap_load(const char *path, void *stream, gmt_roadm
     RoadmapHeader h;
     std::vector<std::vector<char>> a(kRoadmapFields);
     bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, kRoadmapMagic, 8) == 0;
+    // the fields must fill the rest of the file exactly: no size in the
+    // header is trusted before it is checked against the file's length
+    long long left = -1;
+    if (ok && std::fseek(f, 0, SEEK_END) == 0) {
+        left = (long long)std::ftell(f) - (long long)sizeof h;
+        ok = std::fseek(f, (long)sizeof h, SEEK_SET) == 0;
+    }
+    unsigned long long want = 0;
     for (int k = 0; k < kRoadmapFields && ok; ++k) {
-        if (h.bytes[k] > (1ull << 40)) ok = false;
-        if (!ok || !h.bytes[k]) continue;
-        a[k].resize(h.bytes[k]);
-        ok = std::fread(a[k].data(), 1, a[k].size(), f) == a[k].size();
+        ok = h.bytes[k] <= (unsigned long long)std::max(left, 0ll);
+        want += h.bytes[k];
+    }
+    ok = ok && left >= 0 && want == (unsigned long long)left;
+    try {
+        for (int k = 0; k < kRoadmapFields && ok; ++k) {
+            if (!h.bytes[k]) continue;
+            a[k].resize(h.bytes[k]);
+            ok = std::fread(a[k].data(), 1, a[k].size(), f) == a[k].size();
+        }
+    } catch (const std::bad_alloc &) {
+        std::fclose(f);
+        return fail(GMT_ENOMEM, "no host memory to read %s", path);
     }
     std::fclose(f);
     if (!ok) return fail(GMT_EINVAL, "%s is not a whole roadmap file", path);

@@ -4,6 +4,7 @@ header declares; host-side helpers agree with the oracle.  No GPU calls."""
 import ctypes
 import os
 import re
+import struct
 
 import numpy as np
 import pytest
@@ -51,6 +52,31 @@ def test_invalid_arguments_rejected_without_gpu():
     bad = gmt.gmt_allocator()
     assert L.gmt_set_allocator(ctypes.byref(bad)) == gmt.GMT_EINVAL
     assert L.gmt_set_allocator(None) == gmt.GMT_OK
+
+
+def test_malformed_roadmap_files_rejected_without_gpu(tmp_path):
+    """A roadmap file's header is checked against the file's length before
+    anything is allocated: a field larger than the file, sizes that do not add
+    up, a wrong magic and a missing file are all errors, with no device work."""
+    L = gmt.lib()
+    h = ctypes.c_void_p()
+    fmt = "<8s6iqdd10Q"
+    body = b"\0" * 64
+
+    def write(magic, sizes, tail):
+        p = str(tmp_path / "x.gmtr")
+        open(p, "wb").write(struct.pack(fmt, magic, 1, 4, 2, 0, 0, 0, 0, 0.1, 0.0, *sizes) + tail)
+        return p.encode()
+
+    huge = [1 << 62] + [0] * 9
+    assert L.gmt_roadmap_load(write(b"GMTRMAP1", huge, body), None, ctypes.byref(h)) == gmt.GMT_EINVAL
+    assert not h.value and "roadmap" in gmt.last_error()
+    wrong_sum = [32, 20] + [0] * 8  # 52 bytes declared, 64 present
+    assert L.gmt_roadmap_load(write(b"GMTRMAP1", wrong_sum, body), None, ctypes.byref(h)) == gmt.GMT_EINVAL
+    two = [(1 << 64) - 32, 96] + [0] * 8  # wraps to 64 when added: still refused
+    assert L.gmt_roadmap_load(write(b"GMTRMAP1", two, body), None, ctypes.byref(h)) == gmt.GMT_EINVAL
+    assert L.gmt_roadmap_load(write(b"NOTAROAD", [64] + [0] * 9, body), None, ctypes.byref(h)) == gmt.GMT_EINVAL
+    assert L.gmt_roadmap_load(str(tmp_path / "none").encode(), None, ctypes.byref(h)) == gmt.GMT_EINVAL
 
 
 def test_product_radius_matches_oracle():
