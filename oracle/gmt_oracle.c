@@ -772,6 +772,48 @@ static int in_goal(const orc_ctx *cx, int v, const float *gc, float gr, int gd)
 }
 
 /*
+ * Per-iteration record sink (test instrumentation of Algorithm 1): while a
+ * buffer is installed on the calling thread, orc_plan appends one record of
+ * ORC_TRACE_INTS ints per iteration whose group is non-empty:
+ *   i, |open set| when the iteration starts, |G_i|, |C| (unexplored
+ *   out-neighbours of G_i, line 4), how many of C lie in an obstacle, how many
+ *   locally optimal edges failed the lazy check (lines 5-7), nodes added.
+ * Records past `cap` are counted but not written.
+ */
+#define ORC_TRACE_INTS 7
+static _Thread_local int *g_tr_buf = NULL;
+static _Thread_local int g_tr_cap = 0, g_tr_len = 0;
+
+void orc_trace_begin(int *buf, int cap)
+{
+    g_tr_buf = buf;
+    g_tr_cap = buf ? cap : 0;
+    g_tr_len = 0;
+}
+
+int orc_trace_end(void)
+{
+    int k = g_tr_len;
+    g_tr_buf = NULL;
+    g_tr_cap = g_tr_len = 0;
+    return k;
+}
+
+/* sample x's position lies in a closed obstacle box (exact on the grid) */
+static int sample_in_box(const orc_ctx *cx, int x)
+{
+    int64_t q[6];
+    node_q(x, cx->n, cx->dim, cx->samples, cx->x_init, q);
+    for (int b = 0; b < cx->m; ++b) {
+        int in = 1;
+        for (int a = 0; a < cx->pd && in; ++a)
+            in = q[a] >= q_of(cx->boxes[b * 2 * cx->pd + a]) && q[a] <= q_of(cx->boxes[b * 2 * cx->pd + cx->pd + a]);
+        if (in) return 1;
+    }
+    return 0;
+}
+
+/*
  * GMT* (Algorithm 1) over samples 0..n-1 and the root n = x_init.
  *
  * in_ptr/in_col/in_cost: N_in over the samples (row x: y with c(y->x) < r),
@@ -860,11 +902,12 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
     for (;;) {
         if (i >= max_iters) { status = ORC_TIMEOUT; break; }
         /* line 3: the group */
-        int nG = 0;
+        int nG = 0, nOpen = 0;
         if (lambda > 0.0) {
             double thr = (double)i * delta;
             for (int v = 0; v < N; ++v) {
                 if (st[v] != ST_OPEN) continue;
+                ++nOpen;
                 if (i > 0) {
                     double mg = fabs(cost[v] - thr) / thr;
                     if (mg < margins[MG_GROUP]) margins[MG_GROUP] = mg;
@@ -875,6 +918,7 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
             double mn = INFINITY, second = INFINITY;
             for (int v = 0; v < N; ++v) {
                 if (st[v] != ST_OPEN) continue;
+                ++nOpen;
                 if (cost[v] < mn) { second = mn; mn = cost[v]; }
                 else if (cost[v] < second) second = cost[v];
             }
@@ -903,7 +947,7 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
             if (cand[x]) { C[nC++] = x; cand[x] = 0; }
 
         /* lines 5-9 against the open set as it stood when the iteration began */
-        int nS = 0;
+        int nS = 0, nFail = 0;
         for (int k = 0; k < nC; ++k) {
             int x = C[k];
             double best = INFINITY, second = INFINITY, best_tau = 0.0;
@@ -937,8 +981,20 @@ int orc_plan(int n, int dim, int kind, const float *samples, const float *x_init
                 stg_y[nS] = by;
                 stg_c[nS] = best;
                 ++nS;
+            } else {
+                ++nFail;
             }
             if (kind != ORC_EUCLID && cm < margins[MG_COLLIDE]) margins[MG_COLLIDE] = cm;
+        }
+        if (g_tr_buf && nG > 0) {
+            if (g_tr_len < g_tr_cap) {
+                int nDead = 0;
+                for (int k = 0; k < nC; ++k) nDead += sample_in_box(&cx, C[k]);
+                int *rec = g_tr_buf + (size_t)g_tr_len * ORC_TRACE_INTS;
+                rec[0] = i; rec[1] = nOpen; rec[2] = nG; rec[3] = nC;
+                rec[4] = nDead; rec[5] = nFail; rec[6] = nS;
+            }
+            ++g_tr_len;
         }
         for (int k = 0; k < nS; ++k) {
             int x = stg_x[k];

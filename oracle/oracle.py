@@ -88,6 +88,10 @@ def lib():
             L.orc_plan.restype = i32
             L.orc_plan.argtypes = [i32, i32, i32, P, P, P, C.c_float, i32, P, i32, f64, f64, f64,
                                    i32, i32, P, P, P, P, P, P, P, P, P, P, P, i32, P, P, P, P]
+            L.orc_trace_begin.restype = None
+            L.orc_trace_begin.argtypes = [P, i32]
+            L.orc_trace_end.restype = i32
+            L.orc_trace_end.argtypes = []
             L.orc_dijkstra.restype = i32
             L.orc_dijkstra.argtypes = [i32, i32, i32, P, P, P, i32, f64, f64, i32, P, P, P, P,
                                        i32, P]
@@ -231,6 +235,12 @@ class Plan:
     path_cost: float
     iters: int
     margins: np.ndarray
+    # per non-empty iteration: i, |open|, |G_i|, |C|, C in obstacles, lazy-check
+    # failures, nodes added (plan(..., trace=True) only)
+    trace: Optional[np.ndarray] = None
+
+
+TRACE_FIELDS = ("iter", "open", "group", "candidates", "candidates_in_obstacles", "check_failures", "added")
 
 
 def kind_of(prob) -> int:
@@ -238,8 +248,10 @@ def kind_of(prob) -> int:
 
 
 def plan(prob, r: float, table: Optional[Csr] = None, lam: Optional[float] = None,
-         max_iters: int = 0) -> Plan:
-    """Run Algorithm 1 on ``prob`` with radius ``r`` (table built when absent)."""
+         max_iters: int = 0, trace: bool = False) -> Plan:
+    """Run Algorithm 1 on ``prob`` with radius ``r`` (table built when absent).
+    ``trace``: also return one record per iteration with a non-empty group
+    (columns TRACE_FIELDS)."""
     kind = kind_of(prob)
     if kind == DUBINS:
         set_turn_radius(prob.turn_radius)
@@ -270,16 +282,22 @@ def plan(prob, r: float, table: Optional[Csr] = None, lam: Optional[float] = Non
     tt = np.ascontiguousarray(table.tau, np.float64)
     op = np.ascontiguousarray(op, np.int32)
     oc = np.ascontiguousarray(oc, np.int32)
+    tr = np.zeros((N + 1, len(TRACE_FIELDS)), np.int32) if trace else None
+    if trace:
+        lib().orc_trace_begin(_p(tr), tr.shape[0])
     st = lib().orc_plan(n, dim, kind, _p(s), _p(xi), _p(gc), C.c_float(prob.goal_radius),
                         prob.pdim, _p(bx), bx.shape[0], float(r),
                         float(prob.lam if lam is None else lam), float(prob.step),
                         int(prob.traj_points), int(max_iters), _p(ip), _p(ic), _p(cc),
                         _p(tt) if kind == DI else None, _p(op), _p(oc), _p(parent), _p(cost),
                         _p(gi), _p(ai), _p(path), N, _p(plen), _p(pcost), _p(iters), _p(mg))
+    if trace:
+        k = lib().orc_trace_end()
+        tr = tr[:min(k, tr.shape[0])].copy()
     if st < 0:
         raise ValueError("oracle rejected the problem (status %d)" % st)
     return Plan(int(st), parent, cost, gi, ai, path[:int(plen[0])].copy(), float(pcost[0]),
-                int(iters[0]), mg)
+                int(iters[0]), mg, tr)
 
 
 def dijkstra(prob, r: float, table: Optional[Csr] = None, only_clear: bool = False) -> np.ndarray:
