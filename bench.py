@@ -26,12 +26,13 @@ FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
 # with this digest and the launch shape named; reported only while both match
-TRAFFIC = {"sources_sha256": "482b27186df2d37188ae501c1913d0824addd32347eb8d820f67cbe32c6e28d7",
+TRAFFIC = {"sources_sha256": "65b92d425e9608be71e8cec7c7d5c940a748763d2270566ff900a8c59f673d99",
            "batch": 4096, "lanes": 8, "threads": 1024,
-           "bytes_per_launch": int((2.0 * 71646376 + 5661304) * 1024)}
+           "bytes_per_launch": int((2.0 * 71590443 + 5659756) * 1024)}
 # the same for the Euclidean row kernel k_eu_rows building the 3D table at
 # n = 1048576 (medians of five builds)
 EU_TRAFFIC = {"sources_sha256": "8706551abd768542af306f0e97e937887a6272b44a79e3d39fc693fdf7a69059", "n": 1048576,
+              "tile": 1,
               "bytes_per_launch": int((2.0 * 55938.5 + 2967653.4) * 1024)}
 
 
@@ -755,6 +756,8 @@ def main():
             p3 = I.problem_3d(0, n=n3)
             r3 = RAD.problem_radius(p3)
             d3 = torch.from_numpy(p3.samples).cuda()
+            # the tuner's tile shape for this (dim, n) bucket, then builds with it
+            tuned = gmt.gmt_autotune_build(d3, r3, reps=3)
             bt, kt = [], []
             gmt.gmt_profile_enable(True)
             for k in range(5):
@@ -763,7 +766,8 @@ def main():
                 rm3 = gmt.gmt_build_neighbors(d3, gmt.GMT_COST_EUCLIDEAN, r3)
                 torch.cuda.synchronize()
                 bt.append((time.perf_counter() - t) * 1e3)
-                kt.append(gmt.gmt_last_build()["kernel_ms"])
+                lb = gmt.gmt_last_build()
+                kt.append(lb["kernel_ms"])
                 e3 = rm3.nnz
                 held = rm3.device_bytes
                 rm3.free()
@@ -774,7 +778,7 @@ def main():
             nbytes = euclid_build_bytes(n3, 3, e3)
             built = euclid_build_bytes(n3, 3, e3) + 4 * n3
             eu_traffic = None
-            if (n3 == EU_TRAFFIC["n"] and
+            if (n3 == EU_TRAFFIC["n"] and lb["tile"] == EU_TRAFFIC["tile"] and
                     kernel_digest(("gmt_build.hpp", "gmt_dev.hpp")) == EU_TRAFFIC["sources_sha256"]):
                 eu_traffic = EU_TRAFFIC["bytes_per_launch"]
             build_line.append({"workload": "3D Euclidean n=%d, r=%.4f" % (n3, r3), "edges": int(e3),
@@ -784,8 +788,11 @@ def main():
                                "unit": "GB/s", "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "bytes_as_built": int(built),
                                "frac_as_built": round(built / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                               "traffic_k_eu_rows": eu_traffic})
-            say("euclid build n=%d: %.3f ms wall, %.3f ms kernels" % (n3, bt, kms))
+                               "traffic_k_eu_rows": eu_traffic, "tile": int(lb["tile"]),
+                               "tuner": {"tile": tuned["tile"], "ms": round(tuned["ms"], 4),
+                                         "default_ms": round(tuned["default_ms"], 4),
+                                         "rejected": tuned["rejected"]}})
+            say("euclid build n=%d: %.3f ms wall, %.3f ms kernels, tile %d" % (n3, bt, kms, lb["tile"]))
             del d3
 
     learned = None

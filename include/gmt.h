@@ -73,11 +73,22 @@ typedef enum {
  * computed again, straight into the table, by a pass of its own.  0 picks
  * max(384, 2^25 / n) (at most n): sizes device memory (20 bytes per entry,
  * freed when the build returns) and speed only, never the table.  Must be
- * >= 0; unused by the Euclidean kind. */
+ * >= 0; unused by the Euclidean kind.  build_tile: the Euclidean build's
+ * tile shape, 1..GMT_BUILD_TILES (see gmt_autotune_build), or 0 for the
+ * library's choice (the tuned shape for the build's (dim, ceil log2 n) if one
+ * is cached, else shape 1); speed only, never the table.  Unused by the other
+ * kinds. */
 typedef struct {
     double turn_radius;
     int32_t row_slots;
+    int32_t build_tile;
 } gmt_cost_params;
+
+/* Tile shapes of the Euclidean build: cells per tile along the slowest axis,
+ * waves per workgroup, samples staged per chunk --
+ * 1: 4 cells, 8 waves, 2304;  2: 6 cells, 12 waves, 2816;
+ * 3: 2 cells, 4 waves, 1536;  4: 8 cells, 16 waves, 3328. */
+#define GMT_BUILD_TILES 4
 
 /* Opaque device-resident roadmap: a sample set with its r-disk neighbour
  * table (Section V-A precomputes exactly this offline).  Read-only while
@@ -120,7 +131,14 @@ typedef struct {
  *              0 (library choice: autotuned if cached, else 16).
  *  threads     threads per workgroup: 256, 512 or 1024, or 0 (library
  *              choice: autotuned if cached, else 1024).
- *  Results do not depend on team_wgs, lanes or threads.  */
+ *  trace       per-iteration records kept per query (gmt_trace_rec, read
+ *              with gmt_last_trace): at most `trace` records, 0 for none,
+ *              at most GMT_TRACE_MAX.  Honoured by gmt_plan and
+ *              gmt_plan_batch; gmt_plan_noalloc, gmt_batch_prepare and
+ *              gmt_engine_create reject a non-zero value (GMT_EINVAL).  A
+ *              traced plan runs with 16 lanes per candidate whatever
+ *              `lanes` asks for.
+ *  Results do not depend on team_wgs, lanes, threads or trace.  */
 typedef struct {
     double edge_step;
     int32_t traj_points;
@@ -128,7 +146,44 @@ typedef struct {
     int32_t team_wgs;
     int32_t lanes;
     int32_t threads;
+    int32_t trace;
 } gmt_plan_opts;
+
+#define GMT_TRACE_MAX (1 << 20)
+
+/* One record per iteration of Algorithm 1 whose group is non-empty (the
+ * planner jumps over empty ones), iteration 0 first:
+ *  iter            the threshold index i (0: the root's iteration)
+ *  open            open nodes when the iteration starts (line 3)
+ *  group           |G_i| (line 3)
+ *  goal_in_group   members of G_i inside the goal region (line 12)
+ *  candidates      unexplored out-neighbours of G_i (line 4); samples inside
+ *                  an obstacle are never candidates (they cannot join the
+ *                  tree, since every edge ending in one fails the check)
+ *  check_failures  candidates whose locally optimal edge failed the lazy
+ *                  check (lines 5-7); every candidate has a parent, as a
+ *                  member of G_i is among its in-neighbours
+ *  added           nodes that joined the tree (lines 8-9)
+ *  select_ns, frontier_ns, connect_ns   device wall clock at the end of
+ *                  the select (line 3), frontier (line 4) and connect (lines
+ *                  5-9) phases since the query's team started it; the
+ *                  iteration-0 record carries the end of setup in all three
+ *  check_ns        time the team's first wavefront has spent in lazy checks
+ *                  since the start (cumulative)  */
+typedef struct {
+    int32_t iter;
+    int32_t open;
+    int32_t group;
+    int32_t goal_in_group;
+    int32_t candidates;
+    int32_t check_failures;
+    int32_t added;
+    int32_t reserved;
+    int64_t select_ns;
+    int64_t frontier_ns;
+    int64_t connect_ns;
+    int64_t check_ns;
+} gmt_trace_rec;
 
 /* Install the device allocator (NULL restores hipMalloc/hipFree).  Affects
  * allocations made after the call; memory is returned to the allocator that
@@ -320,6 +375,15 @@ typedef struct {
 /* Work of the last gmt_plan / gmt_plan_batch call on this thread. */
 gmt_status gmt_last_work(gmt_work *out);
 
+/* Per-iteration records of query `query` (0 for gmt_plan; the caller's index
+ * for gmt_plan_batch) of the last gmt_plan / gmt_plan_batch call on this
+ * thread that ran with opts.trace > 0.  *len receives the number of records
+ * kept (the iterations run, iteration 0 included, up to opts.trace); the first
+ * min(*len, cap) are copied to `out` (host memory; may be NULL when cap is
+ * 0).  GMT_EINVAL when the last call kept no records or `query` lies outside
+ * it; a call that fails leaves none. */
+gmt_status gmt_last_trace(int32_t query, gmt_trace_rec *out, int32_t cap, int32_t *len);
+
 /* Kernel timing: while enabled, planning launches are bracketed by HIP events
  * on their stream and the elapsed kernel time is accumulated.
  * gmt_profile_read returns the total milliseconds and launch count since the
@@ -340,13 +404,16 @@ gmt_status gmt_profile_read(double *kernel_ms, int64_t *launches);
  *                the table sized on the host between them; Euclidean: one
  *                pass, and one more when a row outgrew the slots), while
  *                gmt_profile_enable is on; 0 otherwise;
- *  segments      timed segments summed into kernel_ms. */
+ *  segments      timed segments summed into kernel_ms;
+ *  tile          Euclidean: the tile shape the build ran with (1 ..
+ *                GMT_BUILD_TILES); 0 for the other kinds. */
 typedef struct {
     int64_t edges;
     int64_t pairs_tested;
     int64_t pairs_solved;
     double kernel_ms;
     int32_t segments;
+    int32_t tile;
 } gmt_build_info;
 
 gmt_status gmt_last_build(gmt_build_info *out);
@@ -516,6 +583,28 @@ gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, int32_t sing
 
 /* Cached choice for a shape (all zero when none). */
 gmt_status gmt_tune_lookup(const gmt_tune_shape *shape, gmt_tune_choice *out);
+
+/* Neighbour-build tile knob (Euclidean tables).  Builds the table of the
+ * caller's samples (device [dim][n], as gmt_build_neighbors) with every tile
+ * shape `reps` times, checks that each gives the table of shape 1 (row
+ * lengths and the multiset of (row, column, squared distance) records, by a
+ * 64-bit digest), and caches the fastest under (dim, ceil log2 n) for later
+ * builds whose params leave build_tile at 0.  out->tile is the chosen shape,
+ * out->ms and out->default_ms the median build wall times with it and with
+ * shape 1, out->candidates the shapes timed, out->rejected those whose table
+ * differed (never chosen).  The cache is saved and loaded with the plan
+ * knobs (gmt_tune_save / gmt_tune_load) and cleared by gmt_tune_clear. */
+typedef struct {
+    int32_t tile;
+    int32_t candidates;
+    int32_t rejected;
+    int32_t pad;
+    double ms;
+    double default_ms;
+} gmt_build_tune;
+
+gmt_status gmt_autotune_build(const float *d_samples, int32_t n, int32_t dim, double r_n, int32_t reps,
+                              gmt_build_tune *out, void *stream);
 
 /* Store a choice for a shape (validated like plan options). */
 gmt_status gmt_tune_store(const gmt_tune_shape *shape, const gmt_tune_choice *choice);

@@ -246,7 +246,7 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
 // of a sample lies in the (2 EU_W + 1)^d cells around its own, and a sample
 // more than EU_W cells away along any axis is at least EU_W h >= r away.
 //
-// Tiles.  A workgroup of EU_WAVES waves takes EU_XB cells that follow each
+// Tiles.  A workgroup of WAVES waves takes XB cells that follow each
 // other along the slowest axis (z in 3D, y in 2D: the "slab" axis) at one
 // (x, y) resp. x; their samples are its rows.  It stages in LDS the samples of
 // the slabs within EU_W cells of them, slab after slab: inside a slab each
@@ -257,7 +257,7 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
 // up to four blocks of 64 samples (one per lane per block, the LDS reads of a
 // step issued together); the last step reads at most 127 samples past the
 // window, which only adds pairs farther than r apart.  Staging goes in chunks
-// of EU_CHUNK followed by EU_PAD samples far outside every r-ball.  Tiles are
+// of CHUNK followed by EU_PAD samples far outside every r-ball.  Tiles are
 // ordered so that each of the eight XCDs (which take workgroups in turn)
 // works through one contiguous range of neighbouring tiles, which stage mostly
 // the same samples, through its own L2.
@@ -280,64 +280,72 @@ __global__ void k_eu_scatter(const float *__restrict__ s, int n, EuGrid g,
 // the full row length and *maxdeg its maximum, so the host can rerun the pass
 // with a larger cap.  Rows come out in staging order (the parent search does
 // not depend on it).
-#ifndef EU_W
 #define EU_W 2
-#endif
-#ifndef EU_XB
-#define EU_XB 4
-#endif
-#ifndef EU_CHUNK
-#define EU_CHUNK 2304
-#endif
-#ifndef EU_WAVES
-#define EU_WAVES 8
-#endif
 #define EU_SPAN (2 * EU_W + 1)
-#define EU_THREADS (EU_WAVES * GMT_WAVE)
 #define EU_ROWS 256
 #define EU_OBUF 256
 #define EU_FAR 536870912.0f  // 2^29 grid units: beyond every r-ball
-#define EU_RUNS ((EU_XB + 2 * EU_W) * EU_SPAN)
 #define EU_PAD 128
-#define EU_STAGE (EU_CHUNK + EU_PAD)
-static_assert(EU_CHUNK % 128 == 0 && EU_CHUNK <= 65536 && EU_OBUF >= 4 * GMT_WAVE && EU_RUNS <= 256 && EU_WAVES >= 2,
-              "staging and output buffer shapes");
 
-// cells along x, y (3D) and tiles along the slab axis, in launch order
-__host__ __device__ inline int eu_tiles(int G, int dim) {
-    return G * (dim == 3 ? G : 1) * ((G + EU_XB - 1) / EU_XB);
+// Tile shapes (cells per tile XB, waves per workgroup, staging chunk): the
+// tuner's neighbour-build knob; shape 0 is the default.
+#define EU_SHAPES 4
+struct EuShape {
+    int xb, waves, chunk;
+};
+__host__ __device__ inline EuShape eu_shape(int k) {
+    switch (k) {
+    case 1: return {6, 12, 2816};
+    case 2: return {2, 4, 1536};
+    case 3: return {8, 16, 3328};
+    default: return {4, 8, 2304};
+    }
+}
+template <int XB, int WAVES, int CHUNK>
+struct EuCheck {
+    static_assert(CHUNK % 128 == 0 && CHUNK <= 65536 && EU_OBUF >= 4 * GMT_WAVE && (XB + 2 * EU_W) * EU_SPAN <= 256 &&
+                      WAVES >= 2,
+                  "staging and output buffer shapes");
+};
+
+// cells along x, y (3D) and tiles of `xb` cells along the slab axis, in
+// launch order
+__host__ __device__ inline int eu_tiles(int G, int dim, int xb) {
+    return G * (dim == 3 ? G : 1) * ((G + xb - 1) / xb);
 }
 
-__global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *__restrict__ pts,
+template <int XB, int WAVES, int CHUNK>
+__global__ void __launch_bounds__(WAVES * GMT_WAVE) k_eu_rows(EuGrid g, const float4 *__restrict__ pts,
                                                         const int *__restrict__ cell_start, float R2f,
                                                         double R2b, int cap, int *__restrict__ deg,
                                                         int *__restrict__ maxdeg,
                                                         unsigned long long *__restrict__ rec,
                                                         unsigned long long *__restrict__ tested) {
-    __shared__ float4 cand[EU_STAGE];
+    (void)sizeof(EuCheck<XB, WAVES, CHUNK>);
+    __shared__ float4 cand[(CHUNK + EU_PAD)];
     // per wave: staging slots of the row's passing pairs, then one slot per lane
-    __shared__ int oslot[EU_WAVES * EU_OBUF];
+    __shared__ int oslot[WAVES * EU_OBUF];
     __shared__ int rcnt[EU_ROWS];
-    __shared__ int sb[EU_RUNS], soff[EU_RUNS + 1];
-    __shared__ int rbeg[EU_XB], rpre[EU_XB + 1];
+    __shared__ int sb[((XB + 2 * EU_W) * EU_SPAN)], soff[((XB + 2 * EU_W) * EU_SPAN) + 1];
+    __shared__ int rbeg[XB], rpre[XB + 1];
     __shared__ unsigned long long wtest;
     const int G = g.G, dim = g.dim;
     const int nm = dim == 3 ? G : 1;
-    const int ntile = eu_tiles(G, dim);
+    const int ntile = eu_tiles(G, dim, XB);
     int b = blockIdx.x;
     {
         const int per = ntile / 8, rem = ntile % 8, x = b % 8;
         b = x * per + min(x, rem) + b / 8;
     }
-    const int cx = b % G, cm = (b / G) % nm, s0 = (b / G / nm) * EU_XB;
-    const int s1 = min(s0 + EU_XB, G) - 1;
+    const int cx = b % G, cm = (b / G) % nm, s0 = (b / G / nm) * XB;
+    const int s1 = min(s0 + XB, G) - 1;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / GMT_WAVE), lane = lane_id();
     const int nmid = dim == 3 ? EU_SPAN : 1;
     const int xs0 = max(s0 - EU_W, 0), xs1 = min(s1 + EU_W, G - 1);
     const int nrun = (xs1 - xs0 + 1) * nmid;
     const int xlo = max(cx - EU_W, 0), xhi = min(cx + EU_W, G - 1);
     // run k: slab xs0 + k / nmid, line y = cm - EU_W + k % nmid, cells xlo..xhi
-    for (int k = tid; k < nrun; k += EU_THREADS) {
+    for (int k = tid; k < nrun; k += (WAVES * GMT_WAVE)) {
         const int sl = xs0 + k / nmid, m = dim == 3 ? cm - EU_W + k % nmid : 0;
         int bb = 0, e = 0;
         if (m >= 0 && m < nm) {
@@ -348,7 +356,7 @@ __global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *
         sb[k] = bb;
         soff[k + 1] = e - bb;
     }
-    if (tid < EU_XB) {
+    if (tid < XB) {
         const int sl = s0 + tid;
         int bb = 0, e = 0;
         if (sl <= s1) {
@@ -387,10 +395,10 @@ __global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *
         }
         if (lane == GMT_WAVE - 1) soff[nrun] = x;
     } else if (tid == GMT_WAVE) {
-        for (int j = 1; j <= EU_XB; ++j) rpre[j] += rpre[j - 1];
+        for (int j = 1; j <= XB; ++j) rpre[j] += rpre[j - 1];
     }
     __syncthreads();
-    const int nrows = rpre[EU_XB];
+    const int nrows = rpre[XB];
     if (nrows == 0) return;  // the same for the whole workgroup
     const int total = soff[nrun];
     int *wslot = oslot + wave * EU_OBUF;
@@ -399,27 +407,27 @@ __global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *
     auto row_at = [&](int ri, int &slab) {
         int j = 0;
 #pragma unroll
-        for (int t = 1; t < EU_XB; ++t)
+        for (int t = 1; t < XB; ++t)
             if (ri >= rpre[t]) j = t;
         slab = s0 + j;
         return rbeg[j] + (ri - rpre[j]);
     };
     for (int r0 = 0; r0 < nrows; r0 += EU_ROWS) {  // blocks of rows
         const int nr = min(EU_ROWS, nrows - r0);
-        for (int i = tid; i < nr; i += EU_THREADS) rcnt[i] = 0;
-        for (int c0 = 0; c0 < total; c0 += EU_CHUNK) {
-            const int cnt = min(EU_CHUNK, total - c0);
+        for (int i = tid; i < nr; i += (WAVES * GMT_WAVE)) rcnt[i] = 0;
+        for (int c0 = 0; c0 < total; c0 += CHUNK) {
+            const int cnt = min(CHUNK, total - c0);
             __syncthreads();  // the previous chunk is no longer read
             // stage [c0, c0 + cnt): run by run, a wave per run, the first 64
             // samples of each of a wave's runs loaded together
             {
                 // stage [c0, c0 + cnt): every thread's loads issued together,
                 // the run of each element found by binary search
-                constexpr int SU = (EU_CHUNK + EU_THREADS - 1) / EU_THREADS;
+                constexpr int SU = (CHUNK + (WAVES * GMT_WAVE) - 1) / (WAVES * GMT_WAVE);
                 float4 v[SU];
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
-                    const int e = tid + u * EU_THREADS;
+                    const int e = tid + u * (WAVES * GMT_WAVE);
                     v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (e < cnt) {
                         const int f = c0 + e;
@@ -434,19 +442,19 @@ __global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *
                 }
 #pragma unroll
                 for (int u = 0; u < SU; ++u)
-                    if (tid + u * EU_THREADS < cnt) cand[tid + u * EU_THREADS] = v[u];
+                    if (tid + u * (WAVES * GMT_WAVE) < cnt) cand[tid + u * (WAVES * GMT_WAVE)] = v[u];
             }
-            for (int k = tid; k < EU_PAD; k += EU_THREADS)
+            for (int k = tid; k < EU_PAD; k += (WAVES * GMT_WAVE))
                 cand[cnt + k] = make_float4(EU_FAR, EU_FAR, EU_FAR, __int_as_float(-1));
             __syncthreads();
             int sn;
             int pn = wave < nr ? row_at(r0 + wave, sn) : 0;
             float4 qn = wave < nr ? pts[pn] : make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int ri = wave; ri < nr; ri += EU_WAVES) {
+            for (int ri = wave; ri < nr; ri += WAVES) {
                 const float4 q = qn;
                 const int slab = sn;
-                if (ri + EU_WAVES < nr) {  // the wave's next row, loaded early
-                    pn = row_at(r0 + ri + EU_WAVES, sn);
+                if (ri + WAVES < nr) {  // the wave's next row, loaded early
+                    pn = row_at(r0 + ri + WAVES, sn);
                     qn = pts[pn];
                 }
                 const int qi = __float_as_int(q.w);
@@ -531,7 +539,7 @@ __global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *
             }
         }
         __syncthreads();
-        for (int i = tid; i < nr; i += EU_THREADS) {
+        for (int i = tid; i < nr; i += (WAVES * GMT_WAVE)) {
             int sl;
             const int pi = row_at(r0 + i, sl);
             deg[__float_as_int(pts[pi].w)] = rcnt[i];
@@ -550,6 +558,32 @@ __global__ void __launch_bounds__(EU_THREADS) k_eu_rows(EuGrid g, const float4 *
 __global__ void k_rec8_pad(unsigned long long *__restrict__ rec, long long at) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < GMT_REC_PAD) rec[at + k] = 0ull;
+}
+
+// order-independent digest of a Euclidean table: the wrapping sum over rows
+// of a mixed (row, length) word and over every record of a mixed (row,
+// record) word, so tables equal as multisets of (row, column, d2) records
+// with equal row lengths give equal digests whatever the order inside rows
+__device__ __forceinline__ unsigned long long eu_mix(unsigned long long z) {
+    // splitmix64's finaliser
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__global__ void k_eu_digest(int n, int cap, const int *__restrict__ deg, const unsigned long long *__restrict__ rec,
+                            unsigned long long *__restrict__ out) {
+    unsigned long long acc = 0;
+    const long long total = (long long)n * cap;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int row = (int)(k / cap), slot = (int)(k % cap);
+        const int d = deg[row];
+        if (slot == 0) acc += eu_mix(((unsigned long long)row << 32) ^ (unsigned)d ^ 0x5bd1e995ull);
+        if (slot < d) acc += eu_mix(rec[k] * 0x9e3779b97f4a7c15ull + (unsigned long long)row);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & (GMT_WAVE - 1)) == 0 && acc) atomicAdd(out, acc);
 }
 
 // compact (column, FP64 cost) copies of the rows (row_ptr: exclusive scan of

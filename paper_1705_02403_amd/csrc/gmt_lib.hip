@@ -118,6 +118,9 @@ extern "C" gmt_status gmt_set_allocator(const gmt_allocator *allocator) {
 extern "C" const char *gmt_last_error(void) { return g_last_error.c_str(); }
 
 static thread_local gmt_work g_last_work = {};
+// per-iteration records of the last traced gmt_plan / gmt_plan_batch call,
+// by the caller's query index
+static thread_local std::vector<std::vector<gmt_trace_rec>> g_last_trace;
 
 extern "C" gmt_status gmt_last_work(gmt_work *out) {
     if (!out) return fail(GMT_EINVAL, "null argument");
@@ -200,6 +203,17 @@ static double tick_ns() {
     return g_tick_ns;
 }
 
+extern "C" gmt_status gmt_last_trace(int32_t query, gmt_trace_rec *out, int32_t cap, int32_t *len) {
+    if (!len || cap < 0 || (cap > 0 && !out)) return fail(GMT_EINVAL, "null argument");
+    if (g_last_trace.empty()) return fail(GMT_EINVAL, "the last plan call on this thread kept no records");
+    if (query < 0 || query >= (int32_t)g_last_trace.size())
+        return fail(GMT_EINVAL, "query %d outside the last call's %zu", query, g_last_trace.size());
+    const std::vector<gmt_trace_rec> &t = g_last_trace[query];
+    *len = (int32_t)t.size();
+    for (int32_t k = 0; k < cap && k < (int32_t)t.size(); ++k) out[k] = t[k];
+    return GMT_OK;
+}
+
 static void work_add(gmt_work &w, const unsigned long long *c) {
     w.out_edges += (int64_t)c[0];
     w.in_edges += (int64_t)c[1];
@@ -228,6 +242,8 @@ struct gmt_roadmap {
     long long nnz = 0;
     int cap = 0;       // Euclidean: slots per row (row x at x * cap), deg[x] used
     int row_slots = 0; // asymmetric kinds: scratch entries per row asked for by the caller (0: default)
+    int build_tile = 0; // Euclidean: tile shape asked for by the caller (1-based; 0: library choice)
+    int tile_used = 0;  // Euclidean: the shape the build ran with (0-based)
     DevBuf deg;        // Euclidean: row lengths
     DevBuf s, in_ptr, in_col, in_tau, out_ptr, out_col;
     DevBuf in_cost;  // FP64 edge costs while a table is built; the records keep them
@@ -365,6 +381,36 @@ static gmt_status pack_records(gmt_roadmap *rm, hipStream_t s) {
     return GMT_OK;
 }
 
+// tuned Euclidean build tiles by (dim, ceil log2 n); guarded by g_build_mu
+static std::mutex g_build_mu;
+static std::map<std::pair<int, int>, gmt_build_tune> g_build_tune;
+
+static int ceil_log2_int(long long v) {
+    int k = 0;
+    while ((1ll << k) < v) ++k;
+    return k;
+}
+
+// 0-based tile shape of a build: the caller's, else the tuned one, else 0
+static int build_tile_of(const gmt_roadmap *rm) {
+    if (rm->build_tile > 0) return rm->build_tile - 1;
+    std::lock_guard<std::mutex> lk(g_build_mu);
+    auto it = g_build_tune.find({rm->dim, ceil_log2_int(rm->n)});
+    return it != g_build_tune.end() ? it->second.tile - 1 : 0;
+}
+
+template <int K>
+static void launch_eu_rows(const EuGrid &g, hipStream_t s, const float4 *pts, const int *cell_start, float R2f,
+                           double R2b, int cap, int *deg, int *maxdeg, unsigned long long *rec,
+                           unsigned long long *tested) {
+    constexpr int XB = K == 1 ? 6 : K == 2 ? 2 : K == 3 ? 8 : 4;
+    constexpr int WAVES = K == 1 ? 12 : K == 2 ? 4 : K == 3 ? 16 : 8;
+    constexpr int CHUNK = K == 1 ? 2816 : K == 2 ? 1536 : K == 3 ? 3328 : 2304;
+    static_assert(XB == 4 || K != 0, "shape table");
+    k_eu_rows<XB, WAVES, CHUNK><<<(unsigned)eu_tiles(g.G, g.dim, XB), WAVES * GMT_WAVE, 0, s>>>(
+        g, pts, cell_start, R2f, R2b, cap, deg, maxdeg, rec, tested);
+}
+
 // slots per row of a Euclidean table: room for the mean degree of an interior
 // sample, (n - 1) times the volume of the r-ball, and its spread (a longer
 // row makes the build run its pass again with the measured maximum)
@@ -430,8 +476,9 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
     TRY(scan_ints((const int *)cell_cnt.p, g.ncell, (int *)cell_start.p, nullptr, s, scan_tmp));
     k_eu_scatter<<<blocks_for(n, 256), 256, 0, s>>>((const float *)rm->s.p, n, g, (const int *)cell_of.p,
                                                    (const int *)cell_start.p, (int *)cursor.p, (float4 *)pts.p);
-    // one workgroup per EU_XB cells along the slowest axis
-    const unsigned wgs = (unsigned)eu_tiles(g.G, dim);
+    // one workgroup per tile of cells along the slowest axis
+    const int tile = build_tile_of(rm);
+    rm->tile_used = tile;
     int cap = eu_capacity(n, dim, rm->r);
     int hs[6];
     for (int attempt = 0;; ++attempt) {
@@ -443,9 +490,18 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
         rm->in_rec = dev_view(rm->tab, o_rec, 8 * slots);
         if (attempt > 0) bt.begin();
         k_fill_int<<<1, 64, 0, s>>>(maxdeg, 5, 0);  // maxdeg, total, tests
-        k_eu_rows<<<wgs, EU_THREADS, 0, s>>>(g, (const float4 *)pts.p, (const int *)cell_start.p, R2f, R2b, cap,
-                                      (int *)rm->deg.p,
-                                      maxdeg, (unsigned long long *)rm->in_rec.p, tested);
+        {
+            const float4 *pp = (const float4 *)pts.p;
+            const int *cs = (const int *)cell_start.p;
+            int *dg = (int *)rm->deg.p;
+            unsigned long long *rc = (unsigned long long *)rm->in_rec.p;
+            switch (tile) {
+            case 1: launch_eu_rows<1>(g, s, pp, cs, R2f, R2b, cap, dg, maxdeg, rc, tested); break;
+            case 2: launch_eu_rows<2>(g, s, pp, cs, R2f, R2b, cap, dg, maxdeg, rc, tested); break;
+            case 3: launch_eu_rows<3>(g, s, pp, cs, R2f, R2b, cap, dg, maxdeg, rc, tested); break;
+            default: launch_eu_rows<0>(g, s, pp, cs, R2f, R2b, cap, dg, maxdeg, rc, tested); break;
+            }
+        }
         TRY(scan_ints((const int *)rm->deg.p, n, (int *)rm->in_ptr.p, total, s, scan_tmp));
         k_rec8_pad<<<blocks_for(GMT_REC_PAD, 256), 256, 0, s>>>((unsigned long long *)rm->in_rec.p,
                                                                (long long)n * cap);
@@ -469,7 +525,7 @@ static gmt_status build_euclid(gmt_roadmap *rm, hipStream_t s) {
         return fail(GMT_EINVAL, "table of %d rows x %d slots exceeds the int32 index range", n, cap);
     rm->nnz = E;
     rm->cap = cap;
-    g_last_build = gmt_build_info{E, (int64_t)ntest, 0, bt.ms, bt.segments};
+    g_last_build = gmt_build_info{E, (int64_t)ntest, 0, bt.ms, bt.segments, tile + 1};
     return GMT_OK;
 }
 
@@ -580,7 +636,7 @@ static gmt_status build_pairs(gmt_roadmap *rm, hipStream_t s) {
     }
     TRY(build_out_table(rm, s, T + o_out));
     bt.end();
-    g_last_build = gmt_build_info{E, (int64_t)n * (int64_t)(n - 1), (int64_t)nsolved, bt.ms, bt.segments};
+    g_last_build = gmt_build_info{E, (int64_t)n * (int64_t)(n - 1), (int64_t)nsolved, bt.ms, bt.segments, 0};
     return GMT_OK;
 }
 
@@ -598,6 +654,9 @@ extern "C" gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, 
     }
     const int row_slots = params ? params->row_slots : 0;
     if (row_slots < 0) return fail(GMT_EINVAL, "row_slots must be >= 0 (got %d)", row_slots);
+    const int build_tile = params ? params->build_tile : 0;
+    if (build_tile < 0 || build_tile > GMT_BUILD_TILES)
+        return fail(GMT_EINVAL, "build_tile must lie in [0, %d] (got %d)", GMT_BUILD_TILES, build_tile);
     hipStream_t s = (hipStream_t)stream;
     gmt_roadmap *rm = new gmt_roadmap;
     rm->n = n;
@@ -606,6 +665,7 @@ extern "C" gmt_status gmt_build_neighbors_ex(const float *d_samples, int32_t n, 
     rm->r = r_n;
     rm->rho = rho;
     rm->row_slots = row_slots;
+    rm->build_tile = build_tile;
     gmt_status st = dev_alloc(rm->s, sizeof(float) * (size_t)dim * n, s);
     if (st == GMT_OK) {
         hipError_t e = hipMemcpyAsync(rm->s.p, d_samples, sizeof(float) * (size_t)dim * n,
@@ -1338,6 +1398,7 @@ static gmt_plan_opts default_opts(const gmt_plan_opts *o) {
     d.team_wgs = 0;
     d.lanes = 0;
     d.threads = 0;
+    d.trace = 0;
     return d;
 }
 
@@ -1402,9 +1463,27 @@ static const void *plan_kernel_k(int level, int cl) {
                         : plan_kernel_cl<K, 0, G>(cl);
 }
 
+// the variant that keeps per-iteration records: 16 lanes per candidate only
+template <int K, bool G>
+static const void *plan_kernel_traced(int level) {
+    return level == 2   ? (const void *)k_plan<K, 2, 16, G, true>
+           : level == 1 ? (const void *)k_plan<K, 1, 16, G, true>
+                        : (const void *)k_plan<K, 0, 16, G, true>;
+}
+
 // the plan kernel of a cost kind, state placement and lane width; `grid`:
-// the variant with box-grid culling (for launches with such queries)
-static const void *plan_kernel(int kind, int level, int cl, bool grid = false) {
+// the variant with box-grid culling (for launches with such queries);
+// `traced`: the record-keeping variant (lane width 16)
+static const void *plan_kernel(int kind, int level, int cl, bool grid = false, bool traced = false) {
+    if (traced) {
+        if (grid)
+            return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_traced<0, true>(level)
+                   : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_traced<1, true>(level)
+                                                         : plan_kernel_traced<2, true>(level);
+        return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_traced<0, false>(level)
+               : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_traced<1, false>(level)
+                                                     : plan_kernel_traced<2, false>(level);
+    }
     if (grid)
         return kind == GMT_COST_EUCLIDEAN            ? plan_kernel_k<0, true>(level, cl)
                : kind == GMT_COST_DOUBLE_INTEGRATOR ? plan_kernel_k<1, true>(level, cl)
@@ -1506,10 +1585,12 @@ struct BatchRun {
     bool prof = false;
     bool own_all = false;  // tree arrays always in the workspace (prepared batches)
     hipEvent_t ev[7] = {};  // kernel brackets of each kind (2k, 2k+1), then done (kEvDone)
+    DevBuf trace;          // per-iteration records, trace_cap per query in kernel order
+    int trace_cap = 0;
 };
 static const int kEvDone = 6;
 
-static void run_release(BatchRun &r) {
+static void run_release(BatchRun &r, hipStream_t s = nullptr) {
     for (hipEvent_t &e : r.ev)
         if (e) {
             (void)hipEventDestroy(e);
@@ -1517,6 +1598,7 @@ static void run_release(BatchRun &r) {
         }
     if (r.w) ws_release(r.w);
     r.w = nullptr;
+    dev_free(r.trace, s);
 }
 
 // Launch init + persistent planning over staged queries [first, first+count)
@@ -1526,7 +1608,8 @@ static void run_release(BatchRun &r) {
 // results.  Events e0 / e1 (may be null) bracket the plan kernel.
 static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, int kind, int first, int count,
                                    int total, int nmax, int teams, int team_wgs, int box_words_in, int qslot, int cl,
-                                   int threads, bool with_grid, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+                                   int threads, bool with_grid, hipEvent_t e0, hipEvent_t e1, hipStream_t s,
+                                   bool traced = false) {
     int box_words = plan_box_words(kind, box_words_in);
     char *sd = (char *)stage_d;
     int *queue = (int *)sd + qslot;
@@ -1536,16 +1619,17 @@ static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, 
     const int level = plan_level(team_wgs, threads, box_words, nmax);
     const size_t plds = plan_lds(box_words, nmax, level);
     if (plds > 64 * 1024)
-        (void)hipFuncSetAttribute(plan_kernel(kind, level, cl, with_grid), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)plds);
+        (void)hipFuncSetAttribute(plan_kernel(kind, level, cl, with_grid, traced),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
     if (e0) HIPCHK(hipEventRecord(e0, s));
     dim3 grid(teams * team_wgs), block(threads);
     int st_bytes = nmax + 1;
     void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
     if (team_wgs > 1)
-        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, 0, cl, with_grid), grid, block, args, (unsigned)plds, s));
+        HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, 0, cl, with_grid, traced), grid, block, args,
+                                          (unsigned)plds, s));
     else
-        HIPCHK(hipLaunchKernel(plan_kernel(kind, level, cl, with_grid), grid, block, args, plds, s));
+        HIPCHK(hipLaunchKernel(plan_kernel(kind, level, cl, with_grid, traced), grid, block, args, plds, s));
     if (e1) HIPCHK(hipEventRecord(e1, s));
     return GMT_OK;
 }
@@ -1588,7 +1672,7 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, b
             TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, kind, r.kfirst[kind],
                                  r.kcount[kind], r.count, r.knmax[kind], std::min(r.teams, r.kcount[kind]),
                                  r.team_wgs, r.box_words, kind, r.cl, r.threads, r.kgrid[kind], r.ev[2 * kind],
-                                 r.ev[2 * kind + 1], s));
+                                 r.ev[2 * kind + 1], s, r.trace_cap > 0));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
     if (events) HIPCHK(hipEventRecord(r.ev[kEvDone], s));
     return GMT_OK;
@@ -1642,6 +1726,8 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     if (!lanes_valid(bo_in.plan.lanes)) return fail(GMT_EINVAL, "lanes must be 0, 4, 8, 16 or 32");
     if (!threads_valid(bo_in.plan.threads)) return fail(GMT_EINVAL, "threads must be 0, 256, 512 or 1024");
     if (bo_in.plan.team_wgs < 0 || bo_in.workgroups < 0) return fail(GMT_EINVAL, "negative launch shape");
+    if (bo_in.plan.trace < 0 || bo_in.plan.trace > GMT_TRACE_MAX)
+        return fail(GMT_EINVAL, "trace must lie in [0, %d]", GMT_TRACE_MAX);
     gmt_batch_opts bo = bo_in;
     r.count = count;
     r.order.clear();
@@ -1687,7 +1773,9 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
                       : r.kcount[2] > 0 ? GMT_COST_DUBINS_AIRPLANE : GMT_COST_EUCLIDEAN;
     if (bo.plan.lanes == 0 || bo.plan.team_wgs == 0 || bo.plan.threads == 0 || (!single && bo.workgroups == 0))
         tune_apply(problems, count, single, bo);
-    r.cl = lanes_of(bo.plan.lanes);
+    // the record-keeping kernel exists for 16 lanes only (results do not
+    // depend on the lane width)
+    r.cl = bo.plan.trace > 0 ? 16 : lanes_of(bo.plan.lanes);
     r.threads = threads_of(bo.plan.threads);
     if (single) {
         r.team_wgs = single_team_wgs(bo.plan.team_wgs, kind0, r.box_words, nmax, r.cl, r.threads, r.kgrid[kind0]);
@@ -1709,6 +1797,8 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     TRY(ws_acquire(ws_bytes, r.teams, s, &r.w));
     r.used = 256 + sizeof(ProbDev) * count + sizeof(int) * total_boxes;
     gmt_status st = ws_stage(r.w, r.used, count, s);
+    r.trace_cap = bo.plan.trace;
+    if (st == GMT_OK && r.trace_cap > 0) st = dev_alloc(r.trace, sizeof(TraceRec) * r.trace_cap * (size_t)count, s);
     if (st == GMT_OK) {
         char *sh = (char *)r.w->stage_h;
         ((int *)sh)[0] = 0;  // queue counters, one per cost kind
@@ -1740,6 +1830,10 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
             // the query's boxes in the device copy of the staging block
             P[j].gbox = (const int *)((char *)r.w->stage_d.p + 256 + sizeof(ProbDev) * count) + off;
             P[j].gcap = (int)std::min<long long>(grids[j].entries, 0x7fffffff);
+            if (r.trace_cap > 0) {
+                P[j].trace = (TraceRec *)r.trace.p + (size_t)j * r.trace_cap;
+                P[j].trace_cap = r.trace_cap;
+            }
             off += P[j].m * 2 * P[j].pd;
         }
     }
@@ -1747,7 +1841,7 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
         std::lock_guard<std::mutex> lk(g_prof_mu);
         r.prof = g_prof_on;
     }
-    if (st != GMT_OK) run_release(r);
+    if (st != GMT_OK) run_release(r, s);
     return st;
 }
 
@@ -1800,6 +1894,36 @@ static gmt_status collect_results(BatchRun &r, gmt_result *results, hipStream_t 
         ws_reset_ctl(r.w, s);
         st = fail(GMT_EDEVICE, "planning kernel reported an internal fault (barrier timeout)");
     }
+    if (st == GMT_OK && r.trace.p) {
+        // device ticks to nanoseconds, by the caller's query index
+        std::vector<TraceRec> h((size_t)r.count * r.trace_cap);
+        if (hipMemcpyAsync(h.data(), r.trace.p, sizeof(TraceRec) * h.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(GMT_EDEVICE, "trace copy failed");
+        const double ns = tick_ns();
+        g_last_trace.assign(r.count, {});
+        for (int j = 0; j < r.count; ++j) {
+            const int len = std::min(r.w->res_h[j].trace_len, r.trace_cap);
+            std::vector<gmt_trace_rec> &o = g_last_trace[r.order[j]];
+            o.resize(std::max(len, 0));
+            for (int k = 0; k < len; ++k) {
+                const TraceRec &t = h[(size_t)j * r.trace_cap + k];
+                gmt_trace_rec &q = o[k];
+                q.iter = t.iter;
+                q.open = t.open;
+                q.group = t.group;
+                q.goal_in_group = t.goal_in_group;
+                q.candidates = t.candidates;
+                q.check_failures = t.check_failures;
+                q.added = t.added;
+                q.reserved = 0;
+                q.select_ns = (int64_t)((double)t.t_select * ns);
+                q.frontier_ns = (int64_t)((double)t.t_frontier * ns);
+                q.connect_ns = (int64_t)((double)t.t_connect * ns);
+                q.check_ns = (int64_t)((double)t.t_check * ns);
+            }
+        }
+    }
     return st;
 }
 
@@ -1807,19 +1931,20 @@ static gmt_status collect_results(BatchRun &r, gmt_result *results, hipStream_t 
 static gmt_status batch_collect(BatchRun &r, gmt_result *results, hipStream_t s) {
     gmt_status st = collect_results(r, results, s);
     batch_profile(r);
-    run_release(r);
+    run_release(r, s);
     return st;
 }
 
 static gmt_status run_sync(const gmt_problem *problems, int count, const gmt_batch_opts &bo, bool single,
                            gmt_result *results, hipStream_t s) {
     BatchRun r;
+    g_last_trace.clear();
     TRY(batch_stage(problems, count, bo, single, results, r, s));
     gmt_status st = batch_launch(r, s);
     if (st == GMT_OK && hipEventSynchronize(r.ev[kEvDone]) != hipSuccess) st = fail(GMT_EDEVICE, "planning launch failed");
     if (st != GMT_OK) {
         (void)hipStreamSynchronize(s);
-        run_release(r);
+        run_release(r, s);
         return st;
     }
     return batch_collect(r, results, s);
@@ -1932,6 +2057,7 @@ extern "C" gmt_status gmt_plan_noalloc(gmt_roadmap_t rm, const float *x_init, co
         return fail(GMT_EINVAL, "Euclidean and Dubins airplane plans need opts.edge_step");
     if (!goal) return fail(GMT_EINVAL, "null goal");
     if (m < 0 || m > GMT_MAX_BOXES) return fail(GMT_EINVAL, "box count %d outside [0, %d]", m, GMT_MAX_BOXES);
+    if (opts_in && opts_in->trace != 0) return fail(GMT_EINVAL, "gmt_plan_noalloc keeps no trace (opts.trace must be 0)");
     hipStream_t s = (hipStream_t)stream;
     const int N = rm->n + 1, pd = pdim_of(rm->kind, rm->dim), words = m * 2 * pd;
     // scratch layout: staging block, result, team control, query workspace
@@ -2040,6 +2166,7 @@ extern "C" gmt_status gmt_batch_prepare(const gmt_problem *problems, int32_t cou
         std::memset(&bo, 0, sizeof bo);
         bo.plan.traj_points = 16;
     }
+    if (bo.plan.trace != 0) return fail(GMT_EINVAL, "prepared batches keep no trace (opts.trace must be 0)");
     gmt_batch *b = new gmt_batch();
     {
         std::lock_guard<std::mutex> lk(g_live_mu);
@@ -2161,6 +2288,7 @@ extern "C" gmt_status gmt_autotune(const gmt_problem *problems, int32_t count, i
     gmt_batch_opts base;
     std::memset(&base, 0, sizeof base);
     base.plan = default_opts(opts);
+    base.plan.trace = 0;  // candidates are timed without records
     base.plan.lanes = 16;
     base.plan.team_wgs = 0;
     base.plan.threads = kDefaultThreads;
@@ -2285,8 +2413,89 @@ extern "C" gmt_status gmt_tune_store(const gmt_tune_shape *shape, const gmt_tune
 }
 
 extern "C" gmt_status gmt_tune_clear(void) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_build_mu);
+    g_build_tune.clear();
+    return GMT_OK;
+}
+
+// digest of a Euclidean table (see k_eu_digest)
+static gmt_status eu_digest(const gmt_roadmap *rm, unsigned long long *out, hipStream_t s) {
+    DevBuf d;
+    Temps keep(s, {&d});
+    TRY(dev_alloc(d, 256, s));
+    k_fill_int<<<1, 64, 0, s>>>((int *)d.p, 2, 0);
+    const long long total = (long long)rm->n * rm->cap;
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((total + 255) / 256, 4096));
+    k_eu_digest<<<blocks, 256, 0, s>>>(rm->n, rm->cap, (const int *)rm->deg.p,
+                                       (const unsigned long long *)rm->in_rec.p, (unsigned long long *)d.p);
+    HIPCHK(hipMemcpyAsync(out, d.p, sizeof *out, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return GMT_OK;
+}
+
+extern "C" gmt_status gmt_autotune_build(const float *d_samples, int32_t n, int32_t dim, double r_n, int32_t reps,
+                                         gmt_build_tune *out, void *stream) {
+    if (!d_samples || !out) return fail(GMT_EINVAL, "null argument");
+    if (reps < 1) return fail(GMT_EINVAL, "reps must be >= 1");
+    TRY(check_shape(n, dim, GMT_COST_EUCLIDEAN, r_n));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> best_ms(GMT_BUILD_TILES, 0.0);
+    std::vector<bool> same(GMT_BUILD_TILES, false);
+    unsigned long long ref = 0;
+    long long ref_nnz = -1;
+    for (int t = 1; t <= GMT_BUILD_TILES; ++t) {
+        std::vector<double> ms;
+        for (int k = 0; k < reps; ++k) {
+            gmt_cost_params pr{};
+            pr.build_tile = t;
+            gmt_roadmap_t rm = nullptr;
+            HIPCHK(hipStreamSynchronize(s));
+            const int64_t t0 = steady_ns();
+            TRY(gmt_build_neighbors_ex(d_samples, n, dim, GMT_COST_EUCLIDEAN, r_n, &pr, stream, &rm));
+            ms.push_back((double)(steady_ns() - t0) * 1e-6);
+            if (k == 0) {
+                unsigned long long dg = 0;
+                gmt_status st = eu_digest(rm, &dg, s);
+                const long long nnz = rm->nnz;
+                if (st != GMT_OK) {
+                    gmt_roadmap_free(rm);
+                    return st;
+                }
+                if (t == 1) {
+                    ref = dg;
+                    ref_nnz = nnz;
+                }
+                same[t - 1] = dg == ref && nnz == ref_nnz;
+            }
+            TRY(gmt_roadmap_free(rm));
+        }
+        std::sort(ms.begin(), ms.end());
+        best_ms[t - 1] = ms[ms.size() / 2];
+    }
+    gmt_build_tune c{};
+    c.tile = 1;
+    c.candidates = GMT_BUILD_TILES;
+    c.default_ms = best_ms[0];
+    c.ms = best_ms[0];
+    for (int t = 2; t <= GMT_BUILD_TILES; ++t) {
+        if (!same[t - 1]) {
+            ++c.rejected;
+            continue;
+        }
+        if (best_ms[t - 1] < c.ms) {
+            c.ms = best_ms[t - 1];
+            c.tile = t;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_build_mu);
+        g_build_tune[{dim, ceil_log2_int(n)}] = c;
+    }
+    *out = c;
     return GMT_OK;
 }
 
@@ -2305,6 +2514,13 @@ extern "C" gmt_status gmt_tune_save(const char *path) {
         std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.6f %.6f\n", k.kind, k.dim, k.nlog, k.mlog, k.mode, k.blog,
                      c.lanes, c.team_wgs, c.workgroups, c.threads, c.ms, c.default_ms);
     }
+    {
+        // Euclidean build tiles: "build dim nlog tile ms default_ms"
+        std::lock_guard<std::mutex> lb(g_build_mu);
+        for (const auto &kv : g_build_tune)
+            std::fprintf(f, "build %d %d %d %.6f %.6f\n", kv.first.first, kv.first.second, kv.second.tile,
+                         kv.second.ms, kv.second.default_ms);
+    }
     const bool ok = std::fclose(f) == 0;
     return ok ? GMT_OK : fail(GMT_EINVAL, "write to %s failed", path);
 }
@@ -2314,12 +2530,27 @@ extern "C" gmt_status gmt_tune_load(const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return fail(GMT_EINVAL, "cannot open %s", path);
     std::map<TuneKey, gmt_tune_choice> got;
+    std::map<std::pair<int, int>, gmt_build_tune> got_build;
     char line[512];
     int lineno = 0;
     gmt_status st = GMT_OK;
     while (std::fgets(line, sizeof line, f)) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
+        if (std::strncmp(line, "build ", 6) == 0) {
+            int dim = 0, nlog = 0;
+            gmt_build_tune c{};
+            char tail = 0;
+            const int got_n = std::sscanf(line + 6, "%d %d %d %lf %lf %c", &dim, &nlog, &c.tile, &c.ms, &c.default_ms,
+                                          &tail);
+            if (got_n != 5 || dim < 2 || dim > 3 || nlog < 0 || nlog > 31 || c.tile < 1 || c.tile > GMT_BUILD_TILES ||
+                !(c.ms >= 0.0) || !(c.default_ms >= 0.0)) {
+                st = fail(GMT_EINVAL, "%s:%d: malformed build tune line", path, lineno);
+                break;
+            }
+            got_build[{dim, nlog}] = c;
+            continue;
+        }
         TuneKey k{};
         gmt_tune_choice c{};
         char tail = 0;
@@ -2337,8 +2568,12 @@ extern "C" gmt_status gmt_tune_load(const char *path) {
     }
     std::fclose(f);
     if (st != GMT_OK) return st;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    }
+    std::lock_guard<std::mutex> lk(g_build_mu);
+    for (const auto &kv : got_build) g_build_tune[kv.first] = kv.second;
     return GMT_OK;
 }
 
@@ -2518,6 +2753,7 @@ extern "C" gmt_status gmt_engine_create(const gmt_engine_opts *opts, gmt_engine_
     if (opts->slots < 1 || opts->slots > 16) return fail(GMT_EINVAL, "slots must lie in [1, 16]");
     if (opts->max_batch < 1) return fail(GMT_EINVAL, "max_batch must be >= 1");
     if (opts->budget_bytes == 0) return fail(GMT_EINVAL, "budget must be > 0");
+    if (opts->plan.trace != 0) return fail(GMT_EINVAL, "the engine keeps no trace (opts.plan.trace must be 0)");
     gmt_engine *E = new gmt_engine;
     E->o = *opts;
     E->budget = opts->budget_bytes;

@@ -124,7 +124,21 @@ struct ProbDev {
     int gG;
     int gcap;  // entries the gids array holds
     const int *gbox;
+    // per-iteration records (null: none); at most trace_cap are written
+    struct TraceRec *trace;
+    int trace_cap;
 };
+
+// one record per iteration with a non-empty group (iteration 0 included):
+// counts read by the first thread after each phase's barrier, and device
+// clock ticks since the query's start at the end of each phase (the
+// iteration-0 record carries the end of setup in all three) plus the first
+// wave's lazy-check ticks so far
+struct TraceRec {
+    int iter, open, group, goal_in_group, candidates, check_failures, added, reserved;
+    unsigned long long t_select, t_frontier, t_connect, t_check;
+};
+static_assert(sizeof(TraceRec) == 64, "trace record layout");
 
 // work counters of one query (exact): out-edges walked, in-edges scanned,
 // candidates processed, nodes committed, open nodes partitioned, non-empty
@@ -137,7 +151,7 @@ enum { W_OUT = 0, W_IN = 1, W_CAND = 2, W_COMMIT = 3, W_OPEN = 4, W_ITERS = 5,
 struct Result {
     int status, iters, path_len, z;
     double path_cost;
-    int abort, pad;
+    int abort, trace_len;
     unsigned long long work[W_COUNT];
     int path[GMT_PATH_INLINE];
 };
@@ -845,7 +859,7 @@ __device__ __forceinline__ unsigned long long clock_ticks() { return wall_clock6
 //   2: also the costs-to-come, copied out to the tree output at the end --
 //      every cost gather of the parent search is then an LDS read.
 // CL: lanes per candidate in the connect phase.
-template <int KIND, int LDS, int CL, bool GRID>
+template <int KIND, int LDS, int CL, bool GRID, bool TRACE>
 __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsigned char *lst, Ctl *lctl,
                           double *lcost, Result *res) {
     const RoadmapDev &R = P.rm;
@@ -1007,6 +1021,20 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
     }
     team_sync(t);
     if (t.rank == 0) {
+        if (TRACE && P.trace && P.trace_cap > 0) {
+            // iteration 0: the root is the open set and the group; root edges
+            // below r are the candidates, those that passed the check joined
+            TraceRec *rec = P.trace;
+            const int cand = ld_cnt(&ctl->g_cnt[0]), added = ld_cnt(&ctl->o_cnt[1]);
+            rec->iter = 0;
+            rec->open = 1;
+            rec->group = 1;
+            rec->goal_in_group = (st[root] & S_GOAL) ? 1 : 0;
+            rec->candidates = cand;
+            rec->check_failures = cand - added;
+            rec->added = added;
+            rec->reserved = 0;
+        }
         ctl->g_cnt[0] = 0;  // compaction counters of iteration 0: no group precedes iteration 1
         ctl->c_cnt = 0;
     }
@@ -1023,6 +1051,11 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         unsigned long long now = clock_ticks();
         tk_setup += now - tk;
         tk = now;
+        if (TRACE && P.trace && P.trace_cap > 0) {
+            TraceRec *rec = P.trace;
+            rec->t_select = rec->t_frontier = rec->t_connect = tk_setup;
+            rec->t_check = tk_check;
+        }
     }
 
     int i_prev = 0;
@@ -1118,6 +1151,15 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             unsigned long long now = clock_ticks();
             tk_select += now - tk;
             tk = now;
+            if (TRACE && P.trace && (long long)w_iters < P.trace_cap) {
+                TraceRec *rec = P.trace + w_iters;
+                rec->iter = ii;
+                rec->open = open_n;
+                rec->group = ld_cnt(&ctl->g_cnt[p]);
+                rec->goal_in_group = ld_cnt(&ctl->hit_cnt[p]);
+                rec->reserved = 0;
+                rec->t_select = tk_setup + tk_select + tk_frontier + tk_connect;
+            }
         }
         // ---- frontier (line 4): CL lanes per group member ----
         {
@@ -1185,6 +1227,11 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             unsigned long long now = clock_ticks();
             tk_frontier += now - tk;
             tk = now;
+            if (TRACE && P.trace && (long long)w_iters < P.trace_cap) {
+                TraceRec *rec = P.trace + w_iters;
+                rec->candidates = ld_cnt(&ctl->c_cnt);
+                rec->t_frontier = tk_setup + tk_select + tk_frontier + tk_connect;
+            }
             // next iteration's counters: their last readers finished before
             // the select barrier
             ctl->g_cnt[p ^ 1] = 0;  // the previous group, closed by this select
@@ -1268,6 +1315,19 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
             unsigned long long now = clock_ticks();
             tk_connect += now - tk;
             tk = now;
+            if (TRACE && P.trace && (long long)w_iters < P.trace_cap) {
+                // every open node was either in the group or carried over, so
+                // the next open list minus the carried nodes is what joined;
+                // every candidate has a group member among its in-neighbours,
+                // so the rest failed the lazy check (the select and frontier
+                // counts are read back from the record, not kept live)
+                TraceRec *rec = P.trace + w_iters;
+                const int added = ld_cnt(&ctl->o_cnt[p ^ 1]) - (rec->open - rec->group);
+                rec->check_failures = rec->candidates - added;
+                rec->added = added;
+                rec->t_connect = tk_setup + tk_select + tk_frontier + tk_connect;
+                rec->t_check = tk_check;
+            }
         }
         iters = ii;
         i_prev = ii;
@@ -1311,6 +1371,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         res->z = z;
         res->path_cost = pc;
         res->abort = (t.nwg > 1) ? ld_acquire(t.abort) : 0;
+        res->trace_len = !(TRACE && P.trace) ? 0 : (long long)w_iters + 1 < P.trace_cap ? (int)w_iters + 1 : P.trace_cap;
         res->work[W_T_SETUP] = tk_setup;
         res->work[W_T_SELECT] = tk_select;
         res->work[W_T_FRONTIER] = tk_frontier;
@@ -1341,7 +1402,7 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
 // ---------------------------------------------------------------------------
 // Workgroups of 256, 512 or 1024 threads; registers are sized for 16 waves
 // per CU (four 256-thread workgroups or one of 1024 threads).
-template <int KIND, int LDS, int CL, bool GRID>
+template <int KIND, int LDS, int CL, bool GRID, bool TRACE = false>
 __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
@@ -1390,7 +1451,7 @@ __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ pr
                 fbox[k] = (float)((double)boxes[P.box_off + k] * GMT_INV_QS);
         }
         __syncthreads();
-        run_query<KIND, LDS, CL, GRID>(t, P, lbox, lst, lctl, lcost, res + job);
+        run_query<KIND, LDS, CL, GRID, TRACE>(t, P, lbox, lst, lctl, lcost, res + job);
         if (t.nwg > 1 && ld_acquire(t.abort)) return;
     }
 }

@@ -44,11 +44,11 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 EXPORTS = ["gmt_set_allocator", "gmt_build_neighbors", "gmt_build_neighbors_ex", "gmt_sample_halton", "gmt_roadmap_from_csr", "gmt_roadmap_info", "gmt_roadmap_bytes",
            "gmt_roadmap_save", "gmt_roadmap_load",
            "gmt_roadmap_export", "gmt_roadmap_free", "gmt_plan", "gmt_plan_noalloc", "gmt_plan_batch",
-           "gmt_last_work", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
+           "gmt_last_work", "gmt_last_trace", "gmt_last_build", "gmt_profile_enable", "gmt_profile_read",
            "gmt_engine_create", "gmt_engine_submit", "gmt_engine_poll", "gmt_engine_poll_any", "gmt_engine_cancel",
            "gmt_engine_set_budget", "gmt_engine_get_stats", "gmt_engine_destroy",
            "gmt_batch_prepare", "gmt_batch_run", "gmt_batch_free",
-           "gmt_autotune", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
+           "gmt_autotune", "gmt_autotune_build", "gmt_tune_lookup", "gmt_tune_store", "gmt_tune_clear", "gmt_tune_save",
            "gmt_tune_load", "gmt_shutdown", "gmt_last_error", "gmt_version", "gmt_steady_ns"]
 
 
@@ -94,7 +94,7 @@ class gmt_allocator(C.Structure):
 
 
 class gmt_cost_params(C.Structure):
-    _fields_ = [("turn_radius", C.c_double), ("row_slots", C.c_int32)]
+    _fields_ = [("turn_radius", C.c_double), ("row_slots", C.c_int32), ("build_tile", C.c_int32)]
 
 
 class gmt_goal(C.Structure):
@@ -103,7 +103,19 @@ class gmt_goal(C.Structure):
 
 class gmt_plan_opts(C.Structure):
     _fields_ = [("edge_step", C.c_double), ("traj_points", C.c_int32), ("max_iters", C.c_int32),
-                ("team_wgs", C.c_int32), ("lanes", C.c_int32), ("threads", C.c_int32)]
+                ("team_wgs", C.c_int32), ("lanes", C.c_int32), ("threads", C.c_int32),
+                ("trace", C.c_int32)]
+
+
+class gmt_trace_rec(C.Structure):
+    _fields_ = [("iter", C.c_int32), ("open", C.c_int32), ("group", C.c_int32), ("goal_in_group", C.c_int32),
+                ("candidates", C.c_int32), ("check_failures", C.c_int32), ("added", C.c_int32),
+                ("reserved", C.c_int32), ("select_ns", C.c_int64), ("frontier_ns", C.c_int64),
+                ("connect_ns", C.c_int64), ("check_ns", C.c_int64)]
+
+
+# numpy view of gmt_trace_rec
+TRACE_DTYPE = np.dtype([(k, np.int32 if t is C.c_int32 else np.int64) for k, t in gmt_trace_rec._fields_])
 
 
 class gmt_problem(C.Structure):
@@ -124,7 +136,7 @@ class gmt_work(C.Structure):
 
 class gmt_build_info(C.Structure):
     _fields_ = [("edges", C.c_int64), ("pairs_tested", C.c_int64), ("pairs_solved", C.c_int64),
-                ("kernel_ms", C.c_double), ("segments", C.c_int32)]
+                ("kernel_ms", C.c_double), ("segments", C.c_int32), ("tile", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -186,6 +198,17 @@ class gmt_tune_shape(C.Structure):
                 ("batch", C.c_int32)]
 
 
+class gmt_build_tune(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("candidates", C.c_int32), ("rejected", C.c_int32), ("pad", C.c_int32),
+                ("ms", C.c_double), ("default_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+GMT_BUILD_TILES = 4
+
+
 class gmt_tune_choice(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("team_wgs", C.c_int32), ("workgroups", C.c_int32),
                 ("threads", C.c_int32), ("ms", C.c_double), ("default_ms", C.c_double),
@@ -224,6 +247,7 @@ def lib():
             L.gmt_plan_batch.argtypes = [C.POINTER(gmt_problem), i32, C.POINTER(gmt_batch_opts),
                                          C.POINTER(gmt_result), P]
             L.gmt_last_work.argtypes = [C.POINTER(gmt_work)]
+            L.gmt_last_trace.argtypes = [i32, P, i32, C.POINTER(i32)]
             L.gmt_last_build.argtypes = [C.POINTER(gmt_build_info)]
             L.gmt_profile_enable.argtypes = [i32]
             L.gmt_profile_read.argtypes = [C.POINTER(f64), C.POINTER(i64)]
@@ -242,6 +266,7 @@ def lib():
             L.gmt_autotune.argtypes = [C.POINTER(gmt_problem), i32, i32, C.POINTER(gmt_plan_opts), i32,
                                        C.POINTER(gmt_tune_choice), P]
             L.gmt_tune_lookup.argtypes = [C.POINTER(gmt_tune_shape), C.POINTER(gmt_tune_choice)]
+            L.gmt_autotune_build.argtypes = [P, i32, i32, f64, i32, C.POINTER(gmt_build_tune), P]
             L.gmt_tune_store.argtypes = [C.POINTER(gmt_tune_shape), C.POINTER(gmt_tune_choice)]
             L.gmt_tune_clear.argtypes = []
             L.gmt_tune_save.argtypes = [C.c_char_p]
@@ -273,6 +298,17 @@ def gmt_last_work() -> dict:
     w = gmt_work()
     _check(lib().gmt_last_work(C.byref(w)), "gmt_last_work")
     return w.as_dict()
+
+
+def gmt_last_trace(query: int = 0) -> np.ndarray:
+    """Per-iteration records (TRACE_DTYPE) of query ``query`` of the last
+    traced gmt_plan / gmt_plan_batch call on this thread."""
+    n = C.c_int32()
+    _check(lib().gmt_last_trace(int(query), None, 0, C.byref(n)), "gmt_last_trace")
+    out = np.zeros(int(n.value), TRACE_DTYPE)
+    if len(out):
+        _check(lib().gmt_last_trace(int(query), out.ctypes.data, len(out), C.byref(n)), "gmt_last_trace")
+    return out
 
 
 def gmt_last_build() -> dict:
@@ -402,20 +438,21 @@ class Roadmap:
 
 
 def gmt_build_neighbors(samples, kind: int, r_n: float, stream=None, turn_radius=None,
-                        row_slots=None) -> Roadmap:
+                        row_slots=None, build_tile=None) -> Roadmap:
     """samples: CUDA float32 tensor [dim][n] (SoA) on the 2^-20 grid;
     turn_radius: the Dubins airplane's; row_slots: scratch entries per row of
-    the asymmetric kinds' build (both through gmt_build_neighbors_ex)."""
+    the asymmetric kinds' build; build_tile: the Euclidean build's tile shape
+    (1..GMT_BUILD_TILES) (all three through gmt_build_neighbors_ex)."""
     import torch
     assert samples.is_cuda and samples.dtype == torch.float32 and samples.dim() == 2
     s = samples.contiguous()
     dim, n = int(s.shape[0]), int(s.shape[1])
     h = C.c_void_p()
-    if turn_radius is None and row_slots is None:
+    if turn_radius is None and row_slots is None and build_tile is None:
         _check(lib().gmt_build_neighbors(s.data_ptr(), n, dim, int(kind), float(r_n), _stream(stream),
                                          C.byref(h)), "gmt_build_neighbors")
     else:
-        prm = gmt_cost_params(float(turn_radius or 0.0), int(row_slots or 0))
+        prm = gmt_cost_params(float(turn_radius or 0.0), int(row_slots or 0), int(build_tile or 0))
         _check(lib().gmt_build_neighbors_ex(s.data_ptr(), n, dim, int(kind), float(r_n), C.byref(prm),
                                             _stream(stream), C.byref(h)), "gmt_build_neighbors_ex")
     return Roadmap(h.value, n, dim, int(kind), float(r_n))
@@ -481,6 +518,7 @@ class PlanResult:
     group_iter: object = None
     added_iter: object = None
     work: Optional[dict] = None
+    trace: Optional[np.ndarray] = None  # per-iteration records when opts.trace > 0
 
 
 def make_goal(center: Sequence[float], radius: float, ndims: int) -> gmt_goal:
@@ -493,9 +531,9 @@ def make_goal(center: Sequence[float], radius: float, ndims: int) -> gmt_goal:
 
 
 def make_opts(edge_step: float = 0.0, traj_points: int = 16, max_iters: int = 0,
-              team_wgs: int = 0, lanes: int = 0, threads: int = 0) -> gmt_plan_opts:
+              team_wgs: int = 0, lanes: int = 0, threads: int = 0, trace: int = 0) -> gmt_plan_opts:
     return gmt_plan_opts(float(edge_step), int(traj_points), int(max_iters), int(team_wgs),
-                         int(lanes), int(threads))
+                         int(lanes), int(threads), int(trace))
 
 
 def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_plan_opts,
@@ -525,7 +563,7 @@ def gmt_plan(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_p
     _check(st, "gmt_plan", ok=(GMT_OK, GMT_NO_PATH, GMT_ETIMEOUT))
     L = int(plen.value) if st == GMT_OK else 0
     return PlanResult(int(st), path[:min(L, path_cap)].copy(), float(pcost.value), int(iters.value),
-                      par, cst, gi, ai, gmt_last_work())
+                      par, cst, gi, ai, gmt_last_work(), gmt_last_trace(0) if opts.trace > 0 else None)
 
 
 def gmt_plan_noalloc(rm: Roadmap, x_init, goal: gmt_goal, boxes, lam: float, opts: gmt_plan_opts,
@@ -614,18 +652,21 @@ class PreparedBatch:
     def run(self, stream=None) -> None:
         _check(lib().gmt_plan_batch(self.probs, self.k, C.byref(self.bo), self.res, _stream(stream)),
                "gmt_plan_batch")
+        # records live in thread-local library state until the next call
+        self.traces = [gmt_last_trace(j) for j in range(self.k)] if self.bo.plan.trace > 0 else None
 
     def statuses(self) -> np.ndarray:
         return np.array([self.res[j].status for j in range(self.k)], np.int32)
 
     def results(self) -> List[PlanResult]:
         out = []
+        traces = getattr(self, "traces", None)
         for j in range(self.k):
             r = self.res[j]
             L = int(r.path_len) if r.status == GMT_OK else 0
             out.append(PlanResult(int(r.status), self.paths[j][:min(L, self.path_cap)].copy(),
                                   float(r.path_cost), int(r.iters), *self.outs[j],
-                                  work=r.work.as_dict()))
+                                  work=r.work.as_dict(), trace=traces[j] if traces else None))
         return out
 
 
@@ -680,6 +721,19 @@ def gmt_autotune(queries: Sequence[BatchQuery], opts: gmt_plan_opts, single: boo
     out = gmt_tune_choice()
     _check(lib().gmt_autotune(pb.probs, pb.k, int(bool(single)), C.byref(opts), int(reps), C.byref(out),
                               _stream(stream)), "gmt_autotune")
+    return out.as_dict()
+
+
+def gmt_autotune_build(samples, r_n: float, reps: int = 3, stream=None) -> dict:
+    """Time every Euclidean build tile shape on ``samples`` (CUDA float32
+    [dim][n]) and cache the fastest whose table equals the default shape's
+    (see gmt_autotune_build in the header)."""
+    import torch
+    assert samples.is_cuda and samples.dtype == torch.float32 and samples.dim() == 2
+    s = samples.contiguous()
+    out = gmt_build_tune()
+    _check(lib().gmt_autotune_build(s.data_ptr(), int(s.shape[1]), int(s.shape[0]), float(r_n), int(reps),
+                                    C.byref(out), _stream(stream)), "gmt_autotune_build")
     return out.as_dict()
 
 

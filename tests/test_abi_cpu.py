@@ -49,6 +49,11 @@ def test_invalid_arguments_rejected_without_gpu():
     assert S.gmt_gemm_bf16(0, 1, 64, 64, 12, None, 16, None, 16, None, 0, None, None, 64, None) == gmt.GMT_EINVAL
     assert S.gmt_sampler_create(None, ctypes.byref(h)) == gmt.GMT_EINVAL
     assert S.gmt_sampler_finish(None, 6, 0, None, 0, None, 0, None, 0, None, None) == gmt.GMT_EINVAL
+    bt = gmt.gmt_build_tune()
+    assert L.gmt_autotune_build(None, 100, 3, 0.1, 1, ctypes.byref(bt), None) == gmt.GMT_EINVAL
+    n = ctypes.c_int32(-1)
+    assert L.gmt_last_trace(0, None, 0, ctypes.byref(n)) == gmt.GMT_EINVAL  # no traced call yet
+    assert L.gmt_last_trace(0, None, 0, None) == gmt.GMT_EINVAL
     bad = gmt.gmt_allocator()
     assert L.gmt_set_allocator(ctypes.byref(bad)) == gmt.GMT_EINVAL
     assert L.gmt_set_allocator(None) == gmt.GMT_OK

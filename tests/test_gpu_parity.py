@@ -122,6 +122,75 @@ def test_euclid_table_clustered(dim, n, extent, r):
     rm.free()
 
 
+TILE_CASES = [("2d", 2, 5003), ("3d", 3, 3001), ("3d", 0, 16384)]
+
+
+@pytest.mark.parametrize("tile", range(1, 5))
+@pytest.mark.parametrize("kind,seed,n", TILE_CASES)
+def test_euclid_table_every_tile_shape(kind, seed, n, tile):
+    """Every tile shape of the build (the tuner's knob) gives the oracle's
+    table; clustered samples too (staging past one chunk)."""
+    say("euclid table tile %d %s seed %d n %d" % (tile, kind, seed, n))
+    prob = I.problem_2d(seed, n=n) if kind == "2d" else I.problem_3d(seed, n=n)
+    r = O.euclid_radius(prob)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(np.ascontiguousarray(prob.samples)).cuda(), gmt.GMT_COST_EUCLIDEAN,
+                                 r, build_tile=tile)
+    assert gmt.gmt_last_build()["tile"] == tile
+    rp, col, cost, _ = rm.export()
+    ref = O.neighbors(prob.samples, O.EUCLID, r)
+    np.testing.assert_array_equal(rp, ref.row_ptr)
+    np.testing.assert_array_equal(col, ref.col)
+    np.testing.assert_array_equal(cost, ref.cost)
+    rm.free()
+    if n == 16384:
+        s = I.clustered_samples(11, 3, 2500, 0.04)
+        rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_EUCLIDEAN, 0.05, build_tile=tile)
+        rp, col, cost, _ = rm.export()
+        ref = O.neighbors(s, O.EUCLID, 0.05)
+        np.testing.assert_array_equal(rp, ref.row_ptr)
+        np.testing.assert_array_equal(col, ref.col)
+        rm.free()
+
+
+def test_build_tile_tuner(tmp_path):
+    """The tuner times every shape, finds every table equal to the default
+    shape's, caches the fastest for (dim, ceil log2 n); later builds of that
+    bucket use it (and still give the oracle's table); the choice survives a
+    save / clear / load cycle."""
+    prob = I.problem_3d(1, n=16384)
+    r = O.euclid_radius(prob)
+    s = torch.from_numpy(np.ascontiguousarray(prob.samples)).cuda()
+    gmt.gmt_tune_clear()
+    rm = gmt.gmt_build_neighbors(s, gmt.GMT_COST_EUCLIDEAN, r)
+    assert gmt.gmt_last_build()["tile"] == 1
+    rm.free()
+    c = gmt.gmt_autotune_build(s, r, reps=2)
+    say("build tuner: %s" % c)
+    assert c["candidates"] == 4 and c["rejected"] == 0 and 1 <= c["tile"] <= 4
+    assert c["ms"] <= c["default_ms"]
+    rm = gmt.gmt_build_neighbors(s, gmt.GMT_COST_EUCLIDEAN, r)
+    assert gmt.gmt_last_build()["tile"] == c["tile"]
+    rp, col, cost, _ = rm.export()
+    ref = O.neighbors(prob.samples, O.EUCLID, r)
+    np.testing.assert_array_equal(rp, ref.row_ptr)
+    np.testing.assert_array_equal(col, ref.col)
+    rm.free()
+    f = str(tmp_path / "tune.txt")
+    gmt.gmt_tune_save(f)
+    assert ("build 3 14 %d " % c["tile"]) in open(f).read()
+    gmt.gmt_tune_clear()
+    rm = gmt.gmt_build_neighbors(s, gmt.GMT_COST_EUCLIDEAN, r)
+    assert gmt.gmt_last_build()["tile"] == 1
+    rm.free()
+    gmt.gmt_tune_load(f)
+    rm = gmt.gmt_build_neighbors(s, gmt.GMT_COST_EUCLIDEAN, r)
+    assert gmt.gmt_last_build()["tile"] == c["tile"]
+    rm.free()
+    gmt.gmt_tune_clear()
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_build_neighbors(s, gmt.GMT_COST_EUCLIDEAN, r, build_tile=5)
+
+
 def test_euclid_table_import_and_bytes():
     """The oracle's table imported through gmt_roadmap_from_csr plans the
     same trees as the built one; a cost that is not the samples' distance is
@@ -236,6 +305,104 @@ def test_launch_shape_does_not_change_results(team_wgs, threads):
     res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5,
                        opts_of(prob, team_wgs=team_wgs, threads=threads))
     compare_tree(res, O.plan(prob, r))
+    rm.free()
+
+
+# --- per-iteration records ---------------------------------------------------
+
+def goal_hits(prob, ref):
+    """members of each recorded group inside the goal ball (closed, on the
+    first goal dimensions), from the oracle's tree"""
+    q = np.round(np.concatenate([prob.samples.astype(np.float64),
+                                 np.asarray(prob.x_init, np.float64)[:, None]], axis=1) * 2.0 ** 20)
+    c = np.round(np.asarray(prob.goal_center, np.float64) * 2.0 ** 20)
+    d2 = ((q[:prob.pdim] - c[:prob.pdim, None]) ** 2).sum(axis=0)
+    in_goal = d2 <= float(np.float64(prob.goal_radius) * np.float64(prob.goal_radius)) * 2.0 ** 40
+    return np.array([int((in_goal & (ref.group_iter == i)).sum()) for i in ref.trace[:, 0]])
+
+
+def compare_trace(tr, ref, prob):
+    """GPU records against the oracle's: same iterations, open sets, groups
+    and additions; the GPU never lists samples inside obstacles as
+    candidates (they are marked dead first), so its candidates and check
+    failures are the oracle's less those"""
+    o = ref.trace
+    assert len(tr) == len(o)
+    np.testing.assert_array_equal(tr["iter"], o[:, 0])
+    np.testing.assert_array_equal(tr["open"], o[:, 1])
+    np.testing.assert_array_equal(tr["group"], o[:, 2])
+    np.testing.assert_array_equal(tr["candidates"], o[:, 3] - o[:, 4])
+    np.testing.assert_array_equal(tr["check_failures"], o[:, 5] - o[:, 4])
+    np.testing.assert_array_equal(tr["added"], o[:, 6])
+    np.testing.assert_array_equal(tr["goal_in_group"], goal_hits(prob, ref))
+    # device clock: phases in order, iterations in order
+    t = np.stack([tr["select_ns"], tr["frontier_ns"], tr["connect_ns"]], axis=1).reshape(-1)
+    assert np.all(np.diff(t) >= 0) and np.all(tr["check_ns"] <= tr["connect_ns"])
+
+
+TRACE_CASES = [("2d", 0, 0.5), ("2d", 1, 0.0), ("2d", 2, 1.0), ("3d", 0, 0.5)]
+
+
+@pytest.mark.parametrize("kind,seed,lam", TRACE_CASES)
+def test_plan_trace_matches_oracle(kind, seed, lam):
+    """Per-iteration records of a traced plan equal the oracle's (Euclidean,
+    exact); the tree equals the untraced plan's; a short record cap keeps the
+    first records."""
+    say("trace %s seed %d lambda %.1f" % (kind, seed, lam))
+    prob = I.problem_2d(seed, lam=lam) if kind == "2d" else I.problem_3d(seed, lam=lam)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    ref = O.plan(prob, r, trace=True)
+    res = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, lam, opts_of(prob, trace=100000))
+    compare_tree(res, ref)
+    compare_trace(res.trace, ref, prob)
+    assert len(res.trace) == res.work["iterations"] + 1
+    short = gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, lam, opts_of(prob, trace=3))
+    compare_tree(short, ref)
+    for f in ("iter", "open", "group", "candidates", "check_failures", "added"):
+        np.testing.assert_array_equal(short.trace[f], res.trace[f][:3])
+    rm.free()
+
+
+def test_plan_trace_double_integrator_and_batch():
+    """A batch of double-integrator queries with records: every decisive query's
+    records equal the oracle's (samples in obstacles included), and a traced
+    batch plans the same trees as an untraced one."""
+    n = 2048
+    r = 1.75 * (16384.0 / n) ** (1.0 / 6.0)
+    s = I.di_samples(3, n)
+    rm = gmt.gmt_build_neighbors(torch.from_numpy(s).cuda(), gmt.GMT_COST_DOUBLE_INTEGRATOR, r)
+    tab = O.neighbors(s, O.DI, r)
+    probs = [I.di_problem(seed, s, r=r) for seed in range(6)]
+    qs = [gmt.BatchQuery(rm, p.x_init, goal_of(p), p.boxes, p.lam) for p in probs]
+    traced = gmt.gmt_plan_batch(qs, opts_of(probs[0], trace=4096))
+    plain = gmt.gmt_plan_batch(qs, opts_of(probs[0]))
+    compared = 0
+    for p, a, b in zip(probs, traced, plain):
+        assert a.status == b.status and list(a.path) == list(b.path) and a.path_cost == b.path_cost
+        ref = O.plan(p, r, tab, trace=True)
+        if O.decisive(ref, O.DI, rel=1e-9, collide_abs=1e-9):
+            compare_trace(a.trace, ref, p)
+            compared += 1
+    say("trace di batch: %d of %d compared" % (compared, len(probs)))
+    assert compared >= 2
+    rm.free()
+
+
+def test_trace_rejected_where_not_kept():
+    prob = I.problem_2d(0)
+    r = O.euclid_radius(prob)
+    rm = build(prob, r)
+    N = rm.n + 1
+    outs = [torch.empty(N, dtype=dt, device="cuda") for dt in (torch.int32, torch.float64, torch.int32, torch.int32)]
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_plan_noalloc(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5, opts_of(prob, trace=8), *outs)
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5, opts_of(prob, trace=-1))
+    # an untraced call leaves no records behind
+    gmt.gmt_plan(rm, prob.x_init, goal_of(prob), prob.boxes, 0.5, opts_of(prob))
+    with pytest.raises(gmt.GmtError):
+        gmt.gmt_last_trace(0)
     rm.free()
 
 

@@ -64,3 +64,22 @@ def test_invalid_store_rejected():
         gmt.gmt_tune_store(gmt.tune_shape(E, 2, 2000, 20, 0), lanes=12, team_wgs=1)
     with pytest.raises(gmt.GmtError):
         gmt.gmt_tune_store(gmt.tune_shape(E, 9, 2000, 20, 0), lanes=8, team_wgs=1)
+
+
+def test_build_tiles_in_the_tune_file(tmp_path):
+    """Euclidean build-tile lines ("build dim nlog tile ms default_ms") load
+    and save with the plan knobs; malformed ones are refused whole."""
+    f = tmp_path / "t.txt"
+    f.write_text("# header\nbuild 3 14 2 1.250000 1.300000\nbuild 2 11 1 0.100000 0.100000\n")
+    gmt.gmt_tune_load(str(f))
+    g = tmp_path / "u.txt"
+    gmt.gmt_tune_save(str(g))
+    text = g.read_text()
+    assert "build 3 14 2 1.250000 1.300000" in text and "build 2 11 1 " in text
+    gmt.gmt_tune_clear()
+    gmt.gmt_tune_save(str(g))
+    assert "build" not in g.read_text().split("\n", 1)[1]
+    for bad in ("build 3 14 5 1.0 1.0", "build 4 14 1 1.0 1.0", "build 3 14 1 1.0", "build 3 14 1 1.0 1.0 x"):
+        f.write_text(bad + "\n")
+        with pytest.raises(gmt.GmtError):
+            gmt.gmt_tune_load(str(f))
