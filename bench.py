@@ -30,10 +30,10 @@ TRAFFIC = {"sources_sha256": "65b92d425e9608be71e8cec7c7d5c940a748763d2270566ff9
            "batch": 4096, "lanes": 8, "threads": 1024,
            "bytes_per_launch": int((2.0 * 71590443 + 5659756) * 1024)}
 # the same for the Euclidean row kernel k_eu_rows building the 3D table at
-# n = 1048576 (medians of five builds)
-EU_TRAFFIC = {"sources_sha256": "8706551abd768542af306f0e97e937887a6272b44a79e3d39fc693fdf7a69059", "n": 1048576,
-              "tile": 1,
-              "bytes_per_launch": int((2.0 * 55938.5 + 2967653.4) * 1024)}
+# n = 1048576 with tile shape 2 (medians of eight builds)
+EU_TRAFFIC = {"sources_sha256": "90ec443b3e4cc5aa71b57d2c8d3f8d52075c01bd93d7903ae2ad93c1174e5a58", "n": 1048576,
+              "tile": 2,
+              "bytes_per_launch": int((2.0 * 62061.8 + 2966571.0) * 1024)}
 
 
 def say(msg):

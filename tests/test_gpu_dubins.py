@@ -124,6 +124,27 @@ def test_dubins_plans_tree_for_tree(world):
     assert compared >= 6 and solved >= 4
 
 
+def test_dubins_trace_matches_oracle(world):
+    """Per-iteration records of traced Dubins plans (forest of 150 trunks,
+    box grid culling) equal the oracle's on decisive runs."""
+    from tests.test_gpu_parity import compare_trace
+    compared = 0
+    for seed in range(12):
+        s, tab, rm = world[seed % 2]
+        p = I.dubins_problem(seed, s, sample_seed=seed % 2)
+        ref = O.plan(p, p.r, tab, trace=True)
+        if not O.decisive(ref, O.DUBINS, rel=1e-9, collide_abs=1e-9):
+            continue
+        res = gmt.gmt_plan(rm, p.x_init, goal_of(p), p.boxes, p.lam, opts_of(p, trace=4096))
+        compare_tree(res, ref)
+        compare_trace(res.trace, ref, p)
+        compared += 1
+        if compared >= 3:
+            break
+    say("dubins traces: %d compared" % compared)
+    assert compared >= 3
+
+
 def test_dubins_edge_cases(world):
     s, tab, rm = world[0]
     base = I.dubins_problem(3, s)
