@@ -1601,6 +1601,12 @@ static void run_release(BatchRun &r, hipStream_t s = nullptr) {
     dev_free(r.trace, s);
 }
 
+// head of a staging block: kQueueInts queue counters per cost kind (the
+// first for one shared queue, all eight for per-XCD queues), then per cost
+// kind the kXcdBounds bounds of the XCDs' job ranges
+static const int kQueueInts = 8, kQueueCounters = 3 * kQueueInts, kXcdBounds = 9;
+static_assert((kQueueCounters + 3 * kXcdBounds) * 4 <= 256, "staging head");
+
 // Launch init + persistent planning over staged queries [first, first+count)
 // of one cost kind.  `stage_d` is the device copy of the staging block (queue
 // counters in its first 256 bytes, `total` ProbDev records, then the boxes);
@@ -1609,10 +1615,13 @@ static void run_release(BatchRun &r, hipStream_t s = nullptr) {
 static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, int kind, int first, int count,
                                    int total, int nmax, int teams, int team_wgs, int box_words_in, int qslot, int cl,
                                    int threads, bool with_grid, hipEvent_t e0, hipEvent_t e1, hipStream_t s,
-                                   bool traced = false) {
+                                   bool traced = false, bool xcd_queues = false) {
     int box_words = plan_box_words(kind, box_words_in);
     char *sd = (char *)stage_d;
-    int *queue = (int *)sd + qslot;
+    // the staging block starts with eight queue counters per cost kind and,
+    // for batches, the bounds of the eight XCDs' job ranges
+    int *queue = (int *)sd + kQueueInts * qslot;
+    const int *xcd_lo = xcd_queues && team_wgs == 1 ? (const int *)sd + kQueueCounters + kXcdBounds * qslot : nullptr;
     const ProbDev *probs = (const ProbDev *)(sd + 256) + first;
     const int *boxes = (const int *)(sd + 256 + sizeof(ProbDev) * total);
     Result *res = res_d + first;
@@ -1624,7 +1633,7 @@ static gmt_status launch_plan_kind(void *stage_d, TeamCtl *tctl, Result *res_d, 
     if (e0) HIPCHK(hipEventRecord(e0, s));
     dim3 grid(teams * team_wgs), block(threads);
     int st_bytes = nmax + 1;
-    void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res};
+    void *args[] = {&probs, &count, &boxes, &box_words, &st_bytes, &queue, &tctl, &team_wgs, &res, &xcd_lo};
     if (team_wgs > 1)
         HIPCHK(hipLaunchCooperativeKernel(plan_kernel(kind, 0, cl, with_grid, traced), grid, block, args,
                                           (unsigned)plds, s));
@@ -1664,7 +1673,7 @@ static int single_team_wgs(int requested, int kind, int box_words, int nmax, int
 static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, bool upload = true) {
     WsBlock *w = r.w;
     if (upload) HIPCHK(hipMemcpyAsync(w->stage_d.p, w->stage_h, r.used, hipMemcpyHostToDevice, s));
-    else k_fill_int<<<1, 64, 0, s>>>((int *)w->stage_d.p, 3, 0);
+    else k_fill_int<<<1, 64, 0, s>>>((int *)w->stage_d.p, kQueueCounters, 0);
     for (int k = 0; k <= kEvDone && events; ++k)
         if (!r.ev[k] && (k == kEvDone || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
     for (int kind = 0; kind < 3; ++kind)
@@ -1672,7 +1681,7 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, b
             TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, kind, r.kfirst[kind],
                                  r.kcount[kind], r.count, r.knmax[kind], std::min(r.teams, r.kcount[kind]),
                                  r.team_wgs, r.box_words, kind, r.cl, r.threads, r.kgrid[kind], r.ev[2 * kind],
-                                 r.ev[2 * kind + 1], s, r.trace_cap > 0));
+                                 r.ev[2 * kind + 1], s, r.trace_cap > 0, true));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
     if (events) HIPCHK(hipEventRecord(r.ev[kEvDone], s));
     return GMT_OK;
@@ -1745,6 +1754,11 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
                 r.knmax[kind] = std::max(r.knmax[kind], pr.roadmap->n);
             }
         }
+        // queries of one roadmap next to each other (each XCD then works
+        // through few tables); the caller's order among them
+        std::stable_sort(r.order.begin() + r.kfirst[kind], r.order.end(), [&](int a, int b) {
+            return std::less<const gmt_roadmap *>()(problems[a].roadmap, problems[b].roadmap);
+        });
     }
     size_t total_boxes = 0, ws_bytes = 0;
     std::vector<size_t> ws_off(count);
@@ -1801,9 +1815,12 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     if (st == GMT_OK && r.trace_cap > 0) st = dev_alloc(r.trace, sizeof(TraceRec) * r.trace_cap * (size_t)count, s);
     if (st == GMT_OK) {
         char *sh = (char *)r.w->stage_h;
-        ((int *)sh)[0] = 0;  // queue counters, one per cost kind
-        ((int *)sh)[1] = 0;
-        ((int *)sh)[2] = 0;
+        // queue counters, then each kind's XCD ranges: eight equal
+        // contiguous parts of its (roadmap-sorted) queries
+        std::memset(sh, 0, 256);
+        for (int kind = 0; kind < 3; ++kind)
+            for (int x = 0; x <= 8; ++x)
+                ((int *)sh)[kQueueCounters + kXcdBounds * kind + x] = (int)((long long)r.kcount[kind] * x / 8);
         ProbDev *P = (ProbDev *)(sh + 256);
         int *bx = (int *)(sh + 256 + sizeof(ProbDev) * count);
         int off = 0;

@@ -1406,7 +1406,8 @@ template <int KIND, int LDS, int CL, bool GRID, bool TRACE = false>
 __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ probs, int count,
                                               const int *__restrict__ boxes, int box_words, int st_bytes,
                                               int *__restrict__ queue, TeamCtl *__restrict__ tctl,
-                                              int team_wgs, Result *__restrict__ res) {
+                                              int team_wgs, Result *__restrict__ res,
+                                              const int *__restrict__ xcd_lo) {
     extern __shared__ __align__(16) int lbox[];
     __shared__ int s_job;
     unsigned char *lst = (unsigned char *)(lbox + ((box_words + 3) & ~3));
@@ -1427,7 +1428,30 @@ __global__ void __launch_bounds__(1024, 1) k_plan(const ProbDev *__restrict__ pr
     for (;;) {
         int job;
         if (team_wgs == 1) {
-            if (threadIdx.x == 0) s_job = atomicAdd(queue, 1);
+            if (threadIdx.x == 0) {
+                if (xcd_lo) {
+                    // eight queues over contiguous ranges of the jobs (sorted
+                    // by roadmap, so one XCD's L2 serves few tables): this
+                    // workgroup's XCD (workgroups go to the XCDs in turn)
+                    // first, then the others'
+                    int j = count;
+                    const int x0 = blockIdx.x & 7;
+                    for (int k = 0; k < 8; ++k) {
+                        const int x = (x0 + k) & 7, lo = xcd_lo[x], size = xcd_lo[x + 1] - lo;
+                        if (size <= 0 ||
+                            __hip_atomic_load(queue + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= size)
+                            continue;
+                        const int idx = atomicAdd(queue + x, 1);
+                        if (idx < size) {
+                            j = lo + idx;
+                            break;
+                        }
+                    }
+                    s_job = j;
+                } else {
+                    s_job = atomicAdd(queue, 1);
+                }
+            }
             __syncthreads();
             job = s_job;
             __syncthreads();
