@@ -26,9 +26,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
 # with this digest and the launch shape named; reported only while both match
-TRAFFIC = {"sources_sha256": "65b92d425e9608be71e8cec7c7d5c940a748763d2270566ff900a8c59f673d99",
+TRAFFIC = {"sources_sha256": "670db52bc596bdca950ec2caa336fbb66e545a08b2d3a6546b98bbeebb502cc4",
            "batch": 4096, "lanes": 8, "threads": 1024,
-           "bytes_per_launch": int((2.0 * 71590443 + 5659756) * 1024)}
+           "bytes_per_launch": int((2.0 * 50945334 + 5657766) * 1024)}
 # the same for the Euclidean row kernel k_eu_rows building the 3D table at
 # n = 1048576 with tile shape 2 (medians of eight builds)
 EU_TRAFFIC = {"sources_sha256": "90ec443b3e4cc5aa71b57d2c8d3f8d52075c01bd93d7903ae2ad93c1174e5a58", "n": 1048576,
