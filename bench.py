@@ -637,6 +637,8 @@ def main():
     if not args.no_autotune:
         tuned = {"batch": gmt.gmt_autotune(queries, opts, single=False, reps=2),
                  "single": gmt.gmt_autotune(queries[:1], opts, single=True, reps=3)}
+        say("tuned batch shape: lanes %(lanes)d, team_wgs %(team_wgs)d, workgroups %(workgroups)d, "
+            "threads %(threads)d" % tuned["batch"])
     # ---- eager steps: each one gmt_plan_batch call on host-side query
     # descriptors (staging and descriptor upload inside every step; PCIe-
     # inclusive); their HIP events give the kernel's duration ----
@@ -757,7 +759,7 @@ def main():
             r3 = RAD.problem_radius(p3)
             d3 = torch.from_numpy(p3.samples).cuda()
             # the tuner's tile shape for this (dim, n) bucket, then builds with it
-            tuned = gmt.gmt_autotune_build(d3, r3, reps=3)
+            btuned = gmt.gmt_autotune_build(d3, r3, reps=3)
             bt, kt = [], []
             gmt.gmt_profile_enable(True)
             for k in range(5):
@@ -789,9 +791,9 @@ def main():
                                "bytes_as_built": int(built),
                                "frac_as_built": round(built / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "traffic_k_eu_rows": eu_traffic, "tile": int(lb["tile"]),
-                               "tuner": {"tile": tuned["tile"], "ms": round(tuned["ms"], 4),
-                                         "default_ms": round(tuned["default_ms"], 4),
-                                         "rejected": tuned["rejected"]}})
+                               "tuner": {"tile": btuned["tile"], "ms": round(btuned["ms"], 4),
+                                         "default_ms": round(btuned["default_ms"], 4),
+                                         "rejected": btuned["rejected"]}})
             say("euclid build n=%d: %.3f ms wall, %.3f ms kernels, tile %d" % (n3, bt, kms, lb["tile"]))
             del d3
 

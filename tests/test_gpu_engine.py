@@ -65,10 +65,12 @@ def test_engine_results_equal_alone(world):
     tickets = [eng.submit(query(rms, *probs[j])) for j in order]
     for j, tk in zip(order, tickets):
         res = eng.poll(tk, -1)
-        assert res.status == ref[j].status
+        assert res.status == ref[j].status and res.iters == ref[j].iters
         assert list(res.path) == list(ref[j].path)
         assert res.path_cost == ref[j].path_cost
         assert res.work["done_ns"] >= res.work["submit_ns"] > 0
+        for k in ("out_edges", "in_edges", "candidates", "commits", "open_entries", "iterations"):
+            assert res.work[k] == ref[j].work[k], k
     st = eng.stats()
     assert st["completed"] == len(order) and st["batches"] >= len(order) // 4
     eng.close()
