@@ -24,11 +24,14 @@ HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 
 # HBM-side bytes per k_plan launch from rocprofv3 counter runs (FETCH_SIZE x 2.00
-# and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives), for the kernel sources
-# with this digest and the launch shape named; reported only while both match
+# and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives; medians of six
+# launches), for the kernel sources with this digest, by launch shape (lanes
+# per candidate, threads per workgroup); reported only while both match
 TRAFFIC = {"sources_sha256": "670db52bc596bdca950ec2caa336fbb66e545a08b2d3a6546b98bbeebb502cc4",
-           "batch": 4096, "lanes": 8, "threads": 1024,
-           "bytes_per_launch": int((2.0 * 50945334 + 5657766) * 1024)}
+           "batch": 4096,
+           "by_shape": {(8, 1024): int((2.0 * 50945334 + 5657766) * 1024),
+                        (16, 1024): int((2.0 * 61719607 + 5627270) * 1024),
+                        (4, 1024): int((2.0 * 46273687 + 5576009) * 1024)}}
 # the same for the Euclidean row kernel k_eu_rows building the 3D table at
 # n = 1048576 with tile shape 2 (medians of eight builds)
 EU_TRAFFIC = {"sources_sha256": "90ec443b3e4cc5aa71b57d2c8d3f8d52075c01bd93d7903ae2ad93c1174e5a58", "n": 1048576,
@@ -685,9 +688,8 @@ def main():
     bytes_as_built = plan_bytes(work, in_edge=28)
     shape = (tuned["batch"] if tuned else {"lanes": args.lanes, "threads": args.threads})
     traffic = None
-    if (kernel_digest() == TRAFFIC["sources_sha256"] and args.batch == TRAFFIC["batch"]
-            and shape.get("lanes") == TRAFFIC["lanes"] and shape.get("threads") == TRAFFIC["threads"]):
-        traffic = TRAFFIC["bytes_per_launch"]
+    if kernel_digest() == TRAFFIC["sources_sha256"] and args.batch == TRAFFIC["batch"]:
+        traffic = TRAFFIC["by_shape"].get((shape.get("lanes"), shape.get("threads")))
 
     # ---- latency: single queries, the whole GPU on one plan ----
     lat = []
