@@ -452,8 +452,12 @@ typedef struct {
 
 /* Batch options: the plan options shared by every query, and the launch
  * shape: `workgroups` persistent workgroups (0: fill the GPU) that pull
- * queries from a device queue, `team_wgs` workgroups per query (1 = one
- * workgroup per query).  Results do not depend on the launch shape. */
+ * queries from device queues, `team_wgs` workgroups per query (1 = one
+ * workgroup per query).  With one workgroup per query the queries of each
+ * cost kind are grouped by roadmap and split into eight contiguous ranges,
+ * one per XCD, which a workgroup drains first on its own XCD and then on the
+ * others, so each XCD's L2 serves few tables.  Results do not depend on the
+ * launch shape or on the order in which queries run. */
 typedef struct {
     gmt_plan_opts plan;
     int32_t workgroups;
