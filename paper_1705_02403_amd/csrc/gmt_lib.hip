@@ -1140,6 +1140,10 @@ struct WsBlock {
     DevBuf res_d;             // Result[count]
     Result *res_h = nullptr;  // pinned
     int res_count = 0;
+    // two more streams and their events: a batch of several cost kinds runs
+    // its kinds' kernels side by side (created on first need)
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
     bool busy = false;
 };
 
@@ -1283,6 +1287,27 @@ static gmt_status ws_stage(WsBlock *w, size_t bytes, int count, hipStream_t s) {
             return fail(GMT_ENOMEM, "pinned result allocation failed");
         TRY(dev_alloc(w->res_d, sizeof(Result) * c, s));
         w->res_count = c;
+    }
+    return GMT_OK;
+}
+
+static gmt_status ws_aux(WsBlock *w) {
+    if (w->fork) return GMT_OK;
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k)
+        ok = hipStreamCreateWithFlags(&w->aux[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&w->join[k], hipEventDisableTiming) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&w->fork, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (int k = 0; k < 2; ++k) {
+            if (w->aux[k]) (void)hipStreamDestroy(w->aux[k]);
+            if (w->join[k]) (void)hipEventDestroy(w->join[k]);
+            w->aux[k] = nullptr;
+            w->join[k] = nullptr;
+        }
+        if (w->fork) (void)hipEventDestroy(w->fork);
+        w->fork = nullptr;
+        return fail(GMT_EDEVICE, "stream creation failed");
     }
     return GMT_OK;
 }
@@ -1676,12 +1701,29 @@ static gmt_status batch_launch(BatchRun &r, hipStream_t s, bool events = true, b
     else k_fill_int<<<1, 64, 0, s>>>((int *)w->stage_d.p, kQueueCounters, 0);
     for (int k = 0; k <= kEvDone && events; ++k)
         if (!r.ev[k] && (k == kEvDone || r.prof)) HIPCHK(hipEventCreate(&r.ev[k]));
+    // one kernel per cost kind; with one workgroup per query (no team
+    // barrier blocks shared between the kernels) and outside graph capture,
+    // the kinds after the first run on their own streams beside it, so a
+    // query of one kind does not wait for another kind's kernel to finish
+    int kinds[3], nk = 0;
     for (int kind = 0; kind < 3; ++kind)
-        if (r.kcount[kind] > 0)
-            TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, kind, r.kfirst[kind],
-                                 r.kcount[kind], r.count, r.knmax[kind], std::min(r.teams, r.kcount[kind]),
-                                 r.team_wgs, r.box_words, kind, r.cl, r.threads, r.kgrid[kind], r.ev[2 * kind],
-                                 r.ev[2 * kind + 1], s, r.trace_cap > 0, true));
+        if (r.kcount[kind] > 0) kinds[nk++] = kind;
+    const bool fork = events && r.team_wgs == 1 && nk > 1;
+    if (fork) {
+        TRY(ws_aux(w));
+        HIPCHK(hipEventRecord(w->fork, s));
+    }
+    for (int i = 0; i < nk; ++i) {
+        const int kind = kinds[i];
+        hipStream_t ks = fork && i > 0 ? w->aux[i - 1] : s;
+        if (ks != s) HIPCHK(hipStreamWaitEvent(ks, w->fork, 0));
+        TRY(launch_plan_kind(w->stage_d.p, (TeamCtl *)w->tctl.p, (Result *)w->res_d.p, kind, r.kfirst[kind],
+                             r.kcount[kind], r.count, r.knmax[kind], std::min(r.teams, r.kcount[kind]), r.team_wgs,
+                             r.box_words, kind, r.cl, r.threads, r.kgrid[kind], r.ev[2 * kind], r.ev[2 * kind + 1], ks,
+                             r.trace_cap > 0, true));
+        if (ks != s) HIPCHK(hipEventRecord(w->join[i - 1], ks));
+    }
+    for (int i = 1; fork && i < nk; ++i) HIPCHK(hipStreamWaitEvent(s, w->join[i - 1], 0));
     HIPCHK(hipMemcpyAsync(w->res_h, w->res_d.p, sizeof(Result) * r.count, hipMemcpyDeviceToHost, s));
     if (events) HIPCHK(hipEventRecord(r.ev[kEvDone], s));
     return GMT_OK;
@@ -2962,6 +3004,11 @@ extern "C" gmt_status gmt_shutdown(void) {
             dev_free(w->res_d, nullptr);
             if (w->stage_h) (void)hipHostFree(w->stage_h);
             if (w->res_h) (void)hipHostFree(w->res_h);
+            for (int k = 0; k < 2; ++k) {
+                if (w->aux[k]) (void)hipStreamDestroy(w->aux[k]);
+                if (w->join[k]) (void)hipEventDestroy(w->join[k]);
+            }
+            if (w->fork) (void)hipEventDestroy(w->fork);
             delete w;
         }
         g_ws.clear();
