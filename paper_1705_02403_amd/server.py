@@ -12,6 +12,7 @@ arrival to completion; throughput is completed queries over the makespan.
 from __future__ import annotations
 
 import collections
+import gc
 import json
 import threading
 import time
@@ -144,6 +145,18 @@ class ReplanServer:
         line per request is appended as it completes (tag, roadmap key,
         arrival, submit and completion times on the engine's steady clock,
         latency, status, iterations, path length and cost)."""
+        # the interpreter's cyclic collector stays off while requests are
+        # replayed: a full collection over a large heap stalls the submitter
+        # thread for tens of milliseconds, which would hold back arrivals
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._serve(requests, realtime, record)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _serve(self, requests: List[Request], realtime: bool, record: Optional[str]) -> ServeReport:
         out = open(record, "a") if record else None
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         t0 = gmt.gmt_steady_ns() + 2_000_000  # start 2 ms from now
