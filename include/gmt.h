@@ -496,9 +496,13 @@ gmt_status gmt_batch_free(gmt_batch_t batch);
  * queue whenever one of `slots` streams is free and the per-query device
  * memory of the in-flight batches stays within the budget (admission by
  * footprint), and launches them asynchronously, so batches overlap on the
- * device while new requests keep arriving.  Each result equals what gmt_plan
- * returns for the same query.  Roadmaps are the caller's and must stay alive
- * until their requests complete.  Thread-safe. */
+ * device while new requests keep arriving.  In a batch of uneven queries
+ * (several cost kinds, or roadmap sizes more than a factor 2 apart) a request
+ * completes as soon as its own query ends, not when its whole batch does:
+ * the planning kernel copies each result to host memory as it finishes (a
+ * result whose path is longer than 500 nodes waits for its batch).  Each result equals what
+ * gmt_plan returns for the same query.  Roadmaps are the caller's and must
+ * stay alive until their requests complete.  Thread-safe. */
 typedef struct gmt_engine *gmt_engine_t;
 
 typedef struct {
@@ -520,6 +524,7 @@ typedef struct {
     int64_t peak_inflight_bytes;
     int64_t peak_inflight_requests;
     int64_t lone_launches;           /* batches launched alone in gmt_plan's shape */
+    int64_t early_completions;       /* requests completed before their batch ended */
 } gmt_engine_stats;
 
 gmt_status gmt_engine_create(const gmt_engine_opts *opts, gmt_engine_t *out);

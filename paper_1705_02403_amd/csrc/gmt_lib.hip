@@ -1144,6 +1144,10 @@ struct WsBlock {
     // its kinds' kernels side by side (created on first need)
     hipStream_t aux[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // coherent pinned copies of the results that the kernel writes as each
+    // query ends (engine batches), and their device address
+    Result *early_h = nullptr, *early_d = nullptr;
+    int early_count = 0;
     bool busy = false;
 };
 
@@ -1309,6 +1313,27 @@ static gmt_status ws_aux(WsBlock *w) {
         w->fork = nullptr;
         return fail(GMT_EDEVICE, "stream creation failed");
     }
+    return GMT_OK;
+}
+
+// room for `count` early result copies (host memory the device writes to)
+static gmt_status ws_early(WsBlock *w, int count) {
+    if (w->early_count >= count) return GMT_OK;
+    if (w->early_h) (void)hipHostFree(w->early_h);
+    w->early_h = w->early_d = nullptr;
+    w->early_count = 0;
+    const int c = std::max(count, 256);
+    if (hipHostMalloc((void **)&w->early_h, sizeof(Result) * c, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
+        w->early_h = nullptr;
+        return fail(GMT_ENOMEM, "pinned result-copy allocation failed");
+    }
+    if (hipHostGetDevicePointer((void **)&w->early_d, w->early_h, 0) != hipSuccess) {
+        (void)hipHostFree(w->early_h);
+        w->early_h = w->early_d = nullptr;
+        return fail(GMT_EDEVICE, "no device address for the result copies");
+    }
+    w->early_count = c;
     return GMT_OK;
 }
 
@@ -1612,6 +1637,7 @@ struct BatchRun {
     hipEvent_t ev[7] = {};  // kernel brackets of each kind (2k, 2k+1), then done (kEvDone)
     DevBuf trace;          // per-iteration records, trace_cap per query in kernel order
     int trace_cap = 0;
+    bool early = false;    // the kernel copies each query's result to w->early_h as it ends
 };
 static const int kEvDone = 6;
 
@@ -1855,6 +1881,12 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
     gmt_status st = ws_stage(r.w, r.used, count, s);
     r.trace_cap = bo.plan.trace;
     if (st == GMT_OK && r.trace_cap > 0) st = dev_alloc(r.trace, sizeof(TraceRec) * r.trace_cap * (size_t)count, s);
+    if (st == GMT_OK && r.early) {
+        st = ws_early(r.w, count);
+        // the block's previous launch has finished: no device write races these
+        if (st == GMT_OK)
+            for (int j = 0; j < count; ++j) __atomic_store_n(&r.w->early_h[j].ready, 0, __ATOMIC_RELAXED);
+    }
     if (st == GMT_OK) {
         char *sh = (char *)r.w->stage_h;
         // queue counters, then each kind's XCD ranges: eight equal
@@ -1893,6 +1925,7 @@ static gmt_status batch_stage(const gmt_problem *problems, int count, const gmt_
                 P[j].trace = (TraceRec *)r.trace.p + (size_t)j * r.trace_cap;
                 P[j].trace_cap = r.trace_cap;
             }
+            if (r.early) P[j].early = r.w->early_d + j;
             off += P[j].m * 2 * P[j].pd;
         }
     }
@@ -2655,7 +2688,8 @@ struct EngineReq {
 struct EngineSlot {
     hipStream_t stream = nullptr;
     BatchRun run;
-    std::vector<EngineReq *> reqs;
+    std::vector<EngineReq *> reqs;  // null once a request completed from its early copy
+    int pending = 0;                // requests of the batch not completed yet
     std::vector<gmt_problem> probs;
     std::vector<gmt_result> results;
     size_t bytes = 0;
@@ -2690,6 +2724,40 @@ static void engine_loop(gmt_engine *E) {
     std::unique_lock<std::mutex> lk(E->mu);
     while (!E->stop) {
         bool progressed = false;
+        // queries that ended inside running batches: their early copies
+        for (EngineSlot &sl : E->slots) {
+            if (!sl.busy || !sl.run.early || sl.pending == 0) continue;
+            const int64_t now = steady_ns();
+            for (int j = 0; j < (int)sl.reqs.size(); ++j) {
+                const int k = sl.run.order[j];
+                EngineReq *r = sl.reqs[k];
+                if (!r) continue;
+                const Result &e = sl.run.w->early_h[j];
+                if (!__atomic_load_n(&e.ready, __ATOMIC_ACQUIRE)) continue;
+                // faults and paths longer than the copy wait for the batch
+                if (e.abort || e.status == ST_FAULT || (e.status == ST_OK && e.path_len > GMT_PATH_INLINE)) continue;
+                gmt_result &o = r->res;
+                o = gmt_result{};
+                o.status = (int)status_of(e.status);
+                o.iters = e.iters;
+                o.path_len = e.path_len;
+                o.path_cost = e.path_cost;
+                work_add(o.work, e.work);
+                if (e.status == ST_OK)
+                    for (int i = 0; i < e.path_len && i < (int)r->path.size(); ++i) r->path[i] = e.path[i];
+                o.submit_ns = r->t_submit;
+                o.done_ns = now;
+                r->state = 2;
+                E->done.push_back(r->id);
+                E->st.completed += 1;
+                E->st.early_completions += 1;
+                sl.reqs[k] = nullptr;
+                sl.results[k].path = nullptr;  // the batch's collection writes no path for it
+                sl.results[k].path_cap = 0;
+                --sl.pending;
+                progressed = true;
+            }
+        }
         // completions
         for (EngineSlot &sl : E->slots) {
             if (!sl.busy) continue;
@@ -2706,6 +2774,7 @@ static void engine_loop(gmt_engine *E) {
             const int64_t now = steady_ns();
             for (size_t k = 0; k < sl.reqs.size(); ++k) {
                 EngineReq *r = sl.reqs[k];
+                if (!r) continue;  // completed from its early copy
                 r->res = sl.results[k];
                 if (cs != GMT_OK) r->res.status = cs;
                 r->res.path = nullptr;
@@ -2771,6 +2840,25 @@ static void engine_loop(gmt_engine *E) {
             std::memset(&bo, 0, sizeof bo);
             bo.plan = E->o.plan;
             bo.workgroups = E->o.workgroups;
+            // batches of uneven queries (several cost kinds, or sizes more
+            // than a factor 2 apart) hand back each query as it ends; in an
+            // even batch the queries end close together and the copies'
+            // system-scope releases would cost more than they gain; a lone
+            // plan ends with its launch
+            bool uneven = false;
+            {
+                int nlo = 0x7fffffff, nhi = 0, kind0 = -1;
+                for (const EngineReq *r : sl.reqs) {
+                    const gmt_roadmap *rm = r->prob.roadmap;
+                    nlo = std::min(nlo, rm->n);
+                    nhi = std::max(nhi, rm->n);
+                    if (kind0 < 0) kind0 = rm->kind;
+                    uneven = uneven || rm->kind != kind0;
+                }
+                uneven = uneven || nhi > 2 * (long long)nlo;
+            }
+            sl.run.early = !lone && sl.reqs.size() > 1 && uneven;
+            sl.pending = (int)sl.reqs.size();
             gmt_status ss = batch_stage(sl.probs.data(), (int)sl.probs.size(), bo, lone, nullptr, sl.run, sl.stream);
             if (lone) E->st.lone_launches += 1;
             if (ss == GMT_OK) ss = batch_launch(sl.run, sl.stream);
@@ -3009,6 +3097,7 @@ extern "C" gmt_status gmt_shutdown(void) {
                 if (w->join[k]) (void)hipEventDestroy(w->join[k]);
             }
             if (w->fork) (void)hipEventDestroy(w->fork);
+            if (w->early_h) (void)hipHostFree(w->early_h);
             delete w;
         }
         g_ws.clear();

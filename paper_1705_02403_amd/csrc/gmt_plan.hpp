@@ -127,6 +127,9 @@ struct ProbDev {
     // per-iteration records (null: none); at most trace_cap are written
     struct TraceRec *trace;
     int trace_cap;
+    // host-visible copy of the query's result, written as soon as the query
+    // ends (null: none) so a host can take it before the launch finishes
+    struct Result *early;
 };
 
 // one record per iteration with a non-empty group (iteration 0 included):
@@ -152,6 +155,7 @@ struct Result {
     int status, iters, path_len, z;
     double path_cost;
     int abort, trace_len;
+    int ready, pad;  // early copies: set (release, system scope) once the rest is written
     unsigned long long work[W_COUNT];
     int path[GMT_PATH_INLINE];
 };
@@ -1389,6 +1393,22 @@ __device__ void run_query(const Team &t, const ProbDev &P, const int *lbox, unsi
         }
     }
     team_sync(t);
+    // ---- early copy of the result for the host (host memory) ----
+    if (t.rank == 0 && P.early) {
+        Result *e = P.early;
+        e->status = res->status;
+        e->iters = res->iters;
+        e->path_len = res->path_len;
+        e->z = res->z;
+        e->path_cost = res->path_cost;
+        e->abort = res->abort;
+        e->trace_len = res->trace_len;
+        for (int k = 0; k < W_COUNT; ++k)
+            e->work[k] = __hip_atomic_load(&res->work[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int np = res->path_len < GMT_PATH_INLINE ? res->path_len : GMT_PATH_INLINE;
+        for (int k = 0; k < np; ++k) e->path[k] = res->path[k];
+        __hip_atomic_store(&e->ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // ---------------------------------------------------------------------------

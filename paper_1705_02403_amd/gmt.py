@@ -163,7 +163,7 @@ class gmt_engine_opts(C.Structure):
 class gmt_engine_stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "cancelled", "rejected", "batches",
                                          "queued", "inflight_bytes", "peak_inflight_bytes",
-                                         "peak_inflight_requests", "lone_launches")]
+                                         "peak_inflight_requests", "lone_launches", "early_completions")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

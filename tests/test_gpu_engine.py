@@ -2,6 +2,7 @@
 solved alone; admission keeps in-flight workspaces under the budget."""
 
 import json
+import time
 
 import numpy as np
 import pytest
@@ -72,7 +73,15 @@ def test_engine_results_equal_alone(world):
         for k in ("out_edges", "in_edges", "candidates", "commits", "open_entries", "iterations"):
             assert res.work[k] == ref[j].work[k], k
     st = eng.stats()
-    assert st["completed"] == len(order) and st["batches"] >= len(order) // 4
+    assert st["completed"] == len(order)
+    # requests of multi-query batches are handed back from the kernel's early
+    # copies, so the last batches may still be collecting: wait for them
+    assert st["early_completions"] > 0
+    t0 = time.time()
+    while st["batches"] < len(order) // 4 and time.time() - t0 < 10:
+        time.sleep(0.01)
+        st = eng.stats()
+    assert st["batches"] >= len(order) // 4
     eng.close()
 
 
