@@ -27,11 +27,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 # and WRITE_SIZE x 1.00, the factors a 1 GiB copy gives; medians of six
 # launches), for the kernel sources with this digest, by launch shape (lanes
 # per candidate, threads per workgroup); reported only while both match
-TRAFFIC = {"sources_sha256": "670db52bc596bdca950ec2caa336fbb66e545a08b2d3a6546b98bbeebb502cc4",
+TRAFFIC = {"sources_sha256": "09142274bfdf39a333cef8ccef16a254ff3fd10b99db7ef9f7df586eb960a60c",
            "batch": 4096,
-           "by_shape": {(8, 1024): int((2.0 * 50945334 + 5657766) * 1024),
-                        (16, 1024): int((2.0 * 61719607 + 5627270) * 1024),
-                        (4, 1024): int((2.0 * 46273687 + 5576009) * 1024)}}
+           "by_shape": {(8, 1024): int((2.0 * 51233252 + 5657746) * 1024),
+                        (16, 1024): int((2.0 * 61386686 + 5627096) * 1024),
+                        (4, 1024): int((2.0 * 46127507 + 5575959) * 1024)}}
 # the same for the Euclidean row kernel k_eu_rows building the 3D table at
 # n = 1048576 with tile shape 2 (medians of eight builds)
 EU_TRAFFIC = {"sources_sha256": "90ec443b3e4cc5aa71b57d2c8d3f8d52075c01bd93d7903ae2ad93c1174e5a58", "n": 1048576,
