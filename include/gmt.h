@@ -377,7 +377,8 @@ gmt_status gmt_last_work(gmt_work *out);
 
 /* Per-iteration records of query `query` (0 for gmt_plan; the caller's index
  * for gmt_plan_batch) of the last gmt_plan / gmt_plan_batch call on this
- * thread that ran with opts.trace > 0.  *len receives the number of records
+ * thread; that call keeps records only if it ran with opts.trace > 0, and
+ * every such call drops the previous call's.  *len receives the number of records
  * kept (the iterations run, iteration 0 included, up to opts.trace); the first
  * min(*len, cap) are copied to `out` (host memory; may be NULL when cap is
  * 0).  GMT_EINVAL when the last call kept no records or `query` lies outside
